@@ -1,0 +1,12 @@
+"""Seeded synthetic inputs shared by the CPU oracle tests and the HIP path.
+
+Holds geometry parameters and phantom/data generation only: no projector, prox or
+iteration of the reconstruction method lives here."""
+from .geometry import (Geometry, config1_2d, mmr, small_3d, slab, slice_2d,
+                       span11_segments)
+from .phantom import (Ellipsoid, brain_problem, config1_problem, line_integrals,
+                      make_data, phantom_2d, phantom_brain, voxelise)
+
+__all__ = ["Geometry", "config1_2d", "mmr", "small_3d", "slab", "slice_2d",
+           "span11_segments", "Ellipsoid", "brain_problem", "config1_problem",
+           "line_integrals", "make_data", "phantom_2d", "phantom_brain", "voxelise"]

@@ -1,0 +1,135 @@
+"""Scanner and image geometry descriptions (parameters only, no arithmetic of the method).
+
+A geometry is the set of numbers that both the CPU oracle and the HIP library need to
+describe the same system: image grid, radial sampling, number of angles over [0, pi),
+and the oblique segments (plane count and axial slope per segment).  The paper leaves
+the geometry to its projector package (Section "Numerical Results"); the reading used
+everywhere in this repository is a parallel-beam, ray-driven Joseph model:
+
+* voxel centres ``(i - (n-1)/2) * v`` per axis, image stored ``[z][y][x]``;
+* angle ``phi_a = a * pi / n_ang``, radial position ``s_k = (k - (n_rad-1)/2) * d_rad``;
+* segment ``g`` holds ``N_g`` planes with axial centres ``(p - (N_g-1)/2) * vz`` and a
+  constant axial slope ``tau_g`` (dz per mm of in-plane path);
+* sinogram stored ``[angle][plane][radial]``, planes ordered by segment 0, +1, -1, +2, -2 ...
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Tuple
+
+
+@dataclasses.dataclass(frozen=True)
+class Geometry:
+    nx: int
+    ny: int
+    nz: int
+    vx: float
+    vy: float
+    vz: float
+    n_rad: int
+    d_rad: float
+    n_ang: int
+    seg_planes: Tuple[int, ...] = (1,)
+    seg_tan: Tuple[float, ...] = (0.0,)
+
+    def __post_init__(self):
+        if len(self.seg_planes) != len(self.seg_tan):
+            raise ValueError("seg_planes and seg_tan differ in length")
+        for n in self.seg_planes:
+            if n <= 0 or n > self.nz or (self.nz - n) % 2:
+                raise ValueError(f"segment plane count {n} incompatible with nz={self.nz}")
+
+    @property
+    def n_seg(self) -> int:
+        return len(self.seg_planes)
+
+    @property
+    def n_planes(self) -> int:
+        return int(sum(self.seg_planes))
+
+    @property
+    def image_shape(self) -> Tuple[int, int, int]:
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def sino_shape(self) -> Tuple[int, int, int]:
+        return (self.n_ang, self.n_planes, self.n_rad)
+
+    @property
+    def n_vox(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_bins(self) -> int:
+        return self.n_ang * self.n_planes * self.n_rad
+
+    def plane_segment(self, q: int) -> Tuple[int, int]:
+        """Return (segment, local plane index) of sinogram plane q."""
+        for g, n in enumerate(self.seg_planes):
+            if q < n:
+                return g, q
+            q -= n
+        raise IndexError(q)
+
+    def subset_angles(self, n_subsets: int, i: int):
+        """Equidistantly divided angles: subset i holds angles i, i+m, i+2m, ..."""
+        return list(range(i, self.n_ang, n_subsets))
+
+
+def config1_2d() -> Geometry:
+    """2-D single slice: 64x64 image at 4 mm, 90 angles x 95 radial bins at 4 mm."""
+    return Geometry(nx=64, ny=64, nz=1, vx=4.0, vy=4.0, vz=4.0,
+                    n_rad=95, d_rad=4.0, n_ang=90)
+
+
+def span11_segments(nz: int, n_seg: int, vz: float, ring_radius: float = 328.0):
+    """Span-11 style oblique segments: 0, +1, -1, ... with N_g = nz - 2(11|g| - 5).
+
+    The axial slope of segment g is the mean ring difference 11|g| times the ring pitch
+    (2 vz) over the detector diameter (2 R)."""
+    planes, tans = [nz], [0.0]
+    g = 1
+    while len(planes) < n_seg:
+        n = nz - 2 * (11 * g - 5)
+        if n <= 0:
+            raise ValueError("too many segments for nz")
+        t = 11 * g * (2.0 * vz) / (2.0 * ring_radius)
+        planes += [n, n]
+        tans += [t, -t]
+        g += 1
+    return tuple(planes[:n_seg]), tuple(tans[:n_seg])
+
+
+def mmr(nz: int = 127, n_seg: int = 11, n_rad: int = 344, n_ang: int = 252,
+        nxy: int = 344, vxy: float = 2.08, vz: float = 2.08) -> Geometry:
+    """mMR-shaped span-11 cylinder: 344x344x127 at 2.08 mm, 344 x 252 x 837."""
+    planes, tans = span11_segments(nz, n_seg, vz)
+    return Geometry(nx=nxy, ny=nxy, nz=nz, vx=vxy, vy=vxy, vz=vz,
+                    n_rad=n_rad, d_rad=vxy, n_ang=n_ang,
+                    seg_planes=planes, seg_tan=tans)
+
+
+def small_3d(nxy: int = 24, nz: int = 9, n_rad: int = 26, n_ang: int = 12,
+             v: float = 4.0, tan1: float = 0.25) -> Geometry:
+    """Small oblique test geometry: segments 0 (nz planes) and +-1 (nz-4 planes)."""
+    return Geometry(nx=nxy, ny=nxy, nz=nz, vx=v, vy=v, vz=v, n_rad=n_rad, d_rad=v,
+                    n_ang=n_ang, seg_planes=(nz, nz - 4, nz - 4),
+                    seg_tan=(0.0, tan1, -tan1))
+
+
+def slab(nz: int, nxy: int = 344, v: float = 2.08) -> Geometry:
+    """mMR slab: segment 0 (nz planes) plus +-1 (nz-12 planes), 252 angles."""
+    planes, tans = span11_segments(nz, 3, v)
+    return Geometry(nx=nxy, ny=nxy, nz=nz, vx=v, vy=v, vz=v, n_rad=nxy, d_rad=v,
+                    n_ang=int(round(252 * nxy / 344)), seg_planes=planes, seg_tan=tans)
+
+
+def slice_2d(n: int, v: float = 2.08) -> Geometry:
+    """2-D N x N slice at 2.08 mm with N radial bins and round(252 N / 344) angles."""
+    return Geometry(nx=n, ny=n, nz=1, vx=v, vy=v, vz=v, n_rad=n, d_rad=v,
+                    n_ang=int(round(252 * n / 344)))
+
+
+def fov_diagonal(g: Geometry) -> float:
+    return math.hypot(g.nx * g.vx, g.ny * g.vy)

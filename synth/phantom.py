@@ -1,0 +1,252 @@
+"""Seeded synthetic PET inputs: ellipse / ellipsoid phantoms with analytic sinograms.
+
+Nothing here is the reconstruction method.  The expected data are exact line integrals
+through the continuous phantom (chord length of each ellipsoid times its value), so the
+data do not come from either projector under test.  Every random number is drawn from a
+``numpy.random.Generator(PCG64(seed))``.
+
+Outputs (all float32, sinogram ``[angle][plane][radial]``, image ``[z][y][x]``):
+``b`` Poisson counts, ``r`` background, ``mult`` = normalisation * attenuation factors,
+``x_true`` voxelised activity, ``mu`` voxelised attenuation, ``side`` MR-like image.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List
+
+import numpy as np
+
+from .geometry import Geometry
+
+MU_WATER = 0.0096  # 1/mm
+
+
+@dataclasses.dataclass
+class Ellipsoid:
+    cx: float
+    cy: float
+    cz: float
+    ax: float
+    ay: float
+    az: float  # math.inf for a 2-D ellipse (infinite cylinder along z)
+    theta: float  # rotation about z
+    value: float
+
+
+def _ray_params(g: Geometry, a: int):
+    """Per-ray start points and direction for angle a (all planes x radial bins)."""
+    phi = math.pi * a / g.n_ang
+    c, s = math.cos(phi), math.sin(phi)
+    r = (np.arange(g.n_rad) - 0.5 * (g.n_rad - 1)) * g.d_rad
+    zp, tau = [], []
+    for n, t in zip(g.seg_planes, g.seg_tan):
+        zp.append((np.arange(n) - 0.5 * (n - 1)) * g.vz)
+        tau.append(np.full(n, t))
+    zp = np.concatenate(zp)[:, None]
+    tau = np.concatenate(tau)[:, None]
+    px = np.broadcast_to(r * c, (g.n_planes, g.n_rad))
+    py = np.broadcast_to(r * s, (g.n_planes, g.n_rad))
+    pz = np.broadcast_to(zp, (g.n_planes, g.n_rad))
+    dx, dy = -s, c
+    dz = np.broadcast_to(tau, (g.n_planes, g.n_rad))
+    return px, py, pz, dx, dy, dz
+
+
+def chord_lengths(g: Geometry, a: int, e: Ellipsoid) -> np.ndarray:
+    """3-D length of every ray of angle a inside ellipsoid e, shape [planes][radial]."""
+    px, py, pz, dx, dy, dz = _ray_params(g, a)
+    ct, st = math.cos(e.theta), math.sin(e.theta)
+    # rotate into the ellipsoid frame
+    ox, oy, oz = px - e.cx, py - e.cy, pz - e.cz
+    ux = ct * ox + st * oy
+    uy = -st * ox + ct * oy
+    uz = oz
+    wx = ct * dx + st * dy
+    wy = -st * dx + ct * dy
+    wz = dz
+    iax, iay = 1.0 / e.ax ** 2, 1.0 / e.ay ** 2
+    iaz = 0.0 if math.isinf(e.az) else 1.0 / e.az ** 2
+    alpha = wx * wx * iax + wy * wy * iay + wz * wz * iaz
+    beta = wx * ux * iax + wy * uy * iay + wz * uz * iaz
+    gamma = ux * ux * iax + uy * uy * iay + uz * uz * iaz - 1.0
+    disc = beta * beta - alpha * gamma
+    dt = np.where(disc > 0, 2.0 * np.sqrt(np.maximum(disc, 0.0)) / alpha, 0.0)
+    return dt * np.sqrt(1.0 + dz * dz)
+
+
+def line_integrals(g: Geometry, ells: List[Ellipsoid]) -> np.ndarray:
+    out = np.zeros(g.sino_shape, dtype=np.float64)
+    for a in range(g.n_ang):
+        acc = out[a]
+        for e in ells:
+            acc += e.value * chord_lengths(g, a, e)
+    return out
+
+
+def voxelise(g: Geometry, ells: List[Ellipsoid], supersample: int = 2) -> np.ndarray:
+    """Mean of the phantom over each voxel, by point sampling on a sub-grid."""
+    img = np.zeros(g.image_shape, dtype=np.float64)
+    ss = supersample
+    offs = (np.arange(ss) + 0.5) / ss - 0.5
+    zs_sub = offs if g.nz > 1 else np.array([0.0])
+    x0 = (np.arange(g.nx) - 0.5 * (g.nx - 1)) * g.vx
+    y0 = (np.arange(g.ny) - 0.5 * (g.ny - 1)) * g.vy
+    z0 = (np.arange(g.nz) - 0.5 * (g.nz - 1)) * g.vz
+    n = 0
+    for oz in zs_sub:
+        Z = (z0 + oz * g.vz)[:, None, None]
+        for oy in offs:
+            Y = (y0 + oy * g.vy)[None, :, None]
+            for ox in offs:
+                X = (x0 + ox * g.vx)[None, None, :]
+                for e in ells:
+                    ct, st = math.cos(e.theta), math.sin(e.theta)
+                    u = ct * (X - e.cx) + st * (Y - e.cy)
+                    v = -st * (X - e.cx) + ct * (Y - e.cy)
+                    w = 0.0 if math.isinf(e.az) else (Z - e.cz) / e.az
+                    inside = (u / e.ax) ** 2 + (v / e.ay) ** 2 + w ** 2 <= 1.0
+                    img += e.value * inside
+                n += 1
+    return img / n
+
+
+def _non_overlapping(rng, body: Ellipsoid, count: int, rmin: float, rmax: float,
+                     flat: bool, taken=None):
+    """Random ellipsoids inside `body` whose bounding spheres do not overlap."""
+    out = [] if taken is None else list(taken)
+    made = []
+    tries = 0
+    while len(made) < count and tries < 20000:
+        tries += 1
+        ax, ay = rng.uniform(rmin, rmax, size=2)
+        az = math.inf if flat else rng.uniform(rmin, rmax)
+        R = max(ax, ay) if flat else max(ax, ay, az)
+        # centre uniformly inside the body's shrunken ellipsoid
+        u = rng.uniform(-1, 1, size=3)
+        if flat:
+            u[2] = 0.0
+        if np.sum(u * u) > 1.0:
+            continue
+        shrink = 0.8
+        cx = body.cx + u[0] * max(body.ax - R / shrink, 0) * shrink
+        cy = body.cy + u[1] * max(body.ay - R / shrink, 0) * shrink
+        cz = 0.0 if flat else body.cz + u[2] * max(body.az - R / shrink, 0) * shrink
+        ok = True
+        for o in out:
+            Ro = max(o.ax, o.ay) if flat else max(o.ax, o.ay, o.az)
+            d = math.sqrt((cx - o.cx) ** 2 + (cy - o.cy) ** 2 + (0 if flat else (cz - o.cz) ** 2))
+            if d < R + Ro + 1.0:
+                ok = False
+                break
+        if not ok:
+            continue
+        e = Ellipsoid(cx, cy, cz, ax, ay, az, rng.uniform(0, math.pi), 0.0)
+        out.append(e)
+        made.append(e)
+    return made
+
+
+def phantom_2d(rng, g: Geometry, n_ellipses: int = 8):
+    """Body ellipse (activity 1, water attenuation) with n random inner ellipses whose
+    total activity is U(0, 4).  Returns (activity ellipses, attenuation ellipses)."""
+    fov = 0.5 * min(g.nx * g.vx, g.ny * g.vy)
+    body = Ellipsoid(0.0, 0.0, 0.0, 0.85 * fov, 0.7 * fov, math.inf, 0.0, 1.0)
+    inner = _non_overlapping(rng, body, n_ellipses, 0.06 * fov, 0.2 * fov, flat=True)
+    for e in inner:
+        e.value = rng.uniform(0.0, 4.0) - body.value
+    act = [body] + inner
+    att = [dataclasses.replace(body, value=MU_WATER)]
+    return act, att
+
+
+def phantom_brain(rng, g: Geometry, n_min: int = 8, n_max: int = 12):
+    """Head ellipsoid (water), brain (activity 1), 8-12 inner ellipsoids with total
+    activity U(0, 4), and two ventricles of activity 0."""
+    zext = 0.5 * g.nz * g.vz
+    head = Ellipsoid(0.0, 0.0, 0.0, 80.0, 100.0, min(95.0, 0.9 * zext), 0.0, 0.25)
+    brain = Ellipsoid(0.0, 5.0, 0.0, 68.0, 86.0, min(80.0, 0.8 * zext), 0.0, 0.75)
+    vz = min(22.0, 0.35 * brain.az)
+    vent = [Ellipsoid(-12.0, 5.0, 0.0, 7.0, 25.0, vz, 0.15, -1.0),
+            Ellipsoid(12.0, 5.0, 0.0, 7.0, 25.0, vz, -0.15, -1.0)]
+    count = int(rng.integers(n_min, n_max + 1))
+    inner = _non_overlapping(rng, brain, count, 6.0, 16.0, flat=False, taken=vent)
+    for e in inner:
+        e.value = rng.uniform(0.0, 4.0) - 1.0
+    act = [head, brain] + vent + inner
+    att = [dataclasses.replace(head, value=MU_WATER)]
+    labels = dict(head=head, brain=brain, vent=vent, inner=inner)
+    return act, att, labels
+
+
+def _gauss_blur_radial(sino: np.ndarray, sigma_bins: float) -> np.ndarray:
+    from scipy.ndimage import gaussian_filter1d
+    return gaussian_filter1d(sino, sigma_bins, axis=-1, mode="constant", truncate=4.0)
+
+
+def make_data(g: Geometry, seed: int, counts: float, act, att,
+              background: str = "const10"):
+    """Analytic expected data and Poisson counts.
+
+    background "const10": r constant = 10% of the mean trues.
+    background "rs30": smooth randoms (constant) + scatter (trues blurred along the radial
+    direction with sigma 50 mm), half each, summing to 30% of the trues.
+    The activity is scaled so that the expected total count equals `counts`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    norm = rng.uniform(0.8, 1.2, size=g.sino_shape)
+    att_int = line_integrals(g, att)
+    mult = norm * np.exp(-att_int)
+    geo = line_integrals(g, act)
+    trues = mult * geo
+    if background == "const10":
+        rshape = np.full(g.sino_shape, 0.1 * trues.mean())
+    elif background == "rs30":
+        scatter = _gauss_blur_radial(trues, 50.0 / g.d_rad)
+        scatter *= 0.15 * trues.sum() / max(scatter.sum(), 1e-30)
+        randoms = np.full(g.sino_shape, 0.15 * trues.mean())
+        rshape = scatter + randoms
+    else:
+        raise ValueError(background)
+    scale = counts / (trues.sum() + rshape.sum())
+    ybar = scale * (trues + rshape)
+    b = rng.poisson(ybar).astype(np.float32)
+    return dict(b=b, r=(scale * rshape).astype(np.float32),
+                mult=mult.astype(np.float32), scale=scale)
+
+
+def config1_problem(seed: int = 18080100):
+    """Config 1: 64x64 slice, 8 ellipses, activity 0-4, water attenuation, normalisation
+    U(0.8, 1.2), constant background 10% of mean, 1e5 expected counts."""
+    from .geometry import config1_2d
+    g = config1_2d()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    act, att = phantom_2d(rng, g)
+    d = make_data(g, seed + 1, 1e5, act, att, "const10")
+    d["x_true"] = (d["scale"] * voxelise(g, act)).astype(np.float32)
+    d["mu"] = voxelise(g, att).astype(np.float32)
+    d["geom"] = g
+    return d
+
+
+def side_image(rng, g: Geometry, labels, noise: float = 0.05) -> np.ndarray:
+    """MR-like side image: WM 1.0 (brain), GM 0.6 (inner ellipsoids), CSF 0.2
+    (ventricles), background 0, plus N(0, noise^2)."""
+    brain = dataclasses.replace(labels["brain"], value=1.0)
+    parts = [brain]
+    parts += [dataclasses.replace(e, value=0.6 - 1.0) for e in labels["inner"]]
+    parts += [dataclasses.replace(e, value=0.2 - 1.0) for e in labels["vent"]]
+    img = voxelise(g, parts, supersample=1)
+    img += rng.normal(0.0, noise, size=img.shape)
+    return img.astype(np.float32)
+
+
+def brain_problem(g: Geometry, seed: int, counts: float, with_side: bool = False):
+    """Brain-like 3-D problem with randoms + scatter at 30% of trues."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    act, att, labels = phantom_brain(rng, g)
+    d = make_data(g, seed + 1, counts, act, att, "rs30")
+    d["x_true"] = (d["scale"] * voxelise(g, act, supersample=1)).astype(np.float32)
+    d["geom"] = g
+    if with_side:
+        d["side"] = side_image(np.random.Generator(np.random.PCG64(seed + 2)), g, labels)
+    return d
