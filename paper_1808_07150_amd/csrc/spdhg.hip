@@ -1,0 +1,754 @@
+// Host side of the C ABI declared in include/spdhg.h: validation, geometry tables,
+// workspace layout, step sizes (Theorem 2), the SPDHG iteration driver (Algorithm 2),
+// objective and checkpoints.  All device work is enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/spdhg.h"
+#include "kernels.hip"
+
+using namespace spdhg;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return fail(SPDHG_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                                  \
+    do {                                                                                \
+        hipError_t _e = hipGetLastError();                                              \
+        if (_e != hipSuccess)                                                           \
+            return fail(SPDHG_E_HIP, std::string("kernel launch: ") + hipGetErrorString(_e)); \
+    } while (0)
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+int64_t n_planes(const spdhg_geom* g) {
+    int64_t n = 0;
+    for (int i = 0; i < g->n_seg; ++i) n += g->seg_planes[i];
+    return n;
+}
+
+int check_geom(const spdhg_geom* g) {
+    if (!g) return fail(SPDHG_E_ARG, "geometry is NULL");
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || g->n_rad <= 0 || g->n_ang <= 0)
+        return fail(SPDHG_E_SHAPE, "geometry sizes must be positive");
+    if (!(g->vx > 0) || !(g->vy > 0) || !(g->vz > 0) || !(g->d_rad > 0))
+        return fail(SPDHG_E_SHAPE, "voxel sizes and radial spacing must be positive");
+    if (g->n_seg <= 0 || g->n_seg > SPDHG_MAX_SEG)
+        return fail(SPDHG_E_SHAPE, "n_seg out of range");
+    for (int i = 0; i < g->n_seg; ++i) {
+        if (g->seg_planes[i] <= 0 || g->seg_planes[i] > g->nz ||
+            ((g->nz - g->seg_planes[i]) & 1))
+            return fail(SPDHG_E_SHAPE, "segment plane count must be in [1, nz] with nz - N even");
+        if (!std::isfinite(g->seg_tan[i])) return fail(SPDHG_E_SHAPE, "segment slope not finite");
+    }
+    const double nv = (double)g->nx * g->ny * g->nz;
+    const double nb = (double)g->n_ang * (double)n_planes(g) * g->n_rad;
+    if (nv > 4.0e9 || nb > 8.0e9) return fail(SPDHG_E_SHAPE, "problem too large");
+    if (g->nx > 16384 || g->ny > 16384 || g->nz > 16384 || g->n_rad > 1 << 20)
+        return fail(SPDHG_E_SHAPE, "dimension too large for FP32 index arithmetic");
+    return SPDHG_OK;
+}
+
+// Host-side tables: per-angle sampling coefficients, per-(angle, segment) axial
+// coefficients (FP64) and FP32 step lengths, plane -> segment map.
+struct HostTables {
+    std::vector<AngleDev> ang;
+    std::vector<SegAngleDev> sa;
+    std::vector<int32_t> plane_seg;
+    GeomDev G;
+};
+
+void build_tables(const spdhg_geom* g, HostTables& T) {
+    const double pi = 3.14159265358979323846;
+    const int na = g->n_ang, ns = g->n_seg;
+    T.ang.resize(na);
+    T.sa.resize((size_t)na * ns);
+    for (int a = 0; a < na; ++a) {
+        const double phi = pi * (double)a / (double)na;
+        const double c = std::cos(phi), s = std::sin(phi);
+        const bool rowdom = (4 * a <= na) || (4 * a >= 3 * na);
+        AngleDev A{};
+        double dt_dj, dt_dk, L;
+        if (rowdom) {
+            const double sec = 1.0 / c, tn = s / c;
+            A.du_dk = g->d_rad * sec / g->vx;
+            A.du_dj = -tn * g->vy / g->vx;
+            A.cu = 0.5 * (g->nx - 1);
+            A.cj = 0.5 * (g->ny - 1);
+            A.n_prim = g->ny;
+            A.n_sec = g->nx;
+            dt_dj = g->vy * sec;
+            dt_dk = -g->d_rad * tn;
+            L = g->vy * std::fabs(sec);
+        } else {
+            const double csc = 1.0 / s, ct = c / s;
+            A.du_dk = g->d_rad * csc / g->vy;
+            A.du_dj = -ct * g->vx / g->vy;
+            A.cu = 0.5 * (g->ny - 1);
+            A.cj = 0.5 * (g->nx - 1);
+            A.n_prim = g->nx;
+            A.n_sec = g->ny;
+            dt_dj = -g->vx * csc;
+            dt_dk = g->d_rad * ct;
+            L = g->vx * std::fabs(csc);
+        }
+        A.rowdom = rowdom ? 1 : 0;
+        T.ang[a] = A;
+        for (int sg = 0; sg < ns; ++sg) {
+            const double tau = g->seg_tan[sg];
+            SegAngleDev S{};
+            S.ez_dj = tau / g->vz * dt_dj;
+            S.ez_dk = tau / g->vz * dt_dk;
+            S.L = (float)(L * std::sqrt(1.0 + tau * tau));
+            T.sa[(size_t)a * ns + sg] = S;
+        }
+    }
+    GeomDev& G = T.G;
+    memset(&G, 0, sizeof(G));
+    G.nx = g->nx;
+    G.ny = g->ny;
+    G.nz = g->nz;
+    G.n_rad = g->n_rad;
+    G.n_ang = na;
+    G.n_seg = ns;
+    G.ck = 0.5 * (g->n_rad - 1);
+    int base = 0;
+    for (int sg = 0; sg < ns; ++sg) {
+        G.seg_planes[sg] = g->seg_planes[sg];
+        G.seg_base[sg] = base;
+        G.seg_off[sg] = (g->nz - g->seg_planes[sg]) / 2;
+        for (int p = 0; p < g->seg_planes[sg]; ++p) T.plane_seg.push_back(sg);
+        base += g->seg_planes[sg];
+    }
+    G.n_planes = base;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t table_bytes(const HostTables& T) {
+    return align256(T.ang.size() * sizeof(AngleDev)) + align256(T.sa.size() * sizeof(SegAngleDev)) +
+           align256(T.plane_seg.size() * sizeof(int32_t));
+}
+
+// Copy the tables to `dev` (table_bytes long) and point G at them.  Blocking copy.
+int upload_tables(HostTables& T, char* dev) {
+    char* p = dev;
+    HIP_TRY(hipMemcpy(p, T.ang.data(), T.ang.size() * sizeof(AngleDev), hipMemcpyHostToDevice));
+    T.G.ang = (const AngleDev*)p;
+    p += align256(T.ang.size() * sizeof(AngleDev));
+    HIP_TRY(hipMemcpy(p, T.sa.data(), T.sa.size() * sizeof(SegAngleDev), hipMemcpyHostToDevice));
+    T.G.sa = (const SegAngleDev*)p;
+    p += align256(T.sa.size() * sizeof(SegAngleDev));
+    HIP_TRY(hipMemcpy(p, T.plane_seg.data(), T.plane_seg.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice));
+    T.G.plane_seg = (const int32_t*)p;
+    return SPDHG_OK;
+}
+
+// Geometry tables for the stand-alone projector calls, cached per (device, geometry).
+std::mutex g_cache_mu;
+std::map<std::string, GeomDev> g_cache;
+
+int cached_geom(const spdhg_geom* g, GeomDev& out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::string key((const char*)g, sizeof(spdhg_geom));
+    key += std::to_string(dev);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        out = it->second;
+        return SPDHG_OK;
+    }
+    HostTables T;
+    build_tables(g, T);
+    void* d = nullptr;
+    HIP_TRY(hipMalloc(&d, table_bytes(T)));
+    int rc = upload_tables(T, (char*)d);
+    if (rc) {
+        (void)hipFree(d);
+        return rc;
+    }
+    g_cache[key] = T.G;
+    out = T.G;
+    return SPDHG_OK;
+}
+
+int subset_angles(const spdhg_geom* g, int32_t m, int32_t i, int& ang0, int& step, int& count) {
+    if (i < 0) {
+        ang0 = 0;
+        step = 1;
+        count = g->n_ang;
+        return SPDHG_OK;
+    }
+    if (m <= 0 || m > g->n_ang || i >= m) return fail(SPDHG_E_ARG, "bad subset index");
+    ang0 = i;
+    step = m;
+    count = (g->n_ang - i + m - 1) / m;
+    return SPDHG_OK;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014), counter form: output k of a generator seeded
+// with `seed` is mix(seed + (k + 1) * golden).
+inline uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double grad_norm(int nx, int ny, int nz) {
+    // largest singular value of forward differences with Neumann ends: the sum over axes
+    // of the path-graph Laplacian maxima 4 sin^2(pi (N-1) / (2N))
+    const double pi = 3.14159265358979323846;
+    double s = 0.0;
+    for (int n : {nx, ny, nz}) {
+        const double v = std::sin(pi * (n - 1) / (2.0 * n));
+        s += v * v;
+    }
+    return 2.0 * std::sqrt(s);
+}
+
+}  // namespace
+
+// ====================================================================== context
+struct spdhg_ctx {
+    spdhg_geom geom;
+    spdhg_params prm;
+    HostTables tab;
+    int device = 0;
+    const float *b = nullptr, *r = nullptr, *mult = nullptr, *side = nullptr;
+    float* x_user = nullptr;
+    // workspace regions
+    float *y = nullptr, *sigma = nullptr, *dscr = nullptr, *x2 = nullptr, *z = nullptr,
+          *T = nullptr, *yn[2] = {nullptr, nullptr}, *xi = nullptr;
+    double* part = nullptr;
+    double* scal = nullptr;  // 8 doubles of device scalars
+    int64_t part_n = 0;
+    int x_cur = 0;   // 0: iterate in x_user, 1: in x2
+    int yn_cur = 0;
+    int m = 1, n = 1, n_prior = 0;
+    std::vector<double> p, cum;
+    std::vector<double> data_norm, data_sigma;
+    double prior_norm = 0.0, prior_sigma = 0.0;
+    int64_t k = 0;
+    int64_t iters_per_epoch = 1;
+    int64_t nv = 0, nb = 0, max_sub_bins = 0;
+    float* xcur() { return x_cur ? x2 : x_user; }
+    float* xother() { return x_cur ? x_user : x2; }
+};
+
+namespace {
+
+struct Layout {
+    size_t tables, y, sigma, dscr, x2, z, T, yn, xi, part, scal, total;
+    int64_t part_n;
+};
+
+Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab) {
+    Layout L{};
+    const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
+    const int64_t np = n_planes(g);
+    const int64_t nb = (int64_t)g->n_ang * np * g->n_rad;
+    const int m = std::max(1, p->n_subsets);
+    const int64_t max_sub = (int64_t)((g->n_ang + m - 1) / m) * np * g->n_rad;
+    const bool prior = p->prior == SPDHG_PRIOR_TV || p->prior == SPDHG_PRIOR_DTV;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.tables = take(table_bytes(tab));
+    L.y = take(nb * 4);
+    L.sigma = take(p->precond ? nb * 4 : 0);
+    L.dscr = take(std::max(max_sub, nv) * 4);
+    L.x2 = take(nv * 4);
+    L.z = take(nv * 4);
+    L.T = take(nv * 4);
+    L.yn = take(prior ? 6 * nv * 4 : 0);
+    L.xi = take(p->prior == SPDHG_PRIOR_DTV ? 3 * nv * 4 : 0);
+    L.part_n = std::max<int64_t>({(nb + BLOCK - 1) / BLOCK, (nv + BLOCK - 1) / BLOCK, 1}) * 2;
+    L.part = take(L.part_n * 8);
+    L.scal = take(8 * 8);
+    L.total = off;
+    return L;
+}
+
+int check_params(const spdhg_geom* g, const spdhg_params* p) {
+    if (!p) return fail(SPDHG_E_ARG, "params is NULL");
+    if (p->n_subsets < 1 || p->n_subsets > g->n_ang)
+        return fail(SPDHG_E_ARG, "n_subsets must be in [1, n_ang]");
+    if (p->prior != SPDHG_PRIOR_NONE && p->prior != SPDHG_PRIOR_TV && p->prior != SPDHG_PRIOR_DTV)
+        return fail(SPDHG_E_NOTIMPL, "prior not implemented");
+    if (p->sampling != SPDHG_SAMPLING_UNIFORM && p->sampling != SPDHG_SAMPLING_BALANCED)
+        return fail(SPDHG_E_ARG, "unknown sampling");
+    if (!(p->gamma > 0) || !(p->rho > 0) || !(p->rho < 1))
+        return fail(SPDHG_E_ARG, "need gamma > 0 and 0 < rho < 1");
+    if (p->prior != SPDHG_PRIOR_NONE && !(p->alpha >= 0))
+        return fail(SPDHG_E_ARG, "prior weight must be >= 0");
+    if (p->prior == SPDHG_PRIOR_DTV && (!(p->eta > 0) || !(p->gamma_d >= 0) || !(p->gamma_d <= 1)))
+        return fail(SPDHG_E_ARG, "dTV needs eta > 0 and gamma_d in [0, 1]");
+    if (!p->precond && p->power_iters < 1) return fail(SPDHG_E_ARG, "power_iters must be >= 1");
+    return SPDHG_OK;
+}
+
+// Sum of `n` partials into scal[slot] (times `scale`), then copy to host if `host`.
+int reduce_to(spdhg_ctx* c, int64_t n, int slot, double scale, hipStream_t st) {
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, n, c->scal, slot, scale);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+// ||A v||^2 / ||v||^2 style power iteration for data block i (scalar steps): returns
+// sqrt of the Rayleigh growth of A_i^T A_i from the ones image.
+int power_norm_data(spdhg_ctx* c, int i, double* out, hipStream_t st) {
+    int ang0, step, cnt;
+    int rc = subset_angles(&c->geom, c->m, i, ang0, step, cnt);
+    if (rc) return rc;
+    const int64_t nv = c->nv;
+    const int64_t nsub = (int64_t)cnt * c->tab.G.n_planes * c->geom.n_rad;
+    float* v = c->x2;
+    float* w = c->z;
+    float* tmp = c->y;  // full-size scratch during init
+    fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, 1.0f);
+    sumsq<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, c->part);
+    reduce_to(c, nblocks(nv), 0, 1.0, st);
+    scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(v, v, nv, c->scal);
+    for (int it = 0; it < c->prm.power_iters; ++it) {
+        // w = A_i^T A_i v = G^T diag(mult) (mult * G v)
+        fwd_plain<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, v, c->mult, tmp, ang0, step, cnt);
+        bwd_plain<<<nblocks(nv), BLOCK, 0, st>>>(c->tab.G, tmp, 0, 1, ang0, step, cnt, w, c->mult);
+        LAUNCH_CHECK();
+        sumsq<<<nblocks(nv), BLOCK, 0, st>>>(w, nv, c->part);
+        reduce_to(c, nblocks(nv), 0, 1.0, st);
+        scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(w, v, nv, c->scal);
+    }
+    double h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&h, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = std::sqrt(std::sqrt(h));
+    return SPDHG_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* spdhg_last_error(void) { return g_err.c_str(); }
+
+int64_t spdhg_subset_bins(const spdhg_geom* geom, int32_t n_subsets, int32_t subset) {
+    if (check_geom(geom)) return -1;
+    int a0, st, cnt;
+    if (subset_angles(geom, n_subsets, subset, a0, st, cnt)) return -1;
+    return (int64_t)cnt * n_planes(geom) * geom->n_rad;
+}
+
+int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, const float* mult,
+                  const float* x, float* y_out, void* stream) {
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (!x || !y_out) return fail(SPDHG_E_ARG, "NULL image or output");
+    int a0, step, cnt;
+    rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
+    if (rc) return rc;
+    GeomDev G;
+    rc = cached_geom(geom, G);
+    if (rc) return rc;
+    const int64_t n = (int64_t)cnt * G.n_planes * G.n_rad;
+    hipStream_t st = (hipStream_t)stream;
+    fwd_plain<<<nblocks(n), BLOCK, 0, st>>>(G, x, mult, y_out, a0, step, cnt);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
+                      const float* mult, const float* y, float* x_out, void* stream) {
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (!y || !x_out) return fail(SPDHG_E_ARG, "NULL sinogram or output");
+    int a0, step, cnt;
+    rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
+    if (rc) return rc;
+    GeomDev G;
+    rc = cached_geom(geom, G);
+    if (rc) return rc;
+    const int64_t nv = (int64_t)geom->nx * geom->ny * geom->nz;
+    hipStream_t st = (hipStream_t)stream;
+    bwd_plain<<<nblocks(nv), BLOCK, 0, st>>>(G, y, 0, 1, a0, step, cnt, x_out, mult);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+int spdhg_workspace_bytes(const spdhg_geom* geom, const spdhg_params* params, size_t* bytes) {
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    rc = check_params(geom, params);
+    if (rc) return rc;
+    if (!bytes) return fail(SPDHG_E_ARG, "bytes is NULL");
+    HostTables T;
+    build_tables(geom, T);
+    *bytes = layout(geom, params, T).total;
+    return SPDHG_OK;
+}
+
+int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* params,
+               const float* b, const float* r, const float* mult, const float* side, float* x,
+               void* ws, size_t ws_bytes, void* stream) {
+    if (!out) return fail(SPDHG_E_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    rc = check_params(geom, params);
+    if (rc) return rc;
+    if (!b || !r || !mult || !x) return fail(SPDHG_E_ARG, "NULL b, r, mult or x");
+    if (params->prior == SPDHG_PRIOR_DTV && !side) return fail(SPDHG_E_ARG, "dTV needs a side image");
+    if (!ws) return fail(SPDHG_E_WORKSPACE, "workspace is NULL");
+    hipStream_t st = (hipStream_t)stream;
+
+    spdhg_ctx* c = new spdhg_ctx();
+    c->geom = *geom;
+    c->prm = *params;
+    build_tables(geom, c->tab);
+    Layout L = layout(geom, params, c->tab);
+    if (ws_bytes < L.total) {
+        delete c;
+        return fail(SPDHG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+    }
+    if (((uintptr_t)ws) & 255) {
+        delete c;
+        return fail(SPDHG_E_WORKSPACE, "workspace must be 256-byte aligned");
+    }
+    hipGetDevice(&c->device);
+    char* w = (char*)ws;
+    // the tables are copied synchronously before any kernel on `st` may use them
+    rc = upload_tables(c->tab, w + L.tables);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    c->b = b;
+    c->r = r;
+    c->mult = mult;
+    c->side = side;
+    c->x_user = x;
+    c->y = (float*)(w + L.y);
+    c->sigma = params->precond ? (float*)(w + L.sigma) : nullptr;
+    c->dscr = (float*)(w + L.dscr);
+    c->x2 = (float*)(w + L.x2);
+    c->z = (float*)(w + L.z);
+    c->T = (float*)(w + L.T);
+    const bool prior = params->prior != SPDHG_PRIOR_NONE;
+    c->nv = (int64_t)geom->nx * geom->ny * geom->nz;
+    c->nb = (int64_t)geom->n_ang * c->tab.G.n_planes * geom->n_rad;
+    if (prior) {
+        c->yn[0] = (float*)(w + L.yn);
+        c->yn[1] = c->yn[0] + 3 * c->nv;
+    }
+    c->xi = params->prior == SPDHG_PRIOR_DTV ? (float*)(w + L.xi) : nullptr;
+    c->part = (double*)(w + L.part);
+    c->part_n = L.part_n;
+    c->scal = (double*)(w + L.scal);
+    c->m = params->n_subsets;
+    c->n_prior = prior ? 1 : 0;
+    c->n = c->m + c->n_prior;
+    // probabilities (Section 4.2)
+    c->p.assign(c->n, 1.0 / c->n);
+    if (params->sampling == SPDHG_SAMPLING_BALANCED && c->n_prior > 0) {
+        for (int i = 0; i < c->m; ++i) c->p[i] = 1.0 / (2.0 * c->m);
+        for (int j = 0; j < c->n_prior; ++j) c->p[c->m + j] = 0.5 / c->n_prior;
+    }
+    c->cum.resize(c->n);
+    double acc = 0.0;
+    for (int i = 0; i < c->n; ++i) {
+        acc += c->p[i];
+        c->cum[i] = acc;
+    }
+    c->cum[c->n - 1] = 1.0;
+    double pdata = 0.0;
+    for (int i = 0; i < c->m; ++i) pdata += c->p[i];
+    c->iters_per_epoch = (int64_t)std::llround(c->m / pdata);
+    const int64_t nv = c->nv, nb = c->nb;
+    const double gam = params->gamma, rho = params->rho;
+
+    // domain check: needs A 1 > 0 per bin; computed into y (zeroed afterwards)
+    fwd_sens<<<nblocks(nb), BLOCK, 0, st>>>(c->tab.G, mult, c->y, 1.0f);
+    LAUNCH_CHECK();
+    {
+        const int64_t nbk = nblocks(nb);
+        if (2 * nbk > c->part_n) {
+            delete c;
+            return fail(SPDHG_E_WORKSPACE, "partials buffer too small");
+        }
+        domain_check<<<nbk, BLOCK, 0, st>>>(b, r, mult, c->y, nb, c->part, nbk);
+        reduce_final<<<1, BLOCK, 0, st>>>(c->part, nbk, c->scal, 0, 1.0);
+        reduce_final<<<1, BLOCK, 0, st>>>(c->part + nbk, nbk, c->scal, 1, 1.0);
+        LAUNCH_CHECK();
+        double h[2];
+        HIP_TRY(hipMemcpyAsync(h, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h[0] > 0) {
+            delete c;
+            return fail(SPDHG_E_DOMAIN, "b < 0, r < 0, mult <= 0 or non-finite data in " +
+                                            std::to_string((long long)h[0]) + " bins");
+        }
+        if (h[1] > 0) {
+            delete c;
+            return fail(SPDHG_E_DOMAIN, std::to_string((long long)h[1]) +
+                                            " bins have b > 0, r = 0 and no voxel on the ray");
+        }
+    }
+    // step sizes (Theorem 2)
+    double t_data_scalar = INFINITY;
+    if (params->precond) {
+        fwd_sens<<<nblocks(nb), BLOCK, 0, st>>>(c->tab.G, mult, c->sigma, (float)(gam * rho));
+        fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->T, nv, INFINITY);
+        for (int i = 0; i < c->m; ++i) {
+            int a0, step, cnt;
+            subset_angles(geom, c->m, i, a0, step, cnt);
+            bwd_sens_min<<<nblocks(nv), BLOCK, 0, st>>>(c->tab.G, mult, a0, step, cnt,
+                                                        (float)(rho * c->p[i] / gam), c->T);
+        }
+        LAUNCH_CHECK();
+    } else {
+        c->data_norm.resize(c->m);
+        c->data_sigma.resize(c->m);
+        for (int i = 0; i < c->m; ++i) {
+            double nrm = 0.0;
+            rc = power_norm_data(c, i, &nrm, st);
+            if (rc) {
+                delete c;
+                return rc;
+            }
+            c->data_norm[i] = nrm;
+            c->data_sigma[i] = gam * rho / nrm;
+            t_data_scalar = std::min(t_data_scalar, rho * c->p[i] / (gam * nrm));
+        }
+        fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->T, nv, (float)t_data_scalar);
+    }
+    double t_prior = INFINITY;
+    if (prior) {
+        if (params->prior == SPDHG_PRIOR_DTV) {
+            dtv_field<<<nblocks(nv), BLOCK, 0, st>>>(geom->nx, geom->ny, geom->nz, side,
+                                                     (float)params->eta, c->xi);
+            LAUNCH_CHECK();
+        }
+        // ||grad|| in closed form; ||D grad|| <= ||D|| ||grad|| <= ||grad|| for
+        // gamma_d in [0, 1], so the same bound keeps the step condition for dTV
+        c->prior_norm = grad_norm(geom->nx, geom->ny, geom->nz);
+        c->prior_sigma = gam * rho / c->prior_norm;
+        t_prior = rho * c->p[c->m] / (gam * c->prior_norm);
+    }
+    finalize_T<<<nblocks(nv), BLOCK, 0, st>>>(c->T, nv, (float)t_prior);
+    // y = 0, z = 0, prior duals = 0, x = max(x0, 0)
+    HIP_TRY(hipMemsetAsync(c->y, 0, nb * 4, st));
+    HIP_TRY(hipMemsetAsync(c->z, 0, nv * 4, st));
+    if (prior) HIP_TRY(hipMemsetAsync(c->yn[0], 0, 6 * nv * 4, st));
+    clip_nonneg<<<nblocks(nv), BLOCK, 0, st>>>(x, nv);
+    LAUNCH_CHECK();
+    int64_t max_sub = 0;
+    for (int i = 0; i < c->m; ++i) {
+        int a0, step, cnt;
+        subset_angles(geom, c->m, i, a0, step, cnt);
+        max_sub = std::max<int64_t>(max_sub, (int64_t)cnt * c->tab.G.n_planes * geom->n_rad);
+    }
+    c->max_sub_bins = max_sub;
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = c;
+    return SPDHG_OK;
+}
+
+int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (n_iters < 0) return fail(SPDHG_E_ARG, "n_iters < 0");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nv = c->nv;
+    PriorArgs P{};
+    P.nx = c->geom.nx;
+    P.ny = c->geom.ny;
+    P.nz = c->geom.nz;
+    P.sigma = (float)c->prior_sigma;
+    P.alpha = (float)c->prm.alpha;
+    P.gamma_d = (float)c->prm.gamma_d;
+    P.dtv = c->prm.prior == SPDHG_PRIOR_DTV;
+    for (int64_t it = 0; it < n_iters; ++it) {
+        const uint64_t z = splitmix64(c->prm.seed, (uint64_t)c->k);
+        const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        int i = 0;
+        while (!(u < c->cum[i])) ++i;
+        const float inv_p = (float)(1.0 / c->p[i]);
+        if (i < c->m) {
+            int a0, step, cnt;
+            subset_angles(&c->geom, c->m, i, a0, step, cnt);
+            const int64_t nsub = (int64_t)cnt * c->tab.G.n_planes * c->geom.n_rad;
+            const float sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[i];
+            fwd_dual<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, c->xcur(), c->mult, c->b, c->r,
+                                                      c->sigma, sig_s, c->y, c->dscr, a0, step,
+                                                      cnt);
+            bwd_iter<<<nblocks(nv), BLOCK, 0, st>>>(c->tab.G, c->dscr, a0, step, cnt, inv_p, c->z,
+                                                    c->xcur(), c->T);
+        } else {
+            P.inv_p = inv_p;
+            tv_iter<<<nblocks(nv), BLOCK, 0, st>>>(P, c->xcur(), c->xother(), c->yn[c->yn_cur],
+                                                   c->yn[1 - c->yn_cur], c->z, c->T, c->xi);
+            c->x_cur ^= 1;
+            c->yn_cur ^= 1;
+        }
+        LAUNCH_CHECK();
+        c->k += 1;
+    }
+    if (c->x_cur) {
+        HIP_TRY(hipMemcpyAsync(c->x_user, c->x2, nv * 4, hipMemcpyDeviceToDevice, st));
+        c->x_cur = 0;
+    }
+    return SPDHG_OK;
+}
+
+int spdhg_epoch(spdhg_ctx* c, int32_t n_epochs, void* stream) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (n_epochs < 0) return fail(SPDHG_E_ARG, "n_epochs < 0");
+    return spdhg_iterate(c, (int64_t)n_epochs * c->iters_per_epoch, stream);
+}
+
+int spdhg_info(const spdhg_ctx* c, int64_t* ipe, int64_t* done) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (ipe) *ipe = c->iters_per_epoch;
+    if (done) *done = c->k;
+    return SPDHG_OK;
+}
+
+int spdhg_objective(spdhg_ctx* c, const float* x, double* out_dev, void* stream) {
+    if (!c || !out_dev) return fail(SPDHG_E_ARG, "NULL ctx or output");
+    hipStream_t st = (hipStream_t)stream;
+    const float* xx = x ? x : c->xcur();
+    const int64_t nb = c->nb, nv = c->nv;
+    fwd_obj<<<nblocks(nb), BLOCK, 0, st>>>(c->tab.G, xx, c->mult, c->b, c->r, c->part);
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nb), out_dev, 1, 1.0);
+    PriorArgs P{};
+    P.nx = c->geom.nx;
+    P.ny = c->geom.ny;
+    P.nz = c->geom.nz;
+    P.alpha = (float)c->prm.alpha;
+    P.gamma_d = (float)c->prm.gamma_d;
+    P.dtv = c->prm.prior == SPDHG_PRIOR_DTV;
+    tv_obj<<<nblocks(nv), BLOCK, 0, st>>>(P, xx, c->xi, c->part, c->prm.prior != SPDHG_PRIOR_NONE);
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), out_dev, 2, 1.0);
+    combine_objective<<<1, 64, 0, st>>>(out_dev);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+int spdhg_buffer(spdhg_ctx* c, int32_t which, float** ptr, int64_t* n) {
+    if (!c || !ptr || !n) return fail(SPDHG_E_ARG, "NULL argument");
+    switch (which) {
+        case 0: *ptr = c->y; *n = c->nb; break;
+        case 1: *ptr = c->z; *n = c->nv; break;
+        case 2: *ptr = c->T; *n = c->nv; break;
+        case 3: *ptr = c->sigma; *n = c->sigma ? c->nb : 0; break;
+        case 4: *ptr = c->yn[c->yn_cur]; *n = c->yn[0] ? 3 * c->nv : 0; break;
+        default: return fail(SPDHG_E_ARG, "unknown buffer id");
+    }
+    return SPDHG_OK;
+}
+
+int spdhg_block_info(const spdhg_ctx* c, int32_t i, double* sigma, double* p, double* norm) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (i < 0 || i >= c->n) return fail(SPDHG_E_ARG, "block index out of range");
+    if (p) *p = c->p[i];
+    if (i < c->m) {
+        if (sigma) *sigma = c->prm.precond ? NAN : c->data_sigma[i];
+        if (norm) *norm = c->prm.precond ? NAN : c->data_norm[i];
+    } else {
+        if (sigma) *sigma = c->prior_sigma;
+        if (norm) *norm = c->prior_norm;
+    }
+    return SPDHG_OK;
+}
+
+int spdhg_state_bytes(const spdhg_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return fail(SPDHG_E_ARG, "NULL argument");
+    *bytes = align256(c->nv * 4) * 2 + align256(c->nb * 4) +
+             (c->yn[0] ? align256(3 * c->nv * 4) : 0) + 256;
+    return SPDHG_OK;
+}
+
+int spdhg_save_state(spdhg_ctx* c, void* dst, size_t bytes, void* stream) {
+    size_t need = 0;
+    int rc = spdhg_state_bytes(c, &need);
+    if (rc) return rc;
+    if (!dst || bytes < need) return fail(SPDHG_E_ARG, "state buffer too small");
+    hipStream_t st = (hipStream_t)stream;
+    char* p = (char*)dst;
+    HIP_TRY(hipMemcpyAsync(p, c->xcur(), c->nv * 4, hipMemcpyDeviceToDevice, st));
+    p += align256(c->nv * 4);
+    HIP_TRY(hipMemcpyAsync(p, c->z, c->nv * 4, hipMemcpyDeviceToDevice, st));
+    p += align256(c->nv * 4);
+    HIP_TRY(hipMemcpyAsync(p, c->y, c->nb * 4, hipMemcpyDeviceToDevice, st));
+    p += align256(c->nb * 4);
+    if (c->yn[0]) {
+        HIP_TRY(hipMemcpyAsync(p, c->yn[c->yn_cur], 3 * c->nv * 4, hipMemcpyDeviceToDevice, st));
+        p += align256(3 * c->nv * 4);
+    }
+    // iteration counter: the random block sequence continues from it
+    int64_t hdr[4] = {c->k, c->nv, c->nb, 0x5350444847ll};
+    HIP_TRY(hipMemcpyAsync(p, hdr, sizeof(hdr), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SPDHG_OK;
+}
+
+int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) {
+    size_t need = 0;
+    int rc = spdhg_state_bytes(c, &need);
+    if (rc) return rc;
+    if (!src || bytes < need) return fail(SPDHG_E_ARG, "state buffer too small");
+    hipStream_t st = (hipStream_t)stream;
+    const char* p = (const char*)src;
+    const char* h = p + align256(c->nv * 4) * 2 + align256(c->nb * 4) +
+                    (c->yn[0] ? align256(3 * c->nv * 4) : 0);
+    int64_t hdr[4];
+    HIP_TRY(hipMemcpyAsync(hdr, h, sizeof(hdr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hdr[1] != c->nv || hdr[2] != c->nb || hdr[3] != 0x5350444847ll)
+        return fail(SPDHG_E_STATE, "state does not belong to this problem");
+    c->x_cur = 0;
+    c->yn_cur = 0;
+    HIP_TRY(hipMemcpyAsync(c->x_user, p, c->nv * 4, hipMemcpyDeviceToDevice, st));
+    p += align256(c->nv * 4);
+    HIP_TRY(hipMemcpyAsync(c->z, p, c->nv * 4, hipMemcpyDeviceToDevice, st));
+    p += align256(c->nv * 4);
+    HIP_TRY(hipMemcpyAsync(c->y, p, c->nb * 4, hipMemcpyDeviceToDevice, st));
+    p += align256(c->nb * 4);
+    if (c->yn[0]) HIP_TRY(hipMemcpyAsync(c->yn[0], p, 3 * c->nv * 4, hipMemcpyDeviceToDevice, st));
+    c->k = hdr[0];
+    return SPDHG_OK;
+}
+
+int spdhg_destroy(spdhg_ctx* c) {
+    delete c;
+    return SPDHG_OK;
+}
+
+}  // extern "C"

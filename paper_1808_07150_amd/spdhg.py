@@ -1,0 +1,276 @@
+"""ctypes binding of libspdhg.so (include/spdhg.h).  Argument marshalling only: every
+step of the reconstruction runs in the library's HIP kernels; PyTorch provides device
+memory and the stream.  The binding fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspdhg.so")
+MAX_SEG = 64
+
+SPDHG_OK = 0
+ERRORS = {-1: "SPDHG_E_ARG", -2: "SPDHG_E_SHAPE", -3: "SPDHG_E_DOMAIN", -4: "SPDHG_E_HIP",
+          -5: "SPDHG_E_WORKSPACE", -6: "SPDHG_E_STATE", -7: "SPDHG_E_NOTIMPL"}
+
+PRIOR = {"none": 0, "tv": 1, "dtv": 3}
+SAMPLING = {"uniform": 0, "balanced": 1}
+
+EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_project", "spdhg_backproject",
+            "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_info",
+            "spdhg_objective", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
+            "spdhg_save_state", "spdhg_load_state", "spdhg_destroy"]
+
+
+class SpdhgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CGeom(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("vx", ctypes.c_double), ("vy", ctypes.c_double), ("vz", ctypes.c_double),
+                ("n_rad", ctypes.c_int32), ("d_rad", ctypes.c_double),
+                ("n_ang", ctypes.c_int32), ("n_seg", ctypes.c_int32),
+                ("seg_planes", ctypes.c_int32 * MAX_SEG),
+                ("seg_tan", ctypes.c_double * MAX_SEG)]
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("n_subsets", ctypes.c_int32), ("prior", ctypes.c_int32),
+                ("sampling", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("eta", ctypes.c_double),
+                ("gamma_d", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("rho", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("power_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the in-tree libspdhg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as "
+                          f"g; g.build()'` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    G, Pm = ctypes.POINTER(CGeom), ctypes.POINTER(CParams)
+    lib.spdhg_last_error.restype = ctypes.c_char_p
+    lib.spdhg_last_error.argtypes = []
+    lib.spdhg_subset_bins.restype = i64
+    lib.spdhg_subset_bins.argtypes = [G, i32, i32]
+    for name in ("spdhg_project", "spdhg_backproject"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [G, i32, i32, vp, vp, vp, vp]
+    lib.spdhg_workspace_bytes.argtypes = [G, Pm, ctypes.POINTER(ctypes.c_size_t)]
+    lib.spdhg_init.argtypes = [ctypes.POINTER(vp), G, Pm, vp, vp, vp, vp, vp, vp,
+                               ctypes.c_size_t, vp]
+    lib.spdhg_iterate.argtypes = [vp, i64, vp]
+    lib.spdhg_epoch.argtypes = [vp, i32, vp]
+    lib.spdhg_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.spdhg_objective.argtypes = [vp, vp, vp, vp]
+    lib.spdhg_buffer.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    lib.spdhg_block_info.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.spdhg_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.spdhg_save_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.spdhg_load_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.spdhg_destroy.argtypes = [vp]
+    for name in EXPORTED[2:]:
+        if getattr(lib, name).restype is not ctypes.c_int64:
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != SPDHG_OK:
+        raise SpdhgError(rc, load_library().spdhg_last_error().decode())
+
+
+def cgeom(g) -> CGeom:
+    """spdhg_geom from any object with the geometry fields (e.g. synth.Geometry)."""
+    s = CGeom()
+    s.nx, s.ny, s.nz = g.nx, g.ny, g.nz
+    s.vx, s.vy, s.vz = g.vx, g.vy, g.vz
+    s.n_rad, s.d_rad, s.n_ang = g.n_rad, g.d_rad, g.n_ang
+    s.n_seg = len(g.seg_planes)
+    for i, (n, t) in enumerate(zip(g.seg_planes, g.seg_tan)):
+        s.seg_planes[i] = n
+        s.seg_tan[i] = t
+    return s
+
+
+def cparams(n_subsets: int, prior: str = "tv", sampling: str = "uniform", precond: bool = True,
+            alpha: float = 0.1, eta: float = 1e-2, gamma_d: float = 1.0, gamma: float = 1.0,
+            rho: float = 0.99, seed: int = 0, power_iters: int = 100) -> CParams:
+    p = CParams()
+    p.n_subsets = n_subsets
+    p.prior = PRIOR[prior]
+    p.sampling = SAMPLING[sampling]
+    p.precond = 1 if precond else 0
+    p.alpha, p.eta, p.gamma_d, p.gamma, p.rho = alpha, eta, gamma_d, gamma, rho
+    p.seed = seed & 0xFFFFFFFFFFFFFFFF
+    p.power_iters = power_iters
+    return p
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float32):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the HIP device")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"tensor must be contiguous {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def subset_bins(g, n_subsets: int, subset: int) -> int:
+    return int(load_library().spdhg_subset_bins(ctypes.byref(cgeom(g)), n_subsets, subset))
+
+
+def spdhg_project(g, n_subsets: int, subset: int, mult: Optional[torch.Tensor],
+                  x: torch.Tensor, y_out: torch.Tensor, stream=None) -> torch.Tensor:
+    n = subset_bins(g, n_subsets, subset)
+    if y_out.numel() != n or x.numel() != g.nx * g.ny * g.nz:
+        raise ValueError("size mismatch")
+    _check(load_library().spdhg_project(ctypes.byref(cgeom(g)), n_subsets, subset, _ptr(mult),
+                                        _ptr(x), _ptr(y_out), _stream(stream)))
+    return y_out
+
+
+def spdhg_backproject(g, n_subsets: int, subset: int, mult: Optional[torch.Tensor],
+                      y: torch.Tensor, x_out: torch.Tensor, stream=None) -> torch.Tensor:
+    n = subset_bins(g, n_subsets, subset)
+    if y.numel() != n or x_out.numel() != g.nx * g.ny * g.nz:
+        raise ValueError("size mismatch")
+    _check(load_library().spdhg_backproject(ctypes.byref(cgeom(g)), n_subsets, subset,
+                                            _ptr(mult), _ptr(y), _ptr(x_out), _stream(stream)))
+    return x_out
+
+
+class Reconstruction:
+    """One SPDHG reconstruction (spdhg_init ... spdhg_destroy).  The workspace is a
+    torch uint8 tensor; b, r, mult, side and x are borrowed and must stay alive."""
+
+    BUFFERS = {"y": 0, "z": 1, "T": 2, "sigma": 3, "prior_dual": 4}
+
+    def __init__(self, g, params: CParams, b, r, mult, x, side=None, stream=None):
+        lib = load_library()
+        self.g = g
+        self.params = params
+        self._keep = (b, r, mult, x, side)
+        self.x = x
+        gs = cgeom(g)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.spdhg_workspace_bytes(ctypes.byref(gs), ctypes.byref(params),
+                                         ctypes.byref(nbytes)))
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=x.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        ctx = ctypes.c_void_p()
+        _check(lib.spdhg_init(ctypes.byref(ctx), ctypes.byref(gs), ctypes.byref(params),
+                              _ptr(b), _ptr(r), _ptr(mult), _ptr(side), _ptr(x),
+                              ctypes.c_void_p(aligned), nbytes.value, _stream(stream)))
+        self.ctx = ctx
+
+    def iterate(self, n_iters: int, stream=None):
+        _check(load_library().spdhg_iterate(self.ctx, int(n_iters), _stream(stream)))
+
+    def epoch(self, n_epochs: int = 1, stream=None):
+        _check(load_library().spdhg_epoch(self.ctx, int(n_epochs), _stream(stream)))
+
+    def info(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().spdhg_info(self.ctx, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    @property
+    def iters_per_epoch(self) -> int:
+        return self.info()[0]
+
+    def objective(self, x: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=self.x.device)
+        _check(load_library().spdhg_objective(self.ctx, _ptr(x), _ptr(out, torch.float64),
+                                              _stream(stream)))
+        return out
+
+    def buffer(self, name: str) -> Optional[torch.Tensor]:
+        """A copy of an internal array (y, z, T, sigma, prior_dual)."""
+        p, n = ctypes.c_void_p(), ctypes.c_int64()
+        _check(load_library().spdhg_buffer(self.ctx, self.BUFFERS[name], ctypes.byref(p),
+                                           ctypes.byref(n)))
+        if not p.value or n.value == 0:
+            return None
+        out = torch.empty(int(n.value), dtype=torch.float32, device=self.x.device)
+        torch.cuda.synchronize()
+        _memcpy_d2d(out.data_ptr(), p.value, 4 * int(n.value))
+        return out
+
+    def block_info(self, i: int):
+        s, p, nrm = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(load_library().spdhg_block_info(self.ctx, i, ctypes.byref(s), ctypes.byref(p),
+                                               ctypes.byref(nrm)))
+        return s.value, p.value, nrm.value
+
+    def state_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(load_library().spdhg_state_bytes(self.ctx, ctypes.byref(n)))
+        return int(n.value)
+
+    def save_state(self, stream=None) -> torch.Tensor:
+        n = self.state_bytes()
+        buf = torch.empty(n, dtype=torch.uint8, device=self.x.device)
+        _check(load_library().spdhg_save_state(self.ctx, ctypes.c_void_p(buf.data_ptr()), n,
+                                               _stream(stream)))
+        return buf
+
+    def load_state(self, buf: torch.Tensor, stream=None):
+        _check(load_library().spdhg_load_state(self.ctx, ctypes.c_void_p(buf.data_ptr()),
+                                               buf.numel(), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load_library().spdhg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def _memcpy_d2d(dst: int, src: int, nbytes: int):
+    """hipMemcpy device-to-device between raw pointers (blocking)."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    rc = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")

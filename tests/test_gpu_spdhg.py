@@ -1,0 +1,162 @@
+"""GPU SPDHG (Algorithm 2) through the C ABI against the FP64 oracle on the same seeded
+inputs and the same SplitMix64 block sequence.
+
+Bar: image after K epochs within 1e-3 (relative L2), objective within 1e-4 (relative);
+step-size maps within 1e-5; reruns bitwise identical; a checkpointed run resumes bitwise."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import spdhg as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1808_07150_amd as lib
+    lib.load_library()
+    return lib
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.config1_problem()
+
+
+@pytest.fixture(scope="module")
+def small3d():
+    g = synth.small_3d(nxy=40, nz=9, n_rad=44, n_ang=24, v=5.0, tan1=0.3)
+    return synth.brain_problem(g, 18080300, 2e5, with_side=True)
+
+
+def run_pair(P, d, n_subsets, prior, epochs, seed, sampling="uniform", precond=True,
+             alpha=0.1, side=None, eta=1e-2):
+    g = d["geom"]
+    prob = S.Problem(g, d["b"], d["r"], d["mult"], n_subsets=n_subsets, prior=prior,
+                     alpha=alpha, sampling=sampling, precond=precond, side=side, eta=eta)
+    t = {k: dev(d[k]) for k in ("b", "r", "mult")}
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    sd = dev(side) if side is not None else None
+    rec = P.Reconstruction(g, P.cparams(n_subsets, prior, sampling, precond, alpha=alpha,
+                                        eta=eta, seed=seed), t["b"], t["r"], t["mult"], x,
+                           side=sd)
+    assert rec.iters_per_epoch == prob.iters_per_epoch()
+    st = S.spdhg(prob, epochs * prob.iters_per_epoch(), seed=seed)
+    rec.epoch(epochs)
+    torch.cuda.synchronize()
+    return prob, st, rec, x
+
+
+@pytest.mark.parametrize("sampling,precond,epochs", [("uniform", True, 50),
+                                                     ("balanced", True, 30),
+                                                     ("balanced", False, 20)])
+def test_config1_tv_parity(P, c1, sampling, precond, epochs):
+    print(f"[spdhg] config1 TV {sampling} precond={precond} epochs={epochs}", flush=True)
+    prob, st, rec, x = run_pair(P, c1, 10, "tv", epochs, seed=1808, sampling=sampling,
+                                precond=precond)
+    xo = prob.reported(st)[0]
+    xg = x.cpu().numpy()
+    assert rel(xg, xo) <= 1e-3
+    obj = rec.objective().cpu().numpy()
+    psi_o = prob.objective(xo[None])
+    assert abs(obj[0] - psi_o) <= 1e-4 * abs(psi_o)
+    # the GPU objective of the oracle image matches the oracle objective closely
+    obj2 = rec.objective(dev(xo)).cpu().numpy()
+    assert abs(obj2[0] - psi_o) <= 1e-5 * abs(psi_o)
+
+
+def test_config1_step_sizes(P, c1):
+    prob, _, rec, _ = run_pair(P, c1, 10, "tv", 0, seed=1, sampling="balanced")
+    T = rec.buffer("T").cpu().numpy()
+    assert rel(T, prob.T[0]) <= 1e-5
+    sig = rec.buffer("sigma").cpu().numpy().reshape(c1["geom"].sino_shape)
+    ref = np.zeros(c1["geom"].sino_shape)
+    for i in range(prob.m):
+        ref[prob.angles[i]] = prob.sigma[i]
+    both = (sig > 0) & (ref > 0)
+    assert np.sum((sig > 0) != (ref > 0)) <= 0.001 * sig.size
+    assert rel(sig[both], ref[both]) <= 1e-5
+    s, p, nrm = rec.block_info(10)
+    assert p == prob.p[10] and s == pytest.approx(prob.prior_sigma[0], rel=1e-12)
+
+
+@pytest.mark.parametrize("prior,sampling,epochs", [("tv", "balanced", 12), ("none", "uniform", 12),
+                                                   ("dtv", "balanced", 12)])
+def test_small3d_parity(P, small3d, prior, sampling, epochs):
+    print(f"[spdhg] small3d {prior} {sampling} epochs={epochs}", flush=True)
+    side = small3d["side"] if prior == "dtv" else None
+    prob, st, rec, x = run_pair(P, small3d, 6, prior, epochs, seed=77, sampling=sampling,
+                                alpha=0.05, side=side)
+    xo = prob.reported(st)[0]
+    xg = x.cpu().numpy()
+    assert rel(xg, xo) <= 1e-3
+    psi_o = prob.objective(xo[None])
+    obj = rec.objective().cpu().numpy()
+    assert abs(obj[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+def test_scalar_steps_norms(P, small3d):
+    prob, _, rec, _ = run_pair(P, small3d, 3, "tv", 0, seed=5, precond=False)
+    for i in range(3):
+        _, _, nrm = rec.block_info(i)
+        assert nrm == pytest.approx(prob.norms[i], rel=1e-5)
+
+
+def test_rerun_bitwise_and_checkpoint(P, c1):
+    g = c1["geom"]
+    t = {k: dev(c1[k]) for k in ("b", "r", "mult")}
+    prm = P.cparams(10, "tv", "balanced", seed=99)
+    xs = []
+    for _ in range(2):
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+        rec.epoch(5)
+        torch.cuda.synchronize()
+        xs.append(x.cpu().numpy())
+    np.testing.assert_array_equal(xs[0], xs[1])
+    # checkpoint after 2 epochs, continue 3; restore, continue 3 again
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+    rec.epoch(2)
+    snap = rec.save_state()
+    rec.epoch(3)
+    torch.cuda.synchronize()
+    a = x.cpu().numpy()
+    np.testing.assert_array_equal(a, xs[0])
+    rec.iterate(7)  # move on, then restore
+    rec.load_state(snap)
+    rec.epoch(3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(x.cpu().numpy(), a)
+
+
+def test_domain_errors(P, c1):
+    from paper_1808_07150_amd.spdhg import SpdhgError
+    g = c1["geom"]
+    b = c1["b"].copy()
+    b[3, 0, 40] = -1.0
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(SpdhgError) as e:
+        P.Reconstruction(g, P.cparams(10, "tv"), dev(b), dev(c1["r"]), dev(c1["mult"]), x)
+    assert e.value.code == -3
+    # b > 0 with r = 0 on a bin no voxel reaches: objective infinite for every image
+    r = c1["r"].copy()
+    b = c1["b"].copy()
+    r[0, 0, 0] = 0.0
+    b[0, 0, 0] = 3.0
+    with pytest.raises(SpdhgError) as e:
+        P.Reconstruction(g, P.cparams(10, "tv"), dev(b), dev(r), dev(c1["mult"]), x)
+    assert e.value.code == -3
