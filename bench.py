@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""SPDHG epoch benchmark on one MI355X.
+
+Workload (one step = one SPDHG epoch of Algorithm 2): mMR-shaped span-11 cylinder,
+image 344 x 344 x 127 voxels at 2.08 mm, sinogram 344 radial x 252 angles x 837 planes
+(72,557,856 bins, FP32); seeded brain-like ellipsoid phantom, randoms + scatter at 30 % of
+the trues, 1e8 expected counts; TV prior beta = 2e-3 with non-negativity; 21 subsets of
+equidistant angles; SPDHG+ (balanced sampling, preconditioned step sizes); an epoch is
+42 iterations.  Inputs are generated on the GPU (analytic line integrals) and resident in
+HBM before the timed region.
+
+Prints one JSON line with epochs/s, the live roofline of the dominant kernel (HIP events
+around each launch inside the timed region) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "mMR-size SPDHG epochs/s, proj+backproj GB/s; time to 1e-3 rel objective"
+HBM_PEAK_GBS = 8000.0
+# FP32 vector FMA without packed-FP32 instructions: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6
+SEED = 18080200
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(g, d_host, m, alpha, seed):
+    """The FP64 oracle (oracle/) on a bounded sample of the same workload: one data
+    iteration (subset 0: 12 angles forward, KL-dual prox, backprojection) and one TV
+    iteration at full mMR size, run by the oracle's own Algorithm 2 loop, scaled to the
+    21 + 21 expected iterations of an epoch."""
+    import numpy as np
+    from oracle import spdhg as S
+
+    class _Steps(S.Problem):  # the oracle problem without its (full-size) step setup
+        def _setup_steps(self):
+            self.sigma = [np.full(b.shape, 1e-3) for b in self.sub_b]
+            self.prior_sigma = [0.1]
+            self.norms = [None] * self.n
+            self.T = np.full(self.image_shape(), 1e-3)
+
+    prob = _Steps(g, d_host["b"], d_host["r"], d_host["mult"], n_subsets=m, prior="tv",
+                  alpha=alpha, sampling="balanced", precond=True)
+    x0 = np.full((1,) + g.image_shape, 0.5)
+    st = prob.new_state(x0)
+    t0 = time.perf_counter()
+    S.spdhg(prob, 1, seed, state=st, blocks=[0])
+    t1 = time.perf_counter()
+    S.spdhg(prob, 1, seed, state=st, blocks=[m])
+    t2 = time.perf_counter()
+    ipe = prob.iters_per_epoch()
+    per_epoch = (t1 - t0) * ipe * sum(prob.p[:m]) + (t2 - t1) * ipe * prob.p[m]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / per_epoch, "unit": "epochs/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 data iteration (subset 0, 12 angles: {t1 - t0:.1f} s) + 1 TV "
+                      f"iteration ({t2 - t1:.1f} s) at full mMR size, FP64, scaled to "
+                      f"{ipe * sum(prob.p[:m]):.0f} + {ipe * prob.p[m]:.0f} iterations/epoch"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed epochs")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed epochs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the single-GPU kernels are the subject of this "
+              "benchmark and no multi-GPU path is built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1808_07150_amd as P
+    import synth
+    from synth.phantom import brain_problem_torch
+
+    dev = torch.device("cuda:0")
+    g = synth.mmr()
+    m, alpha = 21, 2e-3
+    t0 = time.time()
+    d = brain_problem_torch(g, SEED, 1e8, dev)
+    torch.cuda.synchronize()
+    log(f"inputs generated in {time.time() - t0:.1f} s (total counts {float(d['b'].sum()):.3e})")
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
+    prm = P.cparams(m, "tv", "balanced", True, alpha=alpha, seed=SEED)
+    t0 = time.time()
+    rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x)
+    torch.cuda.synchronize()
+    log(f"init (step sizes) {time.time() - t0:.2f} s; {rec.iters_per_epoch} iterations/epoch")
+    obj = rec.objective()
+    psi0 = float(obj[0].item())
+
+    for _ in range(args.warmup):
+        rec.epoch(1)
+    torch.cuda.synchronize()
+    rec.set_profiling(True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    rec.epoch(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    prof = rec.profile()
+    rec.set_profiling(False)
+    psi = float(rec.objective()[0].item())
+    log(f"{args.steps} epochs in {ms:.1f} ms; objective {psi0:.6e} -> {psi:.6e}")
+    log("kernels: " + ", ".join(f"{k} {v[0]:.1f} ms / {v[1]}" for k, v in prof.items()))
+
+    nv = g.n_vox
+    n_i = P.subset_bins(g, m, 0)
+    nnz = P.spdhg_nnz(g, m, 0)
+    # algorithmic bytes per launch (FP32, compulsory traffic, no re-reads)
+    bytes_fwd = 4 * nv + 28 * n_i          # x; y b r mult sigma in, y d out
+    bytes_bwd = 20 * nv + 4 * n_i          # d in; z x T in, z x out
+    bytes_prior = 44 * nv                  # x, 3 duals, z, T in; x, 3 duals, z out
+    flops_fwd = 2.0 * nnz + 20.0 * n_i     # one FMA per nonzero + the prox per bin
+    flops_bwd = 2.0 * nnz + 6.0 * nv
+    n_fwd, n_prior = prof["fwd"][1], prof["prior"][1]
+    epoch_bytes = (n_fwd * (bytes_fwd + bytes_bwd) + n_prior * bytes_prior) / args.steps
+    kinds = {
+        "fwd": dict(bound="alu", work=flops_fwd, unit="TFLOP/s", peak=ALU_PEAK_TFLOPS,
+                    name="fwd_dual (projection + KL-dual prox)"),
+        "bwd": dict(bound="alu", work=flops_bwd, unit="TFLOP/s", peak=ALU_PEAK_TFLOPS,
+                    name="bwd_iter (gather backprojection + primal epilogue)"),
+        "prior": dict(bound="hbm", work=bytes_prior, unit="GB/s", peak=HBM_PEAK_GBS,
+                      name="tv_iter (TV dual + adjoint + primal epilogue)"),
+    }
+    dom = max(prof, key=lambda k: prof[k][0])
+    avg_ms = prof[dom][0] / max(prof[dom][1], 1)
+    kd = kinds[dom]
+    scale = 1e-12 if kd["unit"] == "TFLOP/s" else 1e-9
+    achieved = kd["work"] * scale / (avg_ms * 1e-3)
+    per_kernel = {}
+    for k, (tot, n) in prof.items():
+        if n:
+            a = tot / n
+            per_kernel[k] = {"avg_ms": round(a, 4), "launches": n,
+                             "algorithmic_GBs": round((dict(fwd=bytes_fwd, bwd=bytes_bwd,
+                                                            prior=bytes_prior)[k]) / (a * 1e6), 1)}
+    roofline = {"bound": kd["bound"], "achieved": round(achieved, 3), "peak": kd["peak"],
+                "unit": kd["unit"], "frac": round(achieved / kd["peak"], 4), "traffic": None,
+                "kernel": kd["name"], "avg_ms": round(avg_ms, 4)}
+    epochs_per_s = args.steps / (ms * 1e-3)
+    pb_ms = (prof["fwd"][0] + prof["bwd"][0]) / max(prof["fwd"][1], 1)
+    out = {
+        "metric": METRIC, "value": round(epochs_per_s, 3), "unit": "epochs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mMR 344x344x127 / 344x252x837 span-11, TV beta=2e-3 + "
+                               "nonneg, 21 subsets, SPDHG+ (balanced, preconditioned), "
+                               "1e8 counts", "iters_per_epoch": rec.iters_per_epoch,
+                   "nnz_per_subset": nnz},
+        "epoch_hbm": {"algorithmic_GB": round(epoch_bytes / 1e9, 2),
+                      "achieved_GBs": round(epoch_bytes / (ms / args.steps * 1e6), 1),
+                      "frac": round(epoch_bytes / (ms / args.steps * 1e6) / HBM_PEAK_GBS, 4)},
+        "proj_backproj": {"subset_ms": round(pb_ms, 3),
+                          "algorithmic_GBs": round((bytes_fwd + bytes_bwd) / (pb_ms * 1e6), 1),
+                          "gtaps_s": round(2 * nnz / (pb_ms * 1e6), 1)},
+        "kernels": per_kernel,
+        "roofline": roofline,
+        "objective": {"initial": psi0, "after": psi},
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.time()
+        host = {k: d[k].cpu().numpy() for k in ("b", "r", "mult")}
+        out["cpu_baseline"] = cpu_baseline(g, host, m, alpha, SEED)
+        log(f"cpu baseline {time.time() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,6 +114,12 @@ int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
 int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
                       const float* mult, const float* y, float* x_out, void* stream);
 
+/* Number of nonzero entries of A_i (taps of the rays of subset `subset` that fall inside
+ * the image with a nonzero interpolation weight), written to *out (host).  Measurement
+ * helper: allocates a small scratch array, synchronises `stream`. */
+int spdhg_nnz(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, double* out,
+              void* stream);
+
 /* Bytes of device workspace a reconstruction needs (duals, z, step sizes, scratch). */
 int spdhg_workspace_bytes(const spdhg_geom* geom, const spdhg_params* params, size_t* bytes);
 
@@ -170,6 +176,17 @@ int spdhg_block_info(const spdhg_ctx* ctx, int32_t i, double* sigma, double* p, 
 int spdhg_state_bytes(const spdhg_ctx* ctx, size_t* bytes);
 int spdhg_save_state(spdhg_ctx* ctx, void* dst, size_t bytes, void* stream);
 int spdhg_load_state(spdhg_ctx* ctx, const void* src, size_t bytes, void* stream);
+
+/* Per-kernel timing of the iteration (HIP events recorded on the caller's stream around
+ * each launch; adds no synchronisation inside spdhg_iterate).  spdhg_set_profiling turns
+ * it on or off and clears the totals; spdhg_profile waits for the recorded events and
+ * returns, per kernel kind (SPDHG_PROF_*), the summed milliseconds and launch counts. */
+#define SPDHG_PROF_FWD 0   /* forward projection fused with the KL-dual prox          */
+#define SPDHG_PROF_BWD 1   /* gather backprojection fused with the primal epilogue    */
+#define SPDHG_PROF_PRIOR 2 /* prior dual update fused with its adjoint and epilogue    */
+#define SPDHG_PROF_KINDS 3
+int spdhg_set_profiling(spdhg_ctx* ctx, int32_t on);
+int spdhg_profile(spdhg_ctx* ctx, double* ms, int64_t* launches);
 
 /* Release the context (host memory only; caller memory is untouched). */
 int spdhg_destroy(spdhg_ctx* ctx);

@@ -4,4 +4,5 @@ The computation lives in libspdhg.so (hand-written HIP kernels for gfx950, C ABI
 include/spdhg.h); this package is its thin Python binding.
 """
 from .spdhg import (CGeom, CParams, Reconstruction, SpdhgError, cgeom, cparams,  # noqa: F401
-                    load_library, spdhg_backproject, spdhg_project, subset_bins)
+                    load_library, spdhg_backproject, spdhg_nnz, spdhg_project,
+                    subset_bins)

@@ -109,6 +109,36 @@ __device__ float ray_sum(const GeomDev& G, const float* __restrict__ x, int a, i
     return acc * S.L;
 }
 
+// Number of taps of ray (a, q, k) with a nonzero weight inside the image: the ray's
+// nonzeros in the system matrix (each tap is one voxel; voxels hit twice along a ray
+// are counted per tap, as the projector evaluates them).
+__device__ double ray_taps(const GeomDev& G, int a, int q, int k) {
+    const AngleDev A = G.ang[a];
+    const int g = G.plane_seg[q];
+    const int p = q - G.seg_base[g];
+    const SegAngleDev S = G.sa[a * G.n_seg + g];
+    const double kk = (double)k - G.ck;
+    const int zb = p + G.seg_off[g];
+    const double u0 = __builtin_fma(A.du_dk, kk, A.cu);
+    int j0, j1;
+    ray_range(G, A, S, u0, kk, zb, j0, j1);
+    double n = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double jj = (double)j - A.cj;
+        const Sample s = split(sec_coord(A, kk, jj));
+        const Sample sz = split(ax_offset(S, kk, jj));
+        const int iz = zb + sz.i0;
+        const float wx[2] = {1.0f - s.fu, s.fu};
+        const float wz[2] = {1.0f - sz.fu, sz.fu};
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dx = 0; dx < 2; ++dx)
+                if ((unsigned)(s.i0 + dx) < (unsigned)A.n_sec &&
+                    (unsigned)(iz + dz) < (unsigned)G.nz && wx[dx] * wz[dz] != 0.0f)
+                    n += 1.0;
+    }
+    return n;
+}
+
 struct RayIdx {
     int ia, q, k;
 };
@@ -223,6 +253,17 @@ fwd_obj(GeomDev G, const float* __restrict__ x, const float* __restrict__ mult,
         const float ax = mult[t] * ray_sum<false>(G, x, ri.ia, ri.q, ri.k);
         v = phi64((double)ax, (double)b[t], (double)r[t]);
     }
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Per-block partial counts of nonzero taps over the rays of the listed angles.
+__global__ void __launch_bounds__(BLOCK)
+fwd_count(GeomDev G, int ang0, int ang_step, int n_ang_sub, double* __restrict__ part) {
+    RayIdx r;
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (ray_index(G, n_ang_sub, t, r)) v = ray_taps(G, ang0 + r.ia * ang_step, r.q, r.k);
     const double s = block_sum(v);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }

@@ -256,6 +256,13 @@ struct spdhg_ctx {
     int64_t k = 0;
     int64_t iters_per_epoch = 1;
     int64_t nv = 0, nb = 0, max_sub_bins = 0;
+    // optional per-kernel timing: event pairs around each launch of the iteration
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;  // kernel kind of each recorded pair
+    size_t ev_used = 0;
+    double prof_ms[SPDHG_PROF_KINDS] = {0};
+    int64_t prof_n[SPDHG_PROF_KINDS] = {0};
     float* xcur() { return x_cur ? x2 : x_user; }
     float* xother() { return x_cur ? x_user : x2; }
 };
@@ -403,6 +410,32 @@ int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
     return SPDHG_OK;
 }
 
+int spdhg_nnz(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, double* out,
+              void* stream) {
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (!out) return fail(SPDHG_E_ARG, "out is NULL");
+    int a0, step, cnt;
+    rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
+    if (rc) return rc;
+    GeomDev G;
+    rc = cached_geom(geom, G);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = (int64_t)cnt * G.n_planes * G.n_rad;
+    const int64_t nbk = nblocks(n);
+    double* part = nullptr;
+    HIP_TRY(hipMalloc(&part, (nbk + 1) * sizeof(double)));
+    fwd_count<<<nbk, BLOCK, 0, st>>>(G, a0, step, cnt, part);
+    reduce_final<<<1, BLOCK, 0, st>>>(part, nbk, part + nbk, 0, 1.0);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out, part + nbk, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("spdhg_nnz: ") + hipGetErrorString(e));
+    return SPDHG_OK;
+}
+
 int spdhg_workspace_bytes(const spdhg_geom* geom, const spdhg_params* params, size_t* bytes) {
     int rc = check_geom(geom);
     if (rc) return rc;
@@ -442,7 +475,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         delete c;
         return fail(SPDHG_E_WORKSPACE, "workspace must be 256-byte aligned");
     }
-    hipGetDevice(&c->device);
+    HIP_TRY(hipGetDevice(&c->device));
     char* w = (char*)ws;
     // the tables are copied synchronously before any kernel on `st` may use them
     rc = upload_tables(c->tab, w + L.tables);
@@ -581,6 +614,70 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     return SPDHG_OK;
 }
 
+namespace {
+// Collect the elapsed times of the recorded event pairs (synchronises on the events).
+int prof_collect(spdhg_ctx* c) {
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        HIP_TRY(hipEventSynchronize(c->ev[2 * i + 1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        c->prof_ms[c->ev_kind[i]] += ms;
+        c->prof_n[c->ev_kind[i]] += 1;
+    }
+    c->ev_used = 0;
+    return SPDHG_OK;
+}
+
+int prof_begin(spdhg_ctx* c, int kind, hipStream_t st) {
+    if (!c->prof) return SPDHG_OK;
+    if (2 * c->ev_used + 2 > c->ev.size()) {
+        int rc = prof_collect(c);
+        if (rc) return rc;
+    }
+    c->ev_kind[c->ev_used] = kind;
+    HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used], st));
+    return SPDHG_OK;
+}
+
+int prof_end(spdhg_ctx* c, hipStream_t st) {
+    if (!c->prof) return SPDHG_OK;
+    HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used + 1], st));
+    c->ev_used += 1;
+    return SPDHG_OK;
+}
+}  // namespace
+
+extern "C" int spdhg_set_profiling(spdhg_ctx* c, int32_t on) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (on && c->ev.empty()) {
+        const size_t pairs = 1024;
+        c->ev.resize(2 * pairs);
+        c->ev_kind.resize(pairs);
+        for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    if (!on && c->prof) {
+        int rc = prof_collect(c);
+        if (rc) return rc;
+    }
+    c->prof = on != 0;
+    for (int i = 0; i < SPDHG_PROF_KINDS; ++i) {
+        c->prof_ms[i] = 0.0;
+        c->prof_n[i] = 0;
+    }
+    return SPDHG_OK;
+}
+
+extern "C" int spdhg_profile(spdhg_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return fail(SPDHG_E_ARG, "NULL argument");
+    int rc = prof_collect(c);
+    if (rc) return rc;
+    for (int i = 0; i < SPDHG_PROF_KINDS; ++i) {
+        ms[i] = c->prof_ms[i];
+        launches[i] = c->prof_n[i];
+    }
+    return SPDHG_OK;
+}
+
 int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
     if (n_iters < 0) return fail(SPDHG_E_ARG, "n_iters < 0");
@@ -605,15 +702,23 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             subset_angles(&c->geom, c->m, i, a0, step, cnt);
             const int64_t nsub = (int64_t)cnt * c->tab.G.n_planes * c->geom.n_rad;
             const float sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[i];
+            int rc = prof_begin(c, SPDHG_PROF_FWD, st);
+            if (rc) return rc;
             fwd_dual<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, c->xcur(), c->mult, c->b, c->r,
                                                       c->sigma, sig_s, c->y, c->dscr, a0, step,
                                                       cnt);
+            if ((rc = prof_end(c, st))) return rc;
+            if ((rc = prof_begin(c, SPDHG_PROF_BWD, st))) return rc;
             bwd_iter<<<nblocks(nv), BLOCK, 0, st>>>(c->tab.G, c->dscr, a0, step, cnt, inv_p, c->z,
                                                     c->xcur(), c->T);
+            if ((rc = prof_end(c, st))) return rc;
         } else {
             P.inv_p = inv_p;
+            int rc = prof_begin(c, SPDHG_PROF_PRIOR, st);
+            if (rc) return rc;
             tv_iter<<<nblocks(nv), BLOCK, 0, st>>>(P, c->xcur(), c->xother(), c->yn[c->yn_cur],
                                                    c->yn[1 - c->yn_cur], c->z, c->T, c->xi);
+            if ((rc = prof_end(c, st))) return rc;
             c->x_cur ^= 1;
             c->yn_cur ^= 1;
         }
@@ -747,6 +852,8 @@ int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) 
 }
 
 int spdhg_destroy(spdhg_ctx* c) {
+    if (!c) return SPDHG_OK;
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
     delete c;
     return SPDHG_OK;
 }

@@ -22,9 +22,12 @@ PRIOR = {"none": 0, "tv": 1, "dtv": 3}
 SAMPLING = {"uniform": 0, "balanced": 1}
 
 EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_project", "spdhg_backproject",
+            "spdhg_nnz",
             "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_info",
             "spdhg_objective", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
-            "spdhg_save_state", "spdhg_load_state", "spdhg_destroy"]
+            "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
+            "spdhg_destroy"]
+PROF_KINDS = ("fwd", "bwd", "prior")
 
 
 class SpdhgError(RuntimeError):
@@ -73,6 +76,7 @@ def load_library() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [G, i32, i32, vp, vp, vp, vp]
+    lib.spdhg_nnz.argtypes = [G, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.spdhg_workspace_bytes.argtypes = [G, Pm, ctypes.POINTER(ctypes.c_size_t)]
     lib.spdhg_init.argtypes = [ctypes.POINTER(vp), G, Pm, vp, vp, vp, vp, vp, vp,
                                ctypes.c_size_t, vp]
@@ -87,6 +91,8 @@ def load_library() -> ctypes.CDLL:
     lib.spdhg_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.spdhg_save_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.spdhg_load_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.spdhg_set_profiling.argtypes = [vp, i32]
+    lib.spdhg_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.spdhg_destroy.argtypes = [vp]
     for name in EXPORTED[2:]:
         if getattr(lib, name).restype is not ctypes.c_int64:
@@ -164,6 +170,14 @@ def spdhg_backproject(g, n_subsets: int, subset: int, mult: Optional[torch.Tenso
     _check(load_library().spdhg_backproject(ctypes.byref(cgeom(g)), n_subsets, subset,
                                             _ptr(mult), _ptr(y), _ptr(x_out), _stream(stream)))
     return x_out
+
+
+def spdhg_nnz(g, n_subsets: int, subset: int, stream=None) -> int:
+    """Nonzero count of A_i (taps inside the image with nonzero weight)."""
+    out = ctypes.c_double()
+    _check(load_library().spdhg_nnz(ctypes.byref(cgeom(g)), n_subsets, subset,
+                                    ctypes.byref(out), _stream(stream)))
+    return int(out.value)
 
 
 class Reconstruction:
@@ -247,6 +261,16 @@ class Reconstruction:
     def load_state(self, buf: torch.Tensor, stream=None):
         _check(load_library().spdhg_load_state(self.ctx, ctypes.c_void_p(buf.data_ptr()),
                                                buf.numel(), _stream(stream)))
+
+    def set_profiling(self, on: bool):
+        _check(load_library().spdhg_set_profiling(self.ctx, 1 if on else 0))
+
+    def profile(self):
+        """{kind: (total ms, launches)} of the kernels launched while profiling was on."""
+        ms = (ctypes.c_double * len(PROF_KINDS))()
+        n = (ctypes.c_int64 * len(PROF_KINDS))()
+        _check(load_library().spdhg_profile(self.ctx, ms, n))
+        return {k: (ms[i], int(n[i])) for i, k in enumerate(PROF_KINDS)}
 
     def close(self):
         if getattr(self, "ctx", None):

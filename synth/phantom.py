@@ -250,3 +250,81 @@ def brain_problem(g: Geometry, seed: int, counts: float, with_side: bool = False
     if with_side:
         d["side"] = side_image(np.random.Generator(np.random.PCG64(seed + 2)), g, labels)
     return d
+
+
+# ---------------------------------------------------------------- torch (device) version
+def _torch_chords(torch, g: Geometry, angles, e: Ellipsoid, device):
+    """Chord lengths of all rays of the given angles through ellipsoid e, FP64 on device:
+    shape [len(angles)][planes][radial]."""
+    f64 = torch.float64
+    a = torch.as_tensor(angles, dtype=f64, device=device)[:, None, None]
+    phi = math.pi * a / g.n_ang
+    c, s = torch.cos(phi), torch.sin(phi)
+    r = ((torch.arange(g.n_rad, dtype=f64, device=device) - 0.5 * (g.n_rad - 1))
+         * g.d_rad)[None, None, :]
+    zp = torch.cat([(torch.arange(n, dtype=f64, device=device) - 0.5 * (n - 1)) * g.vz
+                    for n in g.seg_planes])[None, :, None]
+    tau = torch.cat([torch.full((n,), t, dtype=f64, device=device)
+                     for n, t in zip(g.seg_planes, g.seg_tan)])[None, :, None]
+    ct, st = math.cos(e.theta), math.sin(e.theta)
+    ox, oy, oz = r * c - e.cx, r * s - e.cy, zp - e.cz
+    ux, uy, uz = ct * ox + st * oy, -st * ox + ct * oy, oz
+    dx, dy = -s, c
+    wx, wy, wz = ct * dx + st * dy, -st * dx + ct * dy, tau
+    iax, iay = 1.0 / e.ax ** 2, 1.0 / e.ay ** 2
+    iaz = 0.0 if math.isinf(e.az) else 1.0 / e.az ** 2
+    alpha = wx * wx * iax + wy * wy * iay + wz * wz * iaz
+    beta = wx * ux * iax + wy * uy * iay + wz * uz * iaz
+    gamma = ux * ux * iax + uy * uy * iay + uz * uz * iaz - 1.0
+    disc = beta * beta - alpha * gamma
+    dt = torch.where(disc > 0, 2.0 * torch.sqrt(torch.clamp(disc, min=0.0)) / alpha,
+                     torch.zeros_like(disc))
+    return dt * torch.sqrt(1.0 + tau * tau)
+
+
+def line_integrals_torch(g: Geometry, ells, device, batch: int = 12):
+    import torch
+    out = torch.empty(g.sino_shape, dtype=torch.float64, device=device)
+    for a0 in range(0, g.n_ang, batch):
+        ang = list(range(a0, min(a0 + batch, g.n_ang)))
+        acc = torch.zeros((len(ang), g.n_planes, g.n_rad), dtype=torch.float64, device=device)
+        for e in ells:
+            acc += e.value * _torch_chords(torch, g, ang, e, device)
+        out[a0:a0 + len(ang)] = acc
+    return out
+
+
+def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side=False):
+    """The brain-like 3-D problem generated on a torch device (float32 outputs): same
+    phantom parameters as brain_problem, analytic data in FP64, randoms + scatter at 30%
+    of trues, normalisation U(0.8, 1.2), Poisson counts (torch generator seeded)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    act, att, labels = phantom_brain(rng, g)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed + 1)
+    norm = torch.rand(g.sino_shape, generator=gen, device=device, dtype=torch.float64) * 0.4 + 0.8
+    mult = norm * torch.exp(-line_integrals_torch(g, att, device))
+    del norm
+    trues = mult * line_integrals_torch(g, act, device)
+    sigma = 50.0 / g.d_rad
+    half = int(math.ceil(4 * sigma))
+    kern = torch.exp(-0.5 * (torch.arange(-half, half + 1, device=device, dtype=torch.float64)
+                             / sigma) ** 2)
+    kern = (kern / kern.sum()).view(1, 1, -1)
+    flat = trues.view(-1, 1, g.n_rad)
+    scatter = torch.cat([torch.nn.functional.conv1d(flat[i:i + 65536], kern, padding=half)
+                         for i in range(0, flat.shape[0], 65536)]).view(g.sino_shape)
+    scatter *= 0.15 * trues.sum() / scatter.sum().clamp(min=1e-30)
+    rshape = scatter + 0.15 * trues.mean()
+    del scatter
+    scale = counts / (trues.sum() + rshape.sum())
+    ybar = scale * (trues + rshape)
+    b = torch.poisson(ybar, generator=gen).to(torch.float32)
+    del ybar, trues
+    d = dict(b=b, r=(scale * rshape).to(torch.float32), mult=mult.to(torch.float32),
+             scale=float(scale), geom=g, ellipsoids=act)
+    if with_side:
+        d["side"] = torch.from_numpy(
+            side_image(np.random.Generator(np.random.PCG64(seed + 2)), g, labels)).to(device)
+    return d
