@@ -1,17 +1,24 @@
 // HIP kernels of the SPDHG subset step for gfx950 (wave64).
 //
-//   fwd_*   ray-driven Joseph forward projection of a subset (one thread per ray, the
-//           thread walks the primary axis); variants fuse the per-bin epilogues:
-//           plain output, preconditioner sigma = gamma rho / (A 1), the KL-dual prox of
-//           Algorithm 2 line 5, or the FP64 data term of the objective.
-//   bwd_*   voxel-driven gather backprojection A_i^T (one thread per voxel, loops over the
-//           subset's angles and the rays that touch the voxel; same weights as fwd_*, no
-//           atomics); variants fuse: plain output, running minimum for the primal step
-//           T, or the primal epilogue of Algorithm 2 lines 7-8 and line 3 of the next
-//           iteration.
-//   tv_*    prior block of TV / dTV (eq. setting TV, Section 4.3): dual ascent with the
-//           l2-ball projection, its adjoint, and the same primal epilogue.
-//   reduce  deterministic FP64 block partials + ordered final sum.
+// Internal layouts (the caller's layouts are converted at the boundary):
+//   image     z-fastest [y][x][z]:  voxel (ix, iy, iz) at (iy * nx + ix) * nz + iz
+//   sinogram  [angle][radial][plane]: bin (a, q, k) at (a * n_rad + k) * n_planes + q
+// In these layouts every stream of the hot loop is contiguous across the 64 lanes of a
+// wavefront for both angle classes (row- and column-sampled rays).
+//
+//   fwd_wave   forward projection, one wavefront per (angle, radial bin): at every
+//              primary step the lanes form the in-plane interpolated axial column
+//              G(z) = (1 - fu) x[j][i0][z] + fu x[j][i0 + 1][z] in LDS, then each ray of
+//              the bin (all planes of all segments) adds its axial interpolation of G.
+//              Epilogues: plain output, preconditioner sigma, KL-dual prox (Algorithm 2
+//              line 5), FP64 data term of the objective.
+//   bwd_col    gather backprojection, one workgroup per group of voxel columns: the
+//              interpolation coordinates of every candidate ray are computed once per
+//              column and angle (FP64, shared through LDS), lanes run along z and read
+//              the dual change d[angle][k][plane] contiguously.  No atomics.  Epilogues:
+//              plain output, running minimum for T, primal epilogue (lines 7-8 and 3).
+//   tv_iter    TV / dTV prior block (dual ascent, l2-ball projection, adjoint, epilogue).
+//   reductions deterministic FP64 block partials + ordered final sum.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -22,211 +29,33 @@
 
 namespace spdhg {
 
-// ---------------------------------------------------------------- ray walk
-// Range of primary indices [j0, j1) outside of which every tap of the ray is zero
-// (conservative by two samples; the loop still tests every tap).
-__device__ __forceinline__ void ray_range(const GeomDev& G, const AngleDev& A,
-                                          const SegAngleDev& S, double u0, double kk, int zb,
-                                          int& j0, int& j1) {
-    double lo = -1e30, hi = 1e30;
-    // secondary: need -1 < u < n_sec, u = du_dj * jj + u0
-    if (A.du_dj != 0.0) {
-        const double t0 = (-1.0 - u0) / A.du_dj, t1 = ((double)A.n_sec - u0) / A.du_dj;
-        lo = fmax(lo, fmin(t0, t1));
-        hi = fmin(hi, fmax(t0, t1));
-    } else if (!(u0 > -1.0 && u0 < (double)A.n_sec)) {
-        j0 = j1 = 0;
-        return;
-    }
-    // axial: need -1 < zb + e < nz, e = ez_dj * jj + ez_dk * kk
-    const double ek = S.ez_dk * kk;
-    if (S.ez_dj != 0.0) {
-        const double t0 = (-1.0 - (double)zb - ek) / S.ez_dj;
-        const double t1 = ((double)G.nz - (double)zb - ek) / S.ez_dj;
-        lo = fmax(lo, fmin(t0, t1));
-        hi = fmin(hi, fmax(t0, t1));
-    } else {
-        const double z = (double)zb + ek;
-        if (!(z > -1.0 && z < (double)G.nz)) {
-            j0 = j1 = 0;
-            return;
-        }
-    }
-    const double a = fmax(lo + A.cj - 2.0, 0.0);
-    const double b = fmin(hi + A.cj + 3.0, (double)A.n_prim);
-    if (!(a < b)) {
-        j0 = j1 = 0;
-        return;
-    }
-    j0 = (int)a;
-    j1 = (int)b;
+// ---------------------------------------------------------------- helpers
+// Blocks are dispatched round-robin over the 8 XCDs; map them so that consecutive
+// logical blocks (neighbouring radial bins / voxel columns, which read overlapping data)
+// run on the same XCD and share its L2.  Bijective on [0, nb).
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+    const int per = nb >> 3;
+    if (bid >= (per << 3)) return bid;
+    return (bid & 7) * per + (bid >> 3);
 }
 
-// Sum over samples of the bilinear interpolant times the segment step length: (G x) of
-// ray (a, q, k).  ONES: the image is 1 everywhere inside (sensitivities).
-template <bool ONES>
-__device__ float ray_sum(const GeomDev& G, const float* __restrict__ x, int a, int q, int k) {
-    const AngleDev A = G.ang[a];
-    const int g = G.plane_seg[q];
-    const int p = q - G.seg_base[g];
-    const SegAngleDev S = G.sa[a * G.n_seg + g];
-    const double kk = (double)k - G.ck;
-    const int zb = p + G.seg_off[g];
-    const int64_t s_sec = A.rowdom ? 1 : G.nx;
-    const int64_t s_prim = A.rowdom ? G.nx : 1;
-    const int64_t s_z = (int64_t)G.nx * G.ny;
-    const double u0 = __builtin_fma(A.du_dk, kk, A.cu);
-    int j0, j1;
-    ray_range(G, A, S, u0, kk, zb, j0, j1);
-    float acc = 0.0f;
-    for (int j = j0; j < j1; ++j) {
-        const double jj = (double)j - A.cj;
-        const Sample s = split(sec_coord(A, kk, jj));
-        const Sample sz = split(ax_offset(S, kk, jj));
-        const float fz = sz.fu;
-        const int iz = zb + sz.i0;
-        const bool x0ok = (unsigned)s.i0 < (unsigned)A.n_sec;
-        const bool x1ok = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
-        const bool z0ok = (unsigned)iz < (unsigned)G.nz;
-        const bool z1ok = (unsigned)(iz + 1) < (unsigned)G.nz;
-        const int64_t base = (int64_t)iz * s_z + (int64_t)j * s_prim + (int64_t)s.i0 * s_sec;
-        float v00 = 0.f, v10 = 0.f, v01 = 0.f, v11 = 0.f;
-        if (ONES) {
-            v00 = (x0ok && z0ok) ? 1.f : 0.f;
-            v10 = (x1ok && z0ok) ? 1.f : 0.f;
-            v01 = (x0ok && z1ok) ? 1.f : 0.f;
-            v11 = (x1ok && z1ok) ? 1.f : 0.f;
-        } else {
-            if (x0ok && z0ok) v00 = x[base];
-            if (x1ok && z0ok) v10 = x[base + s_sec];
-            if (x0ok && z1ok) v01 = x[base + s_z];
-            if (x1ok && z1ok) v11 = x[base + s_z + s_sec];
-        }
-        const float wx0 = 1.0f - s.fu, wx1 = s.fu;
-        const float wz0 = 1.0f - fz, wz1 = fz;
-        acc += wz0 * (wx0 * v00 + wx1 * v10) + wz1 * (wx0 * v01 + wx1 * v11);
-    }
-    return acc * S.L;
-}
-
-// Number of taps of ray (a, q, k) with a nonzero weight inside the image: the ray's
-// nonzeros in the system matrix (each tap is one voxel; voxels hit twice along a ray
-// are counted per tap, as the projector evaluates them).
-__device__ double ray_taps(const GeomDev& G, int a, int q, int k) {
-    const AngleDev A = G.ang[a];
-    const int g = G.plane_seg[q];
-    const int p = q - G.seg_base[g];
-    const SegAngleDev S = G.sa[a * G.n_seg + g];
-    const double kk = (double)k - G.ck;
-    const int zb = p + G.seg_off[g];
-    const double u0 = __builtin_fma(A.du_dk, kk, A.cu);
-    int j0, j1;
-    ray_range(G, A, S, u0, kk, zb, j0, j1);
-    double n = 0.0;
-    for (int j = j0; j < j1; ++j) {
-        const double jj = (double)j - A.cj;
-        const Sample s = split(sec_coord(A, kk, jj));
-        const Sample sz = split(ax_offset(S, kk, jj));
-        const int iz = zb + sz.i0;
-        const float wx[2] = {1.0f - s.fu, s.fu};
-        const float wz[2] = {1.0f - sz.fu, sz.fu};
-        for (int dz = 0; dz < 2; ++dz)
-            for (int dx = 0; dx < 2; ++dx)
-                if ((unsigned)(s.i0 + dx) < (unsigned)A.n_sec &&
-                    (unsigned)(iz + dz) < (unsigned)G.nz && wx[dx] * wz[dz] != 0.0f)
-                    n += 1.0;
-    }
-    return n;
-}
-
-struct RayIdx {
-    int ia, q, k;
-};
-
-__device__ __forceinline__ bool ray_index(const GeomDev& G, int n_ang_sub, int64_t t, RayIdx& r) {
-    const int64_t per_ang = (int64_t)G.n_planes * G.n_rad;
-    if (t >= per_ang * n_ang_sub) return false;
-    r.ia = (int)(t / per_ang);
-    const int64_t rem = t - (int64_t)r.ia * per_ang;
-    r.q = (int)(rem / G.n_rad);
-    r.k = (int)(rem - (int64_t)r.q * G.n_rad);
-    return true;
-}
-
-// out[packed] = mult? * (G x) over the angles ang0 + ia * ang_step.
-__global__ void __launch_bounds__(BLOCK)
-fwd_plain(GeomDev G, const float* __restrict__ x, const float* __restrict__ mult,
-          float* __restrict__ out, int ang0, int ang_step, int n_ang_sub) {
-    RayIdx r;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (!ray_index(G, n_ang_sub, t, r)) return;
-    const int a = ang0 + r.ia * ang_step;
-    float v = ray_sum<false>(G, x, a, r.q, r.k);
-    if (mult) v *= mult[((int64_t)a * G.n_planes + r.q) * G.n_rad + r.k];
-    out[t] = v;
-}
-
-// sigma[full] = gamma rho / (A 1) where A 1 > 0, else 0 (eq. STEPSIZE:PRECOND).
-__global__ void __launch_bounds__(BLOCK)
-fwd_sens(GeomDev G, const float* __restrict__ mult, float* __restrict__ sigma, float gr) {
-    RayIdx r;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (!ray_index(G, G.n_ang, t, r)) return;
-    const float a1 = mult[t] * ray_sum<true>(G, nullptr, r.ia, r.q, r.k);
-    sigma[t] = a1 > 0.0f ? gr / a1 : 0.0f;
-}
-
-// prox^sigma_{phi*}(v) = (w + 1 - sqrt((w - 1)^2 + 4 sigma b)) / 2, w = v + sigma r, in
-// the cancellation-free form obtained by rationalising the surd when w > 1.
-__device__ __forceinline__ float prox_kl_dual(float v, float sigma, float b, float r) {
-    const float w = __builtin_fmaf(sigma, r, v);
-    const float q = w - 1.0f;
-    const float c = 4.0f * sigma * b;
-    const float root = __builtin_sqrtf(__builtin_fmaf(q, q, c));
-    return q > 0.0f ? 1.0f - c / (2.0f * (q + root)) : 1.0f + 0.5f * (q - root);
-}
-
-// Algorithm 2 line 5 for data block i (and the dual change for line 6):
-//   y+ = prox(y + S_i A_i x),  d = mult (y+ - y)  (packed),  y <- y+.
-// sigma: per-bin array (preconditioned) or NULL with the scalar sig_s.
-__global__ void __launch_bounds__(BLOCK)
-fwd_dual(GeomDev G, const float* __restrict__ x, const float* __restrict__ mult,
-         const float* __restrict__ b, const float* __restrict__ r,
-         const float* __restrict__ sigma, float sig_s, float* __restrict__ y,
-         float* __restrict__ d, int ang0, int ang_step, int n_ang_sub) {
-    RayIdx ri;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (!ray_index(G, n_ang_sub, t, ri)) return;
-    const int a = ang0 + ri.ia * ang_step;
-    const int64_t j = ((int64_t)a * G.n_planes + ri.q) * G.n_rad + ri.k;
-    const float sg = sigma ? sigma[j] : sig_s;
-    const float m = mult[j];
-    const float yo = y[j];
-    float yn = yo;
-    if (sg > 0.0f) {
-        const float ax = m * ray_sum<false>(G, x, a, ri.q, ri.k);
-        yn = prox_kl_dual(__builtin_fmaf(sg, ax, yo), sg, b[j], r[j]);
-    }
-    y[j] = yn;
-    d[t] = m * (yn - yo);
-}
-
-// ---------------------------------------------------------------- FP64 reductions
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return v;
 }
 
 // Deterministic block sum: fixed shuffle tree per wave, waves added in order.
+template <int NT>
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double part[BLOCK / 64];
+    __shared__ double part[NT / 64];
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) part[w] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < BLOCK / 64; ++i) s += part[i];
+        for (int i = 0; i < NT / 64; ++i) s += part[i];
+    __syncthreads();
     return s;  // valid in thread 0
 }
 
@@ -242,40 +71,422 @@ __device__ __forceinline__ double phi64(double u, double b, double r) {
     return s;
 }
 
-// Data term of the objective: per-block FP64 partial sums of phi((A x)_j) over all bins.
-__global__ void __launch_bounds__(BLOCK)
-fwd_obj(GeomDev G, const float* __restrict__ x, const float* __restrict__ mult,
-        const float* __restrict__ b, const float* __restrict__ r, double* __restrict__ part) {
-    RayIdx ri;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    double v = 0.0;
-    if (ray_index(G, G.n_ang, t, ri)) {
-        const float ax = mult[t] * ray_sum<false>(G, x, ri.ia, ri.q, ri.k);
-        v = phi64((double)ax, (double)b[t], (double)r[t]);
+// prox^sigma_{phi*}(v) = (w + 1 - sqrt((w - 1)^2 + 4 sigma b)) / 2, w = v + sigma r, in
+// the cancellation-free form obtained by rationalising the surd when w > 1.
+__device__ __forceinline__ float prox_kl_dual(float v, float sigma, float b, float r) {
+    const float w = __builtin_fmaf(sigma, r, v);
+    const float q = w - 1.0f;
+    const float c = 4.0f * sigma * b;
+    const float root = __builtin_sqrtf(__builtin_fmaf(q, q, c));
+    return q > 0.0f ? 1.0f - c / (2.0f * (q + root)) : 1.0f + 0.5f * (q - root);
+}
+
+// Primary-index range [j0, j1) outside which the ray's in-plane taps are all outside the
+// image (conservative by two samples; the samples themselves test every tap).
+__device__ __forceinline__ void sec_range(const AngleDev& A, double u0, int& j0, int& j1) {
+    double lo = -1e30, hi = 1e30;
+    if (A.du_dj != 0.0) {
+        const double t0 = (-1.0 - u0) / A.du_dj, t1 = ((double)A.n_sec - u0) / A.du_dj;
+        lo = fmin(t0, t1);
+        hi = fmax(t0, t1);
+    } else if (!(u0 > -1.0 && u0 < (double)A.n_sec)) {
+        j0 = j1 = 0;
+        return;
     }
-    const double s = block_sum(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    const double a = fmax(lo + A.cj - 2.0, 0.0);
+    const double b = fmin(hi + A.cj + 3.0, (double)A.n_prim);
+    if (!(a < b)) {
+        j0 = j1 = 0;
+        return;
+    }
+    j0 = (int)a;
+    j1 = (int)b;
 }
 
-// Per-block partial counts of nonzero taps over the rays of the listed angles.
-__global__ void __launch_bounds__(BLOCK)
-fwd_count(GeomDev G, int ang0, int ang_step, int n_ang_sub, double* __restrict__ part) {
-    RayIdx r;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    double v = 0.0;
-    if (ray_index(G, n_ang_sub, t, r)) v = ray_taps(G, ang0 + r.ia * ang_step, r.q, r.k);
-    const double s = block_sum(v);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+// ---------------------------------------------------------------- forward projection
+enum FwdMode { F_PLAIN_QK = 0, F_PLAIN_KQ = 1, F_SENS = 2, F_DUAL = 3, F_OBJ = 4 };
+
+struct FwdArgs {
+    GeomDev G;
+    const float* x;  // z-fastest image (unused for F_SENS)
+    int ang0, ang_step, n_ang_sub;
+    int pad, gsize;  // zero padding of the axial column, padded column length
+    const float* mult;   // F_PLAIN_QK: caller layout, full; others: internal, full
+    float* out;          // F_PLAIN_*: packed output; F_SENS: sigma (internal, full)
+    const float* b;      // internal, full
+    const float* r;      // internal, full
+    const float* sigma;  // internal, full, or NULL (scalar sig_s)
+    float sig_s;
+    float* y;            // internal, full
+    float* d;            // packed internal
+    double* part;        // F_OBJ partials (one per block)
+    float gr;            // F_SENS: gamma * rho
+};
+
+// One wavefront per (angle, radial bin); RPL = rays per lane (planes / 64, rounded up).
+template <int RPL, int MODE>
+__global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
+    extern __shared__ float smem[];
+    const GeomDev& G = P.G;
+    const int ns = G.n_seg;
+    float* Gb = smem;                                  // [2][gsize] axial columns
+    int* segc = (int*)(smem + 2 * P.gsize);            // [2][ns] axial cell offsets
+    float* segf = (float*)(segc + 2 * ns);             // [2][ns] axial fractions
+    const int lane = threadIdx.x;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int ia = bid / G.n_rad;
+    const int k = bid - ia * G.n_rad;
+    const int a = P.ang0 + ia * P.ang_step;
+    const AngleDev A = G.ang[a];
+    const double kk = (double)k - G.ck;
+    const int nz = G.nz;
+    const int64_t s_prim = A.rowdom ? G.nx : 1;
+    const int64_t s_sec = A.rowdom ? 1 : G.nx;
+
+    int pinfo[RPL];  // (padded axial base of the plane) << 6 | segment
+    float acc[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int q = lane + 64 * r;
+        acc[r] = 0.0f;
+        pinfo[r] = 0;
+        if (q < G.n_planes) {
+            const int g = G.plane_seg[q];
+            pinfo[r] = ((q - G.seg_base[g] + G.seg_off[g] + P.pad) << 6) | g;
+        }
+    }
+    for (int i = lane; i < 2 * P.gsize; i += 64) Gb[i] = 0.0f;
+    int j0, j1;
+    sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
+    __syncthreads();
+    int buf = 0;
+    for (int j = j0; j < j1; ++j) {
+        const double jj = (double)j - A.cj;
+        const Sample s = split(sec_coord(A, kk, jj));
+        float* Gc = Gb + buf * P.gsize + P.pad;
+        const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
+        const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
+        const float w0 = 1.0f - s.fu, w1 = s.fu;
+        if (MODE == F_SENS) {
+            const float v = (ok0 ? w0 : 0.0f) + (ok1 ? w1 : 0.0f);
+            for (int iz = lane; iz < nz; iz += 64) Gc[iz] = v;
+        } else {
+            const int i0c = ok0 ? s.i0 : 0;
+            const float* c0 = P.x + ((int64_t)j * s_prim + (int64_t)i0c * s_sec) * nz;
+            const float* c1 = P.x + ((int64_t)j * s_prim + (int64_t)(s.i0 + 1) * s_sec) * nz;
+            for (int iz = lane; iz < nz; iz += 64) {
+                const float v0 = ok0 ? c0[iz] : 0.0f;
+                const float v1 = ok1 ? c1[iz] : 0.0f;
+                Gc[iz] = __builtin_fmaf(w1, v1, w0 * v0);
+            }
+        }
+        if (lane < ns) {
+            const Sample sz = split(ax_offset(G.sa[a * ns + lane], kk, jj));
+            segc[buf * ns + lane] = sz.i0;
+            segf[buf * ns + lane] = sz.fu;
+        }
+        __syncthreads();
+        const float* Gr = Gb + buf * P.gsize;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            if (lane + 64 * r < G.n_planes) {
+                const int g = pinfo[r] & 63;
+                const int idx = (pinfo[r] >> 6) + segc[buf * ns + g];
+                const float fz = segf[buf * ns + g];
+                acc[r] = __builtin_fmaf(1.0f - fz, Gr[idx], acc[r]);
+                acc[r] = __builtin_fmaf(fz, Gr[idx + 1], acc[r]);
+            }
+        }
+        buf ^= 1;
+    }
+
+    // epilogues
+    double obj = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int q = lane + 64 * r;
+        if (q >= G.n_planes) continue;
+        const int g = pinfo[r] & 63;
+        const float v = acc[r] * G.sa[a * ns + g].L;
+        const int64_t full = ((int64_t)a * G.n_rad + k) * G.n_planes + q;
+        if (MODE == F_PLAIN_QK) {
+            const float m = P.mult ? P.mult[((int64_t)a * G.n_planes + q) * G.n_rad + k] : 1.0f;
+            P.out[((int64_t)ia * G.n_planes + q) * G.n_rad + k] = v * m;
+        } else if (MODE == F_PLAIN_KQ) {
+            const float m = P.mult ? P.mult[full] : 1.0f;
+            P.out[((int64_t)ia * G.n_rad + k) * G.n_planes + q] = v * m;
+        } else if (MODE == F_SENS) {
+            const float a1 = P.mult[full] * v;
+            P.out[full] = a1 > 0.0f ? P.gr / a1 : 0.0f;
+        } else if (MODE == F_DUAL) {
+            const float sg = P.sigma ? P.sigma[full] : P.sig_s;
+            const float m = P.mult[full];
+            const float yo = P.y[full];
+            float yn = yo;
+            if (sg > 0.0f) yn = prox_kl_dual(__builtin_fmaf(sg, m * v, yo), sg, P.b[full], P.r[full]);
+            P.y[full] = yn;
+            P.d[((int64_t)ia * G.n_rad + k) * G.n_planes + q] = m * (yn - yo);
+        } else if (MODE == F_OBJ) {
+            obj += phi64((double)(P.mult[full] * v), (double)P.b[full], (double)P.r[full]);
+        }
+    }
+    if (MODE == F_OBJ) {
+        obj = wave_sum(obj);
+        if (lane == 0) P.part[bid] = obj;
+    }
 }
 
-// Sum of n partials in index order by one block: each thread sums a strided slice in
-// order, then the fixed block tree.  out[slot] = scale * total (+ out[add_slot] if >= 0).
+// ---------------------------------------------------------------- gather backprojection
+enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2 };
+#define BWD_THREADS 128
+#define BWD_KC 4  // candidate radial bins per column and angle
+
+struct BwdArgs {
+    GeomDev G;
+    const float* d;  // dual change / sinogram: packed (D_QK: caller [ia][q][k], else
+                     // internal [ia][k][q]) or, for B_SENS, the internal full mult
+    int d_ang0, d_step;
+    const float* mult;  // optional factors, caller layout full (D_QK) or internal full
+    int ang0, ang_step, n_ang_sub;
+    int cols;           // voxel columns per block (BWD_THREADS / nz, at least 1)
+    float* out;         // B_PLAIN: z-fastest image
+    float scale;        // B_SENS: rho p_i / gamma
+    float* T;
+    float inv_p;
+    float* z;
+    float* x;
+};
+
+// A candidate ray of a column for one angle: radial bin and in-plane weight (0: none).
+struct ColCoord {
+    int k;
+    float wx;
+};
+
+template <int MODE, bool D_QK, bool MULT>
+__global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P) {
+    const GeomDev& G = P.G;
+    const int ns = G.n_seg;
+    const int nz = G.nz;
+    extern __shared__ float smem[];
+    const int cols = P.cols;
+    ColCoord* cc = (ColCoord*)smem;                       // [cols][KC]
+    int* zc = (int*)(cc + cols * BWD_KC);                 // [cols][KC][ns]
+    float* zf = (float*)(zc + cols * BWD_KC * ns);        // [cols][KC][ns]
+    const int ncol = G.nx * G.ny;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int col0 = blk * cols;
+    // thread -> (column within the block, first z)
+    const int zchunk = nz < BWD_THREADS ? nz : BWD_THREADS;
+    const int cl = threadIdx.x / zchunk;
+    const int z0 = threadIdx.x - cl * zchunk;
+    const int col = col0 + cl;
+    const bool active = cl < cols && col < ncol;
+    const int nzz = (nz + zchunk - 1) / zchunk;  // z values per thread (<= 4, nz <= 512)
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const int64_t per_ang = (int64_t)G.n_planes * G.n_rad;
+
+    for (int ia = 0; ia < P.n_ang_sub; ++ia) {
+        const int a = P.ang0 + ia * P.ang_step;
+        const AngleDev A = G.ang[a];
+        __syncthreads();  // the previous angle's coordinates are no longer read
+        // candidate rays of each column (u evaluated in FP64 once per column and angle)
+        for (int t = threadIdx.x; t < cols * BWD_KC; t += BWD_THREADS) {
+            const int c = t / BWD_KC, kc = t - c * BWD_KC;
+            const int cq = col0 + c;
+            ColCoord o{0, 0.0f};
+            if (cq < ncol) {
+                const int qy = cq / G.nx, qx = cq - qy * G.nx;
+                const int j = A.rowdom ? qy : qx;
+                const int isec = A.rowdom ? qx : qy;
+                const double jj = (double)j - A.cj;
+                const double base = __builtin_fma(A.du_dj, jj, A.cu);
+                const double ka = ((double)(isec - 1) - base) / A.du_dk + G.ck;
+                const double kb = ((double)(isec + 1) - base) / A.du_dk + G.ck;
+                const int klo = max(0, (int)__builtin_floor(fmin(ka, kb)) - 1);
+                const int khi = min(G.n_rad - 1, (int)__builtin_ceil(fmax(ka, kb)) + 1);
+                int found = 0;
+                for (int k = klo; k <= khi; ++k) {
+                    const Sample s = split(sec_coord(A, (double)k - G.ck, jj));
+                    float w = -1.0f;
+                    if (s.i0 == isec)
+                        w = 1.0f - s.fu;
+                    else if (s.i0 + 1 == isec)
+                        w = s.fu;
+                    if (w > 0.0f) {
+                        if (found == kc) {
+                            o.k = k;
+                            o.wx = w;
+                        }
+                        ++found;
+                    }
+                }
+            }
+            cc[t] = o;
+        }
+        __syncthreads();
+        // axial cell and fraction of every (column, candidate, segment)
+        for (int t = threadIdx.x; t < cols * BWD_KC * ns; t += BWD_THREADS) {
+            const int c = t / (BWD_KC * ns);
+            const int rem = t - c * BWD_KC * ns;
+            const int kc = rem / ns, g = rem - kc * ns;
+            const int cq = col0 + c;
+            int zci = 0;
+            float zfr = 0.0f;
+            const ColCoord o = cc[c * BWD_KC + kc];
+            if (cq < ncol && o.wx != 0.0f) {
+                const int qy = cq / G.nx, qx = cq - qy * G.nx;
+                const int j = A.rowdom ? qy : qx;
+                const Sample sz = split(ax_offset(G.sa[a * ns + g], (double)o.k - G.ck,
+                                                  (double)j - A.cj));
+                zci = G.seg_off[g] + sz.i0;
+                zfr = sz.fu;
+            }
+            zc[t] = zci;
+            zf[t] = zfr;
+        }
+        __syncthreads();
+        if (!active) continue;
+        const float* drow = P.d + (int64_t)(P.d_ang0 + ia * P.d_step) * per_ang;
+        const float* mrow = MULT ? P.mult + (int64_t)a * per_ang : nullptr;
+        for (int kc = 0; kc < BWD_KC; ++kc) {
+            const ColCoord o = cc[cl * BWD_KC + kc];
+            if (o.wx == 0.0f) continue;
+            for (int zz = 0; zz < nzz; ++zz) {
+                const int iz = z0 + zz * zchunk;
+                if (iz >= nz) break;
+                float accr = 0.0f;
+                for (int g = 0; g < ns; ++g) {
+                    const int e = (cl * BWD_KC + kc) * ns + g;
+                    const int p0 = iz - zc[e];  // the voxel is the lower tap of plane p0
+                    const int p1 = p0 - 1;      // and the upper tap of plane p0 - 1
+                    const float fz = zf[e];
+                    const int ng = G.seg_planes[g];
+                    const int qb = G.seg_base[g];
+                    float sg = 0.0f;
+                    if ((unsigned)p0 < (unsigned)ng) {
+                        const int64_t i = D_QK ? (int64_t)(qb + p0) * G.n_rad + o.k
+                                               : (int64_t)o.k * G.n_planes + qb + p0;
+                        float v = drow[i];
+                        if (MULT) v *= mrow[i];
+                        sg = __builtin_fmaf(1.0f - fz, v, sg);
+                    }
+                    if ((unsigned)p1 < (unsigned)ng) {
+                        const int64_t i = D_QK ? (int64_t)(qb + p1) * G.n_rad + o.k
+                                               : (int64_t)o.k * G.n_planes + qb + p1;
+                        float v = drow[i];
+                        if (MULT) v *= mrow[i];
+                        sg = __builtin_fmaf(fz, v, sg);
+                    }
+                    accr = __builtin_fmaf(G.sa[a * ns + g].L, sg, accr);
+                }
+                acc[zz] = __builtin_fmaf(o.wx, accr, acc[zz]);
+            }
+        }
+    }
+    if (!active) return;
+    for (int zz = 0; zz < nzz; ++zz) {
+        const int iz = z0 + zz * zchunk;
+        if (iz >= nz) break;
+        const int64_t t = (int64_t)col * nz + iz;
+        const float dz = acc[zz];
+        if (MODE == B_PLAIN) {
+            P.out[t] = dz;
+        } else if (MODE == B_SENS) {
+            if (dz > 0.0f) P.T[t] = fminf(P.T[t], P.scale / dz);
+        } else {
+            // Algorithm 2 lines 7-8 and line 3 of the next iteration:
+            // z += dz;  x = max(x - T (z + dz / p_i), 0)
+            const float zn = P.z[t] + dz;
+            P.z[t] = zn;
+            const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
+            P.x[t] = fmaxf(P.x[t] - P.T[t] * zbar, 0.0f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- layout transposes
+// caller image [z][y][x] <-> internal [y][x][z]: per row y a 2-D transpose of (z, x).
+#define TT 32
+__global__ void __launch_bounds__(TT * 8)
+img_to_zf(int nx, int ny, int nz, const float* __restrict__ src, float* __restrict__ dst) {
+    __shared__ float tile[TT][TT + 1];
+    const int x0 = blockIdx.x * TT, z0 = blockIdx.y * TT, y = blockIdx.z;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+    for (int i = ty; i < TT; i += 8) {
+        const int z = z0 + i, x = x0 + tx;
+        if (z < nz && x < nx) tile[i][tx] = src[((int64_t)z * ny + y) * nx + x];
+    }
+    __syncthreads();
+    for (int i = ty; i < TT; i += 8) {
+        const int x = x0 + i, z = z0 + tx;
+        if (z < nz && x < nx) dst[((int64_t)y * nx + x) * nz + z] = tile[tx][i];
+    }
+}
+
+__global__ void __launch_bounds__(TT * 8)
+img_from_zf(int nx, int ny, int nz, const float* __restrict__ src, float* __restrict__ dst) {
+    __shared__ float tile[TT][TT + 1];
+    const int x0 = blockIdx.x * TT, z0 = blockIdx.y * TT, y = blockIdx.z;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+    for (int i = ty; i < TT; i += 8) {
+        const int x = x0 + i, z = z0 + tx;
+        if (z < nz && x < nx) tile[i][tx] = src[((int64_t)y * nx + x) * nz + z];
+    }
+    __syncthreads();
+    for (int i = ty; i < TT; i += 8) {
+        const int z = z0 + i, x = x0 + tx;
+        if (z < nz && x < nx) dst[((int64_t)z * ny + y) * nx + x] = tile[tx][i];
+    }
+}
+
+// caller sinogram [a][q][k] -> internal [a][k][q] (per angle a 2-D transpose).
+__global__ void __launch_bounds__(TT * 8)
+sino_to_kq(int n_planes, int n_rad, const float* __restrict__ src, float* __restrict__ dst) {
+    __shared__ float tile[TT][TT + 1];
+    const int k0 = blockIdx.x * TT, q0 = blockIdx.y * TT;
+    const int64_t a = blockIdx.z;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+    const float* s = src + a * n_planes * (int64_t)n_rad;
+    float* dd = dst + a * n_planes * (int64_t)n_rad;
+    for (int i = ty; i < TT; i += 8) {
+        const int q = q0 + i, k = k0 + tx;
+        if (q < n_planes && k < n_rad) tile[i][tx] = s[(int64_t)q * n_rad + k];
+    }
+    __syncthreads();
+    for (int i = ty; i < TT; i += 8) {
+        const int k = k0 + i, q = q0 + tx;
+        if (q < n_planes && k < n_rad) dd[(int64_t)k * n_planes + q] = tile[tx][i];
+    }
+}
+
+// internal [a][k][q] -> caller [a][q][k]
+__global__ void __launch_bounds__(TT * 8)
+sino_to_qk(int n_planes, int n_rad, const float* __restrict__ src, float* __restrict__ dst) {
+    __shared__ float tile[TT][TT + 1];
+    const int q0 = blockIdx.x * TT, k0 = blockIdx.y * TT;
+    const int64_t a = blockIdx.z;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+    const float* s = src + a * n_planes * (int64_t)n_rad;
+    float* dd = dst + a * n_planes * (int64_t)n_rad;
+    for (int i = ty; i < TT; i += 8) {
+        const int k = k0 + i, q = q0 + tx;
+        if (q < n_planes && k < n_rad) tile[i][tx] = s[(int64_t)k * n_planes + q];
+    }
+    __syncthreads();
+    for (int i = ty; i < TT; i += 8) {
+        const int q = q0 + i, k = k0 + tx;
+        if (q < n_planes && k < n_rad) dd[(int64_t)q * n_rad + k] = tile[tx][i];
+    }
+}
+
+// ---------------------------------------------------------------- FP64 reductions
 __global__ void __launch_bounds__(BLOCK)
 reduce_final(const double* __restrict__ part, int64_t n, double* __restrict__ out, int slot,
              double scale) {
     double v = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += BLOCK) v += part[i];
-    const double s = block_sum(v);
+    const double s = block_sum<BLOCK>(v);
     if (threadIdx.x == 0) out[slot] = scale * s;
 }
 
@@ -284,119 +495,6 @@ __global__ void combine_objective(double* out) {
         out[0] = out[1] + out[2];
         out[3] = 0.0;
     }
-}
-
-// ---------------------------------------------------------------- gather backprojection
-// (A_i^T d) at voxel (ix, iy, iz): every ray of the listed angles whose bilinear taps
-// include the voxel, with the weights of ray_sum.  d rows: d_ang0 + ia * d_step.
-// MULT: each d value is multiplied by mult at the full-sinogram position of the ray.
-template <bool MULT>
-__device__ float voxel_gather(const GeomDev& G, const float* __restrict__ d, int d_ang0,
-                              int d_step, int ang0, int ang_step, int n_ang_sub, int ix,
-                              int iy, int iz, const float* __restrict__ mult = nullptr) {
-    float acc = 0.0f;
-    const int64_t per_ang = (int64_t)G.n_planes * G.n_rad;
-    for (int ia = 0; ia < n_ang_sub; ++ia) {
-        const int a = ang0 + ia * ang_step;
-        const AngleDev A = G.ang[a];
-        const int j = A.rowdom ? iy : ix;
-        const int isec = A.rowdom ? ix : iy;
-        const double jj = (double)j - A.cj;
-        // candidate radial bins: u(k) in [isec - 1, isec + 1]
-        const double base = __builtin_fma(A.du_dj, jj, A.cu);
-        const double k_a = ((double)(isec - 1) - base) / A.du_dk + G.ck;
-        const double k_b = ((double)(isec + 1) - base) / A.du_dk + G.ck;
-        const int k0 = max(0, (int)__builtin_floor(fmin(k_a, k_b)) - 1);
-        const int k1 = min(G.n_rad - 1, (int)__builtin_ceil(fmax(k_a, k_b)) + 1);
-        const float* drow = d + (int64_t)(d_ang0 + ia * d_step) * per_ang;
-        const float* mrow = MULT ? mult + (int64_t)a * per_ang : nullptr;
-        for (int k = k0; k <= k1; ++k) {
-            const double kk = (double)k - G.ck;
-            const Sample s = split(sec_coord(A, kk, jj));
-            float wx;
-            if (s.i0 == isec)
-                wx = 1.0f - s.fu;
-            else if (s.i0 + 1 == isec)
-                wx = s.fu;
-            else
-                continue;
-            float accr = 0.0f;
-            for (int g = 0; g < G.n_seg; ++g) {
-                const SegAngleDev S = G.sa[a * G.n_seg + g];
-                const Sample sz = split(ax_offset(S, kk, jj));
-                const float fz = sz.fu;
-                const int p0 = iz - G.seg_off[g] - sz.i0;  // voxel is the lower tap
-                const int p1 = p0 - 1;                      // voxel is the upper tap
-                const int ng = G.seg_planes[g];
-                const int64_t o = (int64_t)G.seg_base[g] * G.n_rad + k;
-                const float* dr = drow + o;
-                float sg = 0.0f;
-                if ((unsigned)p0 < (unsigned)ng) {
-                    float v = dr[(int64_t)p0 * G.n_rad];
-                    if (MULT) v *= mrow[o + (int64_t)p0 * G.n_rad];
-                    sg += (1.0f - fz) * v;
-                }
-                if ((unsigned)p1 < (unsigned)ng) {
-                    float v = dr[(int64_t)p1 * G.n_rad];
-                    if (MULT) v *= mrow[o + (int64_t)p1 * G.n_rad];
-                    sg += fz * v;
-                }
-                accr += S.L * sg;
-            }
-            acc += wx * accr;
-        }
-    }
-    return acc;
-}
-
-__device__ __forceinline__ bool voxel_index(const GeomDev& G, int64_t t, int& ix, int& iy,
-                                            int& iz) {
-    const int64_t nxy = (int64_t)G.nx * G.ny;
-    if (t >= nxy * G.nz) return false;
-    iz = (int)(t / nxy);
-    const int64_t rem = t - (int64_t)iz * nxy;
-    iy = (int)(rem / G.nx);
-    ix = (int)(rem - (int64_t)iy * G.nx);
-    return true;
-}
-
-// out = G^T d, or G^T diag(mult) d when mult is given (full sinogram of factors).
-__global__ void __launch_bounds__(BLOCK)
-bwd_plain(GeomDev G, const float* __restrict__ d, int d_ang0, int d_step, int ang0,
-          int ang_step, int n_ang_sub, float* __restrict__ out, const float* __restrict__ mult) {
-    int ix, iy, iz;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (!voxel_index(G, t, ix, iy, iz)) return;
-    out[t] = mult ? voxel_gather<true>(G, d, d_ang0, d_step, ang0, ang_step, n_ang_sub, ix, iy,
-                                       iz, mult)
-                  : voxel_gather<false>(G, d, d_ang0, d_step, ang0, ang_step, n_ang_sub, ix, iy,
-                                        iz);
-}
-
-// T = min(T, scale / (A_i^T 1)) where A_i^T 1 > 0 (eq. STEPSIZE:PRECOND, Theorem 1).
-__global__ void __launch_bounds__(BLOCK)
-bwd_sens_min(GeomDev G, const float* __restrict__ mult, int ang0, int ang_step,
-             int n_ang_sub, float scale, float* __restrict__ T) {
-    int ix, iy, iz;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (!voxel_index(G, t, ix, iy, iz)) return;
-    const float s = voxel_gather<false>(G, mult, ang0, ang_step, ang0, ang_step, n_ang_sub, ix, iy, iz);
-    if (s > 0.0f) T[t] = fminf(T[t], scale / s);
-}
-
-// Algorithm 2 lines 6-8 for a data block, fused with line 3 of the next iteration:
-//   dz = A_i^T d;  z += dz;  x = max(x - T (z + dz / p_i), 0).
-__global__ void __launch_bounds__(BLOCK)
-bwd_iter(GeomDev G, const float* __restrict__ d, int ang0, int ang_step, int n_ang_sub,
-         float inv_p, float* __restrict__ z, float* __restrict__ x, const float* __restrict__ T) {
-    int ix, iy, iz;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (!voxel_index(G, t, ix, iy, iz)) return;
-    const float dz = voxel_gather<false>(G, d, 0, 1, ang0, ang_step, n_ang_sub, ix, iy, iz);
-    const float zn = z[t] + dz;
-    z[t] = zn;
-    const float zbar = __builtin_fmaf(dz, inv_p, zn);
-    x[t] = fmaxf(x[t] - T[t] * zbar, 0.0f);
 }
 
 // ---------------------------------------------------------------- TV / dTV prior block
@@ -409,7 +507,13 @@ struct PriorArgs {
     int dtv;
 };
 
-__device__ __forceinline__ float ld(const float* a, int64_t i) { return a[i]; }
+__device__ __forceinline__ void zf_coords(const PriorArgs& P, int64_t t, int& cx, int& cy,
+                                          int& cz) {
+    const int64_t col = t / P.nz;
+    cz = (int)(t - col * P.nz);
+    cy = (int)(col / P.nx);
+    cx = (int)(col - (int64_t)cy * P.nx);
+}
 
 // Dual update of the prior block at voxel c: q = P_alpha(y(c) + sigma A_n x (c)); returns
 // dy = q - y(c) (for dTV the D-weighted change D dy, i.e. the input of grad^T).
@@ -417,24 +521,24 @@ __device__ __forceinline__ void prior_dual_at(const PriorArgs& P, const float* _
                                               const float* __restrict__ y,
                                               const float* __restrict__ xi, int cx, int cy,
                                               int cz, float q[3], float dy[3]) {
-    const int64_t nxy = (int64_t)P.nx * P.ny;
-    const int64_t nv = nxy * P.nz;
-    const int64_t c = (int64_t)cz * nxy + (int64_t)cy * P.nx + cx;
-    const float xc = ld(x, c);
-    float g0 = cx < P.nx - 1 ? ld(x, c + 1) - xc : 0.0f;
-    float g1 = cy < P.ny - 1 ? ld(x, c + P.nx) - xc : 0.0f;
-    float g2 = cz < P.nz - 1 ? ld(x, c + nxy) - xc : 0.0f;
+    const int64_t sz = 1, sx = P.nz, sy = (int64_t)P.nz * P.nx;
+    const int64_t nv = sy * P.ny;
+    const int64_t c = (int64_t)cy * sy + (int64_t)cx * sx + cz;
+    const float xc = x[c];
+    float g0 = cx < P.nx - 1 ? x[c + sx] - xc : 0.0f;
+    float g1 = cy < P.ny - 1 ? x[c + sy] - xc : 0.0f;
+    float g2 = cz < P.nz - 1 ? x[c + sz] - xc : 0.0f;
     float x0 = 0.f, x1 = 0.f, x2 = 0.f;
     if (P.dtv) {
-        x0 = ld(xi, c);
-        x1 = ld(xi, c + nv);
-        x2 = ld(xi, c + 2 * nv);
+        x0 = xi[c];
+        x1 = xi[c + nv];
+        x2 = xi[c + 2 * nv];
         const float dot = x0 * g0 + x1 * g1 + x2 * g2;
         g0 -= P.gamma_d * dot * x0;
         g1 -= P.gamma_d * dot * x1;
         g2 -= P.gamma_d * dot * x2;
     }
-    const float y0 = ld(y, c), y1 = ld(y, c + nv), y2 = ld(y, c + 2 * nv);
+    const float y0 = y[c], y1 = y[c + nv], y2 = y[c + 2 * nv];
     q[0] = __builtin_fmaf(P.sigma, g0, y0);
     q[1] = __builtin_fmaf(P.sigma, g1, y1);
     q[2] = __builtin_fmaf(P.sigma, g2, y2);
@@ -463,13 +567,11 @@ __global__ void __launch_bounds__(BLOCK)
 tv_iter(PriorArgs P, const float* __restrict__ x_in, float* __restrict__ x_out,
         const float* __restrict__ y_in, float* __restrict__ y_out, float* __restrict__ z,
         const float* __restrict__ T, const float* __restrict__ xi) {
-    const int64_t nxy = (int64_t)P.nx * P.ny;
-    const int64_t nv = nxy * P.nz;
+    const int64_t nv = (int64_t)P.nx * P.ny * P.nz;
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (t >= nv) return;
-    const int cz = (int)(t / nxy);
-    const int cy = (int)((t - (int64_t)cz * nxy) / P.nx);
-    const int cx = (int)(t - (int64_t)cz * nxy - (int64_t)cy * P.nx);
+    int cx, cy, cz;
+    zf_coords(P, t, cx, cy, cz);
     float q[3], dy[3], qn[3], dn[3];
     prior_dual_at(P, x_in, y_in, xi, cx, cy, cz, q, dy);
     // grad^T p (v) = sum_d [v_d > 0] p_d(v - e_d) - [v_d < N_d - 1] p_d(v)
@@ -503,18 +605,17 @@ tv_iter(PriorArgs P, const float* __restrict__ x_in, float* __restrict__ x_out,
 __global__ void __launch_bounds__(BLOCK)
 tv_obj(PriorArgs P, const float* __restrict__ x, const float* __restrict__ xi,
        double* __restrict__ part, int use_grad) {
-    const int64_t nxy = (int64_t)P.nx * P.ny;
-    const int64_t nv = nxy * P.nz;
+    const int64_t sx = P.nz, sy = (int64_t)P.nz * P.nx;
+    const int64_t nv = sy * P.ny;
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     double v = 0.0;
     if (t < nv) {
-        const int cz = (int)(t / nxy);
-        const int cy = (int)((t - (int64_t)cz * nxy) / P.nx);
-        const int cx = (int)(t - (int64_t)cz * nxy - (int64_t)cy * P.nx);
+        int cx, cy, cz;
+        zf_coords(P, t, cx, cy, cz);
         const double xc = x[t];
-        double g0 = cx < P.nx - 1 ? (double)x[t + 1] - xc : 0.0;
-        double g1 = cy < P.ny - 1 ? (double)x[t + P.nx] - xc : 0.0;
-        double g2 = cz < P.nz - 1 ? (double)x[t + nxy] - xc : 0.0;
+        double g0 = cx < P.nx - 1 ? (double)x[t + sx] - xc : 0.0;
+        double g1 = cy < P.ny - 1 ? (double)x[t + sy] - xc : 0.0;
+        double g2 = cz < P.nz - 1 ? (double)x[t + 1] - xc : 0.0;
         if (P.dtv) {
             const double x0 = xi[t], x1 = xi[t + nv], x2 = xi[t + 2 * nv];
             const double dot = x0 * g0 + x1 * g1 + x2 * g2;
@@ -525,24 +626,23 @@ tv_obj(PriorArgs P, const float* __restrict__ x, const float* __restrict__ xi,
         v = use_grad ? (double)P.alpha * sqrt(g0 * g0 + g1 * g1 + g2 * g2) : 0.0;
         if (xc < 0.0) v = INFINITY;
     }
-    const double s = block_sum(v);
+    const double s = block_sum<BLOCK>(v);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// xi = grad s / sqrt(|grad s|^2 + eta^2) for the dTV side image s.
+// xi = grad s / sqrt(|grad s|^2 + eta^2) for the dTV side image s (z-fastest).
 __global__ void __launch_bounds__(BLOCK)
-dtv_field(int nx, int ny, int nz, const float* __restrict__ s, float eta, float* __restrict__ xi) {
-    const int64_t nxy = (int64_t)nx * ny;
-    const int64_t nv = nxy * nz;
+dtv_field(PriorArgs P, const float* __restrict__ s, float eta, float* __restrict__ xi) {
+    const int64_t sx = P.nz, sy = (int64_t)P.nz * P.nx;
+    const int64_t nv = sy * P.ny;
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (t >= nv) return;
-    const int cz = (int)(t / nxy);
-    const int cy = (int)((t - (int64_t)cz * nxy) / nx);
-    const int cx = (int)(t - (int64_t)cz * nxy - (int64_t)cy * nx);
+    int cx, cy, cz;
+    zf_coords(P, t, cx, cy, cz);
     const double sc = s[t];
-    const double g0 = cx < nx - 1 ? (double)s[t + 1] - sc : 0.0;
-    const double g1 = cy < ny - 1 ? (double)s[t + nx] - sc : 0.0;
-    const double g2 = cz < nz - 1 ? (double)s[t + nxy] - sc : 0.0;
+    const double g0 = cx < P.nx - 1 ? (double)s[t + sx] - sc : 0.0;
+    const double g1 = cy < P.ny - 1 ? (double)s[t + sy] - sc : 0.0;
+    const double g2 = cz < P.nz - 1 ? (double)s[t + 1] - sc : 0.0;
     const double nrm = sqrt(g0 * g0 + g1 * g1 + g2 * g2 + (double)eta * eta);
     xi[t] = (float)(g0 / nrm);
     xi[t + nv] = (float)(g1 / nrm);
@@ -570,7 +670,7 @@ __global__ void finalize_T(float* __restrict__ T, int64_t n, float t_prior) {
 
 // Domain check partials: counts of bins with b < 0 or r < 0 or mult <= 0 or non-finite
 // values (slot 0), and of bins whose objective term is infinite for every image:
-// b > 0, r = 0 and no voxel reaches the bin (sigma = 0 there) (slot 1).
+// b > 0, r = 0 and no voxel reaches the bin (a1 = 0 there) (slot 1).
 __global__ void __launch_bounds__(BLOCK)
 domain_check(const float* __restrict__ b, const float* __restrict__ r,
              const float* __restrict__ mult, const float* __restrict__ a1, int64_t n,
@@ -584,9 +684,8 @@ domain_check(const float* __restrict__ b, const float* __restrict__ r,
             bad = 1.0;
         if (bb > 0.0f && rr == 0.0f && !(a1[t] > 0.0f)) inf = 1.0;
     }
-    const double s0 = block_sum(bad);
-    __syncthreads();
-    const double s1 = block_sum(inf);
+    const double s0 = block_sum<BLOCK>(bad);
+    const double s1 = block_sum<BLOCK>(inf);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = s0;
         part[nblocks + blockIdx.x] = s1;
@@ -599,7 +698,7 @@ sumsq(const float* __restrict__ a, int64_t n, double* __restrict__ part) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     double v = 0.0;
     if (t < n) v = (double)a[t] * (double)a[t];
-    const double s = block_sum(v);
+    const double s = block_sum<BLOCK>(v);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -612,4 +711,111 @@ __global__ void scale_by_rnorm(const float* __restrict__ in, float* __restrict__
     }
 }
 
+// ---------------------------------------------------------------- tap counting
+// Number of taps of ray (a, q, k) with a nonzero weight inside the image: the ray's
+// nonzeros in the system matrix (measurement helper).
+__device__ double ray_taps(const GeomDev& G, int a, int q, int k) {
+    const AngleDev A = G.ang[a];
+    const int g = G.plane_seg[q];
+    const int p = q - G.seg_base[g];
+    const SegAngleDev S = G.sa[a * G.n_seg + g];
+    const double kk = (double)k - G.ck;
+    const int zb = p + G.seg_off[g];
+    int j0, j1;
+    sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
+    double n = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double jj = (double)j - A.cj;
+        const Sample s = split(sec_coord(A, kk, jj));
+        const Sample sz = split(ax_offset(S, kk, jj));
+        const int iz = zb + sz.i0;
+        const float wx[2] = {1.0f - s.fu, s.fu};
+        const float wz[2] = {1.0f - sz.fu, sz.fu};
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dx = 0; dx < 2; ++dx)
+                if ((unsigned)(s.i0 + dx) < (unsigned)A.n_sec &&
+                    (unsigned)(iz + dz) < (unsigned)G.nz && wx[dx] * wz[dz] != 0.0f)
+                    n += 1.0;
+    }
+    return n;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+fwd_count(GeomDev G, int ang0, int ang_step, int n_ang_sub, double* __restrict__ part) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t per_ang = (int64_t)G.n_planes * G.n_rad;
+    double v = 0.0;
+    if (t < per_ang * n_ang_sub) {
+        const int ia = (int)(t / per_ang);
+        const int64_t rem = t - (int64_t)ia * per_ang;
+        const int q = (int)(rem / G.n_rad);
+        const int k = (int)(rem - (int64_t)q * G.n_rad);
+        v = ray_taps(G, ang0 + ia * ang_step, q, k);
+    }
+    const double s = block_sum<BLOCK>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+}  // namespace spdhg
+
+namespace spdhg {
+// ---------------------------------------------------------------- dTV operator norm
+// (-1)^(ix + iy + iz): start vector of the power iteration for difference operators.
+__global__ void checkerboard_zf(PriorArgs P, float* __restrict__ out) {
+    const int64_t nv = (int64_t)P.nx * P.ny * P.nz;
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= nv) return;
+    int cx, cy, cz;
+    zf_coords(P, t, cx, cy, cz);
+    out[t] = ((cx + cy + cz) & 1) ? -1.0f : 1.0f;
+}
+
+// out[3][v] = D_v grad x (v)
+__global__ void __launch_bounds__(BLOCK)
+dgrad_apply(PriorArgs P, const float* __restrict__ x, const float* __restrict__ xi,
+            float* __restrict__ out) {
+    const int64_t sx = P.nz, sy = (int64_t)P.nz * P.nx;
+    const int64_t nv = sy * P.ny;
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= nv) return;
+    int cx, cy, cz;
+    zf_coords(P, t, cx, cy, cz);
+    const float xc = x[t];
+    float g0 = cx < P.nx - 1 ? x[t + sx] - xc : 0.0f;
+    float g1 = cy < P.ny - 1 ? x[t + sy] - xc : 0.0f;
+    float g2 = cz < P.nz - 1 ? x[t + 1] - xc : 0.0f;
+    const float x0 = xi[t], x1 = xi[t + nv], x2 = xi[t + 2 * nv];
+    const float dot = x0 * g0 + x1 * g1 + x2 * g2;
+    out[t] = g0 - P.gamma_d * dot * x0;
+    out[t + nv] = g1 - P.gamma_d * dot * x1;
+    out[t + 2 * nv] = g2 - P.gamma_d * dot * x2;
+}
+
+// out[v] = grad^T (D p) (v)
+__global__ void __launch_bounds__(BLOCK)
+dgrad_adj(PriorArgs P, const float* __restrict__ p, const float* __restrict__ xi,
+          float* __restrict__ out) {
+    const int64_t sx = P.nz, sy = (int64_t)P.nz * P.nx;
+    const int64_t nv = sy * P.ny;
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= nv) return;
+    int cx, cy, cz;
+    zf_coords(P, t, cx, cy, cz);
+    auto dp = [&](int64_t c, int comp) {
+        const float x0 = xi[c], x1 = xi[c + nv], x2 = xi[c + 2 * nv];
+        const float p0 = p[c], p1 = p[c + nv], p2 = p[c + 2 * nv];
+        const float dot = x0 * p0 + x1 * p1 + x2 * p2;
+        const float xs = comp == 0 ? x0 : (comp == 1 ? x1 : x2);
+        const float ps = comp == 0 ? p0 : (comp == 1 ? p1 : p2);
+        return ps - P.gamma_d * dot * xs;
+    };
+    float v = 0.0f;
+    if (cx < P.nx - 1) v -= dp(t, 0);
+    if (cy < P.ny - 1) v -= dp(t, 1);
+    if (cz < P.nz - 1) v -= dp(t, 2);
+    if (cx > 0) v += dp(t - sx, 0);
+    if (cy > 0) v += dp(t - sy, 1);
+    if (cz > 0) v += dp(t - 1, 2);
+    out[t] = v;
+}
 }  // namespace spdhg

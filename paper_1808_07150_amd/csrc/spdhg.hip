@@ -233,21 +233,110 @@ double grad_norm(int nx, int ny, int nz) {
 
 }  // namespace
 
+namespace {
+
+// Zero padding of the axial column in the forward kernel: every axial cell offset
+// floor(e) of a sample inside the in-plane range satisfies |floor(e)| <= pad - 2, since
+// |e| <= |ez_dj| (n_prim - 1) / 2 + |ez_dk| (n_rad - 1) / 2 (e is affine in the centred
+// indices).
+int axial_pad(const HostTables& T) {
+    double m = 0.0;
+    const int ns = T.G.n_seg;
+    for (size_t a = 0; a < T.ang.size(); ++a)
+        for (int g = 0; g < ns; ++g) {
+            const SegAngleDev& S = T.sa[a * ns + g];
+            m = std::max(m, std::fabs(S.ez_dj) * T.ang[a].cj + std::fabs(S.ez_dk) * T.G.ck);
+        }
+    return (int)std::ceil(m) + 2;
+}
+
+// Rays per lane of the forward kernel: smallest supported power of two >= planes / 64.
+int rays_per_lane(int n_planes) {
+    const int need = (n_planes + 63) / 64;
+    for (int r : {1, 2, 4, 8, 16, 32, 64})
+        if (r >= need) return r;
+    return -1;
+}
+
+int check_kernel_limits(const spdhg_geom* g) {
+    if (rays_per_lane((int)n_planes(g)) < 0)
+        return fail(SPDHG_E_SHAPE, "more than 4096 sinogram planes");
+    if (g->nz > 512) return fail(SPDHG_E_SHAPE, "nz above 512");
+    // the gather keeps at most 4 candidate radial bins per voxel column and angle: the
+    // radial spacing must be at least half the in-plane voxel size
+    if (g->d_rad < 0.5 * std::max(g->vx, g->vy))
+        return fail(SPDHG_E_SHAPE, "radial spacing below half the voxel size");
+    return SPDHG_OK;
+}
+
+// ---------------------------------------------------------------- launch helpers
+template <int MODE>
+int launch_fwd_rpl(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
+    const size_t lds = (2 * (size_t)A.gsize + 4 * (size_t)A.G.n_seg) * 4;
+    switch (rpl) {
+        case 1: fwd_wave<1, MODE><<<nblk, 64, lds, st>>>(A); break;
+        case 2: fwd_wave<2, MODE><<<nblk, 64, lds, st>>>(A); break;
+        case 4: fwd_wave<4, MODE><<<nblk, 64, lds, st>>>(A); break;
+        case 8: fwd_wave<8, MODE><<<nblk, 64, lds, st>>>(A); break;
+        case 16: fwd_wave<16, MODE><<<nblk, 64, lds, st>>>(A); break;
+        case 32: fwd_wave<32, MODE><<<nblk, 64, lds, st>>>(A); break;
+        case 64: fwd_wave<64, MODE><<<nblk, 64, lds, st>>>(A); break;
+        default: return fail(SPDHG_E_SHAPE, "unsupported plane count");
+    }
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+// One block per (angle of the list, radial bin).
+template <int MODE>
+int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
+    A.ang0 = ang0;
+    A.ang_step = step;
+    A.n_ang_sub = cnt;
+    const int64_t nblk = (int64_t)cnt * A.G.n_rad;
+    if (nblk == 0) return SPDHG_OK;
+    if (nblk > INT32_MAX) return fail(SPDHG_E_SHAPE, "too many rays");
+    return launch_fwd_rpl<MODE>(rays_per_lane(A.G.n_planes), A, (int)nblk, st);
+}
+
+int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }
+
+template <int MODE, bool D_QK, bool MULT>
+int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
+    A.ang0 = ang0;
+    A.ang_step = step;
+    A.n_ang_sub = cnt;
+    A.cols = bwd_cols(A.G.nz);
+    const int64_t ncol = (int64_t)A.G.nx * A.G.ny;
+    const int64_t nblk = (ncol + A.cols - 1) / A.cols;
+    const size_t lds = (size_t)A.cols * BWD_KC * (sizeof(ColCoord) + 8 * (size_t)A.G.n_seg);
+    bwd_col<MODE, D_QK, MULT><<<(unsigned)nblk, BWD_THREADS, lds, st>>>(A);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+dim3 img_grid(int nx, int ny, int nz) { return dim3((nx + TT - 1) / TT, (nz + TT - 1) / TT, ny); }
+
+}  // namespace
+
 // ====================================================================== context
 struct spdhg_ctx {
     spdhg_geom geom;
     spdhg_params prm;
     HostTables tab;
     int device = 0;
-    const float *b = nullptr, *r = nullptr, *mult = nullptr, *side = nullptr;
+    int pad = 0, gsize = 0;
+    const float* side = nullptr;
     float* x_user = nullptr;
-    // workspace regions
-    float *y = nullptr, *sigma = nullptr, *dscr = nullptr, *x2 = nullptr, *z = nullptr,
-          *T = nullptr, *yn[2] = {nullptr, nullptr}, *xi = nullptr;
+    // workspace regions (internal layouts: images z-fastest, sinograms [a][k][q])
+    float *bp = nullptr, *rp = nullptr, *mp = nullptr;  // private b, r, mult
+    float *y = nullptr, *sigma = nullptr, *dscr = nullptr;
+    float *xa = nullptr, *xb = nullptr, *z = nullptr, *T = nullptr, *scr = nullptr;
+    float *yn[2] = {nullptr, nullptr}, *xi = nullptr;
     double* part = nullptr;
     double* scal = nullptr;  // 8 doubles of device scalars
     int64_t part_n = 0;
-    int x_cur = 0;   // 0: iterate in x_user, 1: in x2
+    int x_cur = 0;  // iterate in xa (0) or xb (1)
     int yn_cur = 0;
     int m = 1, n = 1, n_prior = 0;
     std::vector<double> p, cum;
@@ -263,14 +352,37 @@ struct spdhg_ctx {
     size_t ev_used = 0;
     double prof_ms[SPDHG_PROF_KINDS] = {0};
     int64_t prof_n[SPDHG_PROF_KINDS] = {0};
-    float* xcur() { return x_cur ? x2 : x_user; }
-    float* xother() { return x_cur ? x_user : x2; }
+    float* xcur() { return x_cur ? xb : xa; }
+    float* xother() { return x_cur ? xa : xb; }
+    FwdArgs fwd_args() const {
+        FwdArgs A{};
+        A.G = tab.G;
+        A.pad = pad;
+        A.gsize = gsize;
+        return A;
+    }
+    BwdArgs bwd_args() const {
+        BwdArgs A{};
+        A.G = tab.G;
+        return A;
+    }
+    PriorArgs prior_args() const {
+        PriorArgs P{};
+        P.nx = geom.nx;
+        P.ny = geom.ny;
+        P.nz = geom.nz;
+        P.sigma = (float)prior_sigma;
+        P.alpha = (float)prm.alpha;
+        P.gamma_d = (float)prm.gamma_d;
+        P.dtv = prm.prior == SPDHG_PRIOR_DTV;
+        return P;
+    }
 };
 
 namespace {
 
 struct Layout {
-    size_t tables, y, sigma, dscr, x2, z, T, yn, xi, part, scal, total;
+    size_t tables, bp, rp, mp, y, sigma, dscr, xa, xb, z, T, scr, yn, xi, part, scal, total;
     int64_t part_n;
 };
 
@@ -289,15 +401,22 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
         return o;
     };
     L.tables = take(table_bytes(tab));
+    L.bp = take(nb * 4);
+    L.rp = take(nb * 4);
+    L.mp = take(nb * 4);
     L.y = take(nb * 4);
     L.sigma = take(p->precond ? nb * 4 : 0);
-    L.dscr = take(std::max(max_sub, nv) * 4);
-    L.x2 = take(nv * 4);
+    L.dscr = take(max_sub * 4);
+    L.xa = take(nv * 4);
+    L.xb = take(nv * 4);
     L.z = take(nv * 4);
     L.T = take(nv * 4);
+    L.scr = take(nv * 4);
     L.yn = take(prior ? 6 * nv * 4 : 0);
     L.xi = take(p->prior == SPDHG_PRIOR_DTV ? 3 * nv * 4 : 0);
-    L.part_n = std::max<int64_t>({(nb + BLOCK - 1) / BLOCK, (nv + BLOCK - 1) / BLOCK, 1}) * 2;
+    const int64_t fwd_blocks = (int64_t)g->n_ang * g->n_rad;
+    L.part_n = std::max<int64_t>({(nb + BLOCK - 1) / BLOCK, (nv + BLOCK - 1) / BLOCK,
+                                  fwd_blocks, 1}) * 2;
     L.part = take(L.part_n * 8);
     L.scal = take(8 * 8);
     L.total = off;
@@ -322,41 +441,117 @@ int check_params(const spdhg_geom* g, const spdhg_params* p) {
     return SPDHG_OK;
 }
 
-// Sum of `n` partials into scal[slot] (times `scale`), then copy to host if `host`.
-int reduce_to(spdhg_ctx* c, int64_t n, int slot, double scale, hipStream_t st) {
-    reduce_final<<<1, BLOCK, 0, st>>>(c->part, n, c->scal, slot, scale);
+int reduce_to(double* part, int64_t n, double* out, int slot, double scale, hipStream_t st) {
+    reduce_final<<<1, BLOCK, 0, st>>>(part, n, out, slot, scale);
     LAUNCH_CHECK();
     return SPDHG_OK;
 }
 
-// ||A v||^2 / ||v||^2 style power iteration for data block i (scalar steps): returns
-// sqrt of the Rayleigh growth of A_i^T A_i from the ones image.
+// Power iteration on A_i^T A_i from the ones image (scalar steps of Theorem 2): norm of
+// data block i.  Uses xb, z and y as scratch (reset by the caller afterwards).
 int power_norm_data(spdhg_ctx* c, int i, double* out, hipStream_t st) {
-    int ang0, step, cnt;
-    int rc = subset_angles(&c->geom, c->m, i, ang0, step, cnt);
+    int a0, step, cnt;
+    int rc = subset_angles(&c->geom, c->m, i, a0, step, cnt);
     if (rc) return rc;
     const int64_t nv = c->nv;
-    const int64_t nsub = (int64_t)cnt * c->tab.G.n_planes * c->geom.n_rad;
-    float* v = c->x2;
+    float* v = c->xb;
     float* w = c->z;
-    float* tmp = c->y;  // full-size scratch during init
+    float* tmp = c->y;
     fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, 1.0f);
     sumsq<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, c->part);
-    reduce_to(c, nblocks(nv), 0, 1.0, st);
+    if ((rc = reduce_to(c->part, nblocks(nv), c->scal, 0, 1.0, st))) return rc;
     scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(v, v, nv, c->scal);
     for (int it = 0; it < c->prm.power_iters; ++it) {
         // w = A_i^T A_i v = G^T diag(mult) (mult * G v)
-        fwd_plain<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, v, c->mult, tmp, ang0, step, cnt);
-        bwd_plain<<<nblocks(nv), BLOCK, 0, st>>>(c->tab.G, tmp, 0, 1, ang0, step, cnt, w, c->mult);
-        LAUNCH_CHECK();
+        FwdArgs F = c->fwd_args();
+        F.x = v;
+        F.mult = c->mp;
+        F.out = tmp;
+        if ((rc = launch_fwd<F_PLAIN_KQ>(F, a0, step, cnt, st))) return rc;
+        BwdArgs B = c->bwd_args();
+        B.d = tmp;
+        B.d_ang0 = 0;
+        B.d_step = 1;
+        B.mult = c->mp;
+        B.out = w;
+        if ((rc = launch_bwd<B_PLAIN, false, true>(B, a0, step, cnt, st))) return rc;
         sumsq<<<nblocks(nv), BLOCK, 0, st>>>(w, nv, c->part);
-        reduce_to(c, nblocks(nv), 0, 1.0, st);
+        if ((rc = reduce_to(c->part, nblocks(nv), c->scal, 0, 1.0, st))) return rc;
         scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(w, v, nv, c->scal);
     }
+    LAUNCH_CHECK();
     double h = 0.0;
     HIP_TRY(hipMemcpyAsync(&h, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *out = std::sqrt(std::sqrt(h));
+    return SPDHG_OK;
+}
+
+// Power iteration on (D grad)^T (D grad) from a checkerboard, 200 iterations: ||D grad||
+// for dTV.  Uses xb, z and yn[0] as scratch.
+int power_norm_dgrad(spdhg_ctx* c, double* out, hipStream_t st) {
+    const int64_t nv = c->nv;
+    PriorArgs P = c->prior_args();
+    float* v = c->xb;
+    float* w = c->z;
+    float* pp = c->yn[0];
+    int rc;
+    checkerboard_zf<<<nblocks(nv), BLOCK, 0, st>>>(P, v);
+    sumsq<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, c->part);
+    if ((rc = reduce_to(c->part, nblocks(nv), c->scal, 0, 1.0, st))) return rc;
+    scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(v, v, nv, c->scal);
+    for (int it = 0; it < 200; ++it) {
+        dgrad_apply<<<nblocks(nv), BLOCK, 0, st>>>(P, v, c->xi, pp);
+        dgrad_adj<<<nblocks(nv), BLOCK, 0, st>>>(P, pp, c->xi, w);
+        sumsq<<<nblocks(nv), BLOCK, 0, st>>>(w, nv, c->part);
+        if ((rc = reduce_to(c->part, nblocks(nv), c->scal, 0, 1.0, st))) return rc;
+        scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(w, v, nv, c->scal);
+    }
+    LAUNCH_CHECK();
+    double h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&h, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = std::sqrt(std::sqrt(h));
+    return SPDHG_OK;
+}
+
+// Copy the internal iterate out to the caller's image.
+int export_x(spdhg_ctx* c, hipStream_t st) {
+    const spdhg_geom& g = c->geom;
+    img_from_zf<<<img_grid(g.nx, g.ny, g.nz), TT * 8, 0, st>>>(g.nx, g.ny, g.nz, c->xcur(),
+                                                               c->x_user);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+// Per-kernel timing (events around launches; collected on demand).
+int prof_collect(spdhg_ctx* c) {
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        HIP_TRY(hipEventSynchronize(c->ev[2 * i + 1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        c->prof_ms[c->ev_kind[i]] += ms;
+        c->prof_n[c->ev_kind[i]] += 1;
+    }
+    c->ev_used = 0;
+    return SPDHG_OK;
+}
+
+int prof_begin(spdhg_ctx* c, int kind, hipStream_t st) {
+    if (!c->prof) return SPDHG_OK;
+    if (2 * c->ev_used + 2 > c->ev.size()) {
+        int rc = prof_collect(c);
+        if (rc) return rc;
+    }
+    c->ev_kind[c->ev_used] = kind;
+    HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used], st));
+    return SPDHG_OK;
+}
+
+int prof_end(spdhg_ctx* c, hipStream_t st) {
+    if (!c->prof) return SPDHG_OK;
+    HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used + 1], st));
+    c->ev_used += 1;
     return SPDHG_OK;
 }
 
@@ -377,7 +572,7 @@ int64_t spdhg_subset_bins(const spdhg_geom* geom, int32_t n_subsets, int32_t sub
 int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, const float* mult,
                   const float* x, float* y_out, void* stream) {
     int rc = check_geom(geom);
-    if (rc) return rc;
+    if (rc || (rc = check_kernel_limits(geom))) return rc;
     if (!x || !y_out) return fail(SPDHG_E_ARG, "NULL image or output");
     int a0, step, cnt;
     rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
@@ -385,17 +580,32 @@ int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, con
     GeomDev G;
     rc = cached_geom(geom, G);
     if (rc) return rc;
-    const int64_t n = (int64_t)cnt * G.n_planes * G.n_rad;
+    HostTables T;
+    build_tables(geom, T);
     hipStream_t st = (hipStream_t)stream;
-    fwd_plain<<<nblocks(n), BLOCK, 0, st>>>(G, x, mult, y_out, a0, step, cnt);
-    LAUNCH_CHECK();
+    const int64_t nv = (int64_t)geom->nx * geom->ny * geom->nz;
+    float* xz = nullptr;  // stream-ordered scratch: the image in the z-fastest layout
+    HIP_TRY(hipMallocAsync((void**)&xz, nv * 4, st));
+    img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(geom->nx, geom->ny,
+                                                                         geom->nz, x, xz);
+    FwdArgs F{};
+    F.G = G;
+    F.pad = axial_pad(T);
+    F.gsize = geom->nz + 2 * F.pad;
+    F.x = xz;
+    F.mult = mult;
+    F.out = y_out;
+    rc = launch_fwd<F_PLAIN_QK>(F, a0, step, cnt, st);
+    hipError_t e = hipFreeAsync(xz, st);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("hipFreeAsync: ") + hipGetErrorString(e));
     return SPDHG_OK;
 }
 
 int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
                       const float* mult, const float* y, float* x_out, void* stream) {
     int rc = check_geom(geom);
-    if (rc) return rc;
+    if (rc || (rc = check_kernel_limits(geom))) return rc;
     if (!y || !x_out) return fail(SPDHG_E_ARG, "NULL sinogram or output");
     int a0, step, cnt;
     rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
@@ -405,8 +615,26 @@ int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
     if (rc) return rc;
     const int64_t nv = (int64_t)geom->nx * geom->ny * geom->nz;
     hipStream_t st = (hipStream_t)stream;
-    bwd_plain<<<nblocks(nv), BLOCK, 0, st>>>(G, y, 0, 1, a0, step, cnt, x_out, mult);
-    LAUNCH_CHECK();
+    float* xz = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&xz, nv * 4, st));
+    BwdArgs B{};
+    B.G = G;
+    B.d = y;
+    B.d_ang0 = 0;
+    B.d_step = 1;
+    B.mult = mult;
+    B.out = xz;
+    rc = mult ? launch_bwd<B_PLAIN, true, true>(B, a0, step, cnt, st)
+              : launch_bwd<B_PLAIN, true, false>(B, a0, step, cnt, st);
+    if (!rc) {
+        img_from_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
+            geom->nx, geom->ny, geom->nz, xz, x_out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(SPDHG_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipFreeAsync(xz, st);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("hipFreeAsync: ") + hipGetErrorString(e));
     return SPDHG_OK;
 }
 
@@ -425,13 +653,14 @@ int spdhg_nnz(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, double*
     const int64_t n = (int64_t)cnt * G.n_planes * G.n_rad;
     const int64_t nbk = nblocks(n);
     double* part = nullptr;
-    HIP_TRY(hipMalloc(&part, (nbk + 1) * sizeof(double)));
+    HIP_TRY(hipMallocAsync((void**)&part, (nbk + 1) * sizeof(double), st));
     fwd_count<<<nbk, BLOCK, 0, st>>>(G, a0, step, cnt, part);
     reduce_final<<<1, BLOCK, 0, st>>>(part, nbk, part + nbk, 0, 1.0);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(out, part + nbk, sizeof(double), hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipFreeAsync(part, st);
+    if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(part);
     if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("spdhg_nnz: ") + hipGetErrorString(e));
     return SPDHG_OK;
 }
@@ -454,46 +683,47 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     if (!out) return fail(SPDHG_E_ARG, "out is NULL");
     *out = nullptr;
     int rc = check_geom(geom);
-    if (rc) return rc;
+    if (rc || (rc = check_kernel_limits(geom))) return rc;
     rc = check_params(geom, params);
     if (rc) return rc;
     if (!b || !r || !mult || !x) return fail(SPDHG_E_ARG, "NULL b, r, mult or x");
     if (params->prior == SPDHG_PRIOR_DTV && !side) return fail(SPDHG_E_ARG, "dTV needs a side image");
     if (!ws) return fail(SPDHG_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) & 255) return fail(SPDHG_E_WORKSPACE, "workspace must be 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
 
     spdhg_ctx* c = new spdhg_ctx();
+    auto bail = [&](int code) {
+        delete c;
+        return code;
+    };
     c->geom = *geom;
     c->prm = *params;
     build_tables(geom, c->tab);
     Layout L = layout(geom, params, c->tab);
-    if (ws_bytes < L.total) {
-        delete c;
-        return fail(SPDHG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+    if (ws_bytes < L.total)
+        return bail(fail(SPDHG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total)));
+    {
+        hipError_t e = hipGetDevice(&c->device);
+        if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
     }
-    if (((uintptr_t)ws) & 255) {
-        delete c;
-        return fail(SPDHG_E_WORKSPACE, "workspace must be 256-byte aligned");
-    }
-    HIP_TRY(hipGetDevice(&c->device));
     char* w = (char*)ws;
-    // the tables are copied synchronously before any kernel on `st` may use them
-    rc = upload_tables(c->tab, w + L.tables);
-    if (rc) {
-        delete c;
-        return rc;
-    }
-    c->b = b;
-    c->r = r;
-    c->mult = mult;
+    if ((rc = upload_tables(c->tab, w + L.tables))) return bail(rc);
+    c->pad = axial_pad(c->tab);
+    c->gsize = geom->nz + 2 * c->pad;
     c->side = side;
     c->x_user = x;
+    c->bp = (float*)(w + L.bp);
+    c->rp = (float*)(w + L.rp);
+    c->mp = (float*)(w + L.mp);
     c->y = (float*)(w + L.y);
     c->sigma = params->precond ? (float*)(w + L.sigma) : nullptr;
     c->dscr = (float*)(w + L.dscr);
-    c->x2 = (float*)(w + L.x2);
+    c->xa = (float*)(w + L.xa);
+    c->xb = (float*)(w + L.xb);
     c->z = (float*)(w + L.z);
     c->T = (float*)(w + L.T);
+    c->scr = (float*)(w + L.scr);
     const bool prior = params->prior != SPDHG_PRIOR_NONE;
     c->nv = (int64_t)geom->nx * geom->ny * geom->nz;
     c->nb = (int64_t)geom->n_ang * c->tab.G.n_planes * geom->n_rad;
@@ -526,56 +756,72 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     c->iters_per_epoch = (int64_t)std::llround(c->m / pdata);
     const int64_t nv = c->nv, nb = c->nb;
     const double gam = params->gamma, rho = params->rho;
+    const int np = c->tab.G.n_planes;
 
-    // domain check: needs A 1 > 0 per bin; computed into y (zeroed afterwards)
-    fwd_sens<<<nblocks(nb), BLOCK, 0, st>>>(c->tab.G, mult, c->y, 1.0f);
-    LAUNCH_CHECK();
+    // private copies of b, r, mult in the [a][k][q] layout
     {
+        dim3 grid((geom->n_rad + TT - 1) / TT, (np + TT - 1) / TT, geom->n_ang);
+        sino_to_kq<<<grid, TT * 8, 0, st>>>(np, geom->n_rad, b, c->bp);
+        sino_to_kq<<<grid, TT * 8, 0, st>>>(np, geom->n_rad, r, c->rp);
+        sino_to_kq<<<grid, TT * 8, 0, st>>>(np, geom->n_rad, mult, c->mp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
+    }
+    // domain check: needs A 1 > 0 per bin (computed into y, zeroed afterwards)
+    {
+        FwdArgs F = c->fwd_args();
+        F.mult = c->mp;
+        F.out = c->y;
+        F.gr = 1.0f;
+        if ((rc = launch_fwd<F_SENS>(F, 0, 1, geom->n_ang, st))) return bail(rc);
         const int64_t nbk = nblocks(nb);
-        if (2 * nbk > c->part_n) {
-            delete c;
-            return fail(SPDHG_E_WORKSPACE, "partials buffer too small");
-        }
-        domain_check<<<nbk, BLOCK, 0, st>>>(b, r, mult, c->y, nb, c->part, nbk);
+        if (2 * nbk > c->part_n) return bail(fail(SPDHG_E_WORKSPACE, "partials buffer too small"));
+        domain_check<<<nbk, BLOCK, 0, st>>>(c->bp, c->rp, c->mp, c->y, nb, c->part, nbk);
         reduce_final<<<1, BLOCK, 0, st>>>(c->part, nbk, c->scal, 0, 1.0);
         reduce_final<<<1, BLOCK, 0, st>>>(c->part + nbk, nbk, c->scal, 1, 1.0);
-        LAUNCH_CHECK();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
         double h[2];
-        HIP_TRY(hipMemcpyAsync(h, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (h[0] > 0) {
-            delete c;
-            return fail(SPDHG_E_DOMAIN, "b < 0, r < 0, mult <= 0 or non-finite data in " +
-                                            std::to_string((long long)h[0]) + " bins");
-        }
-        if (h[1] > 0) {
-            delete c;
-            return fail(SPDHG_E_DOMAIN, std::to_string((long long)h[1]) +
-                                            " bins have b > 0, r = 0 and no voxel on the ray");
-        }
+        e = hipMemcpyAsync(h, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
+        if (h[0] > 0)
+            return bail(fail(SPDHG_E_DOMAIN, "b < 0, r < 0, mult <= 0 or non-finite data in " +
+                                                 std::to_string((long long)h[0]) + " bins"));
+        if (h[1] > 0)
+            return bail(fail(SPDHG_E_DOMAIN, std::to_string((long long)h[1]) +
+                                                 " bins have b > 0, r = 0 and no voxel on the ray"));
     }
+    // the image: caller layout -> z-fastest, line 3 with z = 0: x = max(x0, 0)
+    img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(geom->nx, geom->ny,
+                                                                         geom->nz, x, c->xa);
+    clip_nonneg<<<nblocks(nv), BLOCK, 0, st>>>(c->xa, nv);
     // step sizes (Theorem 2)
     double t_data_scalar = INFINITY;
     if (params->precond) {
-        fwd_sens<<<nblocks(nb), BLOCK, 0, st>>>(c->tab.G, mult, c->sigma, (float)(gam * rho));
+        FwdArgs F = c->fwd_args();
+        F.mult = c->mp;
+        F.out = c->sigma;
+        F.gr = (float)(gam * rho);
+        if ((rc = launch_fwd<F_SENS>(F, 0, 1, geom->n_ang, st))) return bail(rc);
         fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->T, nv, INFINITY);
         for (int i = 0; i < c->m; ++i) {
             int a0, step, cnt;
             subset_angles(geom, c->m, i, a0, step, cnt);
-            bwd_sens_min<<<nblocks(nv), BLOCK, 0, st>>>(c->tab.G, mult, a0, step, cnt,
-                                                        (float)(rho * c->p[i] / gam), c->T);
+            BwdArgs B = c->bwd_args();
+            B.d = c->mp;
+            B.d_ang0 = a0;
+            B.d_step = step;
+            B.scale = (float)(rho * c->p[i] / gam);
+            B.T = c->T;
+            if ((rc = launch_bwd<B_SENS, false, false>(B, a0, step, cnt, st))) return bail(rc);
         }
-        LAUNCH_CHECK();
     } else {
         c->data_norm.resize(c->m);
         c->data_sigma.resize(c->m);
         for (int i = 0; i < c->m; ++i) {
             double nrm = 0.0;
-            rc = power_norm_data(c, i, &nrm, st);
-            if (rc) {
-                delete c;
-                return rc;
-            }
+            if ((rc = power_norm_data(c, i, &nrm, st))) return bail(rc);
             c->data_norm[i] = nrm;
             c->data_sigma[i] = gam * rho / nrm;
             t_data_scalar = std::min(t_data_scalar, rho * c->p[i] / (gam * nrm));
@@ -585,69 +831,45 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     double t_prior = INFINITY;
     if (prior) {
         if (params->prior == SPDHG_PRIOR_DTV) {
-            dtv_field<<<nblocks(nv), BLOCK, 0, st>>>(geom->nx, geom->ny, geom->nz, side,
+            img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
+                geom->nx, geom->ny, geom->nz, side, c->scr);
+            dtv_field<<<nblocks(nv), BLOCK, 0, st>>>(c->prior_args(), c->scr,
                                                      (float)params->eta, c->xi);
-            LAUNCH_CHECK();
+            double nrm = 0.0;
+            if ((rc = power_norm_dgrad(c, &nrm, st))) return bail(rc);
+            c->prior_norm = nrm;
+        } else {
+            c->prior_norm = grad_norm(geom->nx, geom->ny, geom->nz);
         }
-        // ||grad|| in closed form; ||D grad|| <= ||D|| ||grad|| <= ||grad|| for
-        // gamma_d in [0, 1], so the same bound keeps the step condition for dTV
-        c->prior_norm = grad_norm(geom->nx, geom->ny, geom->nz);
         c->prior_sigma = gam * rho / c->prior_norm;
         t_prior = rho * c->p[c->m] / (gam * c->prior_norm);
     }
     finalize_T<<<nblocks(nv), BLOCK, 0, st>>>(c->T, nv, (float)t_prior);
-    // y = 0, z = 0, prior duals = 0, x = max(x0, 0)
-    HIP_TRY(hipMemsetAsync(c->y, 0, nb * 4, st));
-    HIP_TRY(hipMemsetAsync(c->z, 0, nv * 4, st));
-    if (prior) HIP_TRY(hipMemsetAsync(c->yn[0], 0, 6 * nv * 4, st));
-    clip_nonneg<<<nblocks(nv), BLOCK, 0, st>>>(x, nv);
-    LAUNCH_CHECK();
+    // y = 0, z = 0, prior duals = 0
+    fill_f32<<<nblocks(nb), BLOCK, 0, st>>>(c->y, nb, 0.0f);
+    fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->z, nv, 0.0f);
+    if (prior) fill_f32<<<nblocks(6 * nv), BLOCK, 0, st>>>(c->yn[0], 6 * nv, 0.0f);
+    {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
+    }
+    if ((rc = export_x(c, st))) return bail(rc);
     int64_t max_sub = 0;
     for (int i = 0; i < c->m; ++i) {
         int a0, step, cnt;
         subset_angles(geom, c->m, i, a0, step, cnt);
-        max_sub = std::max<int64_t>(max_sub, (int64_t)cnt * c->tab.G.n_planes * geom->n_rad);
+        max_sub = std::max<int64_t>(max_sub, (int64_t)cnt * np * geom->n_rad);
     }
     c->max_sub_bins = max_sub;
-    HIP_TRY(hipStreamSynchronize(st));
+    {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
+    }
     *out = c;
     return SPDHG_OK;
 }
 
-namespace {
-// Collect the elapsed times of the recorded event pairs (synchronises on the events).
-int prof_collect(spdhg_ctx* c) {
-    for (size_t i = 0; i < c->ev_used; ++i) {
-        HIP_TRY(hipEventSynchronize(c->ev[2 * i + 1]));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
-        c->prof_ms[c->ev_kind[i]] += ms;
-        c->prof_n[c->ev_kind[i]] += 1;
-    }
-    c->ev_used = 0;
-    return SPDHG_OK;
-}
-
-int prof_begin(spdhg_ctx* c, int kind, hipStream_t st) {
-    if (!c->prof) return SPDHG_OK;
-    if (2 * c->ev_used + 2 > c->ev.size()) {
-        int rc = prof_collect(c);
-        if (rc) return rc;
-    }
-    c->ev_kind[c->ev_used] = kind;
-    HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used], st));
-    return SPDHG_OK;
-}
-
-int prof_end(spdhg_ctx* c, hipStream_t st) {
-    if (!c->prof) return SPDHG_OK;
-    HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used + 1], st));
-    c->ev_used += 1;
-    return SPDHG_OK;
-}
-}  // namespace
-
-extern "C" int spdhg_set_profiling(spdhg_ctx* c, int32_t on) {
+int spdhg_set_profiling(spdhg_ctx* c, int32_t on) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
     if (on && c->ev.empty()) {
         const size_t pairs = 1024;
@@ -667,7 +889,7 @@ extern "C" int spdhg_set_profiling(spdhg_ctx* c, int32_t on) {
     return SPDHG_OK;
 }
 
-extern "C" int spdhg_profile(spdhg_ctx* c, double* ms, int64_t* launches) {
+int spdhg_profile(spdhg_ctx* c, double* ms, int64_t* launches) {
     if (!c || !ms || !launches) return fail(SPDHG_E_ARG, "NULL argument");
     int rc = prof_collect(c);
     if (rc) return rc;
@@ -683,53 +905,53 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
     if (n_iters < 0) return fail(SPDHG_E_ARG, "n_iters < 0");
     hipStream_t st = (hipStream_t)stream;
     const int64_t nv = c->nv;
-    PriorArgs P{};
-    P.nx = c->geom.nx;
-    P.ny = c->geom.ny;
-    P.nz = c->geom.nz;
-    P.sigma = (float)c->prior_sigma;
-    P.alpha = (float)c->prm.alpha;
-    P.gamma_d = (float)c->prm.gamma_d;
-    P.dtv = c->prm.prior == SPDHG_PRIOR_DTV;
+    PriorArgs P = c->prior_args();
+    int rc;
     for (int64_t it = 0; it < n_iters; ++it) {
-        const uint64_t z = splitmix64(c->prm.seed, (uint64_t)c->k);
-        const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        const uint64_t zr = splitmix64(c->prm.seed, (uint64_t)c->k);
+        const double u = (double)(zr >> 11) * (1.0 / 9007199254740992.0);
         int i = 0;
         while (!(u < c->cum[i])) ++i;
         const float inv_p = (float)(1.0 / c->p[i]);
         if (i < c->m) {
             int a0, step, cnt;
             subset_angles(&c->geom, c->m, i, a0, step, cnt);
-            const int64_t nsub = (int64_t)cnt * c->tab.G.n_planes * c->geom.n_rad;
-            const float sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[i];
-            int rc = prof_begin(c, SPDHG_PROF_FWD, st);
-            if (rc) return rc;
-            fwd_dual<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, c->xcur(), c->mult, c->b, c->r,
-                                                      c->sigma, sig_s, c->y, c->dscr, a0, step,
-                                                      cnt);
+            FwdArgs F = c->fwd_args();
+            F.x = c->xcur();
+            F.mult = c->mp;
+            F.b = c->bp;
+            F.r = c->rp;
+            F.sigma = c->sigma;
+            F.sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[i];
+            F.y = c->y;
+            F.d = c->dscr;
+            if ((rc = prof_begin(c, SPDHG_PROF_FWD, st))) return rc;
+            if ((rc = launch_fwd<F_DUAL>(F, a0, step, cnt, st))) return rc;
             if ((rc = prof_end(c, st))) return rc;
+            BwdArgs B = c->bwd_args();
+            B.d = c->dscr;
+            B.d_ang0 = 0;
+            B.d_step = 1;
+            B.inv_p = inv_p;
+            B.z = c->z;
+            B.x = c->xcur();
+            B.T = c->T;
             if ((rc = prof_begin(c, SPDHG_PROF_BWD, st))) return rc;
-            bwd_iter<<<nblocks(nv), BLOCK, 0, st>>>(c->tab.G, c->dscr, a0, step, cnt, inv_p, c->z,
-                                                    c->xcur(), c->T);
+            if ((rc = launch_bwd<B_ITER, false, false>(B, a0, step, cnt, st))) return rc;
             if ((rc = prof_end(c, st))) return rc;
         } else {
             P.inv_p = inv_p;
-            int rc = prof_begin(c, SPDHG_PROF_PRIOR, st);
-            if (rc) return rc;
+            if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
             tv_iter<<<nblocks(nv), BLOCK, 0, st>>>(P, c->xcur(), c->xother(), c->yn[c->yn_cur],
                                                    c->yn[1 - c->yn_cur], c->z, c->T, c->xi);
+            LAUNCH_CHECK();
             if ((rc = prof_end(c, st))) return rc;
             c->x_cur ^= 1;
             c->yn_cur ^= 1;
         }
-        LAUNCH_CHECK();
         c->k += 1;
     }
-    if (c->x_cur) {
-        HIP_TRY(hipMemcpyAsync(c->x_user, c->x2, nv * 4, hipMemcpyDeviceToDevice, st));
-        c->x_cur = 0;
-    }
-    return SPDHG_OK;
+    return export_x(c, st);
 }
 
 int spdhg_epoch(spdhg_ctx* c, int32_t n_epochs, void* stream) {
@@ -748,18 +970,25 @@ int spdhg_info(const spdhg_ctx* c, int64_t* ipe, int64_t* done) {
 int spdhg_objective(spdhg_ctx* c, const float* x, double* out_dev, void* stream) {
     if (!c || !out_dev) return fail(SPDHG_E_ARG, "NULL ctx or output");
     hipStream_t st = (hipStream_t)stream;
-    const float* xx = x ? x : c->xcur();
-    const int64_t nb = c->nb, nv = c->nv;
-    fwd_obj<<<nblocks(nb), BLOCK, 0, st>>>(c->tab.G, xx, c->mult, c->b, c->r, c->part);
-    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nb), out_dev, 1, 1.0);
-    PriorArgs P{};
-    P.nx = c->geom.nx;
-    P.ny = c->geom.ny;
-    P.nz = c->geom.nz;
-    P.alpha = (float)c->prm.alpha;
-    P.gamma_d = (float)c->prm.gamma_d;
-    P.dtv = c->prm.prior == SPDHG_PRIOR_DTV;
-    tv_obj<<<nblocks(nv), BLOCK, 0, st>>>(P, xx, c->xi, c->part, c->prm.prior != SPDHG_PRIOR_NONE);
+    const spdhg_geom& g = c->geom;
+    const float* xx = c->xcur();
+    if (x) {
+        img_to_zf<<<img_grid(g.nx, g.ny, g.nz), TT * 8, 0, st>>>(g.nx, g.ny, g.nz, x, c->scr);
+        xx = c->scr;
+    }
+    const int64_t nv = c->nv;
+    FwdArgs F = c->fwd_args();
+    F.x = xx;
+    F.mult = c->mp;
+    F.b = c->bp;
+    F.r = c->rp;
+    F.part = c->part;
+    int rc;
+    if ((rc = launch_fwd<F_OBJ>(F, 0, 1, g.n_ang, st))) return rc;
+    const int64_t nblk = (int64_t)g.n_ang * g.n_rad;
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblk, out_dev, 1, 1.0);
+    tv_obj<<<nblocks(nv), BLOCK, 0, st>>>(c->prior_args(), xx, c->xi, c->part,
+                                          c->prm.prior != SPDHG_PRIOR_NONE);
     reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), out_dev, 2, 1.0);
     combine_objective<<<1, 64, 0, st>>>(out_dev);
     LAUNCH_CHECK();
@@ -840,7 +1069,7 @@ int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) 
         return fail(SPDHG_E_STATE, "state does not belong to this problem");
     c->x_cur = 0;
     c->yn_cur = 0;
-    HIP_TRY(hipMemcpyAsync(c->x_user, p, c->nv * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->xa, p, c->nv * 4, hipMemcpyDeviceToDevice, st));
     p += align256(c->nv * 4);
     HIP_TRY(hipMemcpyAsync(c->z, p, c->nv * 4, hipMemcpyDeviceToDevice, st));
     p += align256(c->nv * 4);
@@ -848,7 +1077,7 @@ int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) 
     p += align256(c->nb * 4);
     if (c->yn[0]) HIP_TRY(hipMemcpyAsync(c->yn[0], p, 3 * c->nv * 4, hipMemcpyDeviceToDevice, st));
     c->k = hdr[0];
-    return SPDHG_OK;
+    return export_x(c, st);
 }
 
 int spdhg_destroy(spdhg_ctx* c) {

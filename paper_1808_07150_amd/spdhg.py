@@ -228,8 +228,11 @@ class Reconstruction:
                                               _stream(stream)))
         return out
 
-    def buffer(self, name: str) -> Optional[torch.Tensor]:
-        """A copy of an internal array (y, z, T, sigma, prior_dual)."""
+    def buffer(self, name: str, caller_layout: bool = True) -> Optional[torch.Tensor]:
+        """A copy of an internal array (y, z, T, sigma, prior_dual).  The library stores
+        images z-fastest [y][x][z] and sinograms [angle][radial][plane]; with
+        caller_layout the copy is returned as [z][y][x] / [angle][plane][radial]
+        (prior_dual as [3][z][y][x])."""
         p, n = ctypes.c_void_p(), ctypes.c_int64()
         _check(load_library().spdhg_buffer(self.ctx, self.BUFFERS[name], ctypes.byref(p),
                                            ctypes.byref(n)))
@@ -238,7 +241,15 @@ class Reconstruction:
         out = torch.empty(int(n.value), dtype=torch.float32, device=self.x.device)
         torch.cuda.synchronize()
         _memcpy_d2d(out.data_ptr(), p.value, 4 * int(n.value))
-        return out
+        if not caller_layout:
+            return out
+        g = self.g
+        n_planes = sum(g.seg_planes)
+        if name in ("y", "sigma"):
+            return out.view(g.n_ang, g.n_rad, n_planes).permute(0, 2, 1).contiguous()
+        if name == "prior_dual":
+            return out.view(3, g.ny, g.nx, g.nz).permute(0, 3, 1, 2).contiguous()
+        return out.view(g.ny, g.nx, g.nz).permute(2, 0, 1).contiguous()
 
     def block_info(self, i: int):
         s, p, nrm = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

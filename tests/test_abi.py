@@ -59,7 +59,8 @@ def test_workspace_bytes(lib):
                                    ctypes.byref(n))
     assert rc == 0
     nb, nv = 252 * 837 * 344, 344 * 344 * 127
-    assert 4 * (2 * nb + 9 * nv) < n.value < 4 * (2 * nb + 9 * nv) * 1.2
+    # private b, r, mult; y, sigma; x (2), z, T, scratch, prior duals (2 x 3)
+    assert 4 * (5 * nb + 11 * nv) < n.value < 4 * (5 * nb + 11 * nv) * 1.1
     rc = lib.spdhg_workspace_bytes(ctypes.byref(P.cgeom(g)), ctypes.byref(P.cparams(300, "tv")),
                                    ctypes.byref(n))
     assert rc == -1  # more subsets than angles

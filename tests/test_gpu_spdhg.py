@@ -80,7 +80,7 @@ def test_config1_tv_parity(P, c1, sampling, precond, epochs):
 
 def test_config1_step_sizes(P, c1):
     prob, _, rec, _ = run_pair(P, c1, 10, "tv", 0, seed=1, sampling="balanced")
-    T = rec.buffer("T").cpu().numpy()
+    T = rec.buffer("T").cpu().numpy().reshape(c1["geom"].image_shape)
     assert rel(T, prob.T[0]) <= 1e-5
     sig = rec.buffer("sigma").cpu().numpy().reshape(c1["geom"].sino_shape)
     ref = np.zeros(c1["geom"].sino_shape)
