@@ -104,7 +104,17 @@ __device__ __forceinline__ void sec_range(const AngleDev& A, double u0, int& j0,
 }
 
 // ---------------------------------------------------------------- forward projection
-enum FwdMode { F_PLAIN_QK = 0, F_PLAIN_KQ = 1, F_SENS = 2, F_DUAL = 3, F_OBJ = 4 };
+enum FwdMode { F_PLAIN_QK = 0, F_POWER = 1, F_SENS = 2, F_DUAL = 3, F_OBJ = 4 };
+
+// Padded plane layout of the dual change read by the backprojectors: per (angle of the
+// list, radial bin) a row of n_planes + 4 n_seg floats in which segment g occupies
+// N_g + 4 floats starting at seg_base[g] + 4 g: two zeros, its N_g planes, two zeros.  A
+// voxel z of a ray whose axial cell offset is c = off_g + floor(e) has its lower tap at
+// plane p0 = z - c and its upper tap at p0 - 1; clamping p0 to [-1, N_g + 1] lands every
+// out-of-segment tap on a zero, so the gather needs no branch.
+__device__ __forceinline__ int64_t pad_row(const GeomDev& G, int ia, int k) {
+    return ((int64_t)ia * G.n_rad + k) * (G.n_planes + 4 * G.n_seg);
+}
 
 struct FwdArgs {
     GeomDev G;
@@ -112,13 +122,13 @@ struct FwdArgs {
     int ang0, ang_step, n_ang_sub;
     int pad, gsize;  // zero padding of the axial column, padded column length
     const float* mult;   // F_PLAIN_QK: caller layout, full; others: internal, full
-    float* out;          // F_PLAIN_*: packed output; F_SENS: sigma (internal, full)
+    float* out;          // F_PLAIN_QK: packed output; F_SENS: sigma; F_POWER: padded
     const float* b;      // internal, full
     const float* r;      // internal, full
     const float* sigma;  // internal, full, or NULL (scalar sig_s)
     float sig_s;
     float* y;            // internal, full
-    float* d;            // packed internal
+    float* d;            // F_DUAL: dual change, padded layout
     double* part;        // F_OBJ partials (one per block)
     float gr;            // F_SENS: gamma * rho
 };
@@ -158,26 +168,43 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
     for (int i = lane; i < 2 * P.gsize; i += 64) Gb[i] = 0.0f;
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
-    __syncthreads();
+    // The workgroup is one wavefront: its LDS accesses execute in order, so a code-motion
+    // barrier is enough between writing and reading the axial column.  The image values
+    // of step j + 1 are loaded before the rays consume step j (latency hiding).
+    constexpr int NZL = 4;  // z values per lane (nz <= 256)
+    float v0[NZL], v1[NZL];
+    Sample s = split(sec_coord(A, kk, (double)j0 - A.cj));
+    auto load_step = [&](int j, const Sample& sm) {
+        const bool ok0 = (unsigned)sm.i0 < (unsigned)A.n_sec;
+        const bool ok1 = (unsigned)(sm.i0 + 1) < (unsigned)A.n_sec;
+        const int i0c = ok0 ? sm.i0 : 0;
+        const int i1c = ok1 ? sm.i0 + 1 : 0;
+        const float* c0 = P.x + ((int64_t)j * s_prim + (int64_t)i0c * s_sec) * nz;
+        const float* c1 = P.x + ((int64_t)j * s_prim + (int64_t)i1c * s_sec) * nz;
+#pragma unroll
+        for (int u = 0; u < NZL; ++u) {
+            const int iz = lane + 64 * u;
+            v0[u] = (ok0 && iz < nz) ? c0[iz] : 0.0f;
+            v1[u] = (ok1 && iz < nz) ? c1[iz] : 0.0f;
+        }
+    };
+    if (MODE != F_SENS && j0 < j1) load_step(j0, s);
+    __builtin_amdgcn_wave_barrier();
     int buf = 0;
     for (int j = j0; j < j1; ++j) {
         const double jj = (double)j - A.cj;
-        const Sample s = split(sec_coord(A, kk, jj));
         float* Gc = Gb + buf * P.gsize + P.pad;
-        const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
-        const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
         const float w0 = 1.0f - s.fu, w1 = s.fu;
         if (MODE == F_SENS) {
+            const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
+            const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
             const float v = (ok0 ? w0 : 0.0f) + (ok1 ? w1 : 0.0f);
             for (int iz = lane; iz < nz; iz += 64) Gc[iz] = v;
         } else {
-            const int i0c = ok0 ? s.i0 : 0;
-            const float* c0 = P.x + ((int64_t)j * s_prim + (int64_t)i0c * s_sec) * nz;
-            const float* c1 = P.x + ((int64_t)j * s_prim + (int64_t)(s.i0 + 1) * s_sec) * nz;
-            for (int iz = lane; iz < nz; iz += 64) {
-                const float v0 = ok0 ? c0[iz] : 0.0f;
-                const float v1 = ok1 ? c1[iz] : 0.0f;
-                Gc[iz] = __builtin_fmaf(w1, v1, w0 * v0);
+#pragma unroll
+            for (int u = 0; u < NZL; ++u) {
+                const int iz = lane + 64 * u;
+                if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[u], w0 * v0[u]);
             }
         }
         if (lane < ns) {
@@ -185,7 +212,12 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
             segc[buf * ns + lane] = sz.i0;
             segf[buf * ns + lane] = sz.fu;
         }
-        __syncthreads();
+        // next step's in-plane sample and image values
+        if (j + 1 < j1) {
+            s = split(sec_coord(A, kk, jj + 1.0));
+            if (MODE != F_SENS) load_step(j + 1, s);
+        }
+        __builtin_amdgcn_wave_barrier();
         const float* Gr = Gb + buf * P.gsize;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -197,6 +229,7 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
                 acc[r] = __builtin_fmaf(fz, Gr[idx + 1], acc[r]);
             }
         }
+        __builtin_amdgcn_wave_barrier();
         buf ^= 1;
     }
 
@@ -212,9 +245,10 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
         if (MODE == F_PLAIN_QK) {
             const float m = P.mult ? P.mult[((int64_t)a * G.n_planes + q) * G.n_rad + k] : 1.0f;
             P.out[((int64_t)ia * G.n_planes + q) * G.n_rad + k] = v * m;
-        } else if (MODE == F_PLAIN_KQ) {
-            const float m = P.mult ? P.mult[full] : 1.0f;
-            P.out[((int64_t)ia * G.n_rad + k) * G.n_planes + q] = v * m;
+        } else if (MODE == F_POWER) {
+            // A_i^T A_i needs mult (G x) times mult again: write mult^2 G x, padded
+            const float m = P.mult[full];
+            P.out[pad_row(G, ia, k) + q + 4 * g + 2] = m * m * v;
         } else if (MODE == F_SENS) {
             const float a1 = P.mult[full] * v;
             P.out[full] = a1 > 0.0f ? P.gr / a1 : 0.0f;
@@ -225,7 +259,7 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
             float yn = yo;
             if (sg > 0.0f) yn = prox_kl_dual(__builtin_fmaf(sg, m * v, yo), sg, P.b[full], P.r[full]);
             P.y[full] = yn;
-            P.d[((int64_t)ia * G.n_rad + k) * G.n_planes + q] = m * (yn - yo);
+            P.d[pad_row(G, ia, k) + q + 4 * g + 2] = m * (yn - yo);
         } else if (MODE == F_OBJ) {
             obj += phi64((double)(P.mult[full] * v), (double)P.b[full], (double)P.r[full]);
         }
@@ -237,25 +271,69 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
 }
 
 // ---------------------------------------------------------------- gather backprojection
-enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2 };
+enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2, B_PARTIAL = 3, B_ACCUM = 4 };
 #define BWD_THREADS 128
 #define BWD_KC 4  // candidate radial bins per column and angle
 
 struct BwdArgs {
     GeomDev G;
-    const float* d;  // dual change / sinogram: packed (D_QK: caller [ia][q][k], else
-                     // internal [ia][k][q]) or, for B_SENS, the internal full mult
-    int d_ang0, d_step;
-    const float* mult;  // optional factors, caller layout full (D_QK) or internal full
+    const float* d;  // padded dual change / sinogram of the listed angles (see pad_row)
     int ang0, ang_step, n_ang_sub;
-    int cols;           // voxel columns per block (BWD_THREADS / nz, at least 1)
-    float* out;         // B_PLAIN: z-fastest image
-    float scale;        // B_SENS: rho p_i / gamma
+    int cols;        // per-column kernel: voxel columns per block
+    float* out;      // B_PLAIN / B_PARTIAL: z-fastest image; B_ACCUM: added to
+    float scale;     // B_SENS: rho p_i / gamma
     float* T;
     float inv_p;
     float* z;
     float* x;
 };
+
+// Per (candidate ray, segment): the lower-tap index of voxel z inside the padded row is
+// clamp(z + off, lo, lo + N_g + 2) with lo = seg_base[g] + 4 g + 1, and the two tap
+// weights carry the segment's step length.
+struct TapCoef {
+    int off, lo, hi;
+    float wa, wb;
+};
+
+__device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, double kk,
+                                            double jj) {
+    const SegAngleDev S = G.sa[a * G.n_seg + g];
+    const Sample sz = split(ax_offset(S, kk, jj));
+    TapCoef t;
+    const int blk = G.seg_base[g] + 4 * g;
+    t.off = blk + 2 - (G.seg_off[g] + sz.i0);
+    t.lo = blk + 1;
+    t.hi = blk + G.seg_planes[g] + 3;
+    t.wa = S.L * (1.0f - sz.fu);
+    t.wb = S.L * sz.fu;
+    return t;
+}
+
+// Lower and upper tap values of voxel z for one (ray, segment).
+__device__ __forceinline__ float tap_sum(const float* __restrict__ row, const TapCoef& t, int z,
+                                         float h) {
+    const int i0 = min(max(z + t.off, t.lo), t.hi);
+    h = __builtin_fmaf(t.wa, row[i0], h);
+    return __builtin_fmaf(t.wb, row[i0 - 1], h);
+}
+
+__device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t t, float dz) {
+    if (MODE == B_PLAIN || MODE == B_PARTIAL) {
+        P.out[t] = dz;
+    } else if (MODE == B_ACCUM) {
+        P.out[t] += dz;
+    } else if (MODE == B_SENS) {
+        if (dz > 0.0f) P.T[t] = fminf(P.T[t], P.scale / dz);
+    } else {
+        // Algorithm 2 lines 7-8 and line 3 of the next iteration:
+        // z += dz;  x = max(x - T (z + dz / p_i), 0)
+        const float zn = P.z[t] + dz;
+        P.z[t] = zn;
+        const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
+        P.x[t] = fmaxf(P.x[t] - P.T[t] * zbar, 0.0f);
+    }
+}
 
 // A candidate ray of a column for one angle: radial bin and in-plane weight (0: none).
 struct ColCoord {
@@ -263,34 +341,34 @@ struct ColCoord {
     float wx;
 };
 
-template <int MODE, bool D_QK, bool MULT>
-__global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P) {
+// Per-column gather (any nz <= 256 and radial spacing >= half a voxel): one block per
+// group of voxel columns; the candidate rays of each column and their tap coefficients
+// are computed once per column and angle (FP64) and shared through LDS; lanes run
+// along z.
+template <int MODE>
+__global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* __restrict__ partial) {
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
     const int nz = G.nz;
     extern __shared__ float smem[];
     const int cols = P.cols;
-    ColCoord* cc = (ColCoord*)smem;                       // [cols][KC]
-    int* zc = (int*)(cc + cols * BWD_KC);                 // [cols][KC][ns]
-    float* zf = (float*)(zc + cols * BWD_KC * ns);        // [cols][KC][ns]
+    ColCoord* cc = (ColCoord*)smem;                 // [cols][KC]
+    TapCoef* tc = (TapCoef*)(cc + cols * BWD_KC);   // [cols][KC][ns]
     const int ncol = G.nx * G.ny;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int col0 = blk * cols;
-    // thread -> (column within the block, first z)
     const int zchunk = nz < BWD_THREADS ? nz : BWD_THREADS;
     const int cl = threadIdx.x / zchunk;
     const int z0 = threadIdx.x - cl * zchunk;
     const int col = col0 + cl;
     const bool active = cl < cols && col < ncol;
-    const int nzz = (nz + zchunk - 1) / zchunk;  // z values per thread (<= 4, nz <= 512)
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    const int64_t per_ang = (int64_t)G.n_planes * G.n_rad;
+    const int nzz = (nz + zchunk - 1) / zchunk;  // z values per thread (<= 2, nz <= 256)
+    float acc[2] = {0.f, 0.f};
 
     for (int ia = 0; ia < P.n_ang_sub; ++ia) {
         const int a = P.ang0 + ia * P.ang_step;
         const AngleDev A = G.ang[a];
         __syncthreads();  // the previous angle's coordinates are no longer read
-        // candidate rays of each column (u evaluated in FP64 once per column and angle)
         for (int t = threadIdx.x; t < cols * BWD_KC; t += BWD_THREADS) {
             const int c = t / BWD_KC, kc = t - c * BWD_KC;
             const int cq = col0 + c;
@@ -307,12 +385,12 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P) {
                 const int khi = min(G.n_rad - 1, (int)__builtin_ceil(fmax(ka, kb)) + 1);
                 int found = 0;
                 for (int k = klo; k <= khi; ++k) {
-                    const Sample s = split(sec_coord(A, (double)k - G.ck, jj));
+                    const Sample sm = split(sec_coord(A, (double)k - G.ck, jj));
                     float w = -1.0f;
-                    if (s.i0 == isec)
-                        w = 1.0f - s.fu;
-                    else if (s.i0 + 1 == isec)
-                        w = s.fu;
+                    if (sm.i0 == isec)
+                        w = 1.0f - sm.fu;
+                    else if (sm.i0 + 1 == isec)
+                        w = sm.fu;
                     if (w > 0.0f) {
                         if (found == kc) {
                             o.k = k;
@@ -325,62 +403,33 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P) {
             cc[t] = o;
         }
         __syncthreads();
-        // axial cell and fraction of every (column, candidate, segment)
         for (int t = threadIdx.x; t < cols * BWD_KC * ns; t += BWD_THREADS) {
             const int c = t / (BWD_KC * ns);
             const int rem = t - c * BWD_KC * ns;
             const int kc = rem / ns, g = rem - kc * ns;
             const int cq = col0 + c;
-            int zci = 0;
-            float zfr = 0.0f;
             const ColCoord o = cc[c * BWD_KC + kc];
+            TapCoef v{0, 0, 0, 0.0f, 0.0f};
             if (cq < ncol && o.wx != 0.0f) {
                 const int qy = cq / G.nx, qx = cq - qy * G.nx;
                 const int j = A.rowdom ? qy : qx;
-                const Sample sz = split(ax_offset(G.sa[a * ns + g], (double)o.k - G.ck,
-                                                  (double)j - A.cj));
-                zci = G.seg_off[g] + sz.i0;
-                zfr = sz.fu;
+                v = tap_coef(G, a, g, (double)o.k - G.ck, (double)j - A.cj);
             }
-            zc[t] = zci;
-            zf[t] = zfr;
+            tc[t] = v;
         }
         __syncthreads();
         if (!active) continue;
-        const float* drow = P.d + (int64_t)(P.d_ang0 + ia * P.d_step) * per_ang;
-        const float* mrow = MULT ? P.mult + (int64_t)a * per_ang : nullptr;
         for (int kc = 0; kc < BWD_KC; ++kc) {
             const ColCoord o = cc[cl * BWD_KC + kc];
             if (o.wx == 0.0f) continue;
+            const float* dk = P.d + pad_row(G, ia, o.k);
+            const TapCoef* tk = tc + (cl * BWD_KC + kc) * ns;
             for (int zz = 0; zz < nzz; ++zz) {
                 const int iz = z0 + zz * zchunk;
                 if (iz >= nz) break;
-                float accr = 0.0f;
-                for (int g = 0; g < ns; ++g) {
-                    const int e = (cl * BWD_KC + kc) * ns + g;
-                    const int p0 = iz - zc[e];  // the voxel is the lower tap of plane p0
-                    const int p1 = p0 - 1;      // and the upper tap of plane p0 - 1
-                    const float fz = zf[e];
-                    const int ng = G.seg_planes[g];
-                    const int qb = G.seg_base[g];
-                    float sg = 0.0f;
-                    if ((unsigned)p0 < (unsigned)ng) {
-                        const int64_t i = D_QK ? (int64_t)(qb + p0) * G.n_rad + o.k
-                                               : (int64_t)o.k * G.n_planes + qb + p0;
-                        float v = drow[i];
-                        if (MULT) v *= mrow[i];
-                        sg = __builtin_fmaf(1.0f - fz, v, sg);
-                    }
-                    if ((unsigned)p1 < (unsigned)ng) {
-                        const int64_t i = D_QK ? (int64_t)(qb + p1) * G.n_rad + o.k
-                                               : (int64_t)o.k * G.n_planes + qb + p1;
-                        float v = drow[i];
-                        if (MULT) v *= mrow[i];
-                        sg = __builtin_fmaf(fz, v, sg);
-                    }
-                    accr = __builtin_fmaf(G.sa[a * ns + g].L, sg, accr);
-                }
-                acc[zz] = __builtin_fmaf(o.wx, accr, acc[zz]);
+                float h = 0.0f;
+                for (int g = 0; g < ns; ++g) h = tap_sum(dk, tk[g], iz, h);
+                acc[zz] = __builtin_fmaf(o.wx, h, acc[zz]);
             }
         }
     }
@@ -389,20 +438,166 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P) {
         const int iz = z0 + zz * zchunk;
         if (iz >= nz) break;
         const int64_t t = (int64_t)col * nz + iz;
-        const float dz = acc[zz];
-        if (MODE == B_PLAIN) {
-            P.out[t] = dz;
-        } else if (MODE == B_SENS) {
-            if (dz > 0.0f) P.T[t] = fminf(P.T[t], P.scale / dz);
-        } else {
-            // Algorithm 2 lines 7-8 and line 3 of the next iteration:
-            // z += dz;  x = max(x - T (z + dz / p_i), 0)
-            const float zn = P.z[t] + dz;
-            P.z[t] = zn;
-            const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
-            P.x[t] = fmaxf(P.x[t] - P.T[t] * zbar, 0.0f);
+        bwd_epilogue(P, MODE, t, acc[zz] + (partial ? partial[t] : 0.0f));
+    }
+}
+
+// ---------------------------------------------------------------- strip gather backprojection
+// One wavefront per strip of BS_W voxel columns that lie along the secondary axis at one
+// primary index j, for the angles of one sampling class (rows or columns), nz <= 128
+// (lane holds z = lane and z = lane + 64 of every strip column).  Per angle:
+//   1. the radial bins of the rays touching the strip (consecutive, at most KR),
+//   2. each ray's in-plane cell / fraction and per segment its tap coefficients (FP64,
+//      the same inline functions as the forward walk),
+//   3. per strip column the rays whose in-plane taps include it (<= 4, with weights) and,
+//      per ray, the axial gather h(z) = sum_g wa_g d(z + zoff_g) + wb_g d(z + zoff_g - 1)
+//      into LDS (lanes along z read the padded dual change contiguously),
+//   4. every voxel adds weight * h(z) of its column's rays.
+// A ray's axial gather is shared by the two columns it touches.  The row-sampled angles
+// of a subset write a partial image that the column-sampled launch adds before its
+// epilogue.  Deterministic, no atomics.  The workgroup is one wavefront, whose LDS
+// accesses execute in order: code-motion barriers separate the phases.
+#define BS_W 16
+#define BS_CAND 4
+
+template <int MODE>
+__global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
+                                                const float* __restrict__ partial) {
+    const GeomDev& G = P.G;
+    const int ns = G.n_seg;
+    const int nz = G.nz;
+    extern __shared__ float smem[];
+    float* hb = smem;                                  // [KR][128] axial gathers
+    int* ri0 = (int*)(hb + KR * 128);                  // [KR] in-plane cell
+    float* rfu = (float*)(ri0 + KR);                   // [KR] in-plane fraction
+    int* cak = (int*)(rfu + KR);                       // [BS_W][CAND] ray
+    float* caw = (float*)(cak + BS_W * BS_CAND);        // [BS_W][CAND] weight
+    TapCoef* tc = (TapCoef*)(caw + BS_W * BS_CAND);     // [KR][ns]
+
+    const int lane = threadIdx.x;
+    const int n_sec = rowdom ? G.nx : G.ny;
+    const int nstrip = (n_sec + BS_W - 1) / BS_W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = blk / nstrip;
+    const int s0 = (blk - j * nstrip) * BS_W;
+    float acc[BS_W][2];
+#pragma unroll
+    for (int c = 0; c < BS_W; ++c) acc[c][0] = acc[c][1] = 0.0f;
+
+    for (int ia = 0; ia < P.n_ang_sub; ++ia) {
+        const int a = P.ang0 + ia * P.ang_step;
+        const AngleDev A = G.ang[a];
+        if (A.rowdom != rowdom) continue;  // the other class has its own launch
+        const double jj = (double)j - A.cj;
+        // 1. rays touching the strip: u in [s0 - 1, s0 + BS_W)  (wave-uniform)
+        const double base = __builtin_fma(A.du_dj, jj, A.cu);
+        const double ka = ((double)(s0 - 1) - base) / A.du_dk + G.ck;
+        const double kb = ((double)(s0 + BS_W) - base) / A.du_dk + G.ck;
+        const int klo = max(0, (int)__builtin_floor(fmin(ka, kb)) - 1);
+        const int khi = min(G.n_rad - 1, (int)__builtin_ceil(fmax(ka, kb)) + 1);
+        const int nr = min(max(khi - klo + 1, 0), KR);
+        __builtin_amdgcn_wave_barrier();  // the previous angle's tables are consumed
+        // 2. coordinates of each ray
+        for (int kr = lane; kr < nr; kr += 64) {
+            const Sample sm = split(sec_coord(A, (double)(klo + kr) - G.ck, jj));
+            const bool touch = sm.i0 >= s0 - 1 && sm.i0 < s0 + BS_W;
+            ri0[kr] = touch ? sm.i0 : INT32_MIN;
+            rfu[kr] = sm.fu;
+        }
+        for (int t = lane; t < nr * ns; t += 64) {
+            const int kr = t / ns, g = t - kr * ns;
+            tc[t] = tap_coef(G, a, g, (double)(klo + kr) - G.ck, jj);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // 3a. rays of each strip column: a window of candidates around the rays whose
+        //     secondary coordinate is closest to the column (u is monotonic in k)
+        if (lane < BS_W) {
+            const int sec = s0 + lane;
+            const double kc = ((double)(sec - 1) - base) / A.du_dk + G.ck;
+            const double kd = ((double)(sec + 1) - base) / A.du_dk + G.ck;
+            const int kf = (int)__builtin_floor(fmin(kc, kd)) - 1 - klo;
+            int found = 0;
+            for (int kr = max(kf, 0); kr < min(kf + 5, nr) && found < BS_CAND; ++kr) {
+                const int i0 = ri0[kr];
+                const float fu = rfu[kr];
+                if (i0 == sec && fu < 1.0f) {
+                    cak[lane * BS_CAND + found] = kr;
+                    caw[lane * BS_CAND + found] = 1.0f - fu;
+                    ++found;
+                } else if (i0 + 1 == sec && fu > 0.0f) {
+                    cak[lane * BS_CAND + found] = kr;
+                    caw[lane * BS_CAND + found] = fu;
+                    ++found;
+                }
+            }
+            for (; found < BS_CAND; ++found) cak[lane * BS_CAND + found] = -1;
+        }
+        // 3b. axial gather of every touching ray
+        for (int kr = 0; kr < nr; ++kr) {
+            if (ri0[kr] == INT32_MIN) continue;
+            const float* dk = P.d + pad_row(G, ia, klo + kr);
+            const TapCoef* tk = tc + kr * ns;
+            float h0 = 0.0f, h1 = 0.0f;
+            for (int g = 0; g < ns; ++g) {
+                const TapCoef t = tk[g];
+                h0 = tap_sum(dk, t, lane, h0);
+                h1 = tap_sum(dk, t, lane + 64, h1);
+            }
+            hb[kr * 128 + lane] = h0;
+            hb[kr * 128 + 64 + lane] = h1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // 4. voxels of the strip
+#pragma unroll
+        for (int c = 0; c < BS_W; ++c) {
+#pragma unroll
+            for (int e = 0; e < BS_CAND; ++e) {
+                const int kr = cak[c * BS_CAND + e];
+                if (kr < 0) break;
+                const float w = caw[c * BS_CAND + e];
+                acc[c][0] = __builtin_fmaf(w, hb[kr * 128 + lane], acc[c][0]);
+                acc[c][1] = __builtin_fmaf(w, hb[kr * 128 + 64 + lane], acc[c][1]);
+            }
         }
     }
+#pragma unroll
+    for (int c = 0; c < BS_W; ++c) {
+        const int sec = s0 + c;
+        if (sec >= n_sec) continue;
+        const int ix = rowdom ? sec : j, iy = rowdom ? j : sec;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int iz = lane + 64 * hh;
+            if (iz >= nz) continue;
+            const int64_t t = ((int64_t)iy * G.nx + ix) * nz + iz;
+            bwd_epilogue(P, MODE, t, acc[c][hh] + (partial ? partial[t] : 0.0f));
+        }
+    }
+}
+
+// Rows of a sinogram (internal full [a][k][q] layout at angles ang0 + ia * step, or the
+// caller's packed [ia][q][k] layout times an optional full caller mult) -> padded layout.
+__global__ void __launch_bounds__(BLOCK)
+to_padded(GeomDev G, const float* __restrict__ src, int caller, const float* __restrict__ mult,
+          int ang0, int step, int n_ang_sub, float* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t per = (int64_t)G.n_planes * G.n_rad;
+    if (t >= per * n_ang_sub) return;
+    const int ia = (int)(t / per);
+    const int64_t rem = t - ia * per;
+    int q, k;
+    float v;
+    if (caller) {  // packed [ia][q][k]: consecutive threads run along k
+        q = (int)(rem / G.n_rad);
+        k = (int)(rem - (int64_t)q * G.n_rad);
+        v = src[t];
+        if (mult) v *= mult[(int64_t)(ang0 + ia * step) * per + rem];
+    } else {  // internal [a][k][q]: consecutive threads run along q
+        k = (int)(rem / G.n_planes);
+        q = (int)(rem - (int64_t)k * G.n_planes);
+        v = src[(int64_t)(ang0 + ia * step) * per + rem];
+    }
+    dst[pad_row(G, ia, k) + q + 4 * G.plane_seg[q] + 2] = v;
 }
 
 // ---------------------------------------------------------------- layout transposes
@@ -818,4 +1013,7 @@ dgrad_adj(PriorArgs P, const float* __restrict__ p, const float* __restrict__ xi
     if (cz > 0) v += dp(t - 1, 2);
     out[t] = v;
 }
+}  // namespace spdhg
+
+namespace spdhg {
 }  // namespace spdhg

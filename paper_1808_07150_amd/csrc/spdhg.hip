@@ -261,7 +261,7 @@ int rays_per_lane(int n_planes) {
 int check_kernel_limits(const spdhg_geom* g) {
     if (rays_per_lane((int)n_planes(g)) < 0)
         return fail(SPDHG_E_SHAPE, "more than 4096 sinogram planes");
-    if (g->nz > 512) return fail(SPDHG_E_SHAPE, "nz above 512");
+    if (g->nz > 256) return fail(SPDHG_E_SHAPE, "nz above 256");
     // the gather keeps at most 4 candidate radial bins per voxel column and angle: the
     // radial spacing must be at least half the in-plane voxel size
     if (g->d_rad < 0.5 * std::max(g->vx, g->vy))
@@ -301,16 +301,69 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
 
 int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }
 
-template <int MODE, bool D_QK, bool MULT>
-int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
+// Backprojection kernel choice: the strip gather for nz <= 128 when the rays touching a
+// strip fit its LDS tables (radial spacing >= voxel size); else the per-column gather.
+struct BwdPlan {
+    bool strip = false;
+    int KR = 0;
+    size_t lds = 0;
+};
+
+BwdPlan bwd_plan(const HostTables& T) {
+    BwdPlan pl;
+    const int nz = T.G.nz, ns = T.G.n_seg;
+    double min_du = 1e30;
+    for (const AngleDev& A : T.ang) min_du = std::min(min_du, std::fabs(A.du_dk));
+    if (nz < 32 || nz > 128 || !(min_du >= 1.0)) return pl;
+    const int KR = (int)std::floor((BS_W + 1) / min_du) + 5;
+    const size_t floats = (size_t)KR * 128 + 2 * (size_t)KR + 2 * BS_W * BS_CAND +
+                          (sizeof(TapCoef) / 4) * (size_t)KR * ns;
+    pl.strip = true;
+    pl.KR = KR;
+    pl.lds = floats * 4;
+    return pl;
+}
+
+// Gather backprojection of the angles ang0 + i * step (i < cnt) with the epilogue MODE;
+// A.d holds their dual change in the padded layout.  With the strip kernel the
+// row-sampled and column-sampled angles run as two launches; when both classes occur and
+// the epilogue needs the whole sum, the first writes its partial image to `partial`.
+template <int MODE>
+int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st, const BwdPlan& plan,
+               const AngleDev* host_ang, float* partial) {
     A.ang0 = ang0;
     A.ang_step = step;
     A.n_ang_sub = cnt;
+    if (plan.strip) {
+        bool has[2] = {false, false};
+        for (int i = 0; i < cnt; ++i) has[host_ang[ang0 + i * step].rowdom] = true;
+        const int nstr_r = ((A.G.nx + BS_W - 1) / BS_W) * A.G.ny;  // rows: strips along x
+        const int nstr_c = ((A.G.ny + BS_W - 1) / BS_W) * A.G.nx;  // columns: strips along y
+        if (has[1] && has[0]) {
+            if (MODE == B_ACCUM) {
+                bwd_strip<B_ACCUM><<<nstr_r, 64, plan.lds, st>>>(A, plan.KR, 1, nullptr);
+                LAUNCH_CHECK();
+                bwd_strip<B_ACCUM><<<nstr_c, 64, plan.lds, st>>>(A, plan.KR, 0, nullptr);
+            } else {
+                BwdArgs Pp = A;
+                Pp.out = partial;
+                bwd_strip<B_PARTIAL><<<nstr_r, 64, plan.lds, st>>>(Pp, plan.KR, 1, nullptr);
+                LAUNCH_CHECK();
+                bwd_strip<MODE><<<nstr_c, 64, plan.lds, st>>>(A, plan.KR, 0, partial);
+            }
+        } else if (has[1]) {
+            bwd_strip<MODE><<<nstr_r, 64, plan.lds, st>>>(A, plan.KR, 1, nullptr);
+        } else if (has[0]) {
+            bwd_strip<MODE><<<nstr_c, 64, plan.lds, st>>>(A, plan.KR, 0, nullptr);
+        }
+        LAUNCH_CHECK();
+        return SPDHG_OK;
+    }
     A.cols = bwd_cols(A.G.nz);
     const int64_t ncol = (int64_t)A.G.nx * A.G.ny;
     const int64_t nblk = (ncol + A.cols - 1) / A.cols;
-    const size_t lds = (size_t)A.cols * BWD_KC * (sizeof(ColCoord) + 8 * (size_t)A.G.n_seg);
-    bwd_col<MODE, D_QK, MULT><<<(unsigned)nblk, BWD_THREADS, lds, st>>>(A);
+    const size_t lds = (size_t)A.cols * BWD_KC * (sizeof(ColCoord) + sizeof(TapCoef) * A.G.n_seg);
+    bwd_col<MODE><<<(unsigned)nblk, BWD_THREADS, lds, st>>>(A, nullptr);
     LAUNCH_CHECK();
     return SPDHG_OK;
 }
@@ -326,6 +379,7 @@ struct spdhg_ctx {
     HostTables tab;
     int device = 0;
     int pad = 0, gsize = 0;
+    BwdPlan bplan;
     const float* side = nullptr;
     float* x_user = nullptr;
     // workspace regions (internal layouts: images z-fastest, sinograms [a][k][q])
@@ -392,7 +446,8 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
     const int64_t np = n_planes(g);
     const int64_t nb = (int64_t)g->n_ang * np * g->n_rad;
     const int m = std::max(1, p->n_subsets);
-    const int64_t max_sub = (int64_t)((g->n_ang + m - 1) / m) * np * g->n_rad;
+    // padded dual change of the largest subset (see pad_row)
+    const int64_t max_sub = (int64_t)((g->n_ang + m - 1) / m) * g->n_rad * (np + 4 * g->n_seg);
     const bool prior = p->prior == SPDHG_PRIOR_TV || p->prior == SPDHG_PRIOR_DTV;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -448,7 +503,7 @@ int reduce_to(double* part, int64_t n, double* out, int slot, double scale, hipS
 }
 
 // Power iteration on A_i^T A_i from the ones image (scalar steps of Theorem 2): norm of
-// data block i.  Uses xb, z and y as scratch (reset by the caller afterwards).
+// data block i.  Uses xb, z, scr and dscr as scratch.
 int power_norm_data(spdhg_ctx* c, int i, double* out, hipStream_t st) {
     int a0, step, cnt;
     int rc = subset_angles(&c->geom, c->m, i, a0, step, cnt);
@@ -456,25 +511,23 @@ int power_norm_data(spdhg_ctx* c, int i, double* out, hipStream_t st) {
     const int64_t nv = c->nv;
     float* v = c->xb;
     float* w = c->z;
-    float* tmp = c->y;
+    float* tmp = c->dscr;  // padded, zero outside the planes
     fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, 1.0f);
     sumsq<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, c->part);
     if ((rc = reduce_to(c->part, nblocks(nv), c->scal, 0, 1.0, st))) return rc;
     scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(v, v, nv, c->scal);
     for (int it = 0; it < c->prm.power_iters; ++it) {
-        // w = A_i^T A_i v = G^T diag(mult) (mult * G v)
+        // w = A_i^T A_i v = G^T (mult^2 G v)
         FwdArgs F = c->fwd_args();
         F.x = v;
         F.mult = c->mp;
         F.out = tmp;
-        if ((rc = launch_fwd<F_PLAIN_KQ>(F, a0, step, cnt, st))) return rc;
+        if ((rc = launch_fwd<F_POWER>(F, a0, step, cnt, st))) return rc;
         BwdArgs B = c->bwd_args();
         B.d = tmp;
-        B.d_ang0 = 0;
-        B.d_step = 1;
-        B.mult = c->mp;
         B.out = w;
-        if ((rc = launch_bwd<B_PLAIN, false, true>(B, a0, step, cnt, st))) return rc;
+        if ((rc = launch_bwd<B_PLAIN>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
+            return rc;
         sumsq<<<nblocks(nv), BLOCK, 0, st>>>(w, nv, c->part);
         if ((rc = reduce_to(c->part, nblocks(nv), c->scal, 0, 1.0, st))) return rc;
         scale_by_rnorm<<<nblocks(nv), BLOCK, 0, st>>>(w, v, nv, c->scal);
@@ -615,26 +668,43 @@ int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
     if (rc) return rc;
     const int64_t nv = (int64_t)geom->nx * geom->ny * geom->nz;
     hipStream_t st = (hipStream_t)stream;
+    HostTables T;
+    build_tables(geom, T);
+    const BwdPlan plan = bwd_plan(T);
+    // angles in chunks: each chunk's rows go to a padded scratch and are added to the
+    // z-fastest image; then one transpose to the caller's layout
+    const int chunk = std::min(cnt, 16);
+    const int64_t npad = (int64_t)chunk * geom->n_rad * (G.n_planes + 4 * geom->n_seg);
+    float* dk = nullptr;
     float* xz = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&dk, npad * 4, st));
     HIP_TRY(hipMallocAsync((void**)&xz, nv * 4, st));
-    BwdArgs B{};
-    B.G = G;
-    B.d = y;
-    B.d_ang0 = 0;
-    B.d_step = 1;
-    B.mult = mult;
-    B.out = xz;
-    rc = mult ? launch_bwd<B_PLAIN, true, true>(B, a0, step, cnt, st)
-              : launch_bwd<B_PLAIN, true, false>(B, a0, step, cnt, st);
-    if (!rc) {
+    hipError_t e = hipMemsetAsync(dk, 0, npad * 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(xz, 0, nv * 4, st);
+    for (int c0 = 0; c0 < cnt && e == hipSuccess && rc == SPDHG_OK; c0 += chunk) {
+        const int cc = std::min(chunk, cnt - c0);
+        const int cang0 = a0 + c0 * step;
+        const int64_t nsub = (int64_t)cc * G.n_planes * G.n_rad;
+        to_padded<<<nblocks(nsub), BLOCK, 0, st>>>(G, y + (int64_t)c0 * G.n_planes * G.n_rad, 1,
+                                                   mult, cang0, step, cc, dk);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        BwdArgs B{};
+        B.G = G;
+        B.d = dk;
+        B.out = xz;
+        rc = launch_bwd<B_ACCUM>(B, cang0, step, cc, st, plan, T.ang.data(), nullptr);
+    }
+    if (e == hipSuccess && rc == SPDHG_OK) {
         img_from_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
             geom->nx, geom->ny, geom->nz, xz, x_out);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) rc = fail(SPDHG_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
+        e = hipGetLastError();
     }
-    hipError_t e = hipFreeAsync(xz, st);
+    hipError_t e1 = hipFreeAsync(xz, st);
+    hipError_t e2 = hipFreeAsync(dk, st);
     if (rc) return rc;
-    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("hipFreeAsync: ") + hipGetErrorString(e));
+    if (e == hipSuccess) e = e1 ? e1 : e2;
+    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("spdhg_backproject: ") + hipGetErrorString(e));
     return SPDHG_OK;
 }
 
@@ -711,6 +781,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     if ((rc = upload_tables(c->tab, w + L.tables))) return bail(rc);
     c->pad = axial_pad(c->tab);
     c->gsize = geom->nz + 2 * c->pad;
+    c->bplan = bwd_plan(c->tab);
     c->side = side;
     c->x_user = x;
     c->bp = (float*)(w + L.bp);
@@ -792,6 +863,12 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
             return bail(fail(SPDHG_E_DOMAIN, std::to_string((long long)h[1]) +
                                                  " bins have b > 0, r = 0 and no voxel on the ray"));
     }
+    // the padded dual-change buffer is zero outside the planes for good
+    {
+        const int64_t nd = (int64_t)((geom->n_ang + c->m - 1) / c->m) * geom->n_rad *
+                           (np + 4 * geom->n_seg);
+        fill_f32<<<nblocks(nd), BLOCK, 0, st>>>(c->dscr, nd, 0.0f);
+    }
     // the image: caller layout -> z-fastest, line 3 with z = 0: x = max(x0, 0)
     img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(geom->nx, geom->ny,
                                                                          geom->nz, x, c->xa);
@@ -808,13 +885,15 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         for (int i = 0; i < c->m; ++i) {
             int a0, step, cnt;
             subset_angles(geom, c->m, i, a0, step, cnt);
+            const int64_t nsub = (int64_t)cnt * np * geom->n_rad;
+            to_padded<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, c->mp, 0, nullptr, a0, step, cnt,
+                                                       c->dscr);
             BwdArgs B = c->bwd_args();
-            B.d = c->mp;
-            B.d_ang0 = a0;
-            B.d_step = step;
+            B.d = c->dscr;
             B.scale = (float)(rho * c->p[i] / gam);
             B.T = c->T;
-            if ((rc = launch_bwd<B_SENS, false, false>(B, a0, step, cnt, st))) return bail(rc);
+            if ((rc = launch_bwd<B_SENS>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
+                return bail(rc);
         }
     } else {
         c->data_norm.resize(c->m);
@@ -930,14 +1009,13 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             if ((rc = prof_end(c, st))) return rc;
             BwdArgs B = c->bwd_args();
             B.d = c->dscr;
-            B.d_ang0 = 0;
-            B.d_step = 1;
             B.inv_p = inv_p;
             B.z = c->z;
             B.x = c->xcur();
             B.T = c->T;
             if ((rc = prof_begin(c, SPDHG_PROF_BWD, st))) return rc;
-            if ((rc = launch_bwd<B_ITER, false, false>(B, a0, step, cnt, st))) return rc;
+            if ((rc = launch_bwd<B_ITER>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
+                return rc;
             if ((rc = prof_end(c, st))) return rc;
         } else {
             P.inv_p = inv_p;

@@ -38,6 +38,10 @@ GEOMS = {
     "ragged": synth.Geometry(nx=19, ny=23, nz=7, vx=3.0, vy=2.5, vz=2.0, n_rad=37, d_rad=2.2,
                              n_ang=10, seg_planes=(7, 5, 5, 3, 3),
                              seg_tan=(0.0, 0.2, -0.2, 0.45, -0.45)),
+    # nz >= 32 (tiled gather), in-plane sizes not multiples of the 8-column tile
+    "tall": synth.Geometry(nx=37, ny=45, nz=41, vx=2.0, vy=2.0, vz=2.0, n_rad=50, d_rad=2.0,
+                           n_ang=16, seg_planes=(41, 37, 37, 31, 31),
+                           seg_tan=(0.0, 0.1, -0.1, 0.3, -0.3)),
 }
 
 

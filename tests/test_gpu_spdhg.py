@@ -42,6 +42,13 @@ def small3d():
     return synth.brain_problem(g, 18080300, 2e5, with_side=True)
 
 
+@pytest.fixture(scope="module")
+def tall3d():
+    g = synth.Geometry(nx=40, ny=40, nz=33, vx=5.0, vy=5.0, vz=5.0, n_rad=44, d_rad=5.0,
+                       n_ang=24, seg_planes=(33, 29, 29), seg_tan=(0.0, 0.25, -0.25))
+    return synth.brain_problem(g, 18080400, 5e5)
+
+
 def run_pair(P, d, n_subsets, prior, epochs, seed, sampling="uniform", precond=True,
              alpha=0.1, side=None, eta=1e-2):
     g = d["geom"]
@@ -106,6 +113,18 @@ def test_small3d_parity(P, small3d, prior, sampling, epochs):
     psi_o = prob.objective(xo[None])
     obj = rec.objective().cpu().numpy()
     assert abs(obj[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+@pytest.mark.parametrize("sampling,precond,m", [("balanced", True, 8), ("uniform", False, 3)])
+def test_tall3d_tv_parity(P, tall3d, sampling, precond, m):
+    """nz = 33: the tiled gather backprojector inside the iteration."""
+    print(f"[spdhg] tall3d TV {sampling} precond={precond} m={m}", flush=True)
+    prob, st, rec, x = run_pair(P, tall3d, m, "tv", 10, seed=31, sampling=sampling,
+                                precond=precond, alpha=0.05)
+    xo = prob.reported(st)[0]
+    assert rel(x.cpu().numpy(), xo) <= 1e-3
+    psi_o = prob.objective(xo[None])
+    assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
 
 
 def test_scalar_steps_norms(P, small3d):
