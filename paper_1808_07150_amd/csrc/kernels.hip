@@ -313,9 +313,11 @@ __device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, doub
 // Lower and upper tap values of voxel z for one (ray, segment).
 __device__ __forceinline__ float tap_sum(const float* __restrict__ row, const TapCoef& t, int z,
                                          float h) {
-    const int i0 = min(max(z + t.off, t.lo), t.hi);
-    h = __builtin_fmaf(t.wa, row[i0], h);
-    return __builtin_fmaf(t.wb, row[i0 - 1], h);
+    // non-negative after the clamp: a 32-bit offset from the row start
+    const unsigned i0 = (unsigned)min(max(z + t.off, t.lo), t.hi);
+    const float* q = row + i0;
+    h = __builtin_fmaf(t.wa, q[0], h);
+    return __builtin_fmaf(t.wb, q[-1], h);
 }
 
 __device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t t, float dz) {
@@ -446,19 +448,21 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 // One wavefront per strip of BS_W voxel columns that lie along the secondary axis at one
 // primary index j, for the angles of one sampling class (rows or columns), nz <= 128
 // (lane holds z = lane and z = lane + 64 of every strip column).  Per angle:
-//   1. the radial bins of the rays touching the strip (consecutive, at most KR),
-//   2. each ray's in-plane cell / fraction and per segment its tap coefficients (FP64,
-//      the same inline functions as the forward walk),
-//   3. per strip column the rays whose in-plane taps include it (<= 4, with weights) and,
-//      per ray, the axial gather h(z) = sum_g wa_g d(z + zoff_g) + wb_g d(z + zoff_g - 1)
-//      into LDS (lanes along z read the padded dual change contiguously),
-//   4. every voxel adds weight * h(z) of its column's rays.
-// A ray's axial gather is shared by the two columns it touches.  The row-sampled angles
-// of a subset write a partial image that the column-sampled launch adds before its
+//   1. the radial bins of the rays touching the strip (consecutive, at most KR), each
+//      ray's in-plane cell / fraction and per segment its tap coefficients (FP64, the
+//      same inline functions as the forward walk), into LDS; then, per in-plane cell
+//      c = -1 .. BS_W - 1 of the strip, the range of rays whose cell it is (the cell is
+//      monotonic in the radial bin, so the range is contiguous);
+//   2. per cell (unrolled) and ray of its range (a wave-uniform loop) the axial gather
+//      h(z) = sum_g wa_g d(z + off_g) + wb_g d(z + off_g - 1), lanes along z reading the
+//      padded dual change contiguously, added with the in-plane weights 1 - fu and fu to
+//      the strip columns c and c + 1.
+// Every ray's axial gather is computed once per strip and angle and serves both columns
+// it touches; the accumulators stay in registers with static indices.  The row-sampled
+// angles of a subset write a partial image that the column-sampled launch adds before its
 // epilogue.  Deterministic, no atomics.  The workgroup is one wavefront, whose LDS
 // accesses execute in order: code-motion barriers separate the phases.
 #define BS_W 16
-#define BS_CAND 4
 
 template <int MODE>
 __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
@@ -467,12 +471,11 @@ __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
     const int ns = G.n_seg;
     const int nz = G.nz;
     extern __shared__ float smem[];
-    float* hb = smem;                                  // [KR][128] axial gathers
-    int* ri0 = (int*)(hb + KR * 128);                  // [KR] in-plane cell
-    float* rfu = (float*)(ri0 + KR);                   // [KR] in-plane fraction
-    int* cak = (int*)(rfu + KR);                       // [BS_W][CAND] ray
-    float* caw = (float*)(cak + BS_W * BS_CAND);        // [BS_W][CAND] weight
-    TapCoef* tc = (TapCoef*)(caw + BS_W * BS_CAND);     // [KR][ns]
+    int* ri0 = (int*)smem;                    // [KR] in-plane cell relative to the strip
+    float* rfu = (float*)(ri0 + KR);          // [KR] in-plane fraction
+    int* cfirst = (int*)(rfu + KR);           // [BS_W + 1] first ray of cell c (index c + 1)
+    int* clast = cfirst + (BS_W + 1);         // [BS_W + 1] last ray of cell c
+    TapCoef* tc = (TapCoef*)(clast + (BS_W + 1));  // [KR][ns]
 
     const int lane = threadIdx.x;
     const int n_sec = rowdom ? G.nx : G.ny;
@@ -497,66 +500,53 @@ __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
         const int khi = min(G.n_rad - 1, (int)__builtin_ceil(fmax(ka, kb)) + 1);
         const int nr = min(max(khi - klo + 1, 0), KR);
         __builtin_amdgcn_wave_barrier();  // the previous angle's tables are consumed
-        // 2. coordinates of each ray
         for (int kr = lane; kr < nr; kr += 64) {
             const Sample sm = split(sec_coord(A, (double)(klo + kr) - G.ck, jj));
-            const bool touch = sm.i0 >= s0 - 1 && sm.i0 < s0 + BS_W;
-            ri0[kr] = touch ? sm.i0 : INT32_MIN;
+            ri0[kr] = sm.i0 - s0;
             rfu[kr] = sm.fu;
+        }
+        if (lane <= BS_W) {
+            cfirst[lane] = 0;
+            clast[lane] = -1;
         }
         for (int t = lane; t < nr * ns; t += 64) {
             const int kr = t / ns, g = t - kr * ns;
             tc[t] = tap_coef(G, a, g, (double)(klo + kr) - G.ck, jj);
         }
         __builtin_amdgcn_wave_barrier();
-        // 3a. rays of each strip column: a window of candidates around the rays whose
-        //     secondary coordinate is closest to the column (u is monotonic in k)
-        if (lane < BS_W) {
-            const int sec = s0 + lane;
-            const double kc = ((double)(sec - 1) - base) / A.du_dk + G.ck;
-            const double kd = ((double)(sec + 1) - base) / A.du_dk + G.ck;
-            const int kf = (int)__builtin_floor(fmin(kc, kd)) - 1 - klo;
-            int found = 0;
-            for (int kr = max(kf, 0); kr < min(kf + 5, nr) && found < BS_CAND; ++kr) {
-                const int i0 = ri0[kr];
-                const float fu = rfu[kr];
-                if (i0 == sec && fu < 1.0f) {
-                    cak[lane * BS_CAND + found] = kr;
-                    caw[lane * BS_CAND + found] = 1.0f - fu;
-                    ++found;
-                } else if (i0 + 1 == sec && fu > 0.0f) {
-                    cak[lane * BS_CAND + found] = kr;
-                    caw[lane * BS_CAND + found] = fu;
-                    ++found;
-                }
+        for (int kr = lane; kr < nr; kr += 64) {
+            const int ci = ri0[kr];
+            if (ci >= -1 && ci < BS_W) {
+                if (kr == 0 || ri0[kr - 1] != ci) cfirst[ci + 1] = kr;
+                if (kr == nr - 1 || ri0[kr + 1] != ci) clast[ci + 1] = kr;
             }
-            for (; found < BS_CAND; ++found) cak[lane * BS_CAND + found] = -1;
-        }
-        // 3b. axial gather of every touching ray
-        for (int kr = 0; kr < nr; ++kr) {
-            if (ri0[kr] == INT32_MIN) continue;
-            const float* dk = P.d + pad_row(G, ia, klo + kr);
-            const TapCoef* tk = tc + kr * ns;
-            float h0 = 0.0f, h1 = 0.0f;
-            for (int g = 0; g < ns; ++g) {
-                const TapCoef t = tk[g];
-                h0 = tap_sum(dk, t, lane, h0);
-                h1 = tap_sum(dk, t, lane + 64, h1);
-            }
-            hb[kr * 128 + lane] = h0;
-            hb[kr * 128 + 64 + lane] = h1;
         }
         __builtin_amdgcn_wave_barrier();
-        // 4. voxels of the strip
+        // 2. axial gather of the rays of each cell, added to the cell's two columns
 #pragma unroll
-        for (int c = 0; c < BS_W; ++c) {
-#pragma unroll
-            for (int e = 0; e < BS_CAND; ++e) {
-                const int kr = cak[c * BS_CAND + e];
-                if (kr < 0) break;
-                const float w = caw[c * BS_CAND + e];
-                acc[c][0] = __builtin_fmaf(w, hb[kr * 128 + lane], acc[c][0]);
-                acc[c][1] = __builtin_fmaf(w, hb[kr * 128 + 64 + lane], acc[c][1]);
+        for (int c = -1; c < BS_W; ++c) {
+            const int r0 = __builtin_amdgcn_readfirstlane(cfirst[c + 1]);
+            const int r1 = __builtin_amdgcn_readfirstlane(clast[c + 1]);
+            for (int kr = r0; kr <= r1; ++kr) {
+                const float fu =
+                    __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rfu[kr])));
+                const float* dk = P.d + pad_row(G, ia, klo + kr);
+                const TapCoef* tk = tc + kr * ns;
+                float h0 = 0.0f, h1 = 0.0f;
+#pragma unroll 2
+                for (int g = 0; g < ns; ++g) {
+                    const TapCoef t = tk[g];
+                    h0 = tap_sum(dk, t, lane, h0);
+                    h1 = tap_sum(dk, t, lane + 64, h1);
+                }
+                if (c >= 0) {
+                    acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
+                    acc[c][1] = __builtin_fmaf(1.0f - fu, h1, acc[c][1]);
+                }
+                if (c + 1 < BS_W) {
+                    acc[c + 1][0] = __builtin_fmaf(fu, h0, acc[c + 1][0]);
+                    acc[c + 1][1] = __builtin_fmaf(fu, h1, acc[c + 1][1]);
+                }
             }
         }
     }

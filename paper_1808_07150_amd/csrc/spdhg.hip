@@ -301,8 +301,9 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
 
 int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }
 
-// Backprojection kernel choice: the strip gather for nz <= 128 when the rays touching a
-// strip fit its LDS tables (radial spacing >= voxel size); else the per-column gather.
+// Backprojection kernel choice: the strip gather for 32 <= nz <= 128; else the per-column
+// gather.  The rays a strip considers per angle span BS_W + 1 in the secondary coordinate
+// plus one radial bin of margin on each side, so at most (BS_W + 1) / min|du_dk| + 5.
 struct BwdPlan {
     bool strip = false;
     int KR = 0;
@@ -314,10 +315,9 @@ BwdPlan bwd_plan(const HostTables& T) {
     const int nz = T.G.nz, ns = T.G.n_seg;
     double min_du = 1e30;
     for (const AngleDev& A : T.ang) min_du = std::min(min_du, std::fabs(A.du_dk));
-    if (nz < 32 || nz > 128 || !(min_du >= 1.0)) return pl;
-    const int KR = (int)std::floor((BS_W + 1) / min_du) + 5;
-    const size_t floats = (size_t)KR * 128 + 2 * (size_t)KR + 2 * BS_W * BS_CAND +
-                          (sizeof(TapCoef) / 4) * (size_t)KR * ns;
+    if (nz < 32 || nz > 128 || !(min_du >= 0.5)) return pl;
+    const int KR = (int)std::ceil((BS_W + 1) / min_du) + 6;
+    const size_t floats = 2 * (size_t)KR + 2 * (BS_W + 1) + (sizeof(TapCoef) / 4) * (size_t)KR * ns;
     pl.strip = true;
     pl.KR = KR;
     pl.lds = floats * 4;
