@@ -25,6 +25,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "mMR-size SPDHG epochs/s, proj+backproj GB/s; time to 1e-3 rel objective"
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE counters, valid only
+# for the kernel sources they were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mmr_tv21.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1808_07150_amd", "csrc", f)
+                  for f in ("kernels.hip", "geom.hpp", "spdhg.hip")]
+COPY_BYTES = 256 << 20
 HBM_PEAK_GBS = 8000.0
 # FP32 vector FMA without packed-FP32 instructions: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 ALU_PEAK_TFLOPS = 78.6
@@ -33,6 +39,40 @@ SEED = 18080200
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch of kernel kind `kind` from the counter summary, or None when
+    the summary is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_digest() or f"{kind}_bytes_per_launch" not in kv:
+        return None
+    return float(kv[f"{kind}_bytes_per_launch"])
+
+
+def copy_calibration(torch, dev):
+    """A plain copy kernel of known size (COPY_BYTES read, COPY_BYTES written), launched
+    4 times: the scale for the HBM byte counters."""
+    src = torch.rand(COPY_BYTES // 4, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def cpu_baseline(g, d_host, m, alpha, seed):
@@ -74,6 +114,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10, help="timed epochs")
     ap.add_argument("--warmup", type=int, default=2, help="untimed epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--inputs", choices=("phantom", "random"), default="phantom",
+                    help="phantom: the brain-phantom workload; random: i.i.d. inputs of the "
+                         "same shapes (the kernels' memory accesses do not depend on values)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="launch a copy kernel of known size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the single-GPU kernels are the subject of this "
@@ -88,10 +133,19 @@ def main():
     from synth.phantom import brain_problem_torch
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
     g = synth.mmr()
     m, alpha = 21, 2e-3
     t0 = time.time()
-    d = brain_problem_torch(g, SEED, 1e8, dev)
+    if args.inputs == "phantom":
+        d = brain_problem_torch(g, SEED, 1e8, dev)
+    else:
+        torch.manual_seed(SEED)
+        mean = 1e8 / g.n_bins
+        d = {"mult": torch.rand(g.sino_shape, device=dev) * 0.4 + 0.8,
+             "b": torch.poisson(torch.full(g.sino_shape, mean, device=dev)),
+             "r": torch.full(g.sino_shape, 0.3 * mean, device=dev)}
     torch.cuda.synchronize()
     log(f"inputs generated in {time.time() - t0:.1f} s (total counts {float(d['b'].sum()):.3e})")
     x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
@@ -153,7 +207,8 @@ def main():
                              "algorithmic_GBs": round((dict(fwd=bytes_fwd, bwd=bytes_bwd,
                                                             prior=bytes_prior)[k]) / (a * 1e6), 1)}
     roofline = {"bound": kd["bound"], "achieved": round(achieved, 3), "peak": kd["peak"],
-                "unit": kd["unit"], "frac": round(achieved / kd["peak"], 4), "traffic": None,
+                "unit": kd["unit"], "frac": round(achieved / kd["peak"], 4),
+                "traffic": measured_traffic(dom),
                 "kernel": kd["name"], "avg_ms": round(avg_ms, 4)}
     epochs_per_s = args.steps / (ms * 1e-3)
     pb_ms = (prof["fwd"][0] + prof["bwd"][0]) / max(prof["fwd"][1], 1)

@@ -133,16 +133,21 @@ struct FwdArgs {
     float gr;            // F_SENS: gamma * rho
 };
 
-// One wavefront per (angle, radial bin); RPL = rays per lane (planes / 64, rounded up).
-template <int RPL, int MODE>
-__global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
+// One workgroup of NW wavefronts per (angle, radial bin); RPL = rays per lane (planes / 64,
+// rounded up).  Wavefront w walks the w-th of NW consecutive parts of the primary steps
+// with its own LDS buffers; the partial ray sums are added in a fixed order by wavefront 0
+// (several wavefronts per ray bundle give small subsets enough parallelism).
+template <int RPL, int MODE, int NW>
+__global__ void __launch_bounds__(64 * NW) fwd_wave(FwdArgs P) {
     extern __shared__ float smem[];
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
-    float* Gb = smem;                                  // [2][gsize] axial columns
-    int* segc = (int*)(smem + 2 * P.gsize);            // [2][ns] axial cell offsets
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    float* Gb = smem + w * (2 * P.gsize + 4 * ns);     // [2][gsize] axial columns
+    int* segc = (int*)(Gb + 2 * P.gsize);              // [2][ns] axial cell offsets
     float* segf = (float*)(segc + 2 * ns);             // [2][ns] axial fractions
-    const int lane = threadIdx.x;
+    float* red = smem + NW * (2 * P.gsize + 4 * ns);   // [NW - 1][RPL][64] partial sums
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int ia = bid / G.n_rad;
     const int k = bid - ia * G.n_rad;
@@ -168,6 +173,11 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
     for (int i = lane; i < 2 * P.gsize; i += 64) Gb[i] = 0.0f;
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
+    if (NW > 1 && j0 < j1) {  // this wavefront's part of the steps
+        const int n = j1 - j0;
+        j1 = j0 + (n * (w + 1)) / NW;
+        j0 = j0 + (n * w) / NW;
+    }
     // The workgroup is one wavefront: its LDS accesses execute in order, so a code-motion
     // barrier is enough between writing and reading the axial column.  The image values
     // of step j + 1 are loaded before the rays consume step j (latency hiding).
@@ -232,6 +242,19 @@ __global__ void __launch_bounds__(64) fwd_wave(FwdArgs P) {
         __builtin_amdgcn_wave_barrier();
         buf ^= 1;
     }
+    if (NW > 1) {
+        if (w > 0) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) red[((w - 1) * RPL + r) * 64 + lane] = acc[r];
+        }
+        __syncthreads();
+        if (w > 0) return;
+#pragma unroll
+        for (int v = 1; v < NW; ++v) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) acc[r] += red[((v - 1) * RPL + r) * 64 + lane];
+        }
+    }
 
     // epilogues
     double obj = 0.0;
@@ -289,32 +312,34 @@ struct BwdArgs {
 };
 
 // Per (candidate ray, segment): the lower-tap index of voxel z inside the padded row is
-// clamp(z + off, lo, lo + N_g + 2) with lo = seg_base[g] + 4 g + 1, and the two tap
-// weights carry the segment's step length.
+// clamp(z + off, lo_g, hi_g) (seg_lo / seg_hi), and the two tap weights carry the
+// segment's step length.
 struct TapCoef {
-    int off, lo, hi;
+    int off;
     float wa, wb;
 };
+
+__device__ __forceinline__ int seg_lo(const GeomDev& G, int g) { return G.seg_base[g] + 4 * g + 1; }
+__device__ __forceinline__ int seg_hi(const GeomDev& G, int g) {
+    return G.seg_base[g] + 4 * g + G.seg_planes[g] + 3;
+}
 
 __device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, double kk,
                                             double jj) {
     const SegAngleDev S = G.sa[a * G.n_seg + g];
     const Sample sz = split(ax_offset(S, kk, jj));
     TapCoef t;
-    const int blk = G.seg_base[g] + 4 * g;
-    t.off = blk + 2 - (G.seg_off[g] + sz.i0);
-    t.lo = blk + 1;
-    t.hi = blk + G.seg_planes[g] + 3;
+    t.off = G.seg_base[g] + 4 * g + 2 - (G.seg_off[g] + sz.i0);
     t.wa = S.L * (1.0f - sz.fu);
     t.wb = S.L * sz.fu;
     return t;
 }
 
 // Lower and upper tap values of voxel z for one (ray, segment).
-__device__ __forceinline__ float tap_sum(const float* __restrict__ row, const TapCoef& t, int z,
-                                         float h) {
+__device__ __forceinline__ float tap_sum(const float* __restrict__ row, const TapCoef& t, int lo,
+                                         int hi, int z, float h) {
     // non-negative after the clamp: a 32-bit offset from the row start
-    const unsigned i0 = (unsigned)min(max(z + t.off, t.lo), t.hi);
+    const unsigned i0 = (unsigned)min(max(z + t.off, lo), hi);
     const float* q = row + i0;
     h = __builtin_fmaf(t.wa, q[0], h);
     return __builtin_fmaf(t.wb, q[-1], h);
@@ -411,7 +436,7 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
             const int kc = rem / ns, g = rem - kc * ns;
             const int cq = col0 + c;
             const ColCoord o = cc[c * BWD_KC + kc];
-            TapCoef v{0, 0, 0, 0.0f, 0.0f};
+            TapCoef v{0, 0.0f, 0.0f};
             if (cq < ncol && o.wx != 0.0f) {
                 const int qy = cq / G.nx, qx = cq - qy * G.nx;
                 const int j = A.rowdom ? qy : qx;
@@ -430,7 +455,8 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
                 const int iz = z0 + zz * zchunk;
                 if (iz >= nz) break;
                 float h = 0.0f;
-                for (int g = 0; g < ns; ++g) h = tap_sum(dk, tk[g], iz, h);
+                for (int g = 0; g < ns; ++g)
+                    h = tap_sum(dk, tk[g], seg_lo(G, g), seg_hi(G, g), iz, h);
                 acc[zz] = __builtin_fmaf(o.wx, h, acc[zz]);
             }
         }
@@ -536,8 +562,9 @@ __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
 #pragma unroll 2
                 for (int g = 0; g < ns; ++g) {
                     const TapCoef t = tk[g];
-                    h0 = tap_sum(dk, t, lane, h0);
-                    h1 = tap_sum(dk, t, lane + 64, h1);
+                    const int lo = seg_lo(G, g), hi = seg_hi(G, g);
+                    h0 = tap_sum(dk, t, lo, hi, lane, h0);
+                    h1 = tap_sum(dk, t, lo, hi, lane + 64, h1);
                 }
                 if (c >= 0) {
                     acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);

@@ -270,24 +270,27 @@ int check_kernel_limits(const spdhg_geom* g) {
 }
 
 // ---------------------------------------------------------------- launch helpers
-template <int MODE>
-int launch_fwd_rpl(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
-    const size_t lds = (2 * (size_t)A.gsize + 4 * (size_t)A.G.n_seg) * 4;
+template <int MODE, int NW>
+int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
+    const size_t lds = (NW * (2 * (size_t)A.gsize + 4 * (size_t)A.G.n_seg) +
+                        (NW - 1) * (size_t)rpl * 64) * 4;
+    const int nt = 64 * NW;
     switch (rpl) {
-        case 1: fwd_wave<1, MODE><<<nblk, 64, lds, st>>>(A); break;
-        case 2: fwd_wave<2, MODE><<<nblk, 64, lds, st>>>(A); break;
-        case 4: fwd_wave<4, MODE><<<nblk, 64, lds, st>>>(A); break;
-        case 8: fwd_wave<8, MODE><<<nblk, 64, lds, st>>>(A); break;
-        case 16: fwd_wave<16, MODE><<<nblk, 64, lds, st>>>(A); break;
-        case 32: fwd_wave<32, MODE><<<nblk, 64, lds, st>>>(A); break;
-        case 64: fwd_wave<64, MODE><<<nblk, 64, lds, st>>>(A); break;
+        case 1: fwd_wave<1, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 2: fwd_wave<2, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 4: fwd_wave<4, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 8: fwd_wave<8, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 16: fwd_wave<16, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 32: fwd_wave<32, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 64: fwd_wave<64, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
         default: return fail(SPDHG_E_SHAPE, "unsupported plane count");
     }
     LAUNCH_CHECK();
     return SPDHG_OK;
 }
 
-// One block per (angle of the list, radial bin).
+// One block per (angle of the list, radial bin); launches with few blocks (fewer than 16
+// per compute unit) split every ray walk over two wavefronts.
 template <int MODE>
 int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     A.ang0 = ang0;
@@ -296,7 +299,9 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     const int64_t nblk = (int64_t)cnt * A.G.n_rad;
     if (nblk == 0) return SPDHG_OK;
     if (nblk > INT32_MAX) return fail(SPDHG_E_SHAPE, "too many rays");
-    return launch_fwd_rpl<MODE>(rays_per_lane(A.G.n_planes), A, (int)nblk, st);
+    const int rpl = rays_per_lane(A.G.n_planes);
+    if (nblk < 16 * 256) return launch_fwd_nw<MODE, 2>(rpl, A, (int)nblk, st);
+    return launch_fwd_nw<MODE, 1>(rpl, A, (int)nblk, st);
 }
 
 int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }

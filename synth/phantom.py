@@ -311,10 +311,14 @@ def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side
     half = int(math.ceil(4 * sigma))
     kern = torch.exp(-0.5 * (torch.arange(-half, half + 1, device=device, dtype=torch.float64)
                              / sigma) ** 2)
-    kern = (kern / kern.sum()).view(1, 1, -1)
-    flat = trues.view(-1, 1, g.n_rad)
-    scatter = torch.cat([torch.nn.functional.conv1d(flat[i:i + 65536], kern, padding=half)
-                         for i in range(0, flat.shape[0], 65536)]).view(g.sino_shape)
+    kern = kern / kern.sum()
+    # zero-padded Gaussian blur along the radial axis as one banded matrix product:
+    # scatter[.., i] = sum_j trues[.., j] kern[j - i + half]
+    idx = torch.arange(g.n_rad, device=device)
+    off = idx.view(-1, 1) - idx.view(1, -1) + half
+    band = torch.where((off >= 0) & (off <= 2 * half), kern[off.clamp(0, 2 * half)],
+                       torch.zeros((), dtype=torch.float64, device=device))
+    scatter = (trues.view(-1, g.n_rad) @ band).view(g.sino_shape)
     scatter *= 0.15 * trues.sum() / scatter.sum().clamp(min=1e-30)
     rshape = scatter + 0.15 * trues.mean()
     del scatter
