@@ -106,14 +106,11 @@ __device__ __forceinline__ void sec_range(const AngleDev& A, double u0, int& j0,
 // ---------------------------------------------------------------- forward projection
 enum FwdMode { F_PLAIN_QK = 0, F_POWER = 1, F_SENS = 2, F_DUAL = 3, F_OBJ = 4 };
 
-// Padded plane layout of the dual change read by the backprojectors: per (angle of the
-// list, radial bin) a row of n_planes + 4 n_seg floats in which segment g occupies
-// N_g + 4 floats starting at seg_base[g] + 4 g: two zeros, its N_g planes, two zeros.  A
-// voxel z of a ray whose axial cell offset is c = off_g + floor(e) has its lower tap at
-// plane p0 = z - c and its upper tap at p0 - 1; clamping p0 to [-1, N_g + 1] lands every
-// out-of-segment tap on a zero, so the gather needs no branch.
-__device__ __forceinline__ int64_t pad_row(const GeomDev& G, int ia, int k) {
-    return ((int64_t)ia * G.n_rad + k) * (G.n_planes + 4 * G.n_seg);
+// Row layout of the dual change read by the backprojectors: per (angle of the list,
+// radial bin) the n_planes values of the ray bundle, segment g at planes seg_base[g] ..
+// seg_base[g] + N_g - 1.
+__device__ __forceinline__ int64_t dual_row(const GeomDev& G, int ia, int k) {
+    return ((int64_t)ia * G.n_rad + k) * G.n_planes;
 }
 
 struct FwdArgs {
@@ -271,7 +268,7 @@ __global__ void __launch_bounds__(64 * NW) fwd_wave(FwdArgs P) {
         } else if (MODE == F_POWER) {
             // A_i^T A_i needs mult (G x) times mult again: write mult^2 G x, padded
             const float m = P.mult[full];
-            P.out[pad_row(G, ia, k) + q + 4 * g + 2] = m * m * v;
+            P.out[dual_row(G, ia, k) + q] = m * m * v;
         } else if (MODE == F_SENS) {
             const float a1 = P.mult[full] * v;
             P.out[full] = a1 > 0.0f ? P.gr / a1 : 0.0f;
@@ -282,7 +279,7 @@ __global__ void __launch_bounds__(64 * NW) fwd_wave(FwdArgs P) {
             float yn = yo;
             if (sg > 0.0f) yn = prox_kl_dual(__builtin_fmaf(sg, m * v, yo), sg, P.b[full], P.r[full]);
             P.y[full] = yn;
-            P.d[pad_row(G, ia, k) + q + 4 * g + 2] = m * (yn - yo);
+            P.d[dual_row(G, ia, k) + q] = m * (yn - yo);
         } else if (MODE == F_OBJ) {
             obj += phi64((double)(P.mult[full] * v), (double)P.b[full], (double)P.r[full]);
         }
@@ -300,7 +297,7 @@ enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2, B_PARTIAL = 3, B_ACCUM = 4 }
 
 struct BwdArgs {
     GeomDev G;
-    const float* d;  // padded dual change / sinogram of the listed angles (see pad_row)
+    const float* d;  // dual change / sinogram rows of the listed angles (see dual_row)
     int ang0, ang_step, n_ang_sub;
     int cols;        // per-column kernel: voxel columns per block
     float* out;      // B_PLAIN / B_PARTIAL: z-fastest image; B_ACCUM: added to
@@ -311,38 +308,51 @@ struct BwdArgs {
     float* x;
 };
 
-// Per (candidate ray, segment): the lower-tap index of voxel z inside the padded row is
-// clamp(z + off, lo_g, hi_g) (seg_lo / seg_hi), and the two tap weights carry the
-// segment's step length.
+// Per (candidate ray, segment): voxel z reads planes p = z + off (weight wa) and p - 1
+// (weight wb) of the segment, zero outside 0 .. N_g - 1; the weights carry the segment's
+// step length.
 struct TapCoef {
     int off;
     float wa, wb;
 };
-
-__device__ __forceinline__ int seg_lo(const GeomDev& G, int g) { return G.seg_base[g] + 4 * g + 1; }
-__device__ __forceinline__ int seg_hi(const GeomDev& G, int g) {
-    return G.seg_base[g] + 4 * g + G.seg_planes[g] + 3;
-}
 
 __device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, double kk,
                                             double jj) {
     const SegAngleDev S = G.sa[a * G.n_seg + g];
     const Sample sz = split(ax_offset(S, kk, jj));
     TapCoef t;
-    t.off = G.seg_base[g] + 4 * g + 2 - (G.seg_off[g] + sz.i0);
+    t.off = -(G.seg_off[g] + sz.i0);
     t.wa = S.L * (1.0f - sz.fu);
     t.wb = S.L * sz.fu;
     return t;
 }
 
-// Lower and upper tap values of voxel z for one (ray, segment).
-__device__ __forceinline__ float tap_sum(const float* __restrict__ row, const TapCoef& t, int lo,
-                                         int hi, int z, float h) {
-    // non-negative after the clamp: a 32-bit offset from the row start
-    const unsigned i0 = (unsigned)min(max(z + t.off, lo), hi);
-    const float* q = row + i0;
-    h = __builtin_fmaf(t.wa, q[0], h);
-    return __builtin_fmaf(t.wb, q[-1], h);
+// Both taps of voxel z for one (ray, segment) through a buffer resource that spans the
+// segment's N_g planes: the hardware range check returns zero for planes outside the
+// segment (a negative plane index wraps to an offset beyond the range).
+__device__ __forceinline__ float tap_sum_rsrc(__amdgpu_buffer_rsrc_t seg, const TapCoef& t, int z,
+                                              float h) {
+    const int va = (z + t.off) * 4;
+    const float ua = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, va, 0, 0));
+    const float ub = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, va - 4, 0, 0));
+    h = __builtin_fmaf(t.wa, ua, h);
+    return __builtin_fmaf(t.wb, ub, h);
+}
+
+// The same with explicit bounds (per-lane rays).
+__device__ __forceinline__ float tap_sum_masked(const float* __restrict__ seg, int n,
+                                                const TapCoef& t, int z, float h) {
+    const int p = z + t.off;
+    if ((unsigned)p < (unsigned)n) h = __builtin_fmaf(t.wa, seg[p], h);
+    if ((unsigned)(p - 1) < (unsigned)n) h = __builtin_fmaf(t.wb, seg[p - 1], h);
+    return h;
+}
+
+// Buffer resource over segment g of a dual-change row (raw, byte offsets, range checked).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const GeomDev& G, const float* row,
+                                                           int g) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(row + G.seg_base[g]), (short)0,
+                                             G.seg_planes[g] * 4, 0x00020000);
 }
 
 __device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t t, float dz) {
@@ -449,14 +459,14 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
         for (int kc = 0; kc < BWD_KC; ++kc) {
             const ColCoord o = cc[cl * BWD_KC + kc];
             if (o.wx == 0.0f) continue;
-            const float* dk = P.d + pad_row(G, ia, o.k);
+            const float* dk = P.d + dual_row(G, ia, o.k);
             const TapCoef* tk = tc + (cl * BWD_KC + kc) * ns;
             for (int zz = 0; zz < nzz; ++zz) {
                 const int iz = z0 + zz * zchunk;
                 if (iz >= nz) break;
                 float h = 0.0f;
                 for (int g = 0; g < ns; ++g)
-                    h = tap_sum(dk, tk[g], seg_lo(G, g), seg_hi(G, g), iz, h);
+                    h = tap_sum_masked(dk + G.seg_base[g], G.seg_planes[g], tk[g], iz, h);
                 acc[zz] = __builtin_fmaf(o.wx, h, acc[zz]);
             }
         }
@@ -556,15 +566,15 @@ __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
             for (int kr = r0; kr <= r1; ++kr) {
                 const float fu =
                     __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rfu[kr])));
-                const float* dk = P.d + pad_row(G, ia, klo + kr);
+                const float* dk = P.d + dual_row(G, ia, klo + kr);
                 const TapCoef* tk = tc + kr * ns;
                 float h0 = 0.0f, h1 = 0.0f;
 #pragma unroll 2
                 for (int g = 0; g < ns; ++g) {
                     const TapCoef t = tk[g];
-                    const int lo = seg_lo(G, g), hi = seg_hi(G, g);
-                    h0 = tap_sum(dk, t, lo, hi, lane, h0);
-                    h1 = tap_sum(dk, t, lo, hi, lane + 64, h1);
+                    const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g);
+                    h0 = tap_sum_rsrc(rs, t, lane, h0);
+                    h1 = tap_sum_rsrc(rs, t, lane + 64, h1);
                 }
                 if (c >= 0) {
                     acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
@@ -593,28 +603,24 @@ __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
 }
 
 // Rows of a sinogram (internal full [a][k][q] layout at angles ang0 + ia * step, or the
-// caller's packed [ia][q][k] layout times an optional full caller mult) -> padded layout.
+// caller's packed [ia][q][k] layout times an optional full caller mult) -> dual_row layout.
 __global__ void __launch_bounds__(BLOCK)
-to_padded(GeomDev G, const float* __restrict__ src, int caller, const float* __restrict__ mult,
-          int ang0, int step, int n_ang_sub, float* __restrict__ dst) {
+to_rows(GeomDev G, const float* __restrict__ src, int caller, const float* __restrict__ mult,
+        int ang0, int step, int n_ang_sub, float* __restrict__ dst) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t per = (int64_t)G.n_planes * G.n_rad;
     if (t >= per * n_ang_sub) return;
     const int ia = (int)(t / per);
     const int64_t rem = t - ia * per;
-    int q, k;
-    float v;
     if (caller) {  // packed [ia][q][k]: consecutive threads run along k
-        q = (int)(rem / G.n_rad);
-        k = (int)(rem - (int64_t)q * G.n_rad);
-        v = src[t];
+        const int q = (int)(rem / G.n_rad);
+        const int k = (int)(rem - (int64_t)q * G.n_rad);
+        float v = src[t];
         if (mult) v *= mult[(int64_t)(ang0 + ia * step) * per + rem];
-    } else {  // internal [a][k][q]: consecutive threads run along q
-        k = (int)(rem / G.n_planes);
-        q = (int)(rem - (int64_t)k * G.n_planes);
-        v = src[(int64_t)(ang0 + ia * step) * per + rem];
+        dst[dual_row(G, ia, k) + q] = v;
+    } else {  // internal [a][k][q]: the same order
+        dst[t] = src[(int64_t)(ang0 + ia * step) * per + rem];
     }
-    dst[pad_row(G, ia, k) + q + 4 * G.plane_seg[q] + 2] = v;
 }
 
 // ---------------------------------------------------------------- layout transposes

@@ -289,7 +289,7 @@ int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
     return SPDHG_OK;
 }
 
-// One block per (angle of the list, radial bin); launches with few blocks (fewer than 16
+// One block per (angle of the list, radial bin); launches with few blocks (fewer than 64
 // per compute unit) split every ray walk over two wavefronts.
 template <int MODE>
 int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
@@ -300,7 +300,7 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     if (nblk == 0) return SPDHG_OK;
     if (nblk > INT32_MAX) return fail(SPDHG_E_SHAPE, "too many rays");
     const int rpl = rays_per_lane(A.G.n_planes);
-    if (nblk < 16 * 256) return launch_fwd_nw<MODE, 2>(rpl, A, (int)nblk, st);
+    if (nblk < 64 * 256) return launch_fwd_nw<MODE, 2>(rpl, A, (int)nblk, st);
     return launch_fwd_nw<MODE, 1>(rpl, A, (int)nblk, st);
 }
 
@@ -330,7 +330,7 @@ BwdPlan bwd_plan(const HostTables& T) {
 }
 
 // Gather backprojection of the angles ang0 + i * step (i < cnt) with the epilogue MODE;
-// A.d holds their dual change in the padded layout.  With the strip kernel the
+// A.d holds their dual change in the dual_row layout.  With the strip kernel the
 // row-sampled and column-sampled angles run as two launches; when both classes occur and
 // the epilogue needs the whole sum, the first writes its partial image to `partial`.
 template <int MODE>
@@ -451,8 +451,8 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
     const int64_t np = n_planes(g);
     const int64_t nb = (int64_t)g->n_ang * np * g->n_rad;
     const int m = std::max(1, p->n_subsets);
-    // padded dual change of the largest subset (see pad_row)
-    const int64_t max_sub = (int64_t)((g->n_ang + m - 1) / m) * g->n_rad * (np + 4 * g->n_seg);
+    // dual change of the largest subset (see dual_row)
+    const int64_t max_sub = (int64_t)((g->n_ang + m - 1) / m) * g->n_rad * np;
     const bool prior = p->prior == SPDHG_PRIOR_TV || p->prior == SPDHG_PRIOR_DTV;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -516,7 +516,7 @@ int power_norm_data(spdhg_ctx* c, int i, double* out, hipStream_t st) {
     const int64_t nv = c->nv;
     float* v = c->xb;
     float* w = c->z;
-    float* tmp = c->dscr;  // padded, zero outside the planes
+    float* tmp = c->dscr;  // dual_row layout
     fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, 1.0f);
     sumsq<<<nblocks(nv), BLOCK, 0, st>>>(v, nv, c->part);
     if ((rc = reduce_to(c->part, nblocks(nv), c->scal, 0, 1.0, st))) return rc;
@@ -676,21 +676,20 @@ int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
     HostTables T;
     build_tables(geom, T);
     const BwdPlan plan = bwd_plan(T);
-    // angles in chunks: each chunk's rows go to a padded scratch and are added to the
-    // z-fastest image; then one transpose to the caller's layout
+    // angles in chunks: each chunk's rows go to a scratch in the dual_row layout and are
+    // added to the z-fastest image; then one transpose to the caller's layout
     const int chunk = std::min(cnt, 16);
-    const int64_t npad = (int64_t)chunk * geom->n_rad * (G.n_planes + 4 * geom->n_seg);
+    const int64_t npad = (int64_t)chunk * geom->n_rad * G.n_planes;
     float* dk = nullptr;
     float* xz = nullptr;
     HIP_TRY(hipMallocAsync((void**)&dk, npad * 4, st));
     HIP_TRY(hipMallocAsync((void**)&xz, nv * 4, st));
-    hipError_t e = hipMemsetAsync(dk, 0, npad * 4, st);
-    if (e == hipSuccess) e = hipMemsetAsync(xz, 0, nv * 4, st);
+    hipError_t e = hipMemsetAsync(xz, 0, nv * 4, st);
     for (int c0 = 0; c0 < cnt && e == hipSuccess && rc == SPDHG_OK; c0 += chunk) {
         const int cc = std::min(chunk, cnt - c0);
         const int cang0 = a0 + c0 * step;
         const int64_t nsub = (int64_t)cc * G.n_planes * G.n_rad;
-        to_padded<<<nblocks(nsub), BLOCK, 0, st>>>(G, y + (int64_t)c0 * G.n_planes * G.n_rad, 1,
+        to_rows<<<nblocks(nsub), BLOCK, 0, st>>>(G, y + (int64_t)c0 * G.n_planes * G.n_rad, 1,
                                                    mult, cang0, step, cc, dk);
         e = hipGetLastError();
         if (e != hipSuccess) break;
@@ -868,12 +867,6 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
             return bail(fail(SPDHG_E_DOMAIN, std::to_string((long long)h[1]) +
                                                  " bins have b > 0, r = 0 and no voxel on the ray"));
     }
-    // the padded dual-change buffer is zero outside the planes for good
-    {
-        const int64_t nd = (int64_t)((geom->n_ang + c->m - 1) / c->m) * geom->n_rad *
-                           (np + 4 * geom->n_seg);
-        fill_f32<<<nblocks(nd), BLOCK, 0, st>>>(c->dscr, nd, 0.0f);
-    }
     // the image: caller layout -> z-fastest, line 3 with z = 0: x = max(x0, 0)
     img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(geom->nx, geom->ny,
                                                                          geom->nz, x, c->xa);
@@ -891,7 +884,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
             int a0, step, cnt;
             subset_angles(geom, c->m, i, a0, step, cnt);
             const int64_t nsub = (int64_t)cnt * np * geom->n_rad;
-            to_padded<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, c->mp, 0, nullptr, a0, step, cnt,
+            to_rows<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, c->mp, 0, nullptr, a0, step, cnt,
                                                        c->dscr);
             BwdArgs B = c->bwd_args();
             B.d = c->dscr;
