@@ -68,7 +68,10 @@ typedef struct spdhg_geom {
 
 #define SPDHG_PRIOR_NONE 0 /* ML: n = m blocks                                        */
 #define SPDHG_PRIOR_TV 1   /* f_n = alpha ||.||_{2,1}, A_n = grad (eq. setting TV)      */
+#define SPDHG_PRIOR_ATV 2  /* f_n = alpha ||.||_{1,1}, A_n = grad (Section 4.3, aTV)    */
 #define SPDHG_PRIOR_DTV 3  /* f_n = alpha ||.||_{2,1}, A_n = D grad (Section 4.3)       */
+#define SPDHG_PRIOR_TGV 4  /* x = (u, w): f_{n-1} = alpha ||.||_{2,1}, A_{n-1} = (grad, -I);
+                            * f_n = alpha1 ||.||_{2,1}, A_n = (0, E) (eq. setting TGV)  */
 
 #define SPDHG_SAMPLING_UNIFORM 0  /* p_i = 1/n (Section 4.2)                          */
 #define SPDHG_SAMPLING_BALANCED 1 /* data 1/(2m) each, prior 1/2 (Section 4.2)        */
@@ -86,6 +89,7 @@ typedef struct spdhg_params {
     uint64_t seed;     /* SplitMix64 seed of the block sequence                        */
     int32_t power_iters; /* scalar steps: power iterations for ||A_i|| (e.g. 100)      */
     int32_t reserved;
+    double alpha1;     /* TGV: weight of ||E w|| (alpha is the weight of ||grad u - w||) */
 } spdhg_params;
 
 typedef struct spdhg_ctx spdhg_ctx;
@@ -162,15 +166,17 @@ int spdhg_objective(spdhg_ctx* ctx, const float* x, double* out_dev, void* strea
 
 /* Device pointers of internal arrays (for inspection and checkpoints):
  *   0 y (full sinogram)   1 z (image)   2 T (image)   3 sigma (full sinogram, or NULL
- *   with scalar steps)   4 prior dual (3 images, current buffer)
- * *n_floats receives the element count. */
+ *   with scalar steps)   4 prior dual (3 images, current buffer; TGV: q1)
+ *   5 TGV w (3 images)   6 TGV q2 (6 images)   7 TGV z_w (3 images)
+ * Images are z-fastest ([y][x][z]) and sinograms [angle][radial][plane] inside the
+ * library; *n_floats receives the element count (0 for an array the problem lacks). */
 int spdhg_buffer(spdhg_ctx* ctx, int32_t which, float** ptr, int64_t* n_floats);
 
-/* Step-size scalars: data sigma (scalar steps) of subset i, or the prior sigma
- * (i = n_subsets), and the probability p_i of block i. */
+/* Step-size scalars: data sigma (scalar steps) of subset i, or the sigma of prior
+ * block i - n_subsets, the probability p_i of block i and the operator norm used. */
 int spdhg_block_info(const spdhg_ctx* ctx, int32_t i, double* sigma, double* p, double* norm);
 
-/* Checkpoint: state = x, y, z, prior duals and the iteration counter (which fixes the
+/* Checkpoint: state = x, y, z, prior duals (TGV: also w, z_w) and the iteration counter (which fixes the
  * rest of the random block sequence).  spdhg_state_bytes gives the size; save writes it
  * to `dst` (device), load reads it back; both enqueue copies on `stream`. */
 int spdhg_state_bytes(const spdhg_ctx* ctx, size_t* bytes);

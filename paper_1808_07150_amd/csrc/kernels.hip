@@ -723,6 +723,7 @@ struct PriorArgs {
     float inv_p;
     float gamma_d;
     int dtv;
+    int atv;      // anisotropic TV: f_n = alpha ||.||_{1,1}, dual prox = clip to [-alpha, alpha]
 };
 
 __device__ __forceinline__ void zf_coords(const PriorArgs& P, int64_t t, int& cx, int& cy,
@@ -760,12 +761,18 @@ __device__ __forceinline__ void prior_dual_at(const PriorArgs& P, const float* _
     q[0] = __builtin_fmaf(P.sigma, g0, y0);
     q[1] = __builtin_fmaf(P.sigma, g1, y1);
     q[2] = __builtin_fmaf(P.sigma, g2, y2);
-    const float nrm = __builtin_sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-    if (nrm > P.alpha) {
-        const float sc = P.alpha / nrm;
-        q[0] *= sc;
-        q[1] *= sc;
-        q[2] *= sc;
+    if (P.atv) {  // conjugate of alpha ||.||_1: the box [-alpha, alpha]^3
+        q[0] = fminf(fmaxf(q[0], -P.alpha), P.alpha);
+        q[1] = fminf(fmaxf(q[1], -P.alpha), P.alpha);
+        q[2] = fminf(fmaxf(q[2], -P.alpha), P.alpha);
+    } else {  // conjugate of alpha ||.||_2 per voxel: the l2 ball of radius alpha
+        const float nrm = __builtin_sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        if (nrm > P.alpha) {
+            const float sc = P.alpha / nrm;
+            q[0] *= sc;
+            q[1] *= sc;
+            q[2] *= sc;
+        }
     }
     dy[0] = q[0] - y0;
     dy[1] = q[1] - y1;
@@ -841,7 +848,8 @@ tv_obj(PriorArgs P, const float* __restrict__ x, const float* __restrict__ xi,
             g1 -= P.gamma_d * dot * x1;
             g2 -= P.gamma_d * dot * x2;
         }
-        v = use_grad ? (double)P.alpha * sqrt(g0 * g0 + g1 * g1 + g2 * g2) : 0.0;
+        const double r = P.atv ? fabs(g0) + fabs(g1) + fabs(g2) : sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+        v = use_grad ? (double)P.alpha * r : 0.0;
         if (xc < 0.0) v = INFINITY;
     }
     const double s = block_sum<BLOCK>(v);
@@ -865,6 +873,300 @@ dtv_field(PriorArgs P, const float* __restrict__ s, float eta, float* __restrict
     xi[t] = (float)(g0 / nrm);
     xi[t + nv] = (float)(g1 / nrm);
     xi[t + 2 * nv] = (float)(g2 / nrm);
+}
+
+// ---------------------------------------------------------------- TGV (two prior blocks)
+// x = (u, w) with w a 3-component field; block n-1: f = alpha0 ||.||_{2,1}, A = (grad, -I)
+// (dual q1, 3 components); block n: f = alpha1 ||.||_{2,1}, A = (0, E) with
+// E w = sym(J w) stored as (J00, J11, J22, (J01+J10)/sqrt2, (J02+J20)/sqrt2,
+// (J12+J21)/sqrt2), J_kl = forward difference of w_k along axis l (Section 4.3, eq.
+// setting TGV).  Components 0, 1, 2 are the x, y, z axes.  w has no prox (g is the
+// non-negativity of u only), and its step T_w is the scalar minimum of the two blocks'.
+struct TgvArgs {
+    int nx, ny, nz;
+    float sigma;  // dual step of the block
+    float alpha;  // ball radius of the block
+    float inv_p;
+    float tw;     // T_w
+};
+
+#define TGV_SQRT_HALF 0.70710678118654752f
+
+struct ZfStrides {
+    int64_t sx, sy, nv;
+};
+
+__device__ __forceinline__ ZfStrides zf_strides(int nx, int ny, int nz) {
+    ZfStrides S;
+    S.sx = nz;
+    S.sy = (int64_t)nz * nx;
+    S.nv = S.sy * ny;
+    return S;
+}
+
+// Block n-1 dual update at voxel (cx, cy, cz): q = P_alpha0(q1 + sigma (grad u - w)),
+// dq = q - q1.
+__device__ __forceinline__ void tgv1_dual_at(const TgvArgs& P, const float* __restrict__ u,
+                                             const float* __restrict__ w,
+                                             const float* __restrict__ q1, int cx, int cy,
+                                             int cz, float q[3], float dq[3]) {
+    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
+    const int64_t c = (int64_t)cy * S.sy + (int64_t)cx * S.sx + cz;
+    const float uc = u[c];
+    const float g0 = cx < P.nx - 1 ? u[c + S.sx] - uc : 0.0f;
+    const float g1 = cy < P.ny - 1 ? u[c + S.sy] - uc : 0.0f;
+    const float g2 = cz < P.nz - 1 ? u[c + 1] - uc : 0.0f;
+    const float y0 = q1[c], y1 = q1[c + S.nv], y2 = q1[c + 2 * S.nv];
+    q[0] = __builtin_fmaf(P.sigma, g0 - w[c], y0);
+    q[1] = __builtin_fmaf(P.sigma, g1 - w[c + S.nv], y1);
+    q[2] = __builtin_fmaf(P.sigma, g2 - w[c + 2 * S.nv], y2);
+    const float nrm = __builtin_sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    if (nrm > P.alpha) {
+        const float sc = P.alpha / nrm;
+        q[0] *= sc;
+        q[1] *= sc;
+        q[2] *= sc;
+    }
+    dq[0] = q[0] - y0;
+    dq[1] = q[1] - y1;
+    dq[2] = q[2] - y2;
+}
+
+// Algorithm 2 lines 5-8 for block n-1 fused with line 3 of the next iteration:
+// dz_u = grad^T dq (the three backward neighbours' dual changes are recomputed),
+// dz_w = -dq; u, w, q1 ping-pong, z_u and z_w in place.
+__global__ void __launch_bounds__(BLOCK)
+tgv1_iter(TgvArgs P, const float* __restrict__ u_in, float* __restrict__ u_out,
+          const float* __restrict__ w_in, float* __restrict__ w_out,
+          const float* __restrict__ q_in, float* __restrict__ q_out, float* __restrict__ zu,
+          float* __restrict__ zw, const float* __restrict__ Tu) {
+    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= S.nv) return;
+    const int64_t col = t / P.nz;
+    const int cz = (int)(t - col * P.nz);
+    const int cy = (int)(col / P.nx), cx = (int)(col - (int64_t)cy * P.nx);
+    float q[3], dq[3], qn[3], dn[3];
+    tgv1_dual_at(P, u_in, w_in, q_in, cx, cy, cz, q, dq);
+    float dzu = 0.0f;
+    if (cx < P.nx - 1) dzu -= dq[0];
+    if (cy < P.ny - 1) dzu -= dq[1];
+    if (cz < P.nz - 1) dzu -= dq[2];
+    if (cx > 0) {
+        tgv1_dual_at(P, u_in, w_in, q_in, cx - 1, cy, cz, qn, dn);
+        dzu += dn[0];
+    }
+    if (cy > 0) {
+        tgv1_dual_at(P, u_in, w_in, q_in, cx, cy - 1, cz, qn, dn);
+        dzu += dn[1];
+    }
+    if (cz > 0) {
+        tgv1_dual_at(P, u_in, w_in, q_in, cx, cy, cz - 1, qn, dn);
+        dzu += dn[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t i = t + k * S.nv;
+        q_out[i] = q[k];
+        const float dzw = -dq[k];
+        const float zn = zw[i] + dzw;
+        zw[i] = zn;
+        w_out[i] = w_in[i] - P.tw * __builtin_fmaf(dzw, P.inv_p, zn);
+    }
+    const float zn = zu[t] + dzu;
+    zu[t] = zn;
+    u_out[t] = fmaxf(u_in[t] - Tu[t] * __builtin_fmaf(dzu, P.inv_p, zn), 0.0f);
+}
+
+// E w at voxel (cx, cy, cz), 6 components.
+__device__ __forceinline__ void sym_grad_at(int nx, int ny, int nz, const float* __restrict__ w,
+                                            int cx, int cy, int cz, float e[6]) {
+    const ZfStrides S = zf_strides(nx, ny, nz);
+    const int64_t c = (int64_t)cy * S.sy + (int64_t)cx * S.sx + cz;
+    const int64_t step[3] = {S.sx, S.sy, 1};
+    const bool in[3] = {cx < nx - 1, cy < ny - 1, cz < nz - 1};
+    float J[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float* wk = w + k * S.nv;
+        const float wc = wk[c];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) J[k][l] = in[l] ? wk[c + step[l]] - wc : 0.0f;
+    }
+    e[0] = J[0][0];
+    e[1] = J[1][1];
+    e[2] = J[2][2];
+    e[3] = TGV_SQRT_HALF * (J[0][1] + J[1][0]);
+    e[4] = TGV_SQRT_HALF * (J[0][2] + J[2][0]);
+    e[5] = TGV_SQRT_HALF * (J[1][2] + J[2][1]);
+}
+
+// Block n dual update at a voxel: q = P_alpha1(q2 + sigma E w), dq = q - q2.
+__device__ __forceinline__ void tgv2_dual_at(const TgvArgs& P, const float* __restrict__ w,
+                                             const float* __restrict__ q2, int cx, int cy,
+                                             int cz, float q[6], float dq[6]) {
+    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
+    const int64_t c = (int64_t)cy * S.sy + (int64_t)cx * S.sx + cz;
+    float e[6];
+    sym_grad_at(P.nx, P.ny, P.nz, w, cx, cy, cz, e);
+    float ss = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        q[k] = __builtin_fmaf(P.sigma, e[k], q2[c + k * S.nv]);
+        ss = __builtin_fmaf(q[k], q[k], ss);
+    }
+    const float nrm = __builtin_sqrtf(ss);
+    const float sc = nrm > P.alpha ? P.alpha / nrm : 1.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (nrm > P.alpha) q[k] *= sc;
+        dq[k] = q[k] - q2[c + k * S.nv];
+    }
+}
+
+// Algorithm 2 lines 5-8 for block n fused with line 3 of the next iteration:
+// dz_w = E^T dq (E^T p)_k = sum_l D_l^T of the (k, l) entry, D_l^T p (v) = [v_l > 0]
+// p(v - e_l) - [v_l < N_l - 1] p(v); dz_u = 0, so u = max(u - T_u z_u, 0).
+__global__ void __launch_bounds__(BLOCK)
+tgv2_iter(TgvArgs P, const float* __restrict__ u_in, float* __restrict__ u_out,
+          const float* __restrict__ w_in, float* __restrict__ w_out,
+          const float* __restrict__ q_in, float* __restrict__ q_out, const float* __restrict__ zu,
+          float* __restrict__ zw, const float* __restrict__ Tu) {
+    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= S.nv) return;
+    const int64_t col = t / P.nz;
+    const int cz = (int)(t - col * P.nz);
+    const int cy = (int)(col / P.nx), cx = (int)(col - (int64_t)cy * P.nx);
+    const int cc[3] = {cx, cy, cz};
+    const int nn[3] = {P.nx, P.ny, P.nz};
+    float q[6], dq[6];
+    tgv2_dual_at(P, w_in, q_in, cx, cy, cz, q, dq);
+    // entry (k, l) of the symmetric matrix -> (component, weight)
+    const int ent[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    float dzw[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        float dn[6];
+        const bool back = cc[l] > 0;
+        if (back) {
+            float qn[6];
+            tgv2_dual_at(P, w_in, q_in, cx - (l == 0), cy - (l == 1), cz - (l == 2), qn, dn);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int e = ent[k][l];
+            const float wgt = (k == l) ? 1.0f : TGV_SQRT_HALF;
+            float v = 0.0f;
+            if (back) v += dn[e];
+            if (cc[l] < nn[l] - 1) v -= dq[e];
+            dzw[k] = __builtin_fmaf(wgt, v, dzw[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) q_out[t + k * S.nv] = q[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t i = t + k * S.nv;
+        const float zn = zw[i] + dzw[k];
+        zw[i] = zn;
+        w_out[i] = w_in[i] - P.tw * __builtin_fmaf(dzw[k], P.inv_p, zn);
+    }
+    u_out[t] = fmaxf(u_in[t] - Tu[t] * zu[t], 0.0f);
+}
+
+// Line 3 for the w component over k data iterations (their dz_w is 0, so z_w is
+// unchanged and every one of them subtracts T_w z_w): w -= k T_w z_w.
+__global__ void w_catchup(float* __restrict__ w, const float* __restrict__ zw, int64_t n, float s) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t < n) w[t] = w[t] - s * zw[t];
+}
+
+// TGV prior term alpha0 sum |grad u - w|_2 + alpha1 sum |E w|_2 (FP64 partials) plus the
+// non-negativity indicator of u.
+__global__ void __launch_bounds__(BLOCK)
+tgv_obj(int nx, int ny, int nz, double alpha0, double alpha1, const float* __restrict__ u,
+        const float* __restrict__ w, double* __restrict__ part) {
+    const ZfStrides S = zf_strides(nx, ny, nz);
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (t < S.nv) {
+        const int64_t col = t / nz;
+        const int cz = (int)(t - col * nz);
+        const int cy = (int)(col / nx), cx = (int)(col - (int64_t)cy * nx);
+        const double uc = u[t];
+        const double g0 = (cx < nx - 1 ? (double)u[t + S.sx] - uc : 0.0) - w[t];
+        const double g1 = (cy < ny - 1 ? (double)u[t + S.sy] - uc : 0.0) - w[t + S.nv];
+        const double g2 = (cz < nz - 1 ? (double)u[t + 1] - uc : 0.0) - w[t + 2 * S.nv];
+        double J[3][3];
+        const int64_t step[3] = {S.sx, S.sy, 1};
+        const bool in[3] = {cx < nx - 1, cy < ny - 1, cz < nz - 1};
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                J[k][l] = in[l] ? (double)w[t + k * S.nv + step[l]] - (double)w[t + k * S.nv] : 0.0;
+        const double h = 0.5;  // (1/sqrt2)^2
+        const double e2 = J[0][0] * J[0][0] + J[1][1] * J[1][1] + J[2][2] * J[2][2] +
+                          h * ((J[0][1] + J[1][0]) * (J[0][1] + J[1][0]) +
+                               (J[0][2] + J[2][0]) * (J[0][2] + J[2][0]) +
+                               (J[1][2] + J[2][1]) * (J[1][2] + J[2][1]));
+        v = alpha0 * sqrt(g0 * g0 + g1 * g1 + g2 * g2) + alpha1 * sqrt(e2);
+        if (uc < 0.0) v = INFINITY;
+    }
+    const double s = block_sum<BLOCK>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Power iteration helpers for ||E||: out6 = E w, out3 = E^T q.
+__global__ void __launch_bounds__(BLOCK)
+sym_grad_apply(int nx, int ny, int nz, const float* __restrict__ w, float* __restrict__ out) {
+    const ZfStrides S = zf_strides(nx, ny, nz);
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= S.nv) return;
+    const int64_t col = t / nz;
+    const int cz = (int)(t - col * nz);
+    const int cy = (int)(col / nx), cx = (int)(col - (int64_t)cy * nx);
+    float e[6];
+    sym_grad_at(nx, ny, nz, w, cx, cy, cz, e);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[t + k * S.nv] = e[k];
+}
+
+__global__ void __launch_bounds__(BLOCK)
+sym_grad_adj(int nx, int ny, int nz, const float* __restrict__ q, float* __restrict__ out) {
+    const ZfStrides S = zf_strides(nx, ny, nz);
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= S.nv) return;
+    const int64_t col = t / nz;
+    const int cz = (int)(t - col * nz);
+    const int cy = (int)(col / nx), cx = (int)(col - (int64_t)cy * nx);
+    const int cc[3] = {cx, cy, cz};
+    const int nn[3] = {nx, ny, nz};
+    const int64_t step[3] = {S.sx, S.sy, 1};
+    const int ent[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (int k = 0; k < 3; ++k) {
+        float acc = 0.0f;
+        for (int l = 0; l < 3; ++l) {
+            const float* qe = q + ent[k][l] * S.nv;
+            float v = 0.0f;
+            if (cc[l] > 0) v += qe[t - step[l]];
+            if (cc[l] < nn[l] - 1) v -= qe[t];
+            acc = __builtin_fmaf(k == l ? 1.0f : TGV_SQRT_HALF, v, acc);
+        }
+        out[t + k * S.nv] = acc;
+    }
+}
+
+// (-1)^(k + x + y + z) over a 3-component z-fastest field.
+__global__ void checkerboard3(int nx, int ny, int nz, float* __restrict__ out) {
+    const ZfStrides S = zf_strides(nx, ny, nz);
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= 3 * S.nv) return;
+    const int k = (int)(t / S.nv);
+    const int64_t r = t - k * S.nv;
+    const int64_t col = r / nz;
+    const int cz = (int)(r - col * nz);
+    const int cy = (int)(col / nx), cx = (int)(col - (int64_t)cy * nx);
+    out[t] = ((k + cx + cy + cz) & 1) ? -1.0f : 1.0f;
 }
 
 // ---------------------------------------------------------------- small helpers

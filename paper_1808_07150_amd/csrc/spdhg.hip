@@ -392,6 +392,12 @@ struct spdhg_ctx {
     float *y = nullptr, *sigma = nullptr, *dscr = nullptr;
     float *xa = nullptr, *xb = nullptr, *z = nullptr, *T = nullptr, *scr = nullptr;
     float *yn[2] = {nullptr, nullptr}, *xi = nullptr;
+    // TGV: w (ping-pong), z_w, q2 (ping-pong); data iterations owe w the line-3 steps
+    // w -= T_w z_w, applied together before the next use of w
+    float *w[2] = {nullptr, nullptr}, *zw = nullptr, *q2[2] = {nullptr, nullptr};
+    int w_cur = 0, q2_cur = 0;
+    int64_t w_pending = 0;
+    double tw = 0.0;
     double* part = nullptr;
     double* scal = nullptr;  // 8 doubles of device scalars
     int64_t part_n = 0;
@@ -401,6 +407,7 @@ struct spdhg_ctx {
     std::vector<double> p, cum;
     std::vector<double> data_norm, data_sigma;
     double prior_norm = 0.0, prior_sigma = 0.0;
+    double prior_norm2 = 0.0, prior_sigma2 = 0.0;  // TGV block n
     int64_t k = 0;
     int64_t iters_per_epoch = 1;
     int64_t nv = 0, nb = 0, max_sub_bins = 0;
@@ -434,6 +441,17 @@ struct spdhg_ctx {
         P.alpha = (float)prm.alpha;
         P.gamma_d = (float)prm.gamma_d;
         P.dtv = prm.prior == SPDHG_PRIOR_DTV;
+        P.atv = prm.prior == SPDHG_PRIOR_ATV;
+        return P;
+    }
+    TgvArgs tgv_args(int block) const {
+        TgvArgs P{};
+        P.nx = geom.nx;
+        P.ny = geom.ny;
+        P.nz = geom.nz;
+        P.sigma = (float)(block == 0 ? prior_sigma : prior_sigma2);
+        P.alpha = (float)(block == 0 ? prm.alpha : prm.alpha1);
+        P.tw = (float)tw;
         return P;
     }
 };
@@ -441,7 +459,8 @@ struct spdhg_ctx {
 namespace {
 
 struct Layout {
-    size_t tables, bp, rp, mp, y, sigma, dscr, xa, xb, z, T, scr, yn, xi, part, scal, total;
+    size_t tables, bp, rp, mp, y, sigma, dscr, xa, xb, z, T, scr, yn, xi, w, zw, q2, part, scal,
+        total;
     int64_t part_n;
 };
 
@@ -453,7 +472,8 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
     const int m = std::max(1, p->n_subsets);
     // dual change of the largest subset (see dual_row)
     const int64_t max_sub = (int64_t)((g->n_ang + m - 1) / m) * g->n_rad * np;
-    const bool prior = p->prior == SPDHG_PRIOR_TV || p->prior == SPDHG_PRIOR_DTV;
+    const bool prior = p->prior != SPDHG_PRIOR_NONE;
+    const bool tgv = p->prior == SPDHG_PRIOR_TGV;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -474,8 +494,11 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
     L.scr = take(nv * 4);
     L.yn = take(prior ? 6 * nv * 4 : 0);
     L.xi = take(p->prior == SPDHG_PRIOR_DTV ? 3 * nv * 4 : 0);
+    L.w = take(tgv ? 6 * nv * 4 : 0);
+    L.zw = take(tgv ? 3 * nv * 4 : 0);
+    L.q2 = take(tgv ? 12 * nv * 4 : 0);
     const int64_t fwd_blocks = (int64_t)g->n_ang * g->n_rad;
-    L.part_n = std::max<int64_t>({(nb + BLOCK - 1) / BLOCK, (nv + BLOCK - 1) / BLOCK,
+    L.part_n = std::max<int64_t>({(nb + BLOCK - 1) / BLOCK, (3 * nv + BLOCK - 1) / BLOCK,
                                   fwd_blocks, 1}) * 2;
     L.part = take(L.part_n * 8);
     L.scal = take(8 * 8);
@@ -487,8 +510,10 @@ int check_params(const spdhg_geom* g, const spdhg_params* p) {
     if (!p) return fail(SPDHG_E_ARG, "params is NULL");
     if (p->n_subsets < 1 || p->n_subsets > g->n_ang)
         return fail(SPDHG_E_ARG, "n_subsets must be in [1, n_ang]");
-    if (p->prior != SPDHG_PRIOR_NONE && p->prior != SPDHG_PRIOR_TV && p->prior != SPDHG_PRIOR_DTV)
+    if (p->prior < SPDHG_PRIOR_NONE || p->prior > SPDHG_PRIOR_TGV)
         return fail(SPDHG_E_NOTIMPL, "prior not implemented");
+    if (p->prior == SPDHG_PRIOR_TGV && !(p->alpha1 >= 0))
+        return fail(SPDHG_E_ARG, "TGV weight alpha1 must be >= 0");
     if (p->sampling != SPDHG_SAMPLING_UNIFORM && p->sampling != SPDHG_SAMPLING_BALANCED)
         return fail(SPDHG_E_ARG, "unknown sampling");
     if (!(p->gamma > 0) || !(p->rho > 0) || !(p->rho < 1))
@@ -570,6 +595,46 @@ int power_norm_dgrad(spdhg_ctx* c, double* out, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(&h, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *out = std::sqrt(std::sqrt(h));
+    return SPDHG_OK;
+}
+
+// ||E|| of the TGV symmetrised gradient: 200 power iterations from a checkerboard over
+// the three components (constants are in the null space).  Uses w[0], w[1] and q2[0]
+// as scratch (before the TGV state is initialised).
+int power_norm_symgrad(spdhg_ctx* c, double* out, hipStream_t st) {
+    const int64_t nv = c->nv, n3 = 3 * nv;
+    const spdhg_geom& g = c->geom;
+    float* v = c->w[0];
+    float* w = c->w[1];
+    float* pp = c->q2[0];
+    int rc;
+    checkerboard3<<<nblocks(n3), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, v);
+    sumsq<<<nblocks(n3), BLOCK, 0, st>>>(v, n3, c->part);
+    if ((rc = reduce_to(c->part, nblocks(n3), c->scal, 0, 1.0, st))) return rc;
+    scale_by_rnorm<<<nblocks(n3), BLOCK, 0, st>>>(v, v, n3, c->scal);
+    for (int it = 0; it < 200; ++it) {
+        sym_grad_apply<<<nblocks(nv), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, v, pp);
+        sym_grad_adj<<<nblocks(nv), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, pp, w);
+        sumsq<<<nblocks(n3), BLOCK, 0, st>>>(w, n3, c->part);
+        if ((rc = reduce_to(c->part, nblocks(n3), c->scal, 0, 1.0, st))) return rc;
+        scale_by_rnorm<<<nblocks(n3), BLOCK, 0, st>>>(w, v, n3, c->scal);
+    }
+    LAUNCH_CHECK();
+    double h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&h, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = std::sqrt(std::sqrt(h));
+    return SPDHG_OK;
+}
+
+// TGV: apply the line-3 updates of w owed by the data iterations since the last use.
+int settle_w(spdhg_ctx* c, hipStream_t st) {
+    if (!c->zw || c->w_pending == 0) return SPDHG_OK;
+    const int64_t n3 = 3 * c->nv;
+    w_catchup<<<nblocks(n3), BLOCK, 0, st>>>(c->w[c->w_cur], c->zw, n3,
+                                              (float)((double)c->w_pending * c->tw));
+    LAUNCH_CHECK();
+    c->w_pending = 0;
     return SPDHG_OK;
 }
 
@@ -807,11 +872,19 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         c->yn[1] = c->yn[0] + 3 * c->nv;
     }
     c->xi = params->prior == SPDHG_PRIOR_DTV ? (float*)(w + L.xi) : nullptr;
+    const bool tgv = params->prior == SPDHG_PRIOR_TGV;
+    if (tgv) {
+        c->w[0] = (float*)(w + L.w);
+        c->w[1] = c->w[0] + 3 * c->nv;
+        c->zw = (float*)(w + L.zw);
+        c->q2[0] = (float*)(w + L.q2);
+        c->q2[1] = c->q2[0] + 6 * c->nv;
+    }
     c->part = (double*)(w + L.part);
     c->part_n = L.part_n;
     c->scal = (double*)(w + L.scal);
     c->m = params->n_subsets;
-    c->n_prior = prior ? 1 : 0;
+    c->n_prior = tgv ? 2 : (prior ? 1 : 0);
     c->n = c->m + c->n_prior;
     // probabilities (Section 4.2)
     c->p.assign(c->n, 1.0 / c->n);
@@ -906,7 +979,19 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->T, nv, (float)t_data_scalar);
     }
     double t_prior = INFINITY;
-    if (prior) {
+    if (tgv) {
+        // block n-1: ||(grad, -I)|| = sqrt(||grad||^2 + 1); block n: ||E|| (power iteration)
+        const double gn = grad_norm(geom->nx, geom->ny, geom->nz);
+        c->prior_norm = std::sqrt(gn * gn + 1.0);
+        double en = 0.0;
+        if ((rc = power_norm_symgrad(c, &en, st))) return bail(rc);
+        c->prior_norm2 = en;
+        c->prior_sigma = gam * rho / c->prior_norm;
+        c->prior_sigma2 = gam * rho / c->prior_norm2;
+        t_prior = std::min(rho * c->p[c->m] / (gam * c->prior_norm),
+                           rho * c->p[c->m + 1] / (gam * c->prior_norm2));
+        c->tw = t_prior;
+    } else if (prior) {
         if (params->prior == SPDHG_PRIOR_DTV) {
             img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
                 geom->nx, geom->ny, geom->nz, side, c->scr);
@@ -926,6 +1011,11 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     fill_f32<<<nblocks(nb), BLOCK, 0, st>>>(c->y, nb, 0.0f);
     fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->z, nv, 0.0f);
     if (prior) fill_f32<<<nblocks(6 * nv), BLOCK, 0, st>>>(c->yn[0], 6 * nv, 0.0f);
+    if (tgv) {  // w = 0, z_w = 0, q2 = 0
+        fill_f32<<<nblocks(6 * nv), BLOCK, 0, st>>>(c->w[0], 6 * nv, 0.0f);
+        fill_f32<<<nblocks(3 * nv), BLOCK, 0, st>>>(c->zw, 3 * nv, 0.0f);
+        fill_f32<<<nblocks(12 * nv), BLOCK, 0, st>>>(c->q2[0], 12 * nv, 0.0f);
+    }
     {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
@@ -1015,6 +1105,28 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             if ((rc = launch_bwd<B_ITER>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
                 return rc;
             if ((rc = prof_end(c, st))) return rc;
+            if (c->zw) c->w_pending += 1;  // line 3 for w: w -= T_w z_w (z_w unchanged)
+        } else if (c->zw) {
+            const int j = i - c->m;
+            if ((rc = settle_w(c, st))) return rc;
+            TgvArgs A = c->tgv_args(j);
+            A.inv_p = inv_p;
+            if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
+            if (j == 0) {
+                tgv1_iter<<<nblocks(nv), BLOCK, 0, st>>>(A, c->xcur(), c->xother(), c->w[c->w_cur],
+                                                         c->w[1 - c->w_cur], c->yn[c->yn_cur],
+                                                         c->yn[1 - c->yn_cur], c->z, c->zw, c->T);
+                c->yn_cur ^= 1;
+            } else {
+                tgv2_iter<<<nblocks(nv), BLOCK, 0, st>>>(A, c->xcur(), c->xother(), c->w[c->w_cur],
+                                                         c->w[1 - c->w_cur], c->q2[c->q2_cur],
+                                                         c->q2[1 - c->q2_cur], c->z, c->zw, c->T);
+                c->q2_cur ^= 1;
+            }
+            LAUNCH_CHECK();
+            if ((rc = prof_end(c, st))) return rc;
+            c->x_cur ^= 1;
+            c->w_cur ^= 1;
         } else {
             P.inv_p = inv_p;
             if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
@@ -1027,6 +1139,7 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
         }
         c->k += 1;
     }
+    if ((rc = settle_w(c, st))) return rc;
     return export_x(c, st);
 }
 
@@ -1063,8 +1176,14 @@ int spdhg_objective(spdhg_ctx* c, const float* x, double* out_dev, void* stream)
     if ((rc = launch_fwd<F_OBJ>(F, 0, 1, g.n_ang, st))) return rc;
     const int64_t nblk = (int64_t)g.n_ang * g.n_rad;
     reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblk, out_dev, 1, 1.0);
-    tv_obj<<<nblocks(nv), BLOCK, 0, st>>>(c->prior_args(), xx, c->xi, c->part,
-                                          c->prm.prior != SPDHG_PRIOR_NONE);
+    if (c->zw) {
+        if ((rc = settle_w(c, st))) return rc;
+        tgv_obj<<<nblocks(nv), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, c->prm.alpha, c->prm.alpha1, xx,
+                                               c->w[c->w_cur], c->part);
+    } else {
+        tv_obj<<<nblocks(nv), BLOCK, 0, st>>>(c->prior_args(), xx, c->xi, c->part,
+                                              c->prm.prior != SPDHG_PRIOR_NONE);
+    }
     reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), out_dev, 2, 1.0);
     combine_objective<<<1, 64, 0, st>>>(out_dev);
     LAUNCH_CHECK();
@@ -1079,6 +1198,9 @@ int spdhg_buffer(spdhg_ctx* c, int32_t which, float** ptr, int64_t* n) {
         case 2: *ptr = c->T; *n = c->nv; break;
         case 3: *ptr = c->sigma; *n = c->sigma ? c->nb : 0; break;
         case 4: *ptr = c->yn[c->yn_cur]; *n = c->yn[0] ? 3 * c->nv : 0; break;
+        case 5: *ptr = c->w[c->w_cur]; *n = c->zw ? 3 * c->nv : 0; break;
+        case 6: *ptr = c->q2[c->q2_cur]; *n = c->zw ? 6 * c->nv : 0; break;
+        case 7: *ptr = c->zw; *n = c->zw ? 3 * c->nv : 0; break;
         default: return fail(SPDHG_E_ARG, "unknown buffer id");
     }
     return SPDHG_OK;
@@ -1091,17 +1213,51 @@ int spdhg_block_info(const spdhg_ctx* c, int32_t i, double* sigma, double* p, do
     if (i < c->m) {
         if (sigma) *sigma = c->prm.precond ? NAN : c->data_sigma[i];
         if (norm) *norm = c->prm.precond ? NAN : c->data_norm[i];
-    } else {
+    } else if (i == c->m) {
         if (sigma) *sigma = c->prior_sigma;
         if (norm) *norm = c->prior_norm;
+    } else {
+        if (sigma) *sigma = c->prior_sigma2;
+        if (norm) *norm = c->prior_norm2;
     }
     return SPDHG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Arrays of a checkpoint, in order: the iterate (and, for TGV, w), z (and z_w), y, the
+// prior duals.  `cur` gives the current buffers (save), else the first ones (load).
+struct StatePart {
+    float* p;
+    int64_t n;
+};
+
+std::vector<StatePart> state_parts(spdhg_ctx* c, bool cur) {
+    std::vector<StatePart> v;
+    const int64_t nv = c->nv;
+    v.push_back({cur ? c->xcur() : c->xa, nv});
+    v.push_back({c->z, nv});
+    v.push_back({c->y, c->nb});
+    if (c->yn[0]) v.push_back({cur ? c->yn[c->yn_cur] : c->yn[0], 3 * nv});
+    if (c->zw) {
+        v.push_back({cur ? c->w[c->w_cur] : c->w[0], 3 * nv});
+        v.push_back({c->zw, 3 * nv});
+        v.push_back({cur ? c->q2[c->q2_cur] : c->q2[0], 6 * nv});
+    }
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
 int spdhg_state_bytes(const spdhg_ctx* c, size_t* bytes) {
     if (!c || !bytes) return fail(SPDHG_E_ARG, "NULL argument");
-    *bytes = align256(c->nv * 4) * 2 + align256(c->nb * 4) +
-             (c->yn[0] ? align256(3 * c->nv * 4) : 0) + 256;
+    size_t n = 256;
+    for (const StatePart& sp : state_parts(const_cast<spdhg_ctx*>(c), true)) n += align256(sp.n * 4);
+    *bytes = n;
     return SPDHG_OK;
 }
 
@@ -1111,16 +1267,11 @@ int spdhg_save_state(spdhg_ctx* c, void* dst, size_t bytes, void* stream) {
     if (rc) return rc;
     if (!dst || bytes < need) return fail(SPDHG_E_ARG, "state buffer too small");
     hipStream_t st = (hipStream_t)stream;
+    if ((rc = settle_w(c, st))) return rc;
     char* p = (char*)dst;
-    HIP_TRY(hipMemcpyAsync(p, c->xcur(), c->nv * 4, hipMemcpyDeviceToDevice, st));
-    p += align256(c->nv * 4);
-    HIP_TRY(hipMemcpyAsync(p, c->z, c->nv * 4, hipMemcpyDeviceToDevice, st));
-    p += align256(c->nv * 4);
-    HIP_TRY(hipMemcpyAsync(p, c->y, c->nb * 4, hipMemcpyDeviceToDevice, st));
-    p += align256(c->nb * 4);
-    if (c->yn[0]) {
-        HIP_TRY(hipMemcpyAsync(p, c->yn[c->yn_cur], 3 * c->nv * 4, hipMemcpyDeviceToDevice, st));
-        p += align256(3 * c->nv * 4);
+    for (const StatePart& sp : state_parts(c, true)) {
+        HIP_TRY(hipMemcpyAsync(p, sp.p, sp.n * 4, hipMemcpyDeviceToDevice, st));
+        p += align256(sp.n * 4);
     }
     // iteration counter: the random block sequence continues from it
     int64_t hdr[4] = {c->k, c->nv, c->nb, 0x5350444847ll};
@@ -1135,23 +1286,21 @@ int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) 
     if (rc) return rc;
     if (!src || bytes < need) return fail(SPDHG_E_ARG, "state buffer too small");
     hipStream_t st = (hipStream_t)stream;
-    const char* p = (const char*)src;
-    const char* h = p + align256(c->nv * 4) * 2 + align256(c->nb * 4) +
-                    (c->yn[0] ? align256(3 * c->nv * 4) : 0);
+    const std::vector<StatePart> parts = state_parts(c, false);
+    size_t off = 0;
+    for (const StatePart& sp : parts) off += align256(sp.n * 4);
     int64_t hdr[4];
-    HIP_TRY(hipMemcpyAsync(hdr, h, sizeof(hdr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hdr, (const char*)src + off, sizeof(hdr), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (hdr[1] != c->nv || hdr[2] != c->nb || hdr[3] != 0x5350444847ll)
         return fail(SPDHG_E_STATE, "state does not belong to this problem");
-    c->x_cur = 0;
-    c->yn_cur = 0;
-    HIP_TRY(hipMemcpyAsync(c->xa, p, c->nv * 4, hipMemcpyDeviceToDevice, st));
-    p += align256(c->nv * 4);
-    HIP_TRY(hipMemcpyAsync(c->z, p, c->nv * 4, hipMemcpyDeviceToDevice, st));
-    p += align256(c->nv * 4);
-    HIP_TRY(hipMemcpyAsync(c->y, p, c->nb * 4, hipMemcpyDeviceToDevice, st));
-    p += align256(c->nb * 4);
-    if (c->yn[0]) HIP_TRY(hipMemcpyAsync(c->yn[0], p, 3 * c->nv * 4, hipMemcpyDeviceToDevice, st));
+    c->x_cur = c->yn_cur = c->w_cur = c->q2_cur = 0;
+    c->w_pending = 0;
+    const char* p = (const char*)src;
+    for (const StatePart& sp : parts) {
+        HIP_TRY(hipMemcpyAsync(sp.p, p, sp.n * 4, hipMemcpyDeviceToDevice, st));
+        p += align256(sp.n * 4);
+    }
     c->k = hdr[0];
     return export_x(c, st);
 }

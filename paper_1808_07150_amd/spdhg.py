@@ -18,7 +18,7 @@ SPDHG_OK = 0
 ERRORS = {-1: "SPDHG_E_ARG", -2: "SPDHG_E_SHAPE", -3: "SPDHG_E_DOMAIN", -4: "SPDHG_E_HIP",
           -5: "SPDHG_E_WORKSPACE", -6: "SPDHG_E_STATE", -7: "SPDHG_E_NOTIMPL"}
 
-PRIOR = {"none": 0, "tv": 1, "dtv": 3}
+PRIOR = {"none": 0, "tv": 1, "atv": 2, "dtv": 3, "tgv": 4}
 SAMPLING = {"uniform": 0, "balanced": 1}
 
 EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_project", "spdhg_backproject",
@@ -51,7 +51,8 @@ class CParams(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("eta", ctypes.c_double),
                 ("gamma_d", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("rho", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("power_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("power_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("alpha1", ctypes.c_double)]
 
 
 _lib = None
@@ -121,7 +122,8 @@ def cgeom(g) -> CGeom:
 
 def cparams(n_subsets: int, prior: str = "tv", sampling: str = "uniform", precond: bool = True,
             alpha: float = 0.1, eta: float = 1e-2, gamma_d: float = 1.0, gamma: float = 1.0,
-            rho: float = 0.99, seed: int = 0, power_iters: int = 100) -> CParams:
+            rho: float = 0.99, seed: int = 0, power_iters: int = 100,
+            alpha1: float = 0.0) -> CParams:
     p = CParams()
     p.n_subsets = n_subsets
     p.prior = PRIOR[prior]
@@ -130,6 +132,7 @@ def cparams(n_subsets: int, prior: str = "tv", sampling: str = "uniform", precon
     p.alpha, p.eta, p.gamma_d, p.gamma, p.rho = alpha, eta, gamma_d, gamma, rho
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.power_iters = power_iters
+    p.alpha1 = alpha1
     return p
 
 
@@ -184,7 +187,7 @@ class Reconstruction:
     """One SPDHG reconstruction (spdhg_init ... spdhg_destroy).  The workspace is a
     torch uint8 tensor; b, r, mult, side and x are borrowed and must stay alive."""
 
-    BUFFERS = {"y": 0, "z": 1, "T": 2, "sigma": 3, "prior_dual": 4}
+    BUFFERS = {"y": 0, "z": 1, "T": 2, "sigma": 3, "prior_dual": 4, "w": 5, "q2": 6, "zw": 7}
 
     def __init__(self, g, params: CParams, b, r, mult, x, side=None, stream=None):
         lib = load_library()
@@ -229,10 +232,10 @@ class Reconstruction:
         return out
 
     def buffer(self, name: str, caller_layout: bool = True) -> Optional[torch.Tensor]:
-        """A copy of an internal array (y, z, T, sigma, prior_dual).  The library stores
-        images z-fastest [y][x][z] and sinograms [angle][radial][plane]; with
-        caller_layout the copy is returned as [z][y][x] / [angle][plane][radial]
-        (prior_dual as [3][z][y][x])."""
+        """A copy of an internal array (y, z, T, sigma, prior_dual; TGV: w, q2, zw).  The
+        library stores images z-fastest [y][x][z] and sinograms [angle][radial][plane];
+        with caller_layout the copy is returned as [z][y][x] / [angle][plane][radial]
+        (fields with c components as [c][z][y][x])."""
         p, n = ctypes.c_void_p(), ctypes.c_int64()
         _check(load_library().spdhg_buffer(self.ctx, self.BUFFERS[name], ctypes.byref(p),
                                            ctypes.byref(n)))
@@ -247,8 +250,9 @@ class Reconstruction:
         n_planes = sum(g.seg_planes)
         if name in ("y", "sigma"):
             return out.view(g.n_ang, g.n_rad, n_planes).permute(0, 2, 1).contiguous()
-        if name == "prior_dual":
-            return out.view(3, g.ny, g.nx, g.nz).permute(0, 3, 1, 2).contiguous()
+        if name in ("prior_dual", "w", "q2", "zw"):
+            c = int(n.value) // (g.nx * g.ny * g.nz)
+            return out.view(c, g.ny, g.nx, g.nz).permute(0, 3, 1, 2).contiguous()
         return out.view(g.ny, g.nx, g.nz).permute(2, 0, 1).contiguous()
 
     def block_info(self, i: int):

@@ -50,16 +50,17 @@ def tall3d():
 
 
 def run_pair(P, d, n_subsets, prior, epochs, seed, sampling="uniform", precond=True,
-             alpha=0.1, side=None, eta=1e-2):
+             alpha=0.1, side=None, eta=1e-2, alpha1=0.0):
     g = d["geom"]
     prob = S.Problem(g, d["b"], d["r"], d["mult"], n_subsets=n_subsets, prior=prior,
-                     alpha=alpha, sampling=sampling, precond=precond, side=side, eta=eta)
+                     alpha=alpha, sampling=sampling, precond=precond, side=side, eta=eta,
+                     alpha1=alpha1)
     t = {k: dev(d[k]) for k in ("b", "r", "mult")}
     x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
     sd = dev(side) if side is not None else None
     rec = P.Reconstruction(g, P.cparams(n_subsets, prior, sampling, precond, alpha=alpha,
-                                        eta=eta, seed=seed), t["b"], t["r"], t["mult"], x,
-                           side=sd)
+                                        eta=eta, seed=seed, alpha1=alpha1),
+                           t["b"], t["r"], t["mult"], x, side=sd)
     assert rec.iters_per_epoch == prob.iters_per_epoch()
     st = S.spdhg(prob, epochs * prob.iters_per_epoch(), seed=seed)
     rec.epoch(epochs)
@@ -113,6 +114,54 @@ def test_small3d_parity(P, small3d, prior, sampling, epochs):
     psi_o = prob.objective(xo[None])
     obj = rec.objective().cpu().numpy()
     assert abs(obj[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+@pytest.mark.parametrize("sampling,precond", [("balanced", True), ("uniform", False)])
+def test_small3d_tgv_parity(P, small3d, sampling, precond):
+    """TGV (two prior blocks, x = (u, w)): u, w and the objective after 12 epochs."""
+    print(f"[spdhg] small3d TGV {sampling} precond={precond}", flush=True)
+    prob, st, rec, x = run_pair(P, small3d, 6, "tgv", 12, seed=91, sampling=sampling,
+                                precond=precond, alpha=0.05, alpha1=0.025)
+    X = prob.reported(st)
+    assert rel(x.cpu().numpy(), X[0]) <= 1e-3
+    w = rec.buffer("w").cpu().numpy()
+    assert rel(w, X[1:4]) <= 2e-3
+    psi_o = prob.objective(X)
+    assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
+    # step scalars of both prior blocks (||(grad, -I)|| closed form, ||E|| by power iteration)
+    for j in range(2):
+        s, p, nrm = rec.block_info(6 + j)
+        assert p == prob.p[6 + j]
+        assert nrm == pytest.approx(prob.norms[6 + j], rel=1e-5)
+        assert s == pytest.approx(prob.prior_sigma[j], rel=1e-5)
+
+
+def test_small3d_atv_parity(P, small3d):
+    print("[spdhg] small3d aTV uniform", flush=True)
+    prob, st, rec, x = run_pair(P, small3d, 6, "atv", 12, seed=13, alpha=0.05)
+    xo = prob.reported(st)[0]
+    assert rel(x.cpu().numpy(), xo) <= 1e-3
+    psi_o = prob.objective(xo[None])
+    assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+def test_tgv_checkpoint_bitwise(P, small3d):
+    """Save after 3 epochs, run 2 more; restore and rerun: identical u and w."""
+    g = small3d["geom"]
+    t = {k: dev(small3d[k]) for k in ("b", "r", "mult")}
+    prm = P.cparams(6, "tgv", "balanced", alpha=0.05, alpha1=0.025, seed=5)
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+    rec.epoch(3)
+    snap = rec.save_state()
+    rec.epoch(2)
+    torch.cuda.synchronize()
+    a, wa = x.cpu().numpy(), rec.buffer("w").cpu().numpy()
+    rec.load_state(snap)
+    rec.epoch(2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(x.cpu().numpy(), a)
+    np.testing.assert_array_equal(rec.buffer("w").cpu().numpy(), wa)
 
 
 @pytest.mark.parametrize("sampling,precond,m", [("balanced", True, 8), ("uniform", False, 3)])
