@@ -164,6 +164,18 @@ int spdhg_info(const spdhg_ctx* ctx, int64_t* iters_per_epoch, int64_t* iters_do
  * is device memory for 4 doubles.  Deterministic (fixed reduction order). */
 int spdhg_objective(spdhg_ctx* ctx, const float* x, double* out_dev, void* stream);
 
+/* Duality gap of the current state (x, y) for the problem with g = indicator of [0, U]
+ * (U above the largest value of a minimiser, so both problems share it; with g = the
+ * non-negativity indicator alone, g* of -A^T y is infinite at almost every iterate):
+ *   gap = Psi(x) + sum_i f_i*(y_i) + U sum_v max(0, -(A^T y)_v)
+ * (Problem "Generic Saddle Point Problem", Theorem "Convergence"; f_i* of the data blocks
+ * is eq. PET:CVX, of the prior blocks the indicator of the dual ball).  Rows with
+ * (A 1)_j = 0 are left out of Psi (they are constants).  A^T y is the iterate's z, which
+ * Algorithm 2 maintains.  out_dev (device, 4 doubles) = [gap, Psi over the rows reached,
+ * sum f_i*(y_i) (+inf for an infeasible prior dual), U-term].  Not defined for TGV
+ * (SPDHG_E_NOTIMPL).  Asynchronous on `stream`. */
+int spdhg_gap(spdhg_ctx* ctx, double U, double* out_dev, void* stream);
+
 /* Device pointers of internal arrays (for inspection and checkpoints):
  *   0 y (full sinogram)   1 z (image)   2 T (image)   3 sigma (full sinogram, or NULL
  *   with scalar steps)   4 prior dual (3 images, current buffer; TGV: q1)

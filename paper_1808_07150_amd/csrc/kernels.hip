@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 
 // ---------------------------------------------------------------- strip gather backprojection
 // One wavefront per strip of BS_W voxel columns that lie along the secondary axis at one
-// primary index j, for the angles of one sampling class (rows or columns), nz <= 128
+// primary index j, for the angles of one sampling class (rows or columns), nz <= 127
 // (lane holds z = lane and z = lane + 64 of every strip column).  Per angle:
 //   1. the radial bins of the rays touching the strip (consecutive, at most KR), each
 //      ray's in-plane cell / fraction and per segment its tap coefficients (FP64, the
@@ -501,7 +501,9 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 #define BS_W 16
 
 template <int MODE>
-__global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
+// Eight waves per SIMD (at most 64 VGPRs, a few spilled): the mMR launch of 7568 strips
+// then runs in one round on 256 compute units.
+__global__ void __launch_bounds__(64, 8) bwd_strip(BwdArgs P, int KR, int rowdom,
                                                 const float* __restrict__ partial) {
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
@@ -515,10 +517,17 @@ __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
 
     const int lane = threadIdx.x;
     const int n_sec = rowdom ? G.nx : G.ny;
-    const int nstrip = (n_sec + BS_W - 1) / BS_W;
+    const int n_prim = rowdom ? G.ny : G.nx;
+    // consecutive blocks (one XCD's share) walk along the primary axis at one strip
+    // position: neighbouring strips read nearly the same rays
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int j = blk / nstrip;
-    const int s0 = (blk - j * nstrip) * BS_W;
+    const int sidx = blk / n_prim;
+    const int j = blk - sidx * n_prim;
+    const int s0 = sidx * BS_W;
+    // lane + 64 through a register copy the compiler cannot fold into an immediate
+    // buffer offset (the hardware range check must see the whole offset)
+    int lane_hi;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_hi) : "v"(lane + 64));
     float acc[BS_W][2];
 #pragma unroll
     for (int c = 0; c < BS_W; ++c) acc[c][0] = acc[c][1] = 0.0f;
@@ -569,12 +578,35 @@ __global__ void __launch_bounds__(64) bwd_strip(BwdArgs P, int KR, int rowdom,
                 const float* dk = P.d + dual_row(G, ia, klo + kr);
                 const TapCoef* tk = tc + kr * ns;
                 float h0 = 0.0f, h1 = 0.0f;
-#pragma unroll 2
-                for (int g = 0; g < ns; ++g) {
+                // segments in pairs: all eight loads of a pair are issued before its taps
+                // are summed
+                int g = 0;
+                for (; g + 2 <= ns; g += 2) {
+                    float v[2][4];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const TapCoef t = tk[g + u];
+                        const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g + u);
+                        const int va = (lane + t.off) * 4, vb = (lane_hi + t.off) * 4;
+                        v[u][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, va, 0, 0));
+                        v[u][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, va - 4, 0, 0));
+                        v[u][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vb, 0, 0));
+                        v[u][3] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vb - 4, 0, 0));
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const TapCoef t = tk[g + u];
+                        h0 = __builtin_fmaf(t.wa, v[u][0], h0);
+                        h0 = __builtin_fmaf(t.wb, v[u][1], h0);
+                        h1 = __builtin_fmaf(t.wa, v[u][2], h1);
+                        h1 = __builtin_fmaf(t.wb, v[u][3], h1);
+                    }
+                }
+                for (; g < ns; ++g) {
                     const TapCoef t = tk[g];
                     const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g);
                     h0 = tap_sum_rsrc(rs, t, lane, h0);
-                    h1 = tap_sum_rsrc(rs, t, lane + 64, h1);
+                    h1 = tap_sum_rsrc(rs, t, lane_hi, h1);
                 }
                 if (c >= 0) {
                     acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
@@ -1170,6 +1202,11 @@ __global__ void checkerboard3(int nx, int ny, int nz, float* __restrict__ out) {
 }
 
 // ---------------------------------------------------------------- small helpers
+__global__ void fill_f64(double* __restrict__ a, int64_t n, double v) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
 __global__ void fill_f32(float* __restrict__ a, int64_t n, float v) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (t < n) a[t] = v;
@@ -1209,6 +1246,75 @@ domain_check(const float* __restrict__ b, const float* __restrict__ r,
     if (threadIdx.x == 0) {
         part[blockIdx.x] = s0;
         part[nblocks + blockIdx.x] = s1;
+    }
+}
+
+// Sum of phi_j(0) over the bins no voxel reaches ((A 1)_j = 0, given in a1): a constant
+// of the objective that the duality gap leaves out (those rows are masked).
+__global__ void __launch_bounds__(BLOCK)
+masked_phi0(const float* __restrict__ b, const float* __restrict__ r,
+            const float* __restrict__ a1, int64_t n, double* __restrict__ part) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (t < n && !(a1[t] > 0.0f)) v = phi64(0.0, (double)b[t], (double)r[t]);
+    const double s = block_sum<BLOCK>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Duality-gap pieces (FP64 partials): phi*(y_j) = -y r - b log(1 - y) (y <= 1; +inf
+// beyond the domain) over the bins (eq. PET:CVX), and U max(0, -z_v) over the voxels.
+__global__ void __launch_bounds__(BLOCK)
+gap_dual(const float* __restrict__ y, const float* __restrict__ b, const float* __restrict__ r,
+         int64_t n, double* __restrict__ part) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (t < n) {
+        const double yy = y[t], bb = b[t], rr = r[t];
+        const double om = 1.0 - yy;
+        if (yy > 1.0 || (bb > 0.0 && om <= 0.0))
+            v = INFINITY;
+        else
+            v = -yy * rr - (bb > 0.0 ? bb * log(om) : 0.0);
+    }
+    const double s = block_sum<BLOCK>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+gap_box(const float* __restrict__ z, int64_t n, double U, double* __restrict__ part) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (t < n) v = U * fmax(0.0, -(double)z[t]);
+    const double s = block_sum<BLOCK>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Prior dual feasibility (the conjugate of alpha ||.|| is the indicator of its dual
+// ball): +inf for a voxel outside the ball by more than FP32 rounding of the projection.
+__global__ void __launch_bounds__(BLOCK)
+gap_prior(const float* __restrict__ q, int64_t nv, double alpha, int atv, double* __restrict__ part) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double v = 0.0;
+    if (t < nv) {
+        const double q0 = q[t], q1 = q[t + nv], q2 = q[t + 2 * nv];
+        const double lim = alpha * (1.0 + 1e-6);
+        const bool out = atv ? (fabs(q0) > lim || fabs(q1) > lim || fabs(q2) > lim)
+                             : sqrt(q0 * q0 + q1 * q1 + q2 * q2) > lim;
+        if (out) v = INFINITY;
+    }
+    const double s = block_sum<BLOCK>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out = [gap, primal, dual, box] from the objective psi = obj[0], the masked constant,
+// the dual sum, the prior feasibility term and the box term.
+__global__ void combine_gap(double* out, const double* obj, double c_mask, const double* dual,
+                            const double* feas, const double* box) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out[1] = obj[0] - c_mask;
+        out[2] = dual[0] + feas[0];
+        out[3] = box[0];
+        out[0] = out[1] + out[2] + out[3];
     }
 }
 

@@ -281,16 +281,20 @@ int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
         case 4: fwd_wave<4, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
         case 8: fwd_wave<8, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
         case 16: fwd_wave<16, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
-        case 32: fwd_wave<32, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
-        case 64: fwd_wave<64, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 32:
+            if constexpr (NW <= 4) fwd_wave<32, MODE, NW><<<nblk, nt, lds, st>>>(A);
+            break;
+        case 64:
+            if constexpr (NW <= 4) fwd_wave<64, MODE, NW><<<nblk, nt, lds, st>>>(A);
+            break;
         default: return fail(SPDHG_E_SHAPE, "unsupported plane count");
     }
     LAUNCH_CHECK();
     return SPDHG_OK;
 }
 
-// One block per (angle of the list, radial bin); launches with few blocks (fewer than 64
-// per compute unit) split every ray walk over two wavefronts.
+// One block per (angle of the list, radial bin); launches with few blocks split every ray
+// walk over 2, 4 or 8 wavefronts (a single angle has only n_rad ray bundles).
 template <int MODE>
 int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     A.ang0 = ang0;
@@ -300,13 +304,15 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     if (nblk == 0) return SPDHG_OK;
     if (nblk > INT32_MAX) return fail(SPDHG_E_SHAPE, "too many rays");
     const int rpl = rays_per_lane(A.G.n_planes);
+    if (nblk < 4 * 256 && rpl <= 16) return launch_fwd_nw<MODE, 8>(rpl, A, (int)nblk, st);
+    if (nblk < 16 * 256) return launch_fwd_nw<MODE, 4>(rpl, A, (int)nblk, st);
     if (nblk < 64 * 256) return launch_fwd_nw<MODE, 2>(rpl, A, (int)nblk, st);
     return launch_fwd_nw<MODE, 1>(rpl, A, (int)nblk, st);
 }
 
 int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }
 
-// Backprojection kernel choice: the strip gather for 32 <= nz <= 128; else the per-column
+// Backprojection kernel choice: the strip gather for 32 <= nz <= 127; else the per-column
 // gather.  The rays a strip considers per angle span BS_W + 1 in the secondary coordinate
 // plus one radial bin of margin on each side, so at most (BS_W + 1) / min|du_dk| + 5.
 struct BwdPlan {
@@ -320,7 +326,7 @@ BwdPlan bwd_plan(const HostTables& T) {
     const int nz = T.G.nz, ns = T.G.n_seg;
     double min_du = 1e30;
     for (const AngleDev& A : T.ang) min_du = std::min(min_du, std::fabs(A.du_dk));
-    if (nz < 32 || nz > 128 || !(min_du >= 0.5)) return pl;
+    if (nz < 32 || nz > 127 || !(min_du >= 0.5)) return pl;
     const int KR = (int)std::ceil((BS_W + 1) / min_du) + 6;
     const size_t floats = 2 * (size_t)KR + 2 * (BS_W + 1) + (sizeof(TapCoef) / 4) * (size_t)KR * ns;
     pl.strip = true;
@@ -408,6 +414,7 @@ struct spdhg_ctx {
     std::vector<double> data_norm, data_sigma;
     double prior_norm = 0.0, prior_sigma = 0.0;
     double prior_norm2 = 0.0, prior_sigma2 = 0.0;  // TGV block n
+    double masked_phi0 = 0.0;  // sum of phi_j(0) over the bins with (A 1)_j = 0
     int64_t k = 0;
     int64_t iters_per_epoch = 1;
     int64_t nv = 0, nb = 0, max_sub_bins = 0;
@@ -939,6 +946,12 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         if (h[1] > 0)
             return bail(fail(SPDHG_E_DOMAIN, std::to_string((long long)h[1]) +
                                                  " bins have b > 0, r = 0 and no voxel on the ray"));
+        masked_phi0<<<nbk, BLOCK, 0, st>>>(c->bp, c->rp, c->y, nb, c->part);
+        reduce_final<<<1, BLOCK, 0, st>>>(c->part, nbk, c->scal, 0, 1.0);
+        e = hipMemcpyAsync(h, c->scal, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
+        c->masked_phi0 = h[0];
     }
     // the image: caller layout -> z-fastest, line 3 with z = 0: x = max(x0, 0)
     img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(geom->nx, geom->ny,
@@ -1035,6 +1048,47 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     *out = c;
     return SPDHG_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// FP64 objective of x (NULL: the current iterate) into out[0..3] = [psi, data, prior, 0].
+int objective_into(spdhg_ctx* c, const float* x, double* out_dev, hipStream_t st) {
+    const spdhg_geom& g = c->geom;
+    const float* xx = c->xcur();
+    if (x) {
+        img_to_zf<<<img_grid(g.nx, g.ny, g.nz), TT * 8, 0, st>>>(g.nx, g.ny, g.nz, x, c->scr);
+        xx = c->scr;
+    }
+    const int64_t nv = c->nv;
+    FwdArgs F = c->fwd_args();
+    F.x = xx;
+    F.mult = c->mp;
+    F.b = c->bp;
+    F.r = c->rp;
+    F.part = c->part;
+    int rc;
+    if ((rc = launch_fwd<F_OBJ>(F, 0, 1, g.n_ang, st))) return rc;
+    const int64_t nblk = (int64_t)g.n_ang * g.n_rad;
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblk, out_dev, 1, 1.0);
+    if (c->zw) {
+        if ((rc = settle_w(c, st))) return rc;
+        tgv_obj<<<nblocks(nv), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, c->prm.alpha, c->prm.alpha1, xx,
+                                               c->w[c->w_cur], c->part);
+    } else {
+        tv_obj<<<nblocks(nv), BLOCK, 0, st>>>(c->prior_args(), xx, c->xi, c->part,
+                                              c->prm.prior != SPDHG_PRIOR_NONE);
+    }
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), out_dev, 2, 1.0);
+    combine_objective<<<1, 64, 0, st>>>(out_dev);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int spdhg_set_profiling(spdhg_ctx* c, int32_t on) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
@@ -1158,34 +1212,30 @@ int spdhg_info(const spdhg_ctx* c, int64_t* ipe, int64_t* done) {
 
 int spdhg_objective(spdhg_ctx* c, const float* x, double* out_dev, void* stream) {
     if (!c || !out_dev) return fail(SPDHG_E_ARG, "NULL ctx or output");
+    return objective_into(c, x, out_dev, (hipStream_t)stream);
+}
+
+int spdhg_gap(spdhg_ctx* c, double U, double* out_dev, void* stream) {
+    if (!c || !out_dev) return fail(SPDHG_E_ARG, "NULL ctx or output");
+    if (c->zw) return fail(SPDHG_E_NOTIMPL, "the duality gap is infinite for TGV (w has no bound)");
+    if (!(U > 0)) return fail(SPDHG_E_ARG, "U must be > 0");
     hipStream_t st = (hipStream_t)stream;
-    const spdhg_geom& g = c->geom;
-    const float* xx = c->xcur();
-    if (x) {
-        img_to_zf<<<img_grid(g.nx, g.ny, g.nz), TT * 8, 0, st>>>(g.nx, g.ny, g.nz, x, c->scr);
-        xx = c->scr;
-    }
-    const int64_t nv = c->nv;
-    FwdArgs F = c->fwd_args();
-    F.x = xx;
-    F.mult = c->mp;
-    F.b = c->bp;
-    F.r = c->rp;
-    F.part = c->part;
     int rc;
-    if ((rc = launch_fwd<F_OBJ>(F, 0, 1, g.n_ang, st))) return rc;
-    const int64_t nblk = (int64_t)g.n_ang * g.n_rad;
-    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblk, out_dev, 1, 1.0);
-    if (c->zw) {
-        if ((rc = settle_w(c, st))) return rc;
-        tgv_obj<<<nblocks(nv), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, c->prm.alpha, c->prm.alpha1, xx,
-                                               c->w[c->w_cur], c->part);
+    double* obj = c->scal + 4;  // [psi, data, prior, -]
+    if ((rc = objective_into(c, nullptr, obj, st))) return rc;
+    const int64_t nb = c->nb, nv = c->nv;
+    gap_dual<<<nblocks(nb), BLOCK, 0, st>>>(c->y, c->bp, c->rp, nb, c->part);
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nb), c->scal, 0, 1.0);
+    gap_box<<<nblocks(nv), BLOCK, 0, st>>>(c->z, nv, U, c->part);
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), c->scal, 1, 1.0);
+    if (c->yn[0]) {
+        gap_prior<<<nblocks(nv), BLOCK, 0, st>>>(c->yn[c->yn_cur], nv, c->prm.alpha,
+                                                 c->prm.prior == SPDHG_PRIOR_ATV, c->part);
+        reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), c->scal, 2, 1.0);
     } else {
-        tv_obj<<<nblocks(nv), BLOCK, 0, st>>>(c->prior_args(), xx, c->xi, c->part,
-                                              c->prm.prior != SPDHG_PRIOR_NONE);
+        fill_f64<<<1, 64, 0, st>>>(c->scal + 2, 1, 0.0);
     }
-    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), out_dev, 2, 1.0);
-    combine_objective<<<1, 64, 0, st>>>(out_dev);
+    combine_gap<<<1, 64, 0, st>>>(out_dev, obj, c->masked_phi0, c->scal, c->scal + 2, c->scal + 1);
     LAUNCH_CHECK();
     return SPDHG_OK;
 }

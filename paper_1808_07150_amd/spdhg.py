@@ -24,7 +24,7 @@ SAMPLING = {"uniform": 0, "balanced": 1}
 EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_project", "spdhg_backproject",
             "spdhg_nnz",
             "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_info",
-            "spdhg_objective", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
+            "spdhg_objective", "spdhg_gap", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
             "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
             "spdhg_destroy"]
 PROF_KINDS = ("fwd", "bwd", "prior")
@@ -85,6 +85,7 @@ def load_library() -> ctypes.CDLL:
     lib.spdhg_epoch.argtypes = [vp, i32, vp]
     lib.spdhg_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.spdhg_objective.argtypes = [vp, vp, vp, vp]
+    lib.spdhg_gap.argtypes = [vp, ctypes.c_double, vp, vp]
     lib.spdhg_buffer.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
     lib.spdhg_block_info.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double),
@@ -229,6 +230,14 @@ class Reconstruction:
             out = torch.empty(4, dtype=torch.float64, device=self.x.device)
         _check(load_library().spdhg_objective(self.ctx, _ptr(x), _ptr(out, torch.float64),
                                               _stream(stream)))
+        return out
+
+    def gap(self, U: float, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """[gap, primal, dual, box term] of the current state for g = indicator of [0, U]."""
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=self.x.device)
+        _check(load_library().spdhg_gap(self.ctx, float(U), _ptr(out, torch.float64),
+                                        _stream(stream)))
         return out
 
     def buffer(self, name: str, caller_layout: bool = True) -> Optional[torch.Tensor]:

@@ -86,6 +86,22 @@ def test_config1_tv_parity(P, c1, sampling, precond, epochs):
     assert abs(obj2[0] - psi_o) <= 1e-5 * abs(psi_o)
 
 
+@pytest.mark.parametrize("prior", ["tv", "atv", "none"])
+def test_config1_duality_gap(P, c1, prior):
+    """GPU duality gap (box U) against the oracle's on the same state after 20 epochs."""
+    print(f"[spdhg] config1 gap {prior}", flush=True)
+    prob, st, rec, x = run_pair(P, c1, 10, prior, 20, seed=4, sampling="balanced")
+    X = prob.reported(st)
+    U = 2.0 * float(X[0].max())
+    ref = S.duality_gap(prob, X, st, U)
+    out = rec.gap(U).cpu().numpy()
+    psi = prob.objective(X)
+    assert np.isfinite(out[0]) and np.isfinite(ref)
+    # pieces: primal (masked objective), dual sum, box term
+    assert abs(out[0] - ref) <= 1e-4 * abs(psi)
+    assert out[0] >= -1e-4 * abs(psi)
+
+
 def test_config1_step_sizes(P, c1):
     prob, _, rec, _ = run_pair(P, c1, 10, "tv", 0, seed=1, sampling="balanced")
     T = rec.buffer("T").cpu().numpy().reshape(c1["geom"].image_shape)
