@@ -175,69 +175,82 @@ __global__ void __launch_bounds__(64 * NW) fwd_wave(FwdArgs P) {
         j1 = j0 + (n * (w + 1)) / NW;
         j0 = j0 + (n * w) / NW;
     }
-    // The workgroup is one wavefront: its LDS accesses execute in order, so a code-motion
-    // barrier is enough between writing and reading the axial column.  The image values
-    // of step j + 1 are loaded before the rays consume step j (latency hiding).
-    constexpr int NZL = 4;  // z values per lane (nz <= 256)
-    float v0[NZL], v1[NZL];
-    Sample s = split(sec_coord(A, kk, (double)j0 - A.cj));
-    auto load_step = [&](int j, const Sample& sm) {
-        const bool ok0 = (unsigned)sm.i0 < (unsigned)A.n_sec;
-        const bool ok1 = (unsigned)(sm.i0 + 1) < (unsigned)A.n_sec;
-        const int i0c = ok0 ? sm.i0 : 0;
-        const int i1c = ok1 ? sm.i0 + 1 : 0;
-        const float* c0 = P.x + ((int64_t)j * s_prim + (int64_t)i0c * s_sec) * nz;
-        const float* c1 = P.x + ((int64_t)j * s_prim + (int64_t)i1c * s_sec) * nz;
+    // Each wavefront has its own LDS buffers and executes its LDS accesses in order, so a
+    // code-motion barrier is enough between writing and reading the axial column.  The
+    // image columns of steps j + 1 .. j + FD are in flight while the rays consume step j
+    // (loads through a range-checked buffer resource: an offset of 1 GiB or more reads
+    // zero, which covers samples outside the image and z beyond nz without branches).
+    // Deeper prefetch (FD > 1) costs more registers than it hides latency on gfx950.
+    constexpr int NZL = 2;  // z values per lane (nz <= 128)
+    constexpr int FD = 1;   // prefetch depth in steps
+    constexpr int OUT = 1 << 30;
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)P.x, (short)0, (int)(P.G.nx * (int64_t)P.G.ny * nz * 4), 0x00020000);
+    int zoff[NZL];
+#pragma unroll
+    for (int u = 0; u < NZL; ++u) zoff[u] = lane + 64 * u < nz ? (lane + 64 * u) * 4 : OUT;
+    float v0[FD][NZL], v1[FD][NZL];
+    Sample sm[FD];
+    auto issue = [&](int slot, int j) {
+        const Sample q = split(sec_coord(A, kk, (double)j - A.cj));
+        sm[slot] = q;
+        if (MODE == F_SENS) return;
+        const bool ok0 = (unsigned)q.i0 < (unsigned)A.n_sec;
+        const bool ok1 = (unsigned)(q.i0 + 1) < (unsigned)A.n_sec;
+        const int c0 = ok0 ? (int)(((int64_t)j * s_prim + (int64_t)q.i0 * s_sec) * nz * 4) : OUT;
+        const int c1 = ok1 ? (int)(((int64_t)j * s_prim + (int64_t)(q.i0 + 1) * s_sec) * nz * 4) : OUT;
 #pragma unroll
         for (int u = 0; u < NZL; ++u) {
-            const int iz = lane + 64 * u;
-            v0[u] = (ok0 && iz < nz) ? c0[iz] : 0.0f;
-            v1[u] = (ok1 && iz < nz) ? c1[iz] : 0.0f;
+            v0[slot][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c0 + zoff[u], 0, 0));
+            v1[slot][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c1 + zoff[u], 0, 0));
         }
     };
-    if (MODE != F_SENS && j0 < j1) load_step(j0, s);
-    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int f = 0; f < FD; ++f)
+        if (j0 + f < j1) issue(f, j0 + f);
     int buf = 0;
-    for (int j = j0; j < j1; ++j) {
-        const double jj = (double)j - A.cj;
-        float* Gc = Gb + buf * P.gsize + P.pad;
-        const float w0 = 1.0f - s.fu, w1 = s.fu;
-        if (MODE == F_SENS) {
-            const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
-            const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
-            const float v = (ok0 ? w0 : 0.0f) + (ok1 ? w1 : 0.0f);
-            for (int iz = lane; iz < nz; iz += 64) Gc[iz] = v;
-        } else {
+    for (int jb = j0; jb < j1; jb += FD) {
 #pragma unroll
-            for (int u = 0; u < NZL; ++u) {
-                const int iz = lane + 64 * u;
-                if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[u], w0 * v0[u]);
-            }
-        }
-        if (lane < ns) {
-            const Sample sz = split(ax_offset(G.sa[a * ns + lane], kk, jj));
-            segc[buf * ns + lane] = sz.i0;
-            segf[buf * ns + lane] = sz.fu;
-        }
-        // next step's in-plane sample and image values
-        if (j + 1 < j1) {
-            s = split(sec_coord(A, kk, jj + 1.0));
-            if (MODE != F_SENS) load_step(j + 1, s);
-        }
-        __builtin_amdgcn_wave_barrier();
-        const float* Gr = Gb + buf * P.gsize;
+        for (int f = 0; f < FD; ++f) {
+            const int j = jb + f;
+            if (j >= j1) break;
+            const double jj = (double)j - A.cj;
+            float* Gc = Gb + buf * P.gsize + P.pad;
+            const Sample s = sm[f];
+            const float w0 = 1.0f - s.fu, w1 = s.fu;
+            if (MODE == F_SENS) {
+                const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
+                const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
+                const float v = (ok0 ? w0 : 0.0f) + (ok1 ? w1 : 0.0f);
+                for (int iz = lane; iz < nz; iz += 64) Gc[iz] = v;
+            } else {
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            if (lane + 64 * r < G.n_planes) {
-                const int g = pinfo[r] & 63;
-                const int idx = (pinfo[r] >> 6) + segc[buf * ns + g];
-                const float fz = segf[buf * ns + g];
-                acc[r] = __builtin_fmaf(1.0f - fz, Gr[idx], acc[r]);
-                acc[r] = __builtin_fmaf(fz, Gr[idx + 1], acc[r]);
+                for (int u = 0; u < NZL; ++u) {
+                    const int iz = lane + 64 * u;
+                    if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[f][u], w0 * v0[f][u]);
+                }
             }
+            if (lane < ns) {
+                const Sample sz = split(ax_offset(G.sa[a * ns + lane], kk, jj));
+                segc[buf * ns + lane] = sz.i0;
+                segf[buf * ns + lane] = sz.fu;
+            }
+            if (j + FD < j1) issue(f, j + FD);
+            __builtin_amdgcn_wave_barrier();
+            const float* Gr = Gb + buf * P.gsize;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                if (lane + 64 * r < G.n_planes) {
+                    const int g = pinfo[r] & 63;
+                    const int idx = (pinfo[r] >> 6) + segc[buf * ns + g];
+                    const float fz = segf[buf * ns + g];
+                    acc[r] = __builtin_fmaf(1.0f - fz, Gr[idx], acc[r]);
+                    acc[r] = __builtin_fmaf(fz, Gr[idx + 1], acc[r]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            buf ^= 1;
         }
-        __builtin_amdgcn_wave_barrier();
-        buf ^= 1;
     }
     if (NW > 1) {
         if (w > 0) {
@@ -246,7 +259,7 @@ __global__ void __launch_bounds__(64 * NW) fwd_wave(FwdArgs P) {
         }
         __syncthreads();
         if (w > 0) return;
-#pragma unroll
+#pragma unroll 1
         for (int v = 1; v < NW; ++v) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) acc[r] += red[((v - 1) * RPL + r) * 64 + lane];

@@ -261,7 +261,10 @@ int rays_per_lane(int n_planes) {
 int check_kernel_limits(const spdhg_geom* g) {
     if (rays_per_lane((int)n_planes(g)) < 0)
         return fail(SPDHG_E_SHAPE, "more than 4096 sinogram planes");
-    if (g->nz > 256) return fail(SPDHG_E_SHAPE, "nz above 256");
+    if (g->nz > 128) return fail(SPDHG_E_SHAPE, "nz above 128");
+    // the forward walk addresses the image through 32-bit byte offsets below 1 GiB
+    if ((int64_t)g->nx * g->ny * g->nz * 4 >= (int64_t(1) << 30))
+        return fail(SPDHG_E_SHAPE, "image of 1 GiB or more");
     // the gather keeps at most 4 candidate radial bins per voxel column and angle: the
     // radial spacing must be at least half the in-plane voxel size
     if (g->d_rad < 0.5 * std::max(g->vx, g->vy))
