@@ -830,37 +830,72 @@ __device__ __forceinline__ void prior_dual_at(const PriorArgs& P, const float* _
     }
 }
 
+// Column tiles of the prior kernels: a workgroup holds TX x TY voxel columns of nz
+// threads each (z fastest), at most 1024 threads.  Every thread computes its own dual
+// update and leaves the change in LDS, where the x-, y- and z-neighbours inside the tile
+// read it; only the tile's low faces recompute a neighbour's update.
+struct PriorTile {
+    int tx, ty;  // columns per tile along x and y
+};
+
+__device__ __forceinline__ bool tile_voxel(const PriorTile& TL, int nx, int ny, int nz, int bid,
+                                           int& cx, int& cy, int& cz, int& lx, int& ly) {
+    const int ntx = (nx + TL.tx - 1) / TL.tx;
+    const int by = bid / ntx, bx = bid - by * ntx;
+    const int l = threadIdx.x;
+    const int col = l / nz;
+    cz = l - col * nz;
+    ly = col / TL.tx;
+    lx = col - ly * TL.tx;
+    cx = bx * TL.tx + lx;
+    cy = by * TL.ty + ly;
+    return ly < TL.ty && cx < nx && cy < ny;
+}
+
 // Algorithm 2 lines 5-8 for the prior block, fused with line 3 of the next iteration.
-// The dual changes of the three backward neighbours are recomputed locally (they enter
-// grad^T at this voxel), so x and y are read from one buffer and written to the other.
-__global__ void __launch_bounds__(BLOCK)
-tv_iter(PriorArgs P, const float* __restrict__ x_in, float* __restrict__ x_out,
+// x and y are read from one buffer and written to the other (a recomputing neighbour
+// reads the old values).
+__global__ void __launch_bounds__(1024)
+tv_iter(PriorArgs P, PriorTile TL, const float* __restrict__ x_in, float* __restrict__ x_out,
         const float* __restrict__ y_in, float* __restrict__ y_out, float* __restrict__ z,
         const float* __restrict__ T, const float* __restrict__ xi) {
+    __shared__ float sdq[3][1024];
     const int64_t nv = (int64_t)P.nx * P.ny * P.nz;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t >= nv) return;
-    int cx, cy, cz;
-    zf_coords(P, t, cx, cy, cz);
-    float q[3], dy[3], qn[3], dn[3];
-    prior_dual_at(P, x_in, y_in, xi, cx, cy, cz, q, dy);
+    int cx, cy, cz, lx, ly;
+    const bool act = tile_voxel(TL, P.nx, P.ny, P.nz, xcd_remap(blockIdx.x, gridDim.x), cx, cy,
+                                cz, lx, ly);
+    const int l = threadIdx.x;
+    float q[3], dy[3] = {0.0f, 0.0f, 0.0f};
+    if (act) prior_dual_at(P, x_in, y_in, xi, cx, cy, cz, q, dy);
+    sdq[0][l] = dy[0];
+    sdq[1][l] = dy[1];
+    sdq[2][l] = dy[2];
+    __syncthreads();
+    if (!act) return;
     // grad^T p (v) = sum_d [v_d > 0] p_d(v - e_d) - [v_d < N_d - 1] p_d(v)
     float dz = 0.0f;
     if (cx < P.nx - 1) dz -= dy[0];
     if (cy < P.ny - 1) dz -= dy[1];
     if (cz < P.nz - 1) dz -= dy[2];
+    float qn[3], dn[3];
     if (cx > 0) {
-        prior_dual_at(P, x_in, y_in, xi, cx - 1, cy, cz, qn, dn);
-        dz += dn[0];
+        if (lx > 0) {
+            dz += sdq[0][l - P.nz];
+        } else {
+            prior_dual_at(P, x_in, y_in, xi, cx - 1, cy, cz, qn, dn);
+            dz += dn[0];
+        }
     }
     if (cy > 0) {
-        prior_dual_at(P, x_in, y_in, xi, cx, cy - 1, cz, qn, dn);
-        dz += dn[1];
+        if (ly > 0) {
+            dz += sdq[1][l - TL.tx * P.nz];
+        } else {
+            prior_dual_at(P, x_in, y_in, xi, cx, cy - 1, cz, qn, dn);
+            dz += dn[1];
+        }
     }
-    if (cz > 0) {
-        prior_dual_at(P, x_in, y_in, xi, cx, cy, cz - 1, qn, dn);
-        dz += dn[2];
-    }
+    if (cz > 0) dz += sdq[2][l - 1];
+    const int64_t t = ((int64_t)cy * P.nx + cx) * P.nz + cz;
     y_out[t] = q[0];
     y_out[t + nv] = q[1];
     y_out[t + 2 * nv] = q[2];
@@ -986,7 +1021,7 @@ tgv1_iter(TgvArgs P, const float* __restrict__ u_in, float* __restrict__ u_out,
           const float* __restrict__ q_in, float* __restrict__ q_out, float* __restrict__ zu,
           float* __restrict__ zw, const float* __restrict__ Tu) {
     const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     if (t >= S.nv) return;
     const int64_t col = t / P.nz;
     const int cz = (int)(t - col * P.nz);
@@ -1078,7 +1113,7 @@ tgv2_iter(TgvArgs P, const float* __restrict__ u_in, float* __restrict__ u_out,
           const float* __restrict__ q_in, float* __restrict__ q_out, const float* __restrict__ zu,
           float* __restrict__ zw, const float* __restrict__ Tu) {
     const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     if (t >= S.nv) return;
     const int64_t col = t / P.nz;
     const int cz = (int)(t - col * P.nz);

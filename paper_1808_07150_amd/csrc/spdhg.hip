@@ -384,6 +384,22 @@ int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st, const Bwd
 
 dim3 img_grid(int nx, int ny, int nz) { return dim3((nx + TT - 1) / TT, (nz + TT - 1) / TT, ny); }
 
+// Column tile of the prior kernels: as many whole columns as fit in 1024 threads,
+// arranged about twice as wide in x as in y (nz <= 128 gives at least 8 columns).
+PriorTile prior_tile(const spdhg_geom& g) {
+    const int cols = 1024 / g.nz;
+    int ty = 1;
+    while ((2 * ty) * (4 * ty) <= cols) ty *= 2;
+    PriorTile TL;
+    TL.ty = std::min(ty, g.ny);
+    TL.tx = std::min(cols / TL.ty, g.nx);
+    return TL;
+}
+
+int prior_blocks(const spdhg_geom& g, const PriorTile& TL) {
+    return ((g.nx + TL.tx - 1) / TL.tx) * ((g.ny + TL.ty - 1) / TL.ty);
+}
+
 }  // namespace
 
 // ====================================================================== context
@@ -1187,8 +1203,10 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
         } else {
             P.inv_p = inv_p;
             if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
-            tv_iter<<<nblocks(nv), BLOCK, 0, st>>>(P, c->xcur(), c->xother(), c->yn[c->yn_cur],
-                                                   c->yn[1 - c->yn_cur], c->z, c->T, c->xi);
+            const PriorTile TL = prior_tile(c->geom);
+            tv_iter<<<prior_blocks(c->geom, TL), TL.tx * TL.ty * c->geom.nz, 0, st>>>(
+                P, TL, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
+                c->T, c->xi);
             LAUNCH_CHECK();
             if ((rc = prof_end(c, st))) return rc;
             c->x_cur ^= 1;
