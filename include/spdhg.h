@@ -155,6 +155,13 @@ int spdhg_iterate(spdhg_ctx* ctx, int64_t n_iters, void* stream);
  * iterations that in expectation use all data once). */
 int spdhg_epoch(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
 
+/* The same iterations as spdhg_epoch (bitwise the same result), with each epoch's
+ * launches recorded by stream capture into one HIP graph and launched as a graph (the
+ * epoch is a fixed sequence of kernels once its random blocks are drawn).  Returns after
+ * the stream has run the graphs (the graphs are then released).  Not with per-kernel
+ * profiling on (SPDHG_E_STATE). */
+int spdhg_epoch_graph(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
+
 /* Iterations per epoch and iterations done so far. */
 int spdhg_info(const spdhg_ctx* ctx, int64_t* iters_per_epoch, int64_t* iters_done);
 

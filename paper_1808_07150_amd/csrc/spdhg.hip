@@ -1224,6 +1224,44 @@ int spdhg_epoch(spdhg_ctx* c, int32_t n_epochs, void* stream) {
     return spdhg_iterate(c, (int64_t)n_epochs * c->iters_per_epoch, stream);
 }
 
+int spdhg_epoch_graph(spdhg_ctx* c, int32_t n_epochs, void* stream) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (n_epochs < 0) return fail(SPDHG_E_ARG, "n_epochs < 0");
+    if (c->prof) return fail(SPDHG_E_STATE, "per-kernel profiling is not recorded in graphs");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<hipGraphExec_t> execs;
+    int rc = SPDHG_OK;
+    for (int e = 0; e < n_epochs && rc == SPDHG_OK; ++e) {
+        hipGraph_t graph = nullptr;
+        hipError_t err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (err != hipSuccess) {
+            rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+            break;
+        }
+        const int rc_it = spdhg_iterate(c, c->iters_per_epoch, stream);
+        err = hipStreamEndCapture(st, &graph);
+        if (rc_it != SPDHG_OK) {
+            rc = rc_it;
+        } else if (err != hipSuccess) {
+            rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+        } else {
+            hipGraphExec_t exec = nullptr;
+            err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (err == hipSuccess) {
+                execs.push_back(exec);
+                err = hipGraphLaunch(exec, st);
+            }
+            if (err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    // the executable graphs are released once the stream has run them
+    const hipError_t err = hipStreamSynchronize(st);
+    for (hipGraphExec_t x : execs) (void)hipGraphExecDestroy(x);
+    if (rc == SPDHG_OK && err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+    return rc;
+}
+
 int spdhg_info(const spdhg_ctx* c, int64_t* ipe, int64_t* done) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
     if (ipe) *ipe = c->iters_per_epoch;

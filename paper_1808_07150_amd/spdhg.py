@@ -23,7 +23,7 @@ SAMPLING = {"uniform": 0, "balanced": 1}
 
 EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_project", "spdhg_backproject",
             "spdhg_nnz",
-            "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_info",
+            "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_epoch_graph", "spdhg_info",
             "spdhg_objective", "spdhg_gap", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
             "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
             "spdhg_destroy"]
@@ -83,6 +83,7 @@ def load_library() -> ctypes.CDLL:
                                ctypes.c_size_t, vp]
     lib.spdhg_iterate.argtypes = [vp, i64, vp]
     lib.spdhg_epoch.argtypes = [vp, i32, vp]
+    lib.spdhg_epoch_graph.argtypes = [vp, i32, vp]
     lib.spdhg_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.spdhg_objective.argtypes = [vp, vp, vp, vp]
     lib.spdhg_gap.argtypes = [vp, ctypes.c_double, vp, vp]
@@ -214,6 +215,17 @@ class Reconstruction:
 
     def epoch(self, n_epochs: int = 1, stream=None):
         _check(load_library().spdhg_epoch(self.ctx, int(n_epochs), _stream(stream)))
+
+    def epoch_graph(self, n_epochs: int = 1):
+        """spdhg_epoch with every epoch recorded into a HIP graph (on a side stream: the
+        default stream cannot be captured); returns when the epochs have run."""
+        cur = torch.cuda.current_stream()
+        side = torch.cuda.Stream(device=self.x.device)
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            _check(load_library().spdhg_epoch_graph(self.ctx, int(n_epochs),
+                                                    ctypes.c_void_p(side.cuda_stream)))
+        cur.wait_stream(side)
 
     def info(self):
         a, b = ctypes.c_int64(), ctypes.c_int64()

@@ -227,6 +227,28 @@ def test_rerun_bitwise_and_checkpoint(P, c1):
     np.testing.assert_array_equal(x.cpu().numpy(), a)
 
 
+@pytest.mark.parametrize("prior", ["tv", "tgv"])
+def test_graph_epochs_bitwise(P, small3d, prior):
+    """Epochs recorded into HIP graphs give bitwise the eager result (three graphs in a
+    row, with eager work and synchronisation between them)."""
+    g = small3d["geom"]
+    t = {k: dev(small3d[k]) for k in ("b", "r", "mult")}
+    prm = P.cparams(6, prior, "balanced", alpha=0.05, alpha1=0.025, seed=21)
+    xs = []
+    for graph in (False, True):
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+        for _ in range(3):
+            if graph:
+                rec.epoch_graph(1)
+            else:
+                rec.epoch(1)
+            torch.cuda.synchronize()
+            _ = rec.objective().cpu()  # eager work between the graphs
+        xs.append(x.cpu().numpy())
+    np.testing.assert_array_equal(xs[0], xs[1])
+
+
 def test_domain_errors(P, c1):
     from paper_1808_07150_amd.spdhg import SpdhgError
     g = c1["geom"]
