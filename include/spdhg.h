@@ -162,6 +162,24 @@ int spdhg_epoch(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
  * profiling on (SPDHG_E_STATE). */
 int spdhg_epoch_graph(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
 
+/* Batched reconstructions: n independent problems (contexts from spdhg_init, each with
+ * its own geometry, subsets, prior and workspace) each advance n_epochs of their own
+ * epochs.  Problem i runs on worker stream i mod n_streams (at most 8, default priority)
+ * forked from and joined back to `stream`, so the problems overlap on the GPU; every
+ * problem's launches are exactly those of a solo spdhg_epoch (bitwise the same result).
+ * use_graph != 0 records the whole forked batch epoch with stream capture into one HIP
+ * graph and launches it (needs a non-default `stream`; returns after it has run);
+ * otherwise the call is asynchronous on `stream`.  A context may appear once. */
+int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32_t n_streams,
+                      int32_t use_graph, void* stream);
+
+/* Ray-bundle tiling of the subset projection: wavefronts per (angle, radial bin) bundle
+ * (1, 2, 4 or 8; 0 = chosen from the launch size).  spdhg_autotune times each choice on
+ * the subset-0 projection of the current image (no state changes) and keeps the fastest;
+ * *fwd_split and *ms receive the choice and its time per launch. */
+int spdhg_set_tuning(spdhg_ctx* ctx, int32_t fwd_split);
+int spdhg_autotune(spdhg_ctx* ctx, int32_t* fwd_split, double* ms, void* stream);
+
 /* Iterations per epoch and iterations done so far. */
 int spdhg_info(const spdhg_ctx* ctx, int64_t* iters_per_epoch, int64_t* iters_done);
 

@@ -128,6 +128,7 @@ struct FwdArgs {
     float* d;            // F_DUAL: dual change, padded layout
     double* part;        // F_OBJ partials (one per block)
     float gr;            // F_SENS: gamma * rho
+    int split;           // host only: wavefronts per ray bundle (0: chosen from the size)
 };
 
 // One workgroup of NW wavefronts per (angle, radial bin); RPL = rays per lane (planes / 64,

@@ -297,7 +297,8 @@ int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
 }
 
 // One block per (angle of the list, radial bin); launches with few blocks split every ray
-// walk over 2, 4 or 8 wavefronts (a single angle has only n_rad ray bundles).
+// walk over 2, 4 or 8 wavefronts (a single angle has only n_rad ray bundles), unless
+// A.split fixes the split (the autotuner's choice).
 template <int MODE>
 int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     A.ang0 = ang0;
@@ -307,10 +308,16 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     if (nblk == 0) return SPDHG_OK;
     if (nblk > INT32_MAX) return fail(SPDHG_E_SHAPE, "too many rays");
     const int rpl = rays_per_lane(A.G.n_planes);
-    if (nblk < 4 * 256 && rpl <= 16) return launch_fwd_nw<MODE, 8>(rpl, A, (int)nblk, st);
-    if (nblk < 16 * 256) return launch_fwd_nw<MODE, 4>(rpl, A, (int)nblk, st);
-    if (nblk < 64 * 256) return launch_fwd_nw<MODE, 2>(rpl, A, (int)nblk, st);
-    return launch_fwd_nw<MODE, 1>(rpl, A, (int)nblk, st);
+    int nw = A.split;
+    if (nw != 1 && nw != 2 && nw != 4 && nw != 8)
+        nw = nblk < 4 * 256 ? 8 : nblk < 16 * 256 ? 4 : nblk < 64 * 256 ? 2 : 1;
+    if (nw == 8 && rpl > 16) nw = 4;
+    switch (nw) {
+        case 8: return launch_fwd_nw<MODE, 8>(rpl, A, (int)nblk, st);
+        case 4: return launch_fwd_nw<MODE, 4>(rpl, A, (int)nblk, st);
+        case 2: return launch_fwd_nw<MODE, 2>(rpl, A, (int)nblk, st);
+        default: return launch_fwd_nw<MODE, 1>(rpl, A, (int)nblk, st);
+    }
 }
 
 int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }
@@ -384,6 +391,22 @@ int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st, const Bwd
 
 dim3 img_grid(int nx, int ny, int nz) { return dim3((nx + TT - 1) / TT, (nz + TT - 1) / TT, ny); }
 
+// Worker streams of batched epochs, one pool per device (default priority, created on
+// first use, kept until the process ends): the first `need` streams of the pool.
+int worker_streams(int dev, int need, std::vector<hipStream_t>& out) {
+    static std::mutex mu;
+    static std::map<int, std::vector<hipStream_t>> pools;
+    std::lock_guard<std::mutex> lk(mu);
+    std::vector<hipStream_t>& pool = pools[dev];
+    while ((int)pool.size() < need) {
+        hipStream_t w = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+        pool.push_back(w);
+    }
+    out.assign(pool.begin(), pool.begin() + need);
+    return SPDHG_OK;
+}
+
 // Column tile of the prior kernels: as many whole columns as fit in 1024 threads,
 // arranged about twice as wide in x as in y (nz <= 128 gives at least 8 columns).
 PriorTile prior_tile(const spdhg_geom& g) {
@@ -423,6 +446,7 @@ struct spdhg_ctx {
     int w_cur = 0, q2_cur = 0;
     int64_t w_pending = 0;
     double tw = 0.0;
+    int fwd_split = 0;  // wavefronts per ray bundle of the subset projection (0: automatic)
     double* part = nullptr;
     double* scal = nullptr;  // 8 doubles of device scalars
     int64_t part_n = 0;
@@ -1165,6 +1189,7 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             F.sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[i];
             F.y = c->y;
             F.d = c->dscr;
+            F.split = c->fwd_split;
             if ((rc = prof_begin(c, SPDHG_PROF_FWD, st))) return rc;
             if ((rc = launch_fwd<F_DUAL>(F, a0, step, cnt, st))) return rc;
             if ((rc = prof_end(c, st))) return rc;
@@ -1412,6 +1437,106 @@ int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) 
     }
     c->k = hdr[0];
     return export_x(c, st);
+}
+
+int spdhg_set_tuning(spdhg_ctx* c, int32_t fwd_split) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (fwd_split != 0 && fwd_split != 1 && fwd_split != 2 && fwd_split != 4 && fwd_split != 8)
+        return fail(SPDHG_E_ARG, "fwd_split must be 0, 1, 2, 4 or 8");
+    c->fwd_split = fwd_split;
+    return SPDHG_OK;
+}
+
+int spdhg_autotune(spdhg_ctx* c, int32_t* fwd_split, double* ms, void* stream) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    int a0, step, cnt;
+    int rc = subset_angles(&c->geom, c->m, 0, a0, step, cnt);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int cand[4] = {1, 2, 4, 8};
+    int best = 0;
+    double best_ms = INFINITY;
+    for (int ci = 0; ci < 4 && rc == SPDHG_OK; ++ci) {
+        // the subset projection walk, timed on the objective epilogue (writes partials only)
+        FwdArgs F = c->fwd_args();
+        F.x = c->xcur();
+        F.mult = c->mp;
+        F.b = c->bp;
+        F.r = c->rp;
+        F.part = c->part;
+        F.split = cand[ci];
+        if ((rc = launch_fwd<F_OBJ>(F, a0, step, cnt, st))) break;  // warm-up
+        hipError_t err = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && rc == SPDHG_OK; ++r) rc = launch_fwd<F_OBJ>(F, a0, step, cnt, st);
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+        if (rc == SPDHG_OK && t / 3.0 < best_ms) {
+            best_ms = t / 3.0;
+            best = cand[ci];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    c->fwd_split = best;
+    if (fwd_split) *fwd_split = best;
+    if (ms) *ms = best_ms;
+    return SPDHG_OK;
+}
+
+int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32_t n_streams,
+                      int32_t use_graph, void* stream) {
+    if (!ctxs || n < 0 || n_epochs < 0) return fail(SPDHG_E_ARG, "bad batch arguments");
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(SPDHG_E_ARG, "NULL context in batch");
+        if (ctxs[i]->prof) return fail(SPDHG_E_STATE, "profiling is not recorded in batches");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(SPDHG_E_ARG, "a context appears twice in the batch");
+    }
+    if (n == 0 || n_epochs == 0) return SPDHG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (use_graph && st == nullptr) return fail(SPDHG_E_ARG, "graph batches need a non-default stream");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const int ns = std::max(1, std::min<int>(std::min(n_streams, 8), n));
+    std::vector<hipStream_t> pool;
+    int rc0 = worker_streams(dev, ns, pool);
+    if (rc0) return rc0;
+    std::vector<hipEvent_t> ev(ns + 1, nullptr);
+    for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    int rc = SPDHG_OK;
+    hipGraph_t graph = nullptr;
+    hipError_t err = hipSuccess;
+    if (use_graph) err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    // fork: every worker stream waits for the caller's stream; problem i runs on worker
+    // i mod ns (its iterations in order, exactly as a solo run); join back
+    if (err == hipSuccess) err = hipEventRecord(ev[ns], st);
+    for (int w = 0; w < ns && err == hipSuccess; ++w) err = hipStreamWaitEvent(pool[w], ev[ns], 0);
+    for (int i = 0; i < n && err == hipSuccess && rc == SPDHG_OK; ++i)
+        rc = spdhg_iterate(ctxs[i], (int64_t)n_epochs * ctxs[i]->iters_per_epoch, pool[i % ns]);
+    for (int w = 0; w < ns && err == hipSuccess; ++w) {
+        err = hipEventRecord(ev[w], pool[w]);
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, ev[w], 0);
+    }
+    if (use_graph) {
+        const hipError_t e2 = hipStreamEndCapture(st, &graph);
+        if (err == hipSuccess) err = e2;
+        hipGraphExec_t exec = nullptr;
+        if (err == hipSuccess && rc == SPDHG_OK) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (err == hipSuccess && rc == SPDHG_OK) err = hipGraphLaunch(exec, st);
+        if (err == hipSuccess && rc == SPDHG_OK) err = hipStreamSynchronize(st);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc == SPDHG_OK && err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+    return rc;
 }
 
 int spdhg_destroy(spdhg_ctx* c) {

@@ -23,7 +23,8 @@ SAMPLING = {"uniform": 0, "balanced": 1}
 
 EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_project", "spdhg_backproject",
             "spdhg_nnz",
-            "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_epoch_graph", "spdhg_info",
+            "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_epoch_graph", "spdhg_batch_epoch",
+            "spdhg_set_tuning", "spdhg_autotune", "spdhg_info",
             "spdhg_objective", "spdhg_gap", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
             "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
             "spdhg_destroy"]
@@ -84,6 +85,9 @@ def load_library() -> ctypes.CDLL:
     lib.spdhg_iterate.argtypes = [vp, i64, vp]
     lib.spdhg_epoch.argtypes = [vp, i32, vp]
     lib.spdhg_epoch_graph.argtypes = [vp, i32, vp]
+    lib.spdhg_batch_epoch.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, vp]
+    lib.spdhg_set_tuning.argtypes = [vp, i32]
+    lib.spdhg_autotune.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
     lib.spdhg_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.spdhg_objective.argtypes = [vp, vp, vp, vp]
     lib.spdhg_gap.argtypes = [vp, ctypes.c_double, vp, vp]
@@ -227,6 +231,17 @@ class Reconstruction:
                                                     ctypes.c_void_p(side.cuda_stream)))
         cur.wait_stream(side)
 
+    def set_tuning(self, fwd_split: int):
+        _check(load_library().spdhg_set_tuning(self.ctx, int(fwd_split)))
+
+    def autotune(self, stream=None):
+        """Time the ray-bundle splits of the subset projection and keep the fastest;
+        returns (split, ms per launch)."""
+        s, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(load_library().spdhg_autotune(self.ctx, ctypes.byref(s), ctypes.byref(ms),
+                                             _stream(stream)))
+        return int(s.value), float(ms.value)
+
     def info(self):
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(load_library().spdhg_info(self.ctx, ctypes.byref(a), ctypes.byref(b)))
@@ -334,3 +349,22 @@ def _memcpy_d2d(dst: int, src: int, nbytes: int):
     rc = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)
     if rc != 0:
         raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
+def batch_epoch(recs, n_epochs: int = 1, n_streams: int = 4, graph: bool = False):
+    """n_epochs epochs of every Reconstruction in `recs`, overlapped on worker streams
+    (optionally recorded into one HIP graph).  Each result equals its solo run bitwise."""
+    lib = load_library()
+    arr = (ctypes.c_void_p * len(recs))(*[r.ctx for r in recs])
+    dev = recs[0].x.device if recs else None
+    cur = torch.cuda.current_stream(dev)
+    if graph:
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            _check(lib.spdhg_batch_epoch(arr, len(recs), int(n_epochs), int(n_streams), 1,
+                                         ctypes.c_void_p(side.cuda_stream)))
+        cur.wait_stream(side)
+    else:
+        _check(lib.spdhg_batch_epoch(arr, len(recs), int(n_epochs), int(n_streams), 0,
+                                     ctypes.c_void_p(cur.cuda_stream)))

@@ -266,3 +266,63 @@ def test_domain_errors(P, c1):
     with pytest.raises(SpdhgError) as e:
         P.Reconstruction(g, P.cparams(10, "tv"), dev(b), dev(r), dev(c1["mult"]), x)
     assert e.value.code == -3
+
+
+def _batch_problems():
+    """A mixed batch: 2-D slices and thin 3-D slabs, different subset counts and priors."""
+    specs = [(synth.slice_2d(48), 8, "tv", 1e5, 101), (synth.slice_2d(64), 12, "none", 3e5, 102),
+             (synth.small_3d(nxy=40, nz=9, n_rad=44, n_ang=24, v=5.0, tan1=0.3), 6, "tv", 2e5, 103),
+             (synth.Geometry(nx=40, ny=40, nz=33, vx=5.0, vy=5.0, vz=5.0, n_rad=44, d_rad=5.0,
+                             n_ang=24, seg_planes=(33, 29, 29), seg_tan=(0.0, 0.25, -0.25)),
+              8, "tv", 5e5, 104),
+             (synth.slice_2d(48), 16, "tv", 1e6, 105)]
+    out = []
+    for g, m, prior, counts, seed in specs:
+        d = synth.brain_problem(g, seed, counts)
+        out.append((g, m, prior, d, seed))
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_bitwise_solo(P, graph):
+    """Batched epochs (worker streams, optionally one HIP graph) equal solo runs bitwise."""
+    probs = _batch_problems()
+
+    def make(g, m, prior, d, seed):
+        t = {k: dev(d[k]) for k in ("b", "r", "mult")}
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, P.cparams(m, prior, "balanced", alpha=0.05, seed=seed),
+                               t["b"], t["r"], t["mult"], x)
+        return rec, x
+
+    solo = []
+    for pr in probs:
+        rec, x = make(*pr)
+        rec.epoch(3)
+        torch.cuda.synchronize()
+        solo.append(x.cpu().numpy())
+    recs, xs = zip(*[make(*pr) for pr in probs])
+    for _ in range(3):
+        P.batch_epoch(list(recs), 1, n_streams=3, graph=graph)
+        torch.cuda.synchronize()
+    for a, x in zip(solo, xs):
+        np.testing.assert_array_equal(x.cpu().numpy(), a)
+
+
+def test_autotune_keeps_results(P, c1):
+    """The autotuner only changes the ray-bundle split of the projection: iterates stay
+    within FP32 summation-order differences of the untuned run."""
+    g = c1["geom"]
+    t = {k: dev(c1[k]) for k in ("b", "r", "mult")}
+    prm = P.cparams(10, "tv", "balanced", seed=8)
+    outs = []
+    for tune in (False, True):
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+        if tune:
+            split, ms = rec.autotune()
+            assert split in (1, 2, 4, 8) and ms > 0
+        rec.epoch(5)
+        torch.cuda.synchronize()
+        outs.append(x.cpu().numpy())
+    assert rel(outs[1], outs[0]) <= 1e-5
