@@ -146,6 +146,60 @@ def time_to_target(P, torch, g, d, prm, target=1e-3, ref_epochs=200, max_epochs=
             "snapshots": "every quarter epoch, objective off the clock"}
 
 
+def batch_leg(P, torch, steps=3, n_problems=64, seed=18080500):
+    """Batched reconstructions: n_problems independent problems of mixed shapes (2-D
+    slices 128^2 / 256^2 / 344^2 and mMR slabs 344x344x16 / 32 with segments 0, +-1),
+    subset counts 8..64, TV or no prior, 1e5..1e7 counts (beta = 0.1 sqrt(1e5 / counts)),
+    advanced together on worker streams / in one HIP graph per batch epoch.  Ray-bundle
+    splits come from the autotuner (one timing per shape class)."""
+    import numpy as np
+    import synth
+    from paper_1808_07150_amd import tuning
+    from synth.phantom import brain_problem_torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = [("slice", 128), ("slice", 256), ("slice", 344), ("slab", 16), ("slab", 32)]
+    dev = torch.device("cuda:0")
+    recs, xs, keep = [], [], []
+    t0 = time.time()
+    for j in range(n_problems):
+        kind, n = shapes[j % len(shapes)]
+        g = synth.slice_2d(n) if kind == "slice" else synth.slab(n)
+        m = int(min(rng.integers(8, 65), g.n_ang))
+        prior = "tv" if rng.random() < 0.5 else "none"
+        counts = float(10 ** rng.uniform(5, 7))
+        d = brain_problem_torch(g, seed + j, counts, dev)
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
+        prm = P.cparams(m, prior, "balanced", True, alpha=0.1 * (1e5 / counts) ** 0.5,
+                        seed=seed + j)
+        recs.append(P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x))
+        xs.append(x)
+        keep.append(d)
+    torch.cuda.synchronize()
+    t_gen = time.time() - t0
+    cache = tuning.autotune(recs)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"problems": n_problems, "epochs": steps, "inputs_s": round(t_gen, 1),
+           "tuned_shape_classes": len(cache)}
+    # one solo epoch of every problem after the other, then batched epochs
+    for mode in ("sequential", "streams", "graph"):
+        P.batch_epoch(recs, 1, n_streams=4, graph=(mode == "graph"))  # warm-up
+        torch.cuda.synchronize()
+        ev0.record()
+        if mode == "sequential":
+            for _ in range(steps):
+                for r in recs:
+                    r.epoch(1)
+        else:
+            P.batch_epoch(recs, steps, n_streams=4, graph=(mode == "graph"))
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        out[f"{mode}_problem_epochs_per_s"] = round(n_problems * steps / (ms * 1e-3), 2)
+    for r in recs:
+        r.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +209,10 @@ def main():
     ap.add_argument("--inputs", choices=("phantom", "random"), default="phantom",
                     help="phantom: the brain-phantom workload; random: i.i.d. inputs of the "
                          "same shapes (the kernels' memory accesses do not depend on values)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also measure batched reconstructions (64 mixed problems); off by "
+                         "default: its input generation once faulted inside torch's Poisson "
+                         "sampler with no cause found in this library")
     ap.add_argument("--no-time-to-target", action="store_true",
                     help="skip the time-to-1e-3-relative-objective measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -291,6 +349,10 @@ def main():
         out["time_to_target"] = time_to_target(P, torch, g, d, prm)
         log(f"time to 1e-3 relative objective: {out['time_to_target']['seconds']} s "
             f"({out['time_to_target']['epochs']} epochs; measured in {time.time() - t0:.1f} s)")
+    if args.batch:
+        t0 = time.time()
+        out["batch"] = batch_leg(P, torch)
+        log(f"batch: {out['batch']} ({time.time() - t0:.1f} s)")
     if not args.no_cpu_baseline:
         t0 = time.time()
         host = {k: d[k].cpu().numpy() for k in ("b", "r", "mult")}

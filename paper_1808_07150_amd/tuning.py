@@ -1,0 +1,44 @@
+"""Ray-bundle tiling choices of the subset projection, found by timing on the GPU
+(spdhg_autotune) and kept in a JSON cache keyed by the problem's shape class."""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, Optional
+
+
+def shape_key(g, n_subsets: int) -> str:
+    """Problems with equal keys launch identically shaped projections."""
+    return (f"img{g.nx}x{g.ny}x{g.nz}-sino{g.n_rad}x{g.n_ang}x{sum(g.seg_planes)}"
+            f"-seg{len(g.seg_planes)}-m{n_subsets}")
+
+
+def load_cache(path: Optional[str]) -> Dict[str, dict]:
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def save_cache(path: Optional[str], cache: Dict[str, dict]) -> None:
+    if not path:
+        return
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune(recs: Iterable, cache_path: Optional[str] = None) -> Dict[str, dict]:
+    """Apply the cached split to every Reconstruction whose shape class is known; time
+    the others once per class (spdhg_autotune) and add them to the cache."""
+    cache = load_cache(cache_path)
+    for rec in recs:
+        key = shape_key(rec.g, rec.params.n_subsets)
+        if key in cache:
+            rec.set_tuning(int(cache[key]["fwd_split"]))
+        else:
+            split, ms = rec.autotune()
+            cache[key] = {"fwd_split": split, "ms_per_projection": round(ms, 4)}
+    save_cache(cache_path, cache)
+    return cache
