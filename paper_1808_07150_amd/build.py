@@ -8,9 +8,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspdhg.so")
-SOURCES = [os.path.join(HERE, "csrc", "spdhg.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "spdhg.hip"), os.path.join(HERE, "csrc", "convnet.hip")]
 DEPENDS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "geom.hpp")] + \
-    [os.path.join(ROOT, "include", "spdhg.h")]
+    [os.path.join(ROOT, "include", h) for h in ("spdhg.h", "spdhg_net.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-shared", "-fPIC",

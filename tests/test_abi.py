@@ -22,10 +22,10 @@ def lib():
     return P.load_library()
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(spdhg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(spdhg_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_exports_match_header(lib):
@@ -35,6 +35,12 @@ def test_exports_match_header(lib):
         assert hasattr(lib, n), n
     import paper_1808_07150_amd.spdhg as S
     assert sorted(S.EXPORTED) == names
+    net = declared_functions(os.path.join(ROOT, "include", "spdhg_net.h"))
+    assert len(net) >= 12
+    for n in net:
+        assert hasattr(lib, n), n
+    from paper_1808_07150_amd import warmstart
+    assert sorted(warmstart.NET_EXPORTED) == net
 
 
 def test_subset_bins_and_validation(lib):
