@@ -200,6 +200,108 @@ def batch_leg(P, torch, steps=3, n_problems=64, seed=18080500):
     return out
 
 
+def run_to_target(P, torch, g, d, prm, x0, psi0, psi_star, target=1e-3, max_epochs=60):
+    """Iteration time (HIP events) from x0 until (Psi - Psi*) / (Psi0 - Psi*) <= target,
+    objective off the clock every quarter epoch; returns (seconds, epochs, reached)."""
+    x = x0.clone()
+    rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x)
+    ipe = rec.iters_per_epoch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_ms, done = 0.0, 0
+    psi = float(rec.objective()[0].item())
+    rel = (psi - psi_star) / (psi0 - psi_star)
+    q = 0
+    while rel > target and q < 4 * max_epochs:
+        n = ipe * (q + 1) // 4 - ipe * q // 4
+        ev0.record()
+        rec.iterate(n)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_ms += ev0.elapsed_time(ev1)
+        done += n
+        q += 1
+        rel = (float(rec.objective()[0].item()) - psi_star) / (psi0 - psi_star)
+    rec.close()
+    return t_ms * 1e-3, done / ipe, bool(rel <= target)
+
+
+def warm_start_leg(P, torch, n_train=32, n_test=4, train_passes=25, seed=18080400):
+    """Warm start (not part of the paper): a 3-level 3-D conv encoder-decoder (16/32/64
+    channels, BF16 MFMA kernels) trained to map the normalised backprojection to the TV MAP
+    solution of plain SPDHG (100 epochs) on seeded brain phantoms at 172x172x127 (sinogram
+    172 x 126 x 837); on held-out seeds, time to 1e-3 relative objective (cold-start
+    denominator, Psi* from 200 epochs) with and without the warm start (inference time
+    included)."""
+    import numpy as np
+    import synth
+    from paper_1808_07150_amd import warmstart as W
+    from synth.phantom import brain_problem_torch
+    dev = torch.device("cuda:0")
+    g = synth.warmstart_geometry()
+    shape = W.padded_shape(g)
+    prm = P.cparams(21, "tv", "balanced", True, alpha=2e-3, seed=seed)
+    samples = []
+    t0 = time.time()
+    for j in range(n_train + n_test):
+        d = brain_problem_torch(g, seed + j, 3e7, dev, host_poisson=True)
+        nbp = W.normalised_backprojection(g, d)
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
+        rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x)
+        psi0 = float(rec.objective()[0].item())
+        rec.epoch(100 if j < n_train else 200)
+        torch.cuda.synchronize()
+        psi_ref = float(rec.objective()[0].item())
+        rec.close()
+        samples.append(dict(d=d, nbp=nbp, target=x.clone(), psi0=psi0, psi_ref=psi_ref,
+                            scale=W.input_scale(nbp)))
+    t_data = time.time() - t0
+    log(f"warm start: {n_train + n_test} samples and targets in {t_data:.1f} s")
+    net = W.WarmStartNet(shape, dev, seed=seed)
+    part = torch.empty(max(W.wgrad_part_floats(shape, ci, co) for _, ci, co, _ in W.LAYERS),
+                       dtype=torch.float32, device=dev)
+    t0 = time.time()
+    losses = []
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for ep in range(train_passes):
+        lr = 1e-3 * (0.5 ** (ep // 10))
+        tot = 0.0
+        for j in rng.permutation(n_train):
+            s_ = samples[j]
+            tot += net.train_step(W.to_net(s_["nbp"], shape), W.to_net(s_["target"], shape),
+                                  s_["scale"], lr=lr, part=part)
+        losses.append(tot / n_train)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"warm start: {train_passes} passes over {n_train} samples in {t_train:.1f} s; "
+        f"loss {losses[0]:.4g} -> {losses[-1]:.4g}")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = []
+    for s_ in samples[n_train:]:
+        zero = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
+        tc, ec, okc = run_to_target(P, torch, g, s_["d"], prm, zero, s_["psi0"], s_["psi_ref"])
+        vol = W.to_net(s_["nbp"], shape)
+        ev0.record()
+        out = net.forward(vol, s_["scale"])
+        xw = W.from_net(out, g).clamp_(min=0.0)
+        ev1.record()
+        torch.cuda.synchronize()
+        t_inf = ev0.elapsed_time(ev1) * 1e-3
+        tw, ew, okw = run_to_target(P, torch, g, s_["d"], prm, xw, s_["psi0"], s_["psi_ref"])
+        rel_init = None
+        res.append(dict(cold_s=round(tc, 4), cold_epochs=ec, cold_reached=okc,
+                        warm_s=round(tw + t_inf, 4), warm_epochs=ew, warm_reached=okw,
+                        inference_s=round(t_inf, 5)))
+    cold = float(np.mean([r_["cold_s"] for r_ in res]))
+    warm = float(np.mean([r_["warm_s"] for r_ in res]))
+    return {"geometry": "172x172x127 at 4.16x4.16x2.08 mm, sinogram 172x126x837",
+            "train_samples": n_train, "test_samples": n_test, "train_passes": train_passes,
+            "targets": "SPDHG+ TV beta=2e-3, 21 subsets, 100 epochs from zero",
+            "psi_star": "200 epochs", "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+            "loss_first_last": [losses[0], losses[-1]], "per_test": res,
+            "mean_cold_s": round(cold, 4), "mean_warm_s": round(warm, 4),
+            "speedup": round(cold / warm, 3) if warm > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +311,9 @@ def main():
     ap.add_argument("--inputs", choices=("phantom", "random"), default="phantom",
                     help="phantom: the brain-phantom workload; random: i.i.d. inputs of the "
                          "same shapes (the kernels' memory accesses do not depend on values)")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="also train the warm-start network and measure its time to target "
+                         "(several minutes)")
     ap.add_argument("--batch", action="store_true",
                     help="also measure batched reconstructions (64 mixed problems); off by "
                          "default: its input generation once faulted inside torch's Poisson "
@@ -349,6 +454,11 @@ def main():
         out["time_to_target"] = time_to_target(P, torch, g, d, prm)
         log(f"time to 1e-3 relative objective: {out['time_to_target']['seconds']} s "
             f"({out['time_to_target']['epochs']} epochs; measured in {time.time() - t0:.1f} s)")
+    if args.warm_start:
+        t0 = time.time()
+        out["warm_start"] = warm_start_leg(P, torch)
+        log(f"warm start: {out['warm_start']['mean_cold_s']} s cold vs "
+            f"{out['warm_start']['mean_warm_s']} s warm ({time.time() - t0:.1f} s)")
     if args.batch:
         t0 = time.time()
         out["batch"] = batch_leg(P, torch)

@@ -306,3 +306,39 @@ class WarmStartNet:
         g = back("c2", a["c1"], a["e1"], g, True)
         back("c1", a["in"], a["c1"], g, True)
         return float(self.lparts.sum().item()), grads
+
+
+# ---------------------------------------------------------------- data and experiment
+def padded_shape(g) -> Tuple[int, int, int]:
+    """Network volume for an image [nz][ny][nx]: [ny][nx][nz] with every size rounded up
+    to a multiple of 4."""
+    r4 = lambda n: (n + 3) // 4 * 4  # noqa: E731
+    return r4(g.ny), r4(g.nx), r4(g.nz)
+
+
+def to_net(img_zyx: torch.Tensor, shape) -> torch.Tensor:
+    """Caller image [nz][ny][nx] -> zero-padded network volume [ny][nx][nz'] (FP32)."""
+    nz, ny, nx = img_zyx.shape
+    out = torch.zeros(shape, dtype=torch.float32, device=img_zyx.device)
+    out[:ny, :nx, :nz] = img_zyx.permute(1, 2, 0)
+    return out.contiguous()
+
+
+def from_net(vol: torch.Tensor, g) -> torch.Tensor:
+    return vol[:g.ny, :g.nx, :g.nz].permute(2, 0, 1).contiguous()
+
+
+def normalised_backprojection(g, d) -> torch.Tensor:
+    """(A^T b) / (A^T 1) on the voxels some ray reaches (0 elsewhere): the network input."""
+    from .spdhg import spdhg_backproject
+    atb = torch.empty(g.image_shape, dtype=torch.float32, device=d["b"].device)
+    at1 = torch.empty_like(atb)
+    spdhg_backproject(g, 1, -1, d["mult"], d["b"], atb)
+    spdhg_backproject(g, 1, -1, d["mult"], torch.ones_like(d["b"]), at1)
+    return torch.where(at1 > 0, atb / at1.clamp(min=1e-30), torch.zeros_like(atb))
+
+
+def input_scale(nbp: torch.Tensor) -> float:
+    """Scale that brings the network input to order one: 1 / mean over its support."""
+    pos = nbp[nbp > 0]
+    return 1.0 / float(pos.mean().item()) if pos.numel() else 1.0

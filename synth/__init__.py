@@ -3,10 +3,10 @@
 Holds geometry parameters and phantom/data generation only: no projector, prox or
 iteration of the reconstruction method lives here."""
 from .geometry import (Geometry, config1_2d, mmr, small_3d, slab, slice_2d,
-                       span11_segments)
+                       span11_segments, warmstart_geometry)
 from .phantom import (Ellipsoid, brain_problem, config1_problem, line_integrals,
                       make_data, phantom_2d, phantom_brain, voxelise)
 
-__all__ = ["Geometry", "config1_2d", "mmr", "small_3d", "slab", "slice_2d",
+__all__ = ["Geometry", "config1_2d", "mmr", "small_3d", "slab", "slice_2d", "warmstart_geometry",
            "span11_segments", "Ellipsoid", "brain_problem", "config1_problem",
            "line_integrals", "make_data", "phantom_2d", "phantom_brain", "voxelise"]

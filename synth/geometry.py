@@ -110,6 +110,12 @@ def mmr(nz: int = 127, n_seg: int = 11, n_rad: int = 344, n_ang: int = 252,
                     seg_planes=planes, seg_tan=tans)
 
 
+def warmstart_geometry() -> Geometry:
+    """Half in-plane resolution mMR: 172x172x127 voxels at 4.16 x 4.16 x 2.08 mm, sinogram
+    172 radial (4.16 mm) x 126 angles x 837 span-11 planes."""
+    return mmr(nxy=172, vxy=4.16, n_rad=172, n_ang=126)
+
+
 def small_3d(nxy: int = 24, nz: int = 9, n_rad: int = 26, n_ang: int = 12,
              v: float = 4.0, tan1: float = 0.25) -> Geometry:
     """Small oblique test geometry: segments 0 (nz planes) and +-1 (nz-4 planes)."""

@@ -294,10 +294,12 @@ def line_integrals_torch(g: Geometry, ells, device, batch: int = 12):
     return out
 
 
-def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side=False):
+def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side=False,
+                        host_poisson=False):
     """The brain-like 3-D problem generated on a torch device (float32 outputs): same
     phantom parameters as brain_problem, analytic data in FP64, randoms + scatter at 30%
-    of trues, normalisation U(0.8, 1.2), Poisson counts (torch generator seeded)."""
+    of trues, normalisation U(0.8, 1.2), Poisson counts (torch generator seeded, or with
+    host_poisson a NumPy PCG64 generator seeded from `seed` on the host)."""
     import torch
     rng = np.random.Generator(np.random.PCG64(seed))
     act, att, labels = phantom_brain(rng, g)
@@ -324,7 +326,11 @@ def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side
     del scatter
     scale = counts / (trues.sum() + rshape.sum())
     ybar = scale * (trues + rshape)
-    b = torch.poisson(ybar, generator=gen).to(torch.float32)
+    if host_poisson:
+        hrng = np.random.Generator(np.random.PCG64(seed + 3))
+        b = torch.from_numpy(hrng.poisson(ybar.cpu().numpy()).astype(np.float32)).to(device)
+    else:
+        b = torch.poisson(ybar, generator=gen).to(torch.float32)
     del ybar, trues
     d = dict(b=b, r=(scale * rshape).to(torch.float32), mult=mult.to(torch.float32),
              scale=float(scale), geom=g, ellipsoids=act)
