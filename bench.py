@@ -31,6 +31,24 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mmr_tv21.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1808_07150_amd", "csrc", f)
                   for f in ("kernels.hip", "geom.hpp", "spdhg.hip")]
 COPY_BYTES = 256 << 20
+
+# Workloads (one step = one epoch of Algorithm 2): mMR geometry, brain phantom, randoms +
+# scatter at 30 % of the trues, SPDHG+ (balanced sampling, preconditioned steps).
+# Algorithmic bytes per voxel of one prior launch: TV reads x, 3 duals, z, T and writes x,
+# 3 duals, z (44 B); dTV also reads the 3-component field xi (56 B); a TGV launch is
+# block n-1 (23 arrays) or block n (28 arrays), drawn equally often (102 B on average).
+WORKLOADS = {
+    "mmr-tv21": dict(m=21, prior="tv", counts=1e8, alpha=2e-3, alpha1=0.0, prior_bpv=44,
+                     label="mMR 344x344x127 / 344x252x837 span-11, TV beta=2e-3 + nonneg, "
+                           "21 subsets, SPDHG+ (balanced, preconditioned), 1e8 counts"),
+    "mmr-tgv252": dict(m=252, prior="tgv", counts=3e7, alpha=2e-3, alpha1=1e-3, prior_bpv=102,
+                       label="mMR 344x344x127 / 344x252x837 span-11, TGV alpha0=2e-3 "
+                             "alpha1=1e-3 + nonneg, 252 single-angle subsets, SPDHG+, 3e7 counts"),
+    "mmr-dtv252": dict(m=252, prior="dtv", counts=3e7, alpha=2e-3, alpha1=0.0, prior_bpv=56,
+                       label="mMR 344x344x127 / 344x252x837 span-11, dTV beta=2e-3 eta=1e-2 "
+                             "(MR-like side image) + nonneg, 252 single-angle subsets, "
+                             "SPDHG+, 3e7 counts"),
+}
 HBM_PEAK_GBS = 8000.0
 # FP32 vector FMA without packed-FP32 instructions: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 ALU_PEAK_TFLOPS = 78.6
@@ -75,37 +93,45 @@ def copy_calibration(torch, dev):
     del src, dst
 
 
-def cpu_baseline(g, d_host, m, alpha, seed):
+def cpu_baseline(g, d_host, wl, seed):
     """The FP64 oracle (oracle/) on a bounded sample of the same workload: one data
-    iteration (subset 0: 12 angles forward, KL-dual prox, backprojection) and one TV
-    iteration at full mMR size, run by the oracle's own Algorithm 2 loop, scaled to the
-    21 + 21 expected iterations of an epoch."""
+    iteration (subset 0: forward, KL-dual prox, backprojection) and one iteration of each
+    prior block at full mMR size, run by the oracle's own Algorithm 2 loop, scaled to the
+    expected iterations of an epoch."""
     import numpy as np
     from oracle import spdhg as S
+    m, prior = wl["m"], wl["prior"]
 
     class _Steps(S.Problem):  # the oracle problem without its (full-size) step setup
         def _setup_steps(self):
             self.sigma = [np.full(b.shape, 1e-3) for b in self.sub_b]
-            self.prior_sigma = [0.1]
+            self.prior_sigma = [0.1] * self.n_prior
             self.norms = [None] * self.n
             self.T = np.full(self.image_shape(), 1e-3)
 
-    prob = _Steps(g, d_host["b"], d_host["r"], d_host["mult"], n_subsets=m, prior="tv",
-                  alpha=alpha, sampling="balanced", precond=True)
-    x0 = np.full((1,) + g.image_shape, 0.5)
+    prob = _Steps(g, d_host["b"], d_host["r"], d_host["mult"], n_subsets=m, prior=prior,
+                  alpha=wl["alpha"], alpha1=wl["alpha1"], sampling="balanced", precond=True,
+                  side=d_host.get("side"))
+    x0 = np.full(prob.image_shape(), 0.5)
     st = prob.new_state(x0)
     t0 = time.perf_counter()
     S.spdhg(prob, 1, seed, state=st, blocks=[0])
-    t1 = time.perf_counter()
-    S.spdhg(prob, 1, seed, state=st, blocks=[m])
-    t2 = time.perf_counter()
+    t_data = time.perf_counter() - t0
+    t_prior = []
+    for j in range(prob.n_prior):
+        t0 = time.perf_counter()
+        S.spdhg(prob, 1, seed, state=st, blocks=[m + j])
+        t_prior.append(time.perf_counter() - t0)
     ipe = prob.iters_per_epoch()
-    per_epoch = (t1 - t0) * ipe * sum(prob.p[:m]) + (t2 - t1) * ipe * prob.p[m]
+    per_epoch = t_data * ipe * sum(prob.p[:m]) + sum(
+        t * ipe * prob.p[m + j] for j, t in enumerate(t_prior))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    prior_txt = " + ".join(f"{t:.1f} s" for t in t_prior)
     return {"value": 1.0 / per_epoch, "unit": "epochs/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 data iteration (subset 0, 12 angles: {t1 - t0:.1f} s) + 1 TV "
-                      f"iteration ({t2 - t1:.1f} s) at full mMR size, FP64, scaled to "
-                      f"{ipe * sum(prob.p[:m]):.0f} + {ipe * prob.p[m]:.0f} iterations/epoch"}
+            "sample": f"1 data iteration (subset 0: {t_data:.1f} s) + 1 iteration of each "
+                      f"prior block ({prior_txt}) at full mMR size, FP64, scaled to "
+                      f"{ipe * sum(prob.p[:m]):.0f} + {ipe * sum(prob.p[m:]):.0f} "
+                      f"iterations/epoch"}
 
 
 def time_to_target(P, torch, g, d, prm, target=1e-3, ref_epochs=200, max_epochs=60):
@@ -116,13 +142,13 @@ def time_to_target(P, torch, g, d, prm, target=1e-3, ref_epochs=200, max_epochs=
     the exact one by at most the reference's own error)."""
     dev = d["b"].device
     x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
-    ref = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x)
+    ref = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x, side=d.get("side"))
     psi0 = float(ref.objective()[0].item())
     ref.epoch(ref_epochs)
     psi_star = float(ref.objective()[0].item())
     ref.close()
     x2 = torch.zeros_like(x)
-    rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x2)
+    rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x2, side=d.get("side"))
     ipe = rec.iters_per_epoch
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_ms, done, rel = 0.0, 0, float("nan")
@@ -308,6 +334,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10, help="timed epochs")
     ap.add_argument("--warmup", type=int, default=2, help="untimed epochs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="mmr-tv21",
+                    help="mmr-tv21: the headline workload; mmr-tgv252 / mmr-dtv252: 252 "
+                         "single-angle subsets with TGV or directional TV at 3e7 counts")
     ap.add_argument("--inputs", choices=("phantom", "random"), default="phantom",
                     help="phantom: the brain-phantom workload; random: i.i.d. inputs of the "
                          "same shapes (the kernels' memory accesses do not depend on values)")
@@ -339,22 +368,26 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch, dev)
     g = synth.mmr()
-    m, alpha = 21, 2e-3
+    wl = WORKLOADS[args.workload]
+    m = wl["m"]
     t0 = time.time()
     if args.inputs == "phantom":
-        d = brain_problem_torch(g, SEED, 1e8, dev)
+        d = brain_problem_torch(g, SEED, wl["counts"], dev, with_side=wl["prior"] == "dtv")
     else:
         torch.manual_seed(SEED)
-        mean = 1e8 / g.n_bins
+        mean = wl["counts"] / g.n_bins
         d = {"mult": torch.rand(g.sino_shape, device=dev) * 0.4 + 0.8,
              "b": torch.poisson(torch.full(g.sino_shape, mean, device=dev)),
              "r": torch.full(g.sino_shape, 0.3 * mean, device=dev)}
+        if wl["prior"] == "dtv":
+            d["side"] = torch.rand(g.image_shape, device=dev)
     torch.cuda.synchronize()
     log(f"inputs generated in {time.time() - t0:.1f} s (total counts {float(d['b'].sum()):.3e})")
     x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
-    prm = P.cparams(m, "tv", "balanced", True, alpha=alpha, seed=SEED)
+    prm = P.cparams(m, wl["prior"], "balanced", True, alpha=wl["alpha"], alpha1=wl["alpha1"],
+                    seed=SEED)
     t0 = time.time()
-    rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x)
+    rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x, side=d.get("side"))
     torch.cuda.synchronize()
     log(f"init (step sizes) {time.time() - t0:.2f} s; {rec.iters_per_epoch} iterations/epoch")
     obj = rec.objective()
@@ -397,7 +430,7 @@ def main():
     # algorithmic bytes per launch (FP32, compulsory traffic, no re-reads)
     bytes_fwd = 4 * nv + 28 * n_i          # x; y b r mult sigma in, y d out
     bytes_bwd = 20 * nv + 4 * n_i          # d in; z x T in, z x out
-    bytes_prior = 44 * nv                  # x, 3 duals, z, T in; x, 3 duals, z out
+    bytes_prior = wl["prior_bpv"] * nv     # see WORKLOADS
     flops_fwd = 2.0 * nnz + 20.0 * n_i     # one FMA per nonzero + the prox per bin
     flops_bwd = 2.0 * nnz + 6.0 * nv
     n_fwd, n_prior = prof["fwd"][1], prof["prior"][1]
@@ -408,7 +441,10 @@ def main():
         "bwd": dict(bound="alu", work=flops_bwd, unit="TFLOP/s", peak=ALU_PEAK_TFLOPS,
                     name="bwd_iter (gather backprojection + primal epilogue)"),
         "prior": dict(bound="hbm", work=bytes_prior, unit="GB/s", peak=HBM_PEAK_GBS,
-                      name="tv_iter (TV dual + adjoint + primal epilogue)"),
+                      name={"tv": "tv_iter (TV dual + adjoint + primal epilogue)",
+                            "dtv": "tv_iter (dTV dual + adjoint + primal epilogue)",
+                            "tgv": "tgv1_iter / tgv2_iter (TGV duals + adjoints + primal "
+                                   "epilogue of u and w)"}[wl["prior"]]),
     }
     dom = max(prof, key=lambda k: prof[k][0])
     avg_ms = prof[dom][0] / max(prof[dom][1], 1)
@@ -424,7 +460,7 @@ def main():
                                                             prior=bytes_prior)[k]) / (a * 1e6), 1)}
     roofline = {"bound": kd["bound"], "achieved": round(achieved, 3), "peak": kd["peak"],
                 "unit": kd["unit"], "frac": round(achieved / kd["peak"], 4),
-                "traffic": measured_traffic(dom),
+                "traffic": measured_traffic(dom) if args.workload == "mmr-tv21" else None,
                 "kernel": kd["name"], "avg_ms": round(avg_ms, 4)}
     epochs_per_s = args.steps / (ms * 1e-3)
     pb_ms = (prof["fwd"][0] + prof["bwd"][0]) / max(prof["fwd"][1], 1)
@@ -433,9 +469,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "mMR 344x344x127 / 344x252x837 span-11, TV beta=2e-3 + "
-                               "nonneg, 21 subsets, SPDHG+ (balanced, preconditioned), "
-                               "1e8 counts", "iters_per_epoch": rec.iters_per_epoch,
+        "config": {"workload": wl["label"], "iters_per_epoch": rec.iters_per_epoch,
                    "nnz_per_subset": nnz},
         "epoch_hbm": {"algorithmic_GB": round(epoch_bytes / 1e9, 2),
                       "achieved_GBs": round(epoch_bytes / (ms / args.steps * 1e6), 1),
@@ -451,7 +485,8 @@ def main():
     if not args.no_time_to_target:
         t0 = time.time()
         rec.close()
-        out["time_to_target"] = time_to_target(P, torch, g, d, prm)
+        out["time_to_target"] = time_to_target(P, torch, g, d, prm,
+                                               ref_epochs=200 if m <= 21 else 40)
         log(f"time to 1e-3 relative objective: {out['time_to_target']['seconds']} s "
             f"({out['time_to_target']['epochs']} epochs; measured in {time.time() - t0:.1f} s)")
     if args.warm_start:
@@ -466,7 +501,9 @@ def main():
     if not args.no_cpu_baseline:
         t0 = time.time()
         host = {k: d[k].cpu().numpy() for k in ("b", "r", "mult")}
-        out["cpu_baseline"] = cpu_baseline(g, host, m, alpha, SEED)
+        if "side" in d:
+            host["side"] = d["side"].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(g, host, wl, SEED)
         log(f"cpu baseline {time.time() - t0:.1f} s")
     print(json.dumps(out), flush=True)
 
