@@ -1014,37 +1014,50 @@ __device__ __forceinline__ void tgv1_dual_at(const TgvArgs& P, const float* __re
 }
 
 // Algorithm 2 lines 5-8 for block n-1 fused with line 3 of the next iteration:
-// dz_u = grad^T dq (the three backward neighbours' dual changes are recomputed),
-// dz_w = -dq; u, w, q1 ping-pong, z_u and z_w in place.
-__global__ void __launch_bounds__(BLOCK)
-tgv1_iter(TgvArgs P, const float* __restrict__ u_in, float* __restrict__ u_out,
+// dz_u = grad^T dq, dz_w = -dq; u, w, q1 ping-pong, z_u and z_w in place.  Column tiles as
+// in tv_iter: the dual changes of the tile's voxels are shared through LDS and only the
+// tile's low faces recompute a neighbour's update.
+__global__ void __launch_bounds__(1024)
+tgv1_iter(TgvArgs P, PriorTile TL, const float* __restrict__ u_in, float* __restrict__ u_out,
           const float* __restrict__ w_in, float* __restrict__ w_out,
           const float* __restrict__ q_in, float* __restrict__ q_out, float* __restrict__ zu,
           float* __restrict__ zw, const float* __restrict__ Tu) {
+    __shared__ float sdq[3][1024];
     const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
-    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    if (t >= S.nv) return;
-    const int64_t col = t / P.nz;
-    const int cz = (int)(t - col * P.nz);
-    const int cy = (int)(col / P.nx), cx = (int)(col - (int64_t)cy * P.nx);
-    float q[3], dq[3], qn[3], dn[3];
-    tgv1_dual_at(P, u_in, w_in, q_in, cx, cy, cz, q, dq);
+    int cx, cy, cz, lx, ly;
+    const bool act = tile_voxel(TL, P.nx, P.ny, P.nz, xcd_remap(blockIdx.x, gridDim.x), cx, cy,
+                                cz, lx, ly);
+    const int l = threadIdx.x;
+    float q[3], dq[3] = {0.0f, 0.0f, 0.0f};
+    if (act) tgv1_dual_at(P, u_in, w_in, q_in, cx, cy, cz, q, dq);
+    sdq[0][l] = dq[0];
+    sdq[1][l] = dq[1];
+    sdq[2][l] = dq[2];
+    __syncthreads();
+    if (!act) return;
+    float qn[3], dn[3];
     float dzu = 0.0f;
     if (cx < P.nx - 1) dzu -= dq[0];
     if (cy < P.ny - 1) dzu -= dq[1];
     if (cz < P.nz - 1) dzu -= dq[2];
     if (cx > 0) {
-        tgv1_dual_at(P, u_in, w_in, q_in, cx - 1, cy, cz, qn, dn);
-        dzu += dn[0];
+        if (lx > 0) {
+            dzu += sdq[0][l - P.nz];
+        } else {
+            tgv1_dual_at(P, u_in, w_in, q_in, cx - 1, cy, cz, qn, dn);
+            dzu += dn[0];
+        }
     }
     if (cy > 0) {
-        tgv1_dual_at(P, u_in, w_in, q_in, cx, cy - 1, cz, qn, dn);
-        dzu += dn[1];
+        if (ly > 0) {
+            dzu += sdq[1][l - TL.tx * P.nz];
+        } else {
+            tgv1_dual_at(P, u_in, w_in, q_in, cx, cy - 1, cz, qn, dn);
+            dzu += dn[1];
+        }
     }
-    if (cz > 0) {
-        tgv1_dual_at(P, u_in, w_in, q_in, cx, cy, cz - 1, qn, dn);
-        dzu += dn[2];
-    }
+    if (cz > 0) dzu += sdq[2][l - 1];
+    const int64_t t = ((int64_t)cy * P.nx + cx) * P.nz + cz;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int64_t i = t + k * S.nv;
@@ -1107,43 +1120,56 @@ __device__ __forceinline__ void tgv2_dual_at(const TgvArgs& P, const float* __re
 
 // Algorithm 2 lines 5-8 for block n fused with line 3 of the next iteration:
 // dz_w = E^T dq (E^T p)_k = sum_l D_l^T of the (k, l) entry, D_l^T p (v) = [v_l > 0]
-// p(v - e_l) - [v_l < N_l - 1] p(v); dz_u = 0, so u = max(u - T_u z_u, 0).
-__global__ void __launch_bounds__(BLOCK)
-tgv2_iter(TgvArgs P, const float* __restrict__ u_in, float* __restrict__ u_out,
+// p(v - e_l) - [v_l < N_l - 1] p(v); dz_u = 0, so u = max(u - T_u z_u, 0).  Column tiles
+// with the 6-component dual changes shared through LDS, as in tgv1_iter.
+__global__ void __launch_bounds__(1024)
+tgv2_iter(TgvArgs P, PriorTile TL, const float* __restrict__ u_in, float* __restrict__ u_out,
           const float* __restrict__ w_in, float* __restrict__ w_out,
           const float* __restrict__ q_in, float* __restrict__ q_out, const float* __restrict__ zu,
           float* __restrict__ zw, const float* __restrict__ Tu) {
+    __shared__ float sdq[6][1024];
     const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
-    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    if (t >= S.nv) return;
-    const int64_t col = t / P.nz;
-    const int cz = (int)(t - col * P.nz);
-    const int cy = (int)(col / P.nx), cx = (int)(col - (int64_t)cy * P.nx);
+    int cx, cy, cz, lx, ly;
+    const bool act = tile_voxel(TL, P.nx, P.ny, P.nz, xcd_remap(blockIdx.x, gridDim.x), cx, cy,
+                                cz, lx, ly);
+    const int l = threadIdx.x;
+    float q[6], dq[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (act) tgv2_dual_at(P, w_in, q_in, cx, cy, cz, q, dq);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sdq[k][l] = dq[k];
+    __syncthreads();
+    if (!act) return;
     const int cc[3] = {cx, cy, cz};
     const int nn[3] = {P.nx, P.ny, P.nz};
-    float q[6], dq[6];
-    tgv2_dual_at(P, w_in, q_in, cx, cy, cz, q, dq);
-    // entry (k, l) of the symmetric matrix -> (component, weight)
+    const bool inner[3] = {lx > 0, ly > 0, true};  // backward neighbour inside the tile
+    const int lstep[3] = {P.nz, TL.tx * P.nz, 1};
+    // entry (k, l) of the symmetric matrix -> component
     const int ent[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
     float dzw[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
+    for (int ax = 0; ax < 3; ++ax) {
         float dn[6];
-        const bool back = cc[l] > 0;
+        const bool back = cc[ax] > 0;
         if (back) {
-            float qn[6];
-            tgv2_dual_at(P, w_in, q_in, cx - (l == 0), cy - (l == 1), cz - (l == 2), qn, dn);
+            if (inner[ax]) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = sdq[k][l - lstep[ax]];
+            } else {
+                float qn[6];
+                tgv2_dual_at(P, w_in, q_in, cx - (ax == 0), cy - (ax == 1), cz - (ax == 2), qn, dn);
+            }
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const int e = ent[k][l];
-            const float wgt = (k == l) ? 1.0f : TGV_SQRT_HALF;
+            const int e = ent[k][ax];
+            const float wgt = (k == ax) ? 1.0f : TGV_SQRT_HALF;
             float v = 0.0f;
             if (back) v += dn[e];
-            if (cc[l] < nn[l] - 1) v -= dq[e];
+            if (cc[ax] < nn[ax] - 1) v -= dq[e];
             dzw[k] = __builtin_fmaf(wgt, v, dzw[k]);
         }
     }
+    const int64_t t = ((int64_t)cy * P.nx + cx) * P.nz + cz;
 #pragma unroll
     for (int k = 0; k < 6; ++k) q_out[t + k * S.nv] = q[k];
 #pragma unroll

@@ -1210,15 +1210,17 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             TgvArgs A = c->tgv_args(j);
             A.inv_p = inv_p;
             if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
+            const PriorTile TL = prior_tile(c->geom);
+            const int nb_t = prior_blocks(c->geom, TL), nt_t = TL.tx * TL.ty * c->geom.nz;
             if (j == 0) {
-                tgv1_iter<<<nblocks(nv), BLOCK, 0, st>>>(A, c->xcur(), c->xother(), c->w[c->w_cur],
-                                                         c->w[1 - c->w_cur], c->yn[c->yn_cur],
-                                                         c->yn[1 - c->yn_cur], c->z, c->zw, c->T);
+                tgv1_iter<<<nb_t, nt_t, 0, st>>>(A, TL, c->xcur(), c->xother(), c->w[c->w_cur],
+                                                 c->w[1 - c->w_cur], c->yn[c->yn_cur],
+                                                 c->yn[1 - c->yn_cur], c->z, c->zw, c->T);
                 c->yn_cur ^= 1;
             } else {
-                tgv2_iter<<<nblocks(nv), BLOCK, 0, st>>>(A, c->xcur(), c->xother(), c->w[c->w_cur],
-                                                         c->w[1 - c->w_cur], c->q2[c->q2_cur],
-                                                         c->q2[1 - c->q2_cur], c->z, c->zw, c->T);
+                tgv2_iter<<<nb_t, nt_t, 0, st>>>(A, TL, c->xcur(), c->xother(), c->w[c->w_cur],
+                                                 c->w[1 - c->w_cur], c->q2[c->q2_cur],
+                                                 c->q2[1 - c->q2_cur], c->z, c->zw, c->T);
                 c->q2_cur ^= 1;
             }
             LAUNCH_CHECK();
