@@ -390,6 +390,8 @@ def main():
     rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x, side=d.get("side"))
     torch.cuda.synchronize()
     log(f"init (step sizes) {time.time() - t0:.2f} s; {rec.iters_per_epoch} iterations/epoch")
+    split, split_ms = rec.autotune()
+    log(f"autotuned ray-bundle split: {split} wavefronts ({split_ms:.3f} ms per subset projection)")
     obj = rec.objective()
     psi0 = float(obj[0].item())
 
@@ -470,6 +472,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["label"], "iters_per_epoch": rec.iters_per_epoch,
+                   "fwd_split": split,
                    "nnz_per_subset": nnz},
         "epoch_hbm": {"algorithmic_GB": round(epoch_bytes / 1e9, 2),
                       "achieved_GBs": round(epoch_bytes / (ms / args.steps * 1e6), 1),

@@ -173,8 +173,9 @@ int spdhg_epoch_graph(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
 int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32_t n_streams,
                       int32_t use_graph, void* stream);
 
-/* Ray-bundle tiling of the subset projection: wavefronts per (angle, radial bin) bundle
- * (1, 2, 4 or 8; 0 = chosen from the launch size).  spdhg_autotune times each choice on
+/* Ray-bundle tiling of the subset projection: wavefronts per (angle, radial bin) bundle,
+ * splitting its primary steps (1, 2, 4 or 8) or its planes (20: two wavefronts, 40: four;
+ * at most 1024 planes per wavefront); 0 = chosen from the launch size.  spdhg_autotune times each choice on
  * the subset-0 projection of the current image (no state changes) and keeps the fastest;
  * *fwd_split and *ms receive the choice and its time per launch. */
 int spdhg_set_tuning(spdhg_ctx* ctx, int32_t fwd_split);

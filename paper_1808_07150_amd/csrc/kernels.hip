@@ -131,6 +131,36 @@ struct FwdArgs {
     int split;           // host only: wavefronts per ray bundle (0: chosen from the size)
 };
 
+// Per-ray epilogue of the forward walk (sum acc of ray (a, k, plane q) in segment g).
+template <int MODE>
+__device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, int k, int q, int g,
+                                             float acc, double& obj) {
+    const GeomDev& G = P.G;
+    const float v = acc * G.sa[a * G.n_seg + g].L;
+    const int64_t full = ((int64_t)a * G.n_rad + k) * G.n_planes + q;
+    if (MODE == F_PLAIN_QK) {
+        const float m = P.mult ? P.mult[((int64_t)a * G.n_planes + q) * G.n_rad + k] : 1.0f;
+        P.out[((int64_t)ia * G.n_planes + q) * G.n_rad + k] = v * m;
+    } else if (MODE == F_POWER) {
+        // A_i^T A_i needs mult (G x) times mult again: write mult^2 G x
+        const float m = P.mult[full];
+        P.out[dual_row(G, ia, k) + q] = m * m * v;
+    } else if (MODE == F_SENS) {
+        const float a1 = P.mult[full] * v;
+        P.out[full] = a1 > 0.0f ? P.gr / a1 : 0.0f;
+    } else if (MODE == F_DUAL) {
+        const float sg = P.sigma ? P.sigma[full] : P.sig_s;
+        const float m = P.mult[full];
+        const float yo = P.y[full];
+        float yn = yo;
+        if (sg > 0.0f) yn = prox_kl_dual(__builtin_fmaf(sg, m * v, yo), sg, P.b[full], P.r[full]);
+        P.y[full] = yn;
+        P.d[dual_row(G, ia, k) + q] = m * (yn - yo);
+    } else if (MODE == F_OBJ) {
+        obj += phi64((double)(P.mult[full] * v), (double)P.b[full], (double)P.r[full]);
+    }
+}
+
 // One workgroup of NW wavefronts per (angle, radial bin); RPL = rays per lane (planes / 64,
 // rounded up).  Wavefront w walks the w-th of NW consecutive parts of the primary steps
 // with its own LDS buffers; the partial ray sums are added in a fixed order by wavefront 0
@@ -272,35 +302,135 @@ __global__ void __launch_bounds__(64 * NW) fwd_wave(FwdArgs P) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int q = lane + 64 * r;
-        if (q >= G.n_planes) continue;
-        const int g = pinfo[r] & 63;
-        const float v = acc[r] * G.sa[a * ns + g].L;
-        const int64_t full = ((int64_t)a * G.n_rad + k) * G.n_planes + q;
-        if (MODE == F_PLAIN_QK) {
-            const float m = P.mult ? P.mult[((int64_t)a * G.n_planes + q) * G.n_rad + k] : 1.0f;
-            P.out[((int64_t)ia * G.n_planes + q) * G.n_rad + k] = v * m;
-        } else if (MODE == F_POWER) {
-            // A_i^T A_i needs mult (G x) times mult again: write mult^2 G x, padded
-            const float m = P.mult[full];
-            P.out[dual_row(G, ia, k) + q] = m * m * v;
-        } else if (MODE == F_SENS) {
-            const float a1 = P.mult[full] * v;
-            P.out[full] = a1 > 0.0f ? P.gr / a1 : 0.0f;
-        } else if (MODE == F_DUAL) {
-            const float sg = P.sigma ? P.sigma[full] : P.sig_s;
-            const float m = P.mult[full];
-            const float yo = P.y[full];
-            float yn = yo;
-            if (sg > 0.0f) yn = prox_kl_dual(__builtin_fmaf(sg, m * v, yo), sg, P.b[full], P.r[full]);
-            P.y[full] = yn;
-            P.d[dual_row(G, ia, k) + q] = m * (yn - yo);
-        } else if (MODE == F_OBJ) {
-            obj += phi64((double)(P.mult[full] * v), (double)P.b[full], (double)P.r[full]);
-        }
+        if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, pinfo[r] & 63, acc[r], obj);
     }
     if (MODE == F_OBJ) {
         obj = wave_sum(obj);
         if (lane == 0) P.part[bid] = obj;
+    }
+}
+
+// Plane-split variant: PS wavefronts per (angle, radial bin) share every step's axial
+// column (built cooperatively, double-buffered in LDS, one workgroup barrier per step)
+// and each walks the whole ray bundle for its own contiguous share of the planes.  Fewer
+// rays per lane than fwd_wave, so fewer registers and more resident wavefronts.
+template <int RPL, int MODE, int PS>
+__global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
+    extern __shared__ float smem[];
+    __shared__ double wsum[PS];
+    const GeomDev& G = P.G;
+    const int ns = G.n_seg;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63;
+    float* Gb = smem;                        // [2][gsize] axial columns
+    int* segc = (int*)(Gb + 2 * P.gsize);    // [2][ns] axial cell offsets
+    float* segf = (float*)(segc + 2 * ns);   // [2][ns] axial fractions
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int ia = bid / G.n_rad;
+    const int k = bid - ia * G.n_rad;
+    const int a = P.ang0 + ia * P.ang_step;
+    const AngleDev A = G.ang[a];
+    const double kk = (double)k - G.ck;
+    const int nz = G.nz;
+    const int64_t s_prim = A.rowdom ? G.nx : 1;
+    const int64_t s_sec = A.rowdom ? 1 : G.nx;
+    const int q0 = w * 64 * RPL;  // first plane of this wavefront
+
+    int pinfo[RPL];  // (padded axial base of the plane) << 6 | segment
+    float acc[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int q = q0 + lane + 64 * r;
+        acc[r] = 0.0f;
+        pinfo[r] = 0;
+        if (q < G.n_planes) {
+            const int g = G.plane_seg[q];
+            pinfo[r] = ((q - G.seg_base[g] + G.seg_off[g] + P.pad) << 6) | g;
+        }
+    }
+    for (int i = tid; i < 2 * P.gsize; i += 64 * PS) Gb[i] = 0.0f;
+    int j0, j1;
+    sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
+    // image columns through a range-checked buffer resource (see fwd_wave)
+    constexpr int ZPT = PS >= 2 ? 1 : 2;  // z values per thread (nz <= 128)
+    constexpr int OUT = 1 << 30;
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)P.x, (short)0, (int)(P.G.nx * (int64_t)P.G.ny * nz * 4), 0x00020000);
+    int zoff[ZPT];
+#pragma unroll
+    for (int u = 0; u < ZPT; ++u) {
+        const int iz = tid + 64 * PS * u;
+        zoff[u] = iz < nz ? iz * 4 : OUT;
+    }
+    float v0[ZPT], v1[ZPT];
+    Sample s{0, 0.0f};
+    auto issue = [&](int j) {
+        s = split(sec_coord(A, kk, (double)j - A.cj));
+        if (MODE == F_SENS) return;
+        const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
+        const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
+        const int c0 = ok0 ? (int)(((int64_t)j * s_prim + (int64_t)s.i0 * s_sec) * nz * 4) : OUT;
+        const int c1 = ok1 ? (int)(((int64_t)j * s_prim + (int64_t)(s.i0 + 1) * s_sec) * nz * 4) : OUT;
+#pragma unroll
+        for (int u = 0; u < ZPT; ++u) {
+            v0[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c0 + zoff[u], 0, 0));
+            v1[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c1 + zoff[u], 0, 0));
+        }
+    };
+    if (j0 < j1) issue(j0);
+    int buf = 0;
+    for (int j = j0; j < j1; ++j) {
+        const double jj = (double)j - A.cj;
+        float* Gc = Gb + buf * P.gsize + P.pad;
+        const float w0 = 1.0f - s.fu, w1 = s.fu;
+        if (MODE == F_SENS) {
+            const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
+            const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
+            const float v = (ok0 ? w0 : 0.0f) + (ok1 ? w1 : 0.0f);
+            for (int iz = tid; iz < nz; iz += 64 * PS) Gc[iz] = v;
+        } else {
+#pragma unroll
+            for (int u = 0; u < ZPT; ++u) {
+                const int iz = tid + 64 * PS * u;
+                if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[u], w0 * v0[u]);
+            }
+        }
+        if (tid < ns) {
+            const Sample sz = split(ax_offset(G.sa[a * ns + tid], kk, jj));
+            segc[buf * ns + tid] = sz.i0;
+            segf[buf * ns + tid] = sz.fu;
+        }
+        if (j + 1 < j1) issue(j + 1);
+        // the other buffer was last read before this barrier's predecessor
+        __syncthreads();
+        const float* Gr = Gb + buf * P.gsize;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            if (q0 + lane + 64 * r < G.n_planes) {
+                const int g = pinfo[r] & 63;
+                const int idx = (pinfo[r] >> 6) + segc[buf * ns + g];
+                const float fz = segf[buf * ns + g];
+                acc[r] = __builtin_fmaf(1.0f - fz, Gr[idx], acc[r]);
+                acc[r] = __builtin_fmaf(fz, Gr[idx + 1], acc[r]);
+            }
+        }
+        buf ^= 1;
+    }
+    double obj = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int q = q0 + lane + 64 * r;
+        if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, pinfo[r] & 63, acc[r], obj);
+    }
+    if (MODE == F_OBJ) {
+        obj = wave_sum(obj);
+        if (lane == 0) wsum[w] = obj;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int v = 0; v < PS; ++v) t += wsum[v];
+            P.part[bid] = t;
+        }
     }
 }
 

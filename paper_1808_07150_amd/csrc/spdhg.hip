@@ -296,6 +296,23 @@ int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
     return SPDHG_OK;
 }
 
+// Plane-split forward: PS wavefronts per ray bundle, each with RPL rays per lane.
+template <int MODE, int PS>
+int launch_fwd_ps(const FwdArgs& A, int nblk, hipStream_t st) {
+    const size_t lds = (2 * (size_t)A.gsize + 4 * (size_t)A.G.n_seg) * 4;
+    const int rpl = rays_per_lane((A.G.n_planes + PS - 1) / PS);
+    switch (rpl) {
+        case 1: fwd_bundle<1, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
+        case 2: fwd_bundle<2, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
+        case 4: fwd_bundle<4, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
+        case 8: fwd_bundle<8, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
+        case 16: fwd_bundle<16, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
+        default: return fail(SPDHG_E_SHAPE, "unsupported plane count for the plane split");
+    }
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
 // One block per (angle of the list, radial bin); launches with few blocks split every ray
 // walk over 2, 4 or 8 wavefronts (a single angle has only n_rad ray bundles), unless
 // A.split fixes the split (the autotuner's choice).
@@ -308,6 +325,8 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     if (nblk == 0) return SPDHG_OK;
     if (nblk > INT32_MAX) return fail(SPDHG_E_SHAPE, "too many rays");
     const int rpl = rays_per_lane(A.G.n_planes);
+    if (A.split == 20) return launch_fwd_ps<MODE, 2>(A, (int)nblk, st);
+    if (A.split == 40) return launch_fwd_ps<MODE, 4>(A, (int)nblk, st);
     int nw = A.split;
     if (nw != 1 && nw != 2 && nw != 4 && nw != 8)
         nw = nblk < 4 * 256 ? 8 : nblk < 16 * 256 ? 4 : nblk < 64 * 256 ? 2 : 1;
@@ -1443,8 +1462,9 @@ int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) 
 
 int spdhg_set_tuning(spdhg_ctx* c, int32_t fwd_split) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
-    if (fwd_split != 0 && fwd_split != 1 && fwd_split != 2 && fwd_split != 4 && fwd_split != 8)
-        return fail(SPDHG_E_ARG, "fwd_split must be 0, 1, 2, 4 or 8");
+    if (fwd_split != 0 && fwd_split != 1 && fwd_split != 2 && fwd_split != 4 && fwd_split != 8 &&
+        fwd_split != 20 && fwd_split != 40)
+        return fail(SPDHG_E_ARG, "fwd_split must be 0, 1, 2, 4, 8, 20 or 40");
     c->fwd_split = fwd_split;
     return SPDHG_OK;
 }
@@ -1458,10 +1478,12 @@ int spdhg_autotune(spdhg_ctx* c, int32_t* fwd_split, double* ms, void* stream) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int cand[4] = {1, 2, 4, 8};
+    const int cand[6] = {1, 2, 4, 8, 20, 40};
     int best = 0;
     double best_ms = INFINITY;
-    for (int ci = 0; ci < 4 && rc == SPDHG_OK; ++ci) {
+    for (int ci = 0; ci < 6 && rc == SPDHG_OK; ++ci) {
+        if (cand[ci] >= 20 && rays_per_lane((c->tab.G.n_planes + cand[ci] / 10 - 1) / (cand[ci] / 10)) > 16)
+            continue;
         // the subset projection walk, timed on the objective epilogue (writes partials only)
         FwdArgs F = c->fwd_args();
         F.x = c->xcur();

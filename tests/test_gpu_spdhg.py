@@ -326,3 +326,23 @@ def test_autotune_keeps_results(P, c1):
         torch.cuda.synchronize()
         outs.append(x.cpu().numpy())
     assert rel(outs[1], outs[0]) <= 1e-5
+
+
+@pytest.mark.parametrize("split", [1, 2, 4, 8, 20, 40])
+def test_forward_splits_parity(P, tall3d, split):
+    """Every ray-bundle tiling of the subset projection (primary-step splits 1..8, plane
+    splits 20/40) reproduces the oracle's iterates."""
+    print(f"[spdhg] tall3d TV split={split}", flush=True)
+    g = tall3d["geom"]
+    prob = S.Problem(g, tall3d["b"], tall3d["r"], tall3d["mult"], n_subsets=4, prior="tv",
+                     alpha=0.05, sampling="balanced", precond=True)
+    t = {k: dev(tall3d[k]) for k in ("b", "r", "mult")}
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    rec = P.Reconstruction(g, P.cparams(4, "tv", "balanced", True, alpha=0.05, seed=17),
+                           t["b"], t["r"], t["mult"], x)
+    rec.set_tuning(split)
+    st = S.spdhg(prob, 6 * prob.iters_per_epoch(), seed=17)
+    rec.epoch(6)
+    torch.cuda.synchronize()
+    xo = prob.reported(st)[0]
+    assert rel(x.cpu().numpy(), xo) <= 1e-3
