@@ -251,7 +251,7 @@ def run_to_target(P, torch, g, d, prm, x0, psi0, psi_star, target=1e-3, max_epoc
     return t_ms * 1e-3, done / ipe, bool(rel <= target)
 
 
-def warm_start_leg(P, torch, n_train=32, n_test=4, train_passes=25, seed=18080400):
+def warm_start_leg(P, torch, n_train=200, n_test=20, train_passes=12, seed=18080400):
     """Warm start (not part of the paper): a 3-level 3-D conv encoder-decoder (16/32/64
     channels, BF16 MFMA kernels) trained to map the normalised backprojection to the TV MAP
     solution of plain SPDHG (100 epochs) on seeded brain phantoms at 172x172x127 (sinogram
@@ -278,8 +278,10 @@ def warm_start_leg(P, torch, n_train=32, n_test=4, train_passes=25, seed=1808040
         torch.cuda.synchronize()
         psi_ref = float(rec.objective()[0].item())
         rec.close()
-        samples.append(dict(d=d, nbp=nbp, target=x.clone(), psi0=psi0, psi_ref=psi_ref,
-                            scale=W.input_scale(nbp)))
+        samples.append(dict(d=d if j >= n_train else None, nbp=nbp, target=x.clone(), psi0=psi0,
+                            psi_ref=psi_ref, scale=W.input_scale(nbp)))
+        if (j + 1) % 10 == 0:
+            log(f"warm start: {j + 1} of {n_train + n_test} samples in {time.time() - t0:.1f} s")
     t_data = time.time() - t0
     log(f"warm start: {n_train + n_test} samples and targets in {t_data:.1f} s")
     net = W.WarmStartNet(shape, dev, seed=seed)
@@ -289,13 +291,14 @@ def warm_start_leg(P, torch, n_train=32, n_test=4, train_passes=25, seed=1808040
     losses = []
     rng = np.random.Generator(np.random.PCG64(seed))
     for ep in range(train_passes):
-        lr = 1e-3 * (0.5 ** (ep // 10))
+        lr = 1e-3 * (0.5 ** (ep * 3 // max(train_passes, 1)))  # halved at each third
         tot = 0.0
         for j in rng.permutation(n_train):
             s_ = samples[j]
             tot += net.train_step(W.to_net(s_["nbp"], shape), W.to_net(s_["target"], shape),
                                   s_["scale"], lr=lr, part=part)
         losses.append(tot / n_train)
+        log(f"warm start: pass {ep + 1} of {train_passes}, mean loss {losses[-1]:.4g}")
     torch.cuda.synchronize()
     t_train = time.time() - t0
     log(f"warm start: {train_passes} passes over {n_train} samples in {t_train:.1f} s; "
@@ -343,6 +346,9 @@ def main():
     ap.add_argument("--warm-start", action="store_true",
                     help="also train the warm-start network and measure its time to target "
                          "(several minutes)")
+    ap.add_argument("--ws-train", type=int, default=200, help="warm start: training phantoms")
+    ap.add_argument("--ws-test", type=int, default=20, help="warm start: held-out phantoms")
+    ap.add_argument("--ws-passes", type=int, default=12, help="warm start: training passes")
     ap.add_argument("--batch", action="store_true",
                     help="also measure batched reconstructions (64 mixed problems); off by "
                          "default: its input generation once faulted inside torch's Poisson "
@@ -494,7 +500,8 @@ def main():
             f"({out['time_to_target']['epochs']} epochs; measured in {time.time() - t0:.1f} s)")
     if args.warm_start:
         t0 = time.time()
-        out["warm_start"] = warm_start_leg(P, torch)
+        out["warm_start"] = warm_start_leg(P, torch, n_train=args.ws_train, n_test=args.ws_test,
+                                           train_passes=args.ws_passes)
         log(f"warm start: {out['warm_start']['mean_cold_s']} s cold vs "
             f"{out['warm_start']['mean_warm_s']} s warm ({time.time() - t0:.1f} s)")
     if args.batch:
