@@ -134,21 +134,26 @@ def cpu_baseline(g, d_host, wl, seed):
                       f"iterations/epoch"}
 
 
-def time_to_target(P, torch, g, d, prm, target=1e-3, ref_epochs=200, max_epochs=60):
+def time_to_target(P, torch, g, d, prm, target=1e-3, ref_epochs=200, max_epochs=60, split=0):
     """Iteration time until the relative objective (Psi(x^k) - Psi*) / (Psi(x^0) - Psi*)
     (Section 4) first falls to `target`, from x^0 = 0, with the objective evaluated off the
     clock at every quarter epoch.  Psi* is the objective after `ref_epochs` epochs of the
     same method (an upper bound of the minimum, so the reported time is a lower bound of
-    the exact one by at most the reference's own error)."""
+    the exact one by at most the reference's own error).  `split` (if not 0) fixes the
+    ray-bundle split of both runs."""
     dev = d["b"].device
     x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
     ref = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x, side=d.get("side"))
+    if split:
+        ref.set_tuning(split)
     psi0 = float(ref.objective()[0].item())
     ref.epoch(ref_epochs)
     psi_star = float(ref.objective()[0].item())
     ref.close()
     x2 = torch.zeros_like(x)
     rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x2, side=d.get("side"))
+    if split:
+        rec.set_tuning(split)
     ipe = rec.iters_per_epoch
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_ms, done, rel = 0.0, 0, float("nan")
@@ -353,6 +358,9 @@ def main():
                     help="also measure batched reconstructions (64 mixed problems); off by "
                          "default: its input generation once faulted inside torch's Poisson "
                          "sampler with no cause found in this library")
+    ap.add_argument("--fwd-split", type=int, default=0,
+                    help="wavefronts per ray bundle of the subset projection (1, 2, 4, 8, or 20 / "
+                         "40 for the plane-split variant); 0 = autotune")
     ap.add_argument("--no-time-to-target", action="store_true",
                     help="skip the time-to-1e-3-relative-objective measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -396,8 +404,13 @@ def main():
     rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x, side=d.get("side"))
     torch.cuda.synchronize()
     log(f"init (step sizes) {time.time() - t0:.2f} s; {rec.iters_per_epoch} iterations/epoch")
-    split, split_ms = rec.autotune()
-    log(f"autotuned ray-bundle split: {split} wavefronts ({split_ms:.3f} ms per subset projection)")
+    if args.fwd_split:
+        rec.set_tuning(args.fwd_split)
+        split = args.fwd_split
+        log(f"ray-bundle split fixed at {split}")
+    else:
+        split, split_ms = rec.autotune()
+        log(f"autotuned ray-bundle split: {split} wavefronts ({split_ms:.3f} ms per subset projection)")
     obj = rec.objective()
     psi0 = float(obj[0].item())
 
@@ -495,7 +508,7 @@ def main():
         t0 = time.time()
         rec.close()
         out["time_to_target"] = time_to_target(P, torch, g, d, prm,
-                                               ref_epochs=200 if m <= 21 else 40)
+                                               ref_epochs=200 if m <= 21 else 40, split=split)
         log(f"time to 1e-3 relative objective: {out['time_to_target']['seconds']} s "
             f"({out['time_to_target']['epochs']} epochs; measured in {time.time() - t0:.1f} s)")
     if args.warm_start:

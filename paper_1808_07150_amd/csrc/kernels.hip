@@ -17,7 +17,9 @@
 //              column and angle (FP64, shared through LDS), lanes run along z and read
 //              the dual change d[angle][k][plane] contiguously.  No atomics.  Epilogues:
 //              plain output, running minimum for T, primal epilogue (lines 7-8 and 3).
-//   tv_iter    TV / dTV prior block (dual ascent, l2-ball projection, adjoint, epilogue).
+//   tv_wave    TV / dTV prior block (dual ascent, l2-ball projection, adjoint, epilogue),
+//              one wavefront per 64-voxel run of a column marching along y (nz >= 32);
+//   tv_iter    the same on column tiles of one workgroup (thin volumes).
 //   reductions deterministic FP64 block partials + ordered final sum.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -910,30 +912,18 @@ __device__ __forceinline__ void zf_coords(const PriorArgs& P, int64_t t, int& cx
     cx = (int)(col - (int64_t)cy * P.nx);
 }
 
-// Dual update of the prior block at voxel c: q = P_alpha(y(c) + sigma A_n x (c)); returns
-// dy = q - y(c) (for dTV the D-weighted change D dy, i.e. the input of grad^T).
-__device__ __forceinline__ void prior_dual_at(const PriorArgs& P, const float* __restrict__ x,
-                                              const float* __restrict__ y,
-                                              const float* __restrict__ xi, int cx, int cy,
-                                              int cz, float q[3], float dy[3]) {
-    const int64_t sz = 1, sx = P.nz, sy = (int64_t)P.nz * P.nx;
-    const int64_t nv = sy * P.ny;
-    const int64_t c = (int64_t)cy * sy + (int64_t)cx * sx + cz;
-    const float xc = x[c];
-    float g0 = cx < P.nx - 1 ? x[c + sx] - xc : 0.0f;
-    float g1 = cy < P.ny - 1 ? x[c + sy] - xc : 0.0f;
-    float g2 = cz < P.nz - 1 ? x[c + sz] - xc : 0.0f;
-    float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+// Dual update of the prior block at one voxel from its forward differences g (zero on
+// the high faces), duals y and (dTV) field xi: q = P_alpha(y + sigma A_n x); returns
+// dy = q - y (for dTV the D-weighted change D dy, i.e. the input of grad^T).
+__device__ __forceinline__ void prior_dual_vals(const PriorArgs& P, float g0, float g1, float g2,
+                                                float y0, float y1, float y2, float x0, float x1,
+                                                float x2, float q[3], float dy[3]) {
     if (P.dtv) {
-        x0 = xi[c];
-        x1 = xi[c + nv];
-        x2 = xi[c + 2 * nv];
         const float dot = x0 * g0 + x1 * g1 + x2 * g2;
         g0 -= P.gamma_d * dot * x0;
         g1 -= P.gamma_d * dot * x1;
         g2 -= P.gamma_d * dot * x2;
     }
-    const float y0 = y[c], y1 = y[c + nv], y2 = y[c + 2 * nv];
     q[0] = __builtin_fmaf(P.sigma, g0, y0);
     q[1] = __builtin_fmaf(P.sigma, g1, y1);
     q[2] = __builtin_fmaf(P.sigma, g2, y2);
@@ -959,6 +949,27 @@ __device__ __forceinline__ void prior_dual_at(const PriorArgs& P, const float* _
         dy[1] -= P.gamma_d * dot * x1;
         dy[2] -= P.gamma_d * dot * x2;
     }
+}
+
+// The same at voxel (cx, cy, cz), loading everything it needs.
+__device__ __forceinline__ void prior_dual_at(const PriorArgs& P, const float* __restrict__ x,
+                                              const float* __restrict__ y,
+                                              const float* __restrict__ xi, int cx, int cy,
+                                              int cz, float q[3], float dy[3]) {
+    const int64_t sz = 1, sx = P.nz, sy = (int64_t)P.nz * P.nx;
+    const int64_t nv = sy * P.ny;
+    const int64_t c = (int64_t)cy * sy + (int64_t)cx * sx + cz;
+    const float xc = x[c];
+    const float g0 = cx < P.nx - 1 ? x[c + sx] - xc : 0.0f;
+    const float g1 = cy < P.ny - 1 ? x[c + sy] - xc : 0.0f;
+    const float g2 = cz < P.nz - 1 ? x[c + sz] - xc : 0.0f;
+    float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+    if (P.dtv) {
+        x0 = xi[c];
+        x1 = xi[c + nv];
+        x2 = xi[c + 2 * nv];
+    }
+    prior_dual_vals(P, g0, g1, g2, y[c], y[c + nv], y[c + 2 * nv], x0, x1, x2, q, dy);
 }
 
 // Column tiles of the prior kernels: a workgroup holds TX x TY voxel columns of nz
@@ -1034,6 +1045,145 @@ tv_iter(PriorArgs P, PriorTile TL, const float* __restrict__ x_in, float* __rest
     z[t] = zn;
     const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
     x_out[t] = fmaxf(x_in[t] - T[t] * zbar, 0.0f);
+}
+
+// Buffer-resource access to an array of at most 4 GiB: a 32-bit byte offset per lane
+// plus a wave-uniform one (plain vector loads and stores through the vector cache).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vol_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+__device__ __forceinline__ float vol_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+__device__ __forceinline__ void vol_st(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff,
+                                       float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, soff, 0);
+}
+
+// The same update with one wavefront per run of 64 consecutive voxels of a column,
+// marching along y through the rows of a chunk and never waiting on another wavefront
+// (no LDS, no barrier).  Runs overlap by one voxel: run h covers z = 63h .. 63h + 63, and
+// its first lane (h > 0) computes the dual update below the run only to pass it on.  In
+// the same way the chunk starts one row early (below y0) without writing that row.  The
+// z-neighbour's change then comes from the next-lower lane, the y-neighbour's from the
+// previous row (a register), and the x-neighbour's is recomputed from its inputs, which
+// the neighbouring column's wavefront reads at about the same time (cache hits).  Each
+// row's loads are issued before the previous row's stores.  Requires nz <= 128.
+struct TvRow {
+    float xp, xn, xz, y0, y1, y2, z, t;  // x(c + e_x), x(c + e_y), x(c + e_z), y(c), z(c), T(c)
+    float lxn, lxz, ly0, ly1, ly2;       // x-neighbour: x(c - e_x + e_y), x(c - e_x + e_z), y
+    float i0, i1, i2, li0, li1, li2;     // dTV field at c and c - e_x
+};
+
+template <bool DTV>
+__device__ __forceinline__ void tv_row_load(TvRow& r, __amdgpu_buffer_rsrc_t rx,
+                                            __amdgpu_buffer_rsrc_t ry, __amdgpu_buffer_rsrc_t rz,
+                                            __amdgpu_buffer_rsrc_t rt, __amdgpu_buffer_rsrc_t rxi,
+                                            uint32_t c, uint32_t sx, uint32_t sy, uint32_t nvb,
+                                            bool hx, bool hy, bool hz, bool lx) {
+    r.xp = hx ? vol_ld(rx, c + sx, 0) : 0.0f;
+    r.xn = hy ? vol_ld(rx, c + sy, 0) : 0.0f;
+    r.xz = hz ? vol_ld(rx, c + 4, 0) : 0.0f;
+    r.y0 = vol_ld(ry, c, 0);
+    r.y1 = vol_ld(ry, c, nvb);
+    r.y2 = vol_ld(ry, c, 2 * nvb);
+    r.z = vol_ld(rz, c, 0);
+    r.t = vol_ld(rt, c, 0);
+    r.i0 = r.i1 = r.i2 = r.li0 = r.li1 = r.li2 = 0.0f;
+    r.lxn = r.lxz = r.ly0 = r.ly1 = r.ly2 = 0.0f;
+    if (DTV) {
+        r.i0 = vol_ld(rxi, c, 0);
+        r.i1 = vol_ld(rxi, c, nvb);
+        r.i2 = vol_ld(rxi, c, 2 * nvb);
+    }
+    if (lx) {
+        const uint32_t cl = c - sx;
+        r.lxn = hy ? vol_ld(rx, cl + sy, 0) : 0.0f;
+        r.lxz = hz ? vol_ld(rx, cl + 4, 0) : 0.0f;
+        r.ly0 = vol_ld(ry, cl, 0);
+        r.ly1 = vol_ld(ry, cl, nvb);
+        r.ly2 = vol_ld(ry, cl, 2 * nvb);
+        if (DTV) {
+            r.li0 = vol_ld(rxi, cl, 0);
+            r.li1 = vol_ld(rxi, cl, nvb);
+            r.li2 = vol_ld(rxi, cl, 2 * nvb);
+        }
+    }
+}
+
+template <bool DTV>
+__global__ void __launch_bounds__(256)
+tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__ x_out,
+        const float* __restrict__ y_in, float* __restrict__ y_out, float* __restrict__ z,
+        const float* __restrict__ T, const float* __restrict__ xi) {
+    // byte strides; 3 nv floats stay below 4 GiB (images are limited to 1 GiB)
+    const uint32_t sx = 4u * P.nz, sy = 4u * P.nz * P.nx;
+    const uint32_t nvb = sy * P.ny;
+    const auto rx = vol_rsrc(x_in, nvb), rxo = vol_rsrc(x_out, nvb);
+    const auto ry = vol_rsrc(y_in, 3 * nvb), ryo = vol_rsrc(y_out, 3 * nvb);
+    const auto rz = vol_rsrc(z, nvb), rt = vol_rsrc(T, nvb);
+    const auto rxi = vol_rsrc(DTV ? xi : x_in, DTV ? 3 * nvb : nvb);
+    const int nh = P.nz <= 64 ? 1 : (P.nz + 61) / 63;  // ceil((nz - 1) / 63)
+    const int lane = threadIdx.x & 63;
+    const int gw = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int h = gw % nh;
+    const int rest = gw / nh;
+    const int cx = rest % P.nx;
+    const int y0 = (rest / P.nx) * ly;
+    if (y0 >= P.ny) return;  // whole wavefront beyond the last chunk
+    const int y1 = min(P.ny, y0 + ly);
+    const int cz = 63 * h + lane;
+    const bool act = cz < P.nz;
+    const bool own = act && (h == 0 || lane > 0);  // writes its voxel
+    const bool hx = cx < P.nx - 1, lx = cx > 0, hz = cz < P.nz - 1;
+    int cy = y0 > 0 ? y0 - 1 : y0;
+    uint32_t c = 4u * (((uint32_t)cy * P.nx + cx) * P.nz + min(cz, P.nz - 1));
+    TvRow cur = {}, nxt = {};
+    float xc = 0.0f, xl = 0.0f, dprev = 0.0f;
+    if (act) {
+        tv_row_load<DTV>(cur, rx, ry, rz, rt, rxi, c, sx, sy, nvb, hx, cy < P.ny - 1, hz, lx);
+        xc = vol_ld(rx, c, 0);
+        if (lx) xl = vol_ld(rx, c - sx, 0);
+    }
+    for (; cy < y1; ++cy, c += sy) {
+        const bool hy = cy < P.ny - 1;
+        if (act && cy + 1 < y1)
+            tv_row_load<DTV>(nxt, rx, ry, rz, rt, rxi, c + sy, sx, sy, nvb, hx, cy + 1 < P.ny - 1,
+                             hz, lx);
+        float q[3], dy[3] = {0.0f, 0.0f, 0.0f}, qn[3], dn[3] = {0.0f, 0.0f, 0.0f};
+        if (act) {
+            prior_dual_vals(P, hx ? cur.xp - xc : 0.0f, hy ? cur.xn - xc : 0.0f,
+                            hz ? cur.xz - xc : 0.0f, cur.y0, cur.y1, cur.y2, cur.i0, cur.i1,
+                            cur.i2, q, dy);
+            // x-neighbour (cx - 1, cy, cz): its +x difference is x(c) - x(c - e_x)
+            if (lx)
+                prior_dual_vals(P, xc - xl, hy ? cur.lxn - xl : 0.0f, hz ? cur.lxz - xl : 0.0f,
+                                cur.ly0, cur.ly1, cur.ly2, cur.li0, cur.li1, cur.li2, qn, dn);
+        }
+        const float dzn = __shfl_up(dy[2], 1, 64);  // all lanes take part
+        if (own && cy >= y0) {
+            // grad^T p (v) = sum_d [v_d > 0] p_d(v - e_d) - [v_d < N_d - 1] p_d(v)
+            float dz = 0.0f;
+            if (hx) dz -= dy[0];
+            if (hy) dz -= dy[1];
+            if (hz) dz -= dy[2];
+            if (lx) dz += dn[0];
+            if (cy > 0) dz += dprev;
+            if (cz > 0) dz += dzn;
+            vol_st(ryo, c, 0, q[0]);
+            vol_st(ryo, c, nvb, q[1]);
+            vol_st(ryo, c, 2 * nvb, q[2]);
+            const float zn = cur.z + dz;
+            vol_st(rz, c, 0, zn);
+            const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
+            vol_st(rxo, c, 0, fmaxf(xc - cur.t * zbar, 0.0f));
+        }
+        dprev = dy[1];
+        xc = cur.xn;
+        xl = cur.lxn;
+        cur = nxt;
+    }
 }
 
 // Prior term alpha sum_v |(A_n x)_v|_2 (FP64 partials; 0 when use_grad is 0) plus the

@@ -442,6 +442,17 @@ int prior_blocks(const spdhg_geom& g, const PriorTile& TL) {
     return ((g.nx + TL.tx - 1) / TL.tx) * ((g.ny + TL.ty - 1) / TL.ty);
 }
 
+constexpr int TV_WAVE_LY = 8;  // rows per chunk of the wavefront TV kernel
+// The wavefront-march TV kernel (one wavefront per 64-voxel run of a column) for volumes
+// with at least 32 planes; thinner volumes use the column tiles.
+bool tv_use_wave(const spdhg_geom& g) { return g.nz >= 32 && g.nz <= 128; }
+
+int tv_wave_blocks(const spdhg_geom& g, int ly) {
+    const int runs = g.nz <= 64 ? 1 : (g.nz + 61) / 63;  // runs of 64 overlapping by one
+    const int64_t waves = (int64_t)runs * g.nx * ((g.ny + ly - 1) / ly);
+    return (int)((waves + 3) / 4);
+}
+
 }  // namespace
 
 // ====================================================================== context
@@ -1249,10 +1260,22 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
         } else {
             P.inv_p = inv_p;
             if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
-            const PriorTile TL = prior_tile(c->geom);
-            tv_iter<<<prior_blocks(c->geom, TL), TL.tx * TL.ty * c->geom.nz, 0, st>>>(
-                P, TL, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
-                c->T, c->xi);
+            if (tv_use_wave(c->geom)) {
+                const int ly = std::min(TV_WAVE_LY, c->geom.ny);
+                if (P.dtv)
+                    tv_wave<true><<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
+                        P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur],
+                        c->z, c->T, c->xi);
+                else
+                    tv_wave<false><<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
+                        P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur],
+                        c->z, c->T, c->xi);
+            } else {
+                const PriorTile TL = prior_tile(c->geom);
+                tv_iter<<<prior_blocks(c->geom, TL), TL.tx * TL.ty * c->geom.nz, 0, st>>>(
+                    P, TL, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
+                    c->T, c->xi);
+            }
             LAUNCH_CHECK();
             if ((rc = prof_end(c, st))) return rc;
             c->x_cur ^= 1;

@@ -49,6 +49,14 @@ def tall3d():
     return synth.brain_problem(g, 18080400, 5e5)
 
 
+@pytest.fixture(scope="module")
+def deep3d():
+    """nz = 70 (two 64-lane runs per column), odd and ragged in-plane sizes."""
+    g = synth.Geometry(nx=21, ny=21, nz=70, vx=5.0, vy=5.0, vz=5.0, n_rad=26, d_rad=5.0,
+                       n_ang=8, seg_planes=(70, 66, 66), seg_tan=(0.0, 0.25, -0.25))
+    return synth.brain_problem(g, 18080600, 5e5, with_side=True)
+
+
 def run_pair(P, d, n_subsets, prior, epochs, seed, sampling="uniform", precond=True,
              alpha=0.1, side=None, eta=1e-2, alpha1=0.0):
     g = d["geom"]
@@ -186,6 +194,20 @@ def test_tall3d_tv_parity(P, tall3d, sampling, precond, m):
     print(f"[spdhg] tall3d TV {sampling} precond={precond} m={m}", flush=True)
     prob, st, rec, x = run_pair(P, tall3d, m, "tv", 10, seed=31, sampling=sampling,
                                 precond=precond, alpha=0.05)
+    xo = prob.reported(st)[0]
+    assert rel(x.cpu().numpy(), xo) <= 1e-3
+    psi_o = prob.objective(xo[None])
+    assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+@pytest.mark.parametrize("prior", ["tv", "dtv", "atv"])
+def test_deep3d_prior_parity(P, deep3d, prior):
+    """nz = 70, ny = 21: the wavefront TV kernel with two runs per column (the upper run's
+    first lane recomputes its z-neighbour) and a ragged last row chunk."""
+    print(f"[spdhg] deep3d {prior}", flush=True)
+    side = deep3d["side"] if prior == "dtv" else None
+    prob, st, rec, x = run_pair(P, deep3d, 4, prior, 10, seed=37, sampling="balanced",
+                                alpha=0.05, side=side)
     xo = prob.reported(st)[0]
     assert rel(x.cpu().numpy(), xo) <= 1e-3
     psi_o = prob.objective(xo[None])
