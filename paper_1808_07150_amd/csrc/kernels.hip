@@ -20,6 +20,7 @@
 //   tv_wave    TV / dTV prior block (dual ascent, l2-ball projection, adjoint, epilogue),
 //              one wavefront per 64-voxel run of a column marching along y (nz >= 32);
 //   tv_iter    the same on column tiles of one workgroup (thin volumes).
+//   tgv1_wave / tgv2_wave (tgv1_iter / tgv2_iter on tiles): the two TGV prior blocks.
 //   reductions deterministic FP64 block partials + ordered final sum.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -1265,22 +1266,14 @@ __device__ __forceinline__ ZfStrides zf_strides(int nx, int ny, int nz) {
     return S;
 }
 
-// Block n-1 dual update at voxel (cx, cy, cz): q = P_alpha0(q1 + sigma (grad u - w)),
-// dq = q - q1.
-__device__ __forceinline__ void tgv1_dual_at(const TgvArgs& P, const float* __restrict__ u,
-                                             const float* __restrict__ w,
-                                             const float* __restrict__ q1, int cx, int cy,
-                                             int cz, float q[3], float dq[3]) {
-    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
-    const int64_t c = (int64_t)cy * S.sy + (int64_t)cx * S.sx + cz;
-    const float uc = u[c];
-    const float g0 = cx < P.nx - 1 ? u[c + S.sx] - uc : 0.0f;
-    const float g1 = cy < P.ny - 1 ? u[c + S.sy] - uc : 0.0f;
-    const float g2 = cz < P.nz - 1 ? u[c + 1] - uc : 0.0f;
-    const float y0 = q1[c], y1 = q1[c + S.nv], y2 = q1[c + 2 * S.nv];
-    q[0] = __builtin_fmaf(P.sigma, g0 - w[c], y0);
-    q[1] = __builtin_fmaf(P.sigma, g1 - w[c + S.nv], y1);
-    q[2] = __builtin_fmaf(P.sigma, g2 - w[c + 2 * S.nv], y2);
+// Block n-1 dual update from the forward differences g of u (zero on the high faces),
+// w and q1 at one voxel: q = P_alpha0(q1 + sigma (grad u - w)), dq = q - q1.
+__device__ __forceinline__ void tgv1_dual_vals(const TgvArgs& P, float g0, float g1, float g2,
+                                               float w0, float w1, float w2, float y0, float y1,
+                                               float y2, float q[3], float dq[3]) {
+    q[0] = __builtin_fmaf(P.sigma, g0 - w0, y0);
+    q[1] = __builtin_fmaf(P.sigma, g1 - w1, y1);
+    q[2] = __builtin_fmaf(P.sigma, g2 - w2, y2);
     const float nrm = __builtin_sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
     if (nrm > P.alpha) {
         const float sc = P.alpha / nrm;
@@ -1291,6 +1284,21 @@ __device__ __forceinline__ void tgv1_dual_at(const TgvArgs& P, const float* __re
     dq[0] = q[0] - y0;
     dq[1] = q[1] - y1;
     dq[2] = q[2] - y2;
+}
+
+// The same at voxel (cx, cy, cz), loading everything it needs.
+__device__ __forceinline__ void tgv1_dual_at(const TgvArgs& P, const float* __restrict__ u,
+                                             const float* __restrict__ w,
+                                             const float* __restrict__ q1, int cx, int cy,
+                                             int cz, float q[3], float dq[3]) {
+    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
+    const int64_t c = (int64_t)cy * S.sy + (int64_t)cx * S.sx + cz;
+    const float uc = u[c];
+    const float g0 = cx < P.nx - 1 ? u[c + S.sx] - uc : 0.0f;
+    const float g1 = cy < P.ny - 1 ? u[c + S.sy] - uc : 0.0f;
+    const float g2 = cz < P.nz - 1 ? u[c + 1] - uc : 0.0f;
+    tgv1_dual_vals(P, g0, g1, g2, w[c], w[c + S.nv], w[c + 2 * S.nv], q1[c], q1[c + S.nv],
+                   q1[c + 2 * S.nv], q, dq);
 }
 
 // Algorithm 2 lines 5-8 for block n-1 fused with line 3 of the next iteration:
@@ -1352,6 +1360,16 @@ tgv1_iter(TgvArgs P, PriorTile TL, const float* __restrict__ u_in, float* __rest
     u_out[t] = fmaxf(u_in[t] - Tu[t] * __builtin_fmaf(dzu, P.inv_p, zn), 0.0f);
 }
 
+// E w from the forward differences J[k][l] of w_k along axis l.
+__device__ __forceinline__ void sym_grad_vals(const float J[3][3], float e[6]) {
+    e[0] = J[0][0];
+    e[1] = J[1][1];
+    e[2] = J[2][2];
+    e[3] = TGV_SQRT_HALF * (J[0][1] + J[1][0]);
+    e[4] = TGV_SQRT_HALF * (J[0][2] + J[2][0]);
+    e[5] = TGV_SQRT_HALF * (J[1][2] + J[2][1]);
+}
+
 // E w at voxel (cx, cy, cz), 6 components.
 __device__ __forceinline__ void sym_grad_at(int nx, int ny, int nz, const float* __restrict__ w,
                                             int cx, int cy, int cz, float e[6]) {
@@ -1367,26 +1385,17 @@ __device__ __forceinline__ void sym_grad_at(int nx, int ny, int nz, const float*
 #pragma unroll
         for (int l = 0; l < 3; ++l) J[k][l] = in[l] ? wk[c + step[l]] - wc : 0.0f;
     }
-    e[0] = J[0][0];
-    e[1] = J[1][1];
-    e[2] = J[2][2];
-    e[3] = TGV_SQRT_HALF * (J[0][1] + J[1][0]);
-    e[4] = TGV_SQRT_HALF * (J[0][2] + J[2][0]);
-    e[5] = TGV_SQRT_HALF * (J[1][2] + J[2][1]);
+    sym_grad_vals(J, e);
 }
 
-// Block n dual update at a voxel: q = P_alpha1(q2 + sigma E w), dq = q - q2.
-__device__ __forceinline__ void tgv2_dual_at(const TgvArgs& P, const float* __restrict__ w,
-                                             const float* __restrict__ q2, int cx, int cy,
-                                             int cz, float q[6], float dq[6]) {
-    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
-    const int64_t c = (int64_t)cy * S.sy + (int64_t)cx * S.sx + cz;
-    float e[6];
-    sym_grad_at(P.nx, P.ny, P.nz, w, cx, cy, cz, e);
+// Block n dual update from e = E w and q2 at one voxel: q = P_alpha1(q2 + sigma e),
+// dq = q - q2.
+__device__ __forceinline__ void tgv2_dual_vals(const TgvArgs& P, const float e[6],
+                                               const float y[6], float q[6], float dq[6]) {
     float ss = 0.0f;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        q[k] = __builtin_fmaf(P.sigma, e[k], q2[c + k * S.nv]);
+        q[k] = __builtin_fmaf(P.sigma, e[k], y[k]);
         ss = __builtin_fmaf(q[k], q[k], ss);
     }
     const float nrm = __builtin_sqrtf(ss);
@@ -1394,8 +1403,21 @@ __device__ __forceinline__ void tgv2_dual_at(const TgvArgs& P, const float* __re
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         if (nrm > P.alpha) q[k] *= sc;
-        dq[k] = q[k] - q2[c + k * S.nv];
+        dq[k] = q[k] - y[k];
     }
+}
+
+// Block n dual update at voxel (cx, cy, cz), loading everything it needs.
+__device__ __forceinline__ void tgv2_dual_at(const TgvArgs& P, const float* __restrict__ w,
+                                             const float* __restrict__ q2, int cx, int cy,
+                                             int cz, float q[6], float dq[6]) {
+    const ZfStrides S = zf_strides(P.nx, P.ny, P.nz);
+    const int64_t c = (int64_t)cy * S.sy + (int64_t)cx * S.sx + cz;
+    float e[6], y[6];
+    sym_grad_at(P.nx, P.ny, P.nz, w, cx, cy, cz, e);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] = q2[c + k * S.nv];
+    tgv2_dual_vals(P, e, y, q, dq);
 }
 
 // Algorithm 2 lines 5-8 for block n fused with line 3 of the next iteration:
@@ -1460,6 +1482,279 @@ tgv2_iter(TgvArgs P, PriorTile TL, const float* __restrict__ u_in, float* __rest
         w_out[i] = w_in[i] - P.tw * __builtin_fmaf(dzw[k], P.inv_p, zn);
     }
     u_out[t] = fmaxf(u_in[t] - Tu[t] * zu[t], 0.0f);
+}
+
+// Wavefront forms of tgv1_iter and tgv2_iter for volumes with 32 <= nz <= 128, laid out
+// as tv_wave: one wavefront per run of 64 voxels of a column (runs overlap by one voxel,
+// the first lane of a run above the first only passes its dual change on), marching
+// along y through a chunk of rows that starts one row early, the y-neighbour's change
+// carried in registers, the z-neighbour's taken from the next-lower lane and the
+// x-neighbour's recomputed.  In tgv1_wave each row's loads are issued before the
+// previous row's stores; tgv2_wave, with twice the inputs per row, loads its row when it
+// gets there (the prefetching form needed 103 registers and was no faster).  Every
+// 6-component field stays below 4 GiB (checked by the host).
+struct WaveMap {
+    int cx, cz, y0, y1, lane;
+    bool act, own;
+};
+
+__device__ __forceinline__ bool wave_map(int nx, int ny, int nz, int ly, WaveMap& m) {
+    const int nh = nz <= 64 ? 1 : (nz + 61) / 63;  // ceil((nz - 1) / 63)
+    m.lane = threadIdx.x & 63;
+    const int gw = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int h = gw % nh;
+    const int rest = gw / nh;
+    m.cx = rest % nx;
+    m.y0 = (rest / nx) * ly;
+    if (m.y0 >= ny) return false;
+    m.y1 = min(ny, m.y0 + ly);
+    m.cz = 63 * h + m.lane;
+    m.act = m.cz < nz;
+    m.own = m.act && (h == 0 || m.lane > 0);
+    return true;
+}
+
+struct Tgv1Row {
+    float up, un, uz;     // u(c + e_x), u(c + e_y), u(c + e_z)
+    float w[3], y[3], zw[3], zu, t;
+    float lun, luz;       // x-neighbour: u(c - e_x + e_y), u(c - e_x + e_z)
+    float lw[3], ly[3];   // w(c - e_x), q1(c - e_x)
+};
+
+__device__ __forceinline__ void tgv1_row_load(Tgv1Row& r, __amdgpu_buffer_rsrc_t ru,
+                                              __amdgpu_buffer_rsrc_t rw, __amdgpu_buffer_rsrc_t rq,
+                                              __amdgpu_buffer_rsrc_t rzu, __amdgpu_buffer_rsrc_t rzw,
+                                              __amdgpu_buffer_rsrc_t rt, uint32_t c, uint32_t sx,
+                                              uint32_t sy, uint32_t nvb, bool hx, bool hy, bool hz,
+                                              bool lx) {
+    r.up = hx ? vol_ld(ru, c + sx, 0) : 0.0f;
+    r.un = hy ? vol_ld(ru, c + sy, 0) : 0.0f;
+    r.uz = hz ? vol_ld(ru, c + 4, 0) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r.w[k] = vol_ld(rw, c, k * nvb);
+        r.y[k] = vol_ld(rq, c, k * nvb);
+        r.zw[k] = vol_ld(rzw, c, k * nvb);
+    }
+    r.zu = vol_ld(rzu, c, 0);
+    r.t = vol_ld(rt, c, 0);
+    r.lun = r.luz = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.lw[k] = r.ly[k] = 0.0f;
+    if (lx) {
+        const uint32_t cl = c - sx;
+        r.lun = hy ? vol_ld(ru, cl + sy, 0) : 0.0f;
+        r.luz = hz ? vol_ld(ru, cl + 4, 0) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            r.lw[k] = vol_ld(rw, cl, k * nvb);
+            r.ly[k] = vol_ld(rq, cl, k * nvb);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+tgv1_wave(TgvArgs P, int ly, const float* __restrict__ u_in, float* __restrict__ u_out,
+          const float* __restrict__ w_in, float* __restrict__ w_out,
+          const float* __restrict__ q_in, float* __restrict__ q_out, float* __restrict__ zu,
+          float* __restrict__ zw, const float* __restrict__ Tu) {
+    const uint32_t sx = 4u * P.nz, sy = 4u * P.nz * P.nx;
+    const uint32_t nvb = sy * P.ny;
+    const auto ru = vol_rsrc(u_in, nvb), ruo = vol_rsrc(u_out, nvb);
+    const auto rw = vol_rsrc(w_in, 3 * nvb), rwo = vol_rsrc(w_out, 3 * nvb);
+    const auto rq = vol_rsrc(q_in, 3 * nvb), rqo = vol_rsrc(q_out, 3 * nvb);
+    const auto rzu = vol_rsrc(zu, nvb), rzw = vol_rsrc(zw, 3 * nvb), rt = vol_rsrc(Tu, nvb);
+    WaveMap m;
+    if (!wave_map(P.nx, P.ny, P.nz, ly, m)) return;
+    const int cx = m.cx, cz = m.cz;
+    const bool hx = cx < P.nx - 1, lx = cx > 0, hz = cz < P.nz - 1;
+    int cy = m.y0 > 0 ? m.y0 - 1 : m.y0;
+    uint32_t c = 4u * (((uint32_t)cy * P.nx + cx) * P.nz + min(cz, P.nz - 1));
+    Tgv1Row cur = {}, nxt = {};
+    float uc = 0.0f, ul = 0.0f, dprev = 0.0f;
+    if (m.act) {
+        tgv1_row_load(cur, ru, rw, rq, rzu, rzw, rt, c, sx, sy, nvb, hx, cy < P.ny - 1, hz, lx);
+        uc = vol_ld(ru, c, 0);
+        if (lx) ul = vol_ld(ru, c - sx, 0);
+    }
+    for (; cy < m.y1; ++cy, c += sy) {
+        const bool hy = cy < P.ny - 1;
+        if (m.act && cy + 1 < m.y1)
+            tgv1_row_load(nxt, ru, rw, rq, rzu, rzw, rt, c + sy, sx, sy, nvb, hx,
+                          cy + 1 < P.ny - 1, hz, lx);
+        float q[3], dq[3] = {0.0f, 0.0f, 0.0f}, qn[3], dn[3] = {0.0f, 0.0f, 0.0f};
+        if (m.act) {
+            tgv1_dual_vals(P, hx ? cur.up - uc : 0.0f, hy ? cur.un - uc : 0.0f,
+                           hz ? cur.uz - uc : 0.0f, cur.w[0], cur.w[1], cur.w[2], cur.y[0],
+                           cur.y[1], cur.y[2], q, dq);
+            if (lx)  // x-neighbour: its +x difference of u is u(c) - u(c - e_x)
+                tgv1_dual_vals(P, uc - ul, hy ? cur.lun - ul : 0.0f, hz ? cur.luz - ul : 0.0f,
+                               cur.lw[0], cur.lw[1], cur.lw[2], cur.ly[0], cur.ly[1], cur.ly[2],
+                               qn, dn);
+        }
+        const float dzn = __shfl_up(dq[2], 1, 64);
+        if (m.own && cy >= m.y0) {
+            float dzu = 0.0f;
+            if (hx) dzu -= dq[0];
+            if (hy) dzu -= dq[1];
+            if (hz) dzu -= dq[2];
+            if (lx) dzu += dn[0];
+            if (cy > 0) dzu += dprev;
+            if (cz > 0) dzu += dzn;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                vol_st(rqo, c, k * nvb, q[k]);
+                const float dzw = -dq[k];
+                const float zn = cur.zw[k] + dzw;
+                vol_st(rzw, c, k * nvb, zn);
+                vol_st(rwo, c, k * nvb, cur.w[k] - P.tw * __builtin_fmaf(dzw, P.inv_p, zn));
+            }
+            const float zn = cur.zu + dzu;
+            vol_st(rzu, c, 0, zn);
+            vol_st(ruo, c, 0, fmaxf(uc - cur.t * __builtin_fmaf(dzu, P.inv_p, zn), 0.0f));
+        }
+        dprev = dq[1];
+        uc = cur.un;
+        ul = cur.lun;
+        cur = nxt;
+    }
+}
+
+struct Tgv2Row {
+    float wp[3], wn[3], wz[3];  // w_k(c + e_x), w_k(c + e_y), w_k(c + e_z)
+    float y[6];                 // q2(c)
+    float zw[3], u, t, zu;      // z_w(c), u(c), T_u(c), z_u(c)
+    float lwn[3], lwz[3];       // x-neighbour: w_k(c - e_x + e_y), w_k(c - e_x + e_z)
+    float ly[6];                // q2(c - e_x)
+};
+
+__device__ __forceinline__ void tgv2_row_load(Tgv2Row& r, __amdgpu_buffer_rsrc_t ru,
+                                              __amdgpu_buffer_rsrc_t rw, __amdgpu_buffer_rsrc_t rq,
+                                              __amdgpu_buffer_rsrc_t rzu, __amdgpu_buffer_rsrc_t rzw,
+                                              __amdgpu_buffer_rsrc_t rt, uint32_t c, uint32_t sx,
+                                              uint32_t sy, uint32_t nvb, bool hx, bool hy, bool hz,
+                                              bool lx) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r.wp[k] = hx ? vol_ld(rw, c + sx, k * nvb) : 0.0f;
+        r.wn[k] = hy ? vol_ld(rw, c + sy, k * nvb) : 0.0f;
+        r.wz[k] = hz ? vol_ld(rw, c + 4, k * nvb) : 0.0f;
+        r.zw[k] = vol_ld(rzw, c, k * nvb);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.y[k] = vol_ld(rq, c, k * nvb);
+    r.u = vol_ld(ru, c, 0);
+    r.t = vol_ld(rt, c, 0);
+    r.zu = vol_ld(rzu, c, 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.lwn[k] = r.lwz[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.ly[k] = 0.0f;
+    if (lx) {
+        const uint32_t cl = c - sx;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            r.lwn[k] = hy ? vol_ld(rw, cl + sy, k * nvb) : 0.0f;
+            r.lwz[k] = hz ? vol_ld(rw, cl + 4, k * nvb) : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) r.ly[k] = vol_ld(rq, cl, k * nvb);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+tgv2_wave(TgvArgs P, int ly, const float* __restrict__ u_in, float* __restrict__ u_out,
+          const float* __restrict__ w_in, float* __restrict__ w_out,
+          const float* __restrict__ q_in, float* __restrict__ q_out, const float* __restrict__ zu,
+          float* __restrict__ zw, const float* __restrict__ Tu) {
+    const uint32_t sx = 4u * P.nz, sy = 4u * P.nz * P.nx;
+    const uint32_t nvb = sy * P.ny;
+    const auto ru = vol_rsrc(u_in, nvb), ruo = vol_rsrc(u_out, nvb);
+    const auto rw = vol_rsrc(w_in, 3 * nvb), rwo = vol_rsrc(w_out, 3 * nvb);
+    const auto rq = vol_rsrc(q_in, 6 * nvb), rqo = vol_rsrc(q_out, 6 * nvb);
+    const auto rzu = vol_rsrc(zu, nvb), rzw = vol_rsrc(zw, 3 * nvb), rt = vol_rsrc(Tu, nvb);
+    WaveMap m;
+    if (!wave_map(P.nx, P.ny, P.nz, ly, m)) return;
+    const int cx = m.cx, cz = m.cz;
+    const bool hx = cx < P.nx - 1, lx = cx > 0, hz = cz < P.nz - 1;
+    int cy = m.y0 > 0 ? m.y0 - 1 : m.y0;
+    uint32_t c = 4u * (((uint32_t)cy * P.nx + cx) * P.nz + min(cz, P.nz - 1));
+    Tgv2Row cur = {};
+    float wc[3] = {0.0f, 0.0f, 0.0f}, wl[3] = {0.0f, 0.0f, 0.0f};
+    float dprev[3] = {0.0f, 0.0f, 0.0f};  // y-neighbour's changes of entries (k, y)
+    if (m.act) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            wc[k] = vol_ld(rw, c, k * nvb);
+            if (lx) wl[k] = vol_ld(rw, c - sx, k * nvb);
+        }
+    }
+    // entry (k, l) of the symmetric matrix -> component
+    constexpr int ent[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (; cy < m.y1; ++cy, c += sy) {
+        const bool hy = cy < P.ny - 1;
+        if (m.act) tgv2_row_load(cur, ru, rw, rq, rzu, rzw, rt, c, sx, sy, nvb, hx, hy, hz, lx);
+        float q[6], dq[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, qn[6];
+        float dn[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (m.act) {
+            float J[3][3], e[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                J[k][0] = hx ? cur.wp[k] - wc[k] : 0.0f;
+                J[k][1] = hy ? cur.wn[k] - wc[k] : 0.0f;
+                J[k][2] = hz ? cur.wz[k] - wc[k] : 0.0f;
+            }
+            sym_grad_vals(J, e);
+            tgv2_dual_vals(P, e, cur.y, q, dq);
+            if (lx) {  // x-neighbour: its +x differences are w_k(c) - w_k(c - e_x)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    J[k][0] = wc[k] - wl[k];
+                    J[k][1] = hy ? cur.lwn[k] - wl[k] : 0.0f;
+                    J[k][2] = hz ? cur.lwz[k] - wl[k] : 0.0f;
+                }
+                sym_grad_vals(J, e);
+                tgv2_dual_vals(P, e, cur.ly, qn, dn);
+            }
+        }
+        float dzn[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dzn[k] = __shfl_up(dq[ent[k][2]], 1, 64);
+        if (m.own && cy >= m.y0) {
+            // dz_w = E^T dq: (E^T p)_k = sum_l wgt(k, l) D_l^T p_(k, l)
+            const bool back[3] = {lx, cy > 0, cz > 0};
+            const bool fwd[3] = {hx, hy, hz};
+            float dzw[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int e = ent[k][ax];
+                    const float wgt = (k == ax) ? 1.0f : TGV_SQRT_HALF;
+                    const float nb = ax == 0 ? dn[e] : (ax == 1 ? dprev[k] : dzn[k]);
+                    float v = 0.0f;
+                    if (back[ax]) v += nb;
+                    if (fwd[ax]) v -= dq[e];
+                    dzw[k] = __builtin_fmaf(wgt, v, dzw[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) vol_st(rqo, c, k * nvb, q[k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float zn = cur.zw[k] + dzw[k];
+                vol_st(rzw, c, k * nvb, zn);
+                vol_st(rwo, c, k * nvb, wc[k] - P.tw * __builtin_fmaf(dzw[k], P.inv_p, zn));
+            }
+            vol_st(ruo, c, 0, fmaxf(cur.u - cur.t * cur.zu, 0.0f));
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dprev[k] = dq[ent[k][1]];
+            wc[k] = cur.wn[k];
+            wl[k] = cur.lwn[k];
+        }
+    }
 }
 
 // Line 3 for the w component over k data iterations (their dz_w is 0, so z_w is

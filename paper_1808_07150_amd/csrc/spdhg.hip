@@ -443,9 +443,13 @@ int prior_blocks(const spdhg_geom& g, const PriorTile& TL) {
 }
 
 constexpr int TV_WAVE_LY = 8;  // rows per chunk of the wavefront TV kernel
-// The wavefront-march TV kernel (one wavefront per 64-voxel run of a column) for volumes
-// with at least 32 planes; thinner volumes use the column tiles.
-bool tv_use_wave(const spdhg_geom& g) { return g.nz >= 32 && g.nz <= 128; }
+// The wavefront-march prior kernels (one wavefront per 64-voxel run of a column) for
+// volumes with at least 32 planes whose `comps`-component fields stay below 4 GiB (32-bit
+// buffer offsets); thinner volumes use the column tiles.
+bool prior_use_wave(const spdhg_geom& g, int comps) {
+    const uint64_t bytes = (uint64_t)comps * 4 * g.nx * g.ny * g.nz;
+    return g.nz >= 32 && g.nz <= 128 && bytes < (1ull << 32);
+}
 
 int tv_wave_blocks(const spdhg_geom& g, int ly) {
     const int runs = g.nz <= 64 ? 1 : (g.nz + 61) / 63;  // runs of 64 overlapping by one
@@ -1242,7 +1246,20 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
             const PriorTile TL = prior_tile(c->geom);
             const int nb_t = prior_blocks(c->geom, TL), nt_t = TL.tx * TL.ty * c->geom.nz;
-            if (j == 0) {
+            const int ly = std::min(TV_WAVE_LY, c->geom.ny);
+            if (prior_use_wave(c->geom, 6)) {
+                if (j == 0) {
+                    tgv1_wave<<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
+                        A, ly, c->xcur(), c->xother(), c->w[c->w_cur], c->w[1 - c->w_cur],
+                        c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z, c->zw, c->T);
+                    c->yn_cur ^= 1;
+                } else {
+                    tgv2_wave<<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
+                        A, ly, c->xcur(), c->xother(), c->w[c->w_cur], c->w[1 - c->w_cur],
+                        c->q2[c->q2_cur], c->q2[1 - c->q2_cur], c->z, c->zw, c->T);
+                    c->q2_cur ^= 1;
+                }
+            } else if (j == 0) {
                 tgv1_iter<<<nb_t, nt_t, 0, st>>>(A, TL, c->xcur(), c->xother(), c->w[c->w_cur],
                                                  c->w[1 - c->w_cur], c->yn[c->yn_cur],
                                                  c->yn[1 - c->yn_cur], c->z, c->zw, c->T);
@@ -1260,7 +1277,7 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
         } else {
             P.inv_p = inv_p;
             if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
-            if (tv_use_wave(c->geom)) {
+            if (prior_use_wave(c->geom, 3)) {
                 const int ly = std::min(TV_WAVE_LY, c->geom.ny);
                 if (P.dtv)
                     tv_wave<true><<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(

@@ -200,17 +200,20 @@ def test_tall3d_tv_parity(P, tall3d, sampling, precond, m):
     assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
 
 
-@pytest.mark.parametrize("prior", ["tv", "dtv", "atv"])
+@pytest.mark.parametrize("prior", ["tv", "dtv", "atv", "tgv"])
 def test_deep3d_prior_parity(P, deep3d, prior):
-    """nz = 70, ny = 21: the wavefront TV kernel with two runs per column (the upper run's
-    first lane recomputes its z-neighbour) and a ragged last row chunk."""
+    """nz = 70, ny = 21: the wavefront prior kernels with two overlapping runs per column
+    (the upper run's first lane only passes its dual change on) and a ragged last row
+    chunk."""
     print(f"[spdhg] deep3d {prior}", flush=True)
     side = deep3d["side"] if prior == "dtv" else None
     prob, st, rec, x = run_pair(P, deep3d, 4, prior, 10, seed=37, sampling="balanced",
-                                alpha=0.05, side=side)
-    xo = prob.reported(st)[0]
-    assert rel(x.cpu().numpy(), xo) <= 1e-3
-    psi_o = prob.objective(xo[None])
+                                alpha=0.05, side=side, alpha1=0.025 if prior == "tgv" else 0.0)
+    X = prob.reported(st)
+    assert rel(x.cpu().numpy(), X[0]) <= 1e-3
+    if prior == "tgv":
+        assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
+    psi_o = prob.objective(X)
     assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
 
 
