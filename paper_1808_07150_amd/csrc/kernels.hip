@@ -486,6 +486,30 @@ __device__ __forceinline__ float tap_sum_rsrc(__amdgpu_buffer_rsrc_t seg, const 
     return __builtin_fmaf(t.wb, ub, h);
 }
 
+// Both taps of z = lane and z = lane + 64 for one (ray, segment) from two loads: plane
+// p - 1 of z = lane (lane_m1 holds lane - 1) and of z = lane + 64 (lane_63 holds
+// lane + 63).  Plane p of each is plane p - 1 of the next-higher lane (a wavefront shift
+// by one lane); for lane 63 of the lower half it is lane 0 of the upper half.  The upper
+// half's lane 63 (z = 127) gets no valid value.
+__device__ __forceinline__ void tap_pair_loads(__amdgpu_buffer_rsrc_t seg, const TapCoef& t,
+                                               int lane_m1, int lane_63, float& b0, float& b1) {
+    b0 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, (lane_m1 + t.off) * 4, 0, 0));
+    b1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, (lane_63 + t.off) * 4, 0, 0));
+}
+
+__device__ __forceinline__ void tap_pair_sum(const TapCoef& t, float b0, float b1, float& h0,
+                                             float& h1) {
+    const int top = __builtin_amdgcn_readlane(__float_as_int(b1), 0);
+    const float a0 = __int_as_float(
+        __builtin_amdgcn_update_dpp(top, __float_as_int(b0), 0x130 /* wave_shl:1 */, 0xF, 0xF, false));
+    const float a1 = __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(b1), 0x130 /* wave_shl:1 */, 0xF, 0xF, false));
+    h0 = __builtin_fmaf(t.wa, a0, h0);
+    h0 = __builtin_fmaf(t.wb, b0, h0);
+    h1 = __builtin_fmaf(t.wa, a1, h1);
+    h1 = __builtin_fmaf(t.wb, b1, h1);
+}
+
 // The same with explicit bounds (per-lane rays).
 __device__ __forceinline__ float tap_sum_masked(const float* __restrict__ seg, int n,
                                                 const TapCoef& t, int z, float h) {
@@ -638,8 +662,9 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 //      monotonic in the radial bin, so the range is contiguous);
 //   2. per cell (unrolled) and ray of its range (a wave-uniform loop) the axial gather
 //      h(z) = sum_g wa_g d(z + off_g) + wb_g d(z + off_g - 1), lanes along z reading the
-//      padded dual change contiguously, added with the in-plane weights 1 - fu and fu to
-//      the strip columns c and c + 1.
+//      dual change contiguously (each plane is loaded once: the second tap comes from
+//      the next lane by a wavefront shift), added with the in-plane weights 1 - fu and
+//      fu to the strip columns c and c + 1.
 // Every ray's axial gather is computed once per strip and angle and serves both columns
 // it touches; the accumulators stay in registers with static indices.  The row-sampled
 // angles of a subset write a partial image that the column-sampled launch adds before its
@@ -671,10 +696,11 @@ __global__ void __launch_bounds__(64, 8) bwd_strip(BwdArgs P, int KR, int rowdom
     const int sidx = blk / n_prim;
     const int j = blk - sidx * n_prim;
     const int s0 = sidx * BS_W;
-    // lane + 64 through a register copy the compiler cannot fold into an immediate
-    // buffer offset (the hardware range check must see the whole offset)
-    int lane_hi;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_hi) : "v"(lane + 64));
+    // lane - 1 and lane + 63 through register copies the compiler cannot fold into an
+    // immediate buffer offset (the hardware range check must see the whole offset)
+    int lane_m1, lane_63;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_m1) : "v"(lane - 1));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_63) : "v"(lane + 63));
     float acc[BS_W][2];
 #pragma unroll
     for (int c = 0; c < BS_W; ++c) acc[c][0] = acc[c][1] = 0.0f;
@@ -725,35 +751,21 @@ __global__ void __launch_bounds__(64, 8) bwd_strip(BwdArgs P, int KR, int rowdom
                 const float* dk = P.d + dual_row(G, ia, klo + kr);
                 const TapCoef* tk = tc + kr * ns;
                 float h0 = 0.0f, h1 = 0.0f;
-                // segments in pairs: all eight loads of a pair are issued before its taps
-                // are summed
+                // segments in fours: all eight loads are issued before the taps are summed
                 int g = 0;
-                for (; g + 2 <= ns; g += 2) {
-                    float v[2][4];
+                for (; g + 4 <= ns; g += 4) {
+                    float v[4][2];
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        const TapCoef t = tk[g + u];
-                        const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g + u);
-                        const int va = (lane + t.off) * 4, vb = (lane_hi + t.off) * 4;
-                        v[u][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, va, 0, 0));
-                        v[u][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, va - 4, 0, 0));
-                        v[u][2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vb, 0, 0));
-                        v[u][3] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vb - 4, 0, 0));
-                    }
+                    for (int u = 0; u < 4; ++u)
+                        tap_pair_loads(seg_rsrc(G, dk, g + u), tk[g + u], lane_m1, lane_63,
+                                       v[u][0], v[u][1]);
 #pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        const TapCoef t = tk[g + u];
-                        h0 = __builtin_fmaf(t.wa, v[u][0], h0);
-                        h0 = __builtin_fmaf(t.wb, v[u][1], h0);
-                        h1 = __builtin_fmaf(t.wa, v[u][2], h1);
-                        h1 = __builtin_fmaf(t.wb, v[u][3], h1);
-                    }
+                    for (int u = 0; u < 4; ++u) tap_pair_sum(tk[g + u], v[u][0], v[u][1], h0, h1);
                 }
                 for (; g < ns; ++g) {
-                    const TapCoef t = tk[g];
-                    const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g);
-                    h0 = tap_sum_rsrc(rs, t, lane, h0);
-                    h1 = tap_sum_rsrc(rs, t, lane_hi, h1);
+                    float b0, b1;
+                    tap_pair_loads(seg_rsrc(G, dk, g), tk[g], lane_m1, lane_63, b0, b1);
+                    tap_pair_sum(tk[g], b0, b1, h0, h1);
                 }
                 if (c >= 0) {
                     acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
