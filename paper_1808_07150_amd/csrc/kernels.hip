@@ -168,8 +168,12 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, in
 // rounded up).  Wavefront w walks the w-th of NW consecutive parts of the primary steps
 // with its own LDS buffers; the partial ray sums are added in a fixed order by wavefront 0
 // (several wavefronts per ray bundle give small subsets enough parallelism).
+// The iteration's projection (F_DUAL) with up to 16 rays per lane is held to six waves
+// per SIMD (at most 80 VGPRs, no spills): more resident wavefronts hide the image-column
+// loads better than the registers the compiler would otherwise take.
 template <int RPL, int MODE, int NW>
-__global__ void __launch_bounds__(64 * NW) fwd_wave(FwdArgs P) {
+__global__ void __launch_bounds__(64 * NW, (MODE == F_DUAL && RPL <= 16) ? 6 : 1)
+fwd_wave(FwdArgs P) {
     extern __shared__ float smem[];
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
