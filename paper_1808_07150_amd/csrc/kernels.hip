@@ -170,9 +170,10 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, in
 // (several wavefronts per ray bundle give small subsets enough parallelism).
 // The iteration's projection (F_DUAL) with up to 16 rays per lane is held to six waves
 // per SIMD (at most 80 VGPRs, no spills): more resident wavefronts hide the image-column
-// loads better than the registers the compiler would otherwise take.
+// loads better than the registers the compiler would otherwise take.  The objective's
+// projection (F_OBJ), which the autotuner times in its place, is held the same way.
 template <int RPL, int MODE, int NW>
-__global__ void __launch_bounds__(64 * NW, (MODE == F_DUAL && RPL <= 16) ? 6 : 1)
+__global__ void __launch_bounds__(64 * NW, ((MODE == F_DUAL || MODE == F_OBJ) && RPL <= 16) ? 6 : 1)
 fwd_wave(FwdArgs P) {
     extern __shared__ float smem[];
     const GeomDev& G = P.G;
