@@ -458,13 +458,13 @@ def main():
     epoch_bytes = (n_fwd * (bytes_fwd + bytes_bwd) + n_prior * bytes_prior) / args.steps
     kinds = {
         "fwd": dict(bound="alu", work=flops_fwd, unit="TFLOP/s", peak=ALU_PEAK_TFLOPS,
-                    name="fwd_dual (projection + KL-dual prox)"),
+                    name="fwd_wave (projection + KL-dual prox)"),
         "bwd": dict(bound="alu", work=flops_bwd, unit="TFLOP/s", peak=ALU_PEAK_TFLOPS,
-                    name="bwd_iter (gather backprojection + primal epilogue)"),
+                    name="bwd_strip partial + iter (gather backprojection + primal epilogue)"),
         "prior": dict(bound="hbm", work=bytes_prior, unit="GB/s", peak=HBM_PEAK_GBS,
-                      name={"tv": "tv_iter (TV dual + adjoint + primal epilogue)",
-                            "dtv": "tv_iter (dTV dual + adjoint + primal epilogue)",
-                            "tgv": "tgv1_iter / tgv2_iter (TGV duals + adjoints + primal "
+                      name={"tv": "tv_wave (TV dual + adjoint + primal epilogue)",
+                            "dtv": "tv_wave (dTV dual + adjoint + primal epilogue)",
+                            "tgv": "tgv1_wave / tgv2_wave (TGV duals + adjoints + primal "
                                    "epilogue of u and w)"}[wl["prior"]]),
     }
     dom = max(prof, key=lambda k: prof[k][0])
