@@ -74,14 +74,18 @@ __device__ __forceinline__ double phi64(double u, double b, double r) {
     return s;
 }
 
-// prox^sigma_{phi*}(v) = (w + 1 - sqrt((w - 1)^2 + 4 sigma b)) / 2, w = v + sigma r, in
-// the cancellation-free form obtained by rationalising the surd when w > 1.
+// prox^sigma_{phi*}(v) = (w + 1 - sqrt((w - 1)^2 + 4 sigma b)) / 2, w = v + sigma r
+// (Section 2.2), rationalised so that no branch subtracts nearly equal numbers: with
+// root = sqrt((w - 1)^2 + 4 sigma b),
+//   w > 1:   1 - 2 sigma b / (w - 1 + root)        (the result is close to 1)
+//   w <= 1:  2 (w - sigma b) / (w + 1 + root)      (denominator >= 2; the printed form
+//            loses the result's low bits to 1 + ... when it is small, as in most bins)
 __device__ __forceinline__ float prox_kl_dual(float v, float sigma, float b, float r) {
     const float w = __builtin_fmaf(sigma, r, v);
     const float q = w - 1.0f;
-    const float c = 4.0f * sigma * b;
-    const float root = __builtin_sqrtf(__builtin_fmaf(q, q, c));
-    return q > 0.0f ? 1.0f - c / (2.0f * (q + root)) : 1.0f + 0.5f * (q - root);
+    const float sb = sigma * b;
+    const float root = __builtin_sqrtf(__builtin_fmaf(q, q, 4.0f * sb));
+    return q > 0.0f ? 1.0f - (2.0f * sb) / (q + root) : (2.0f * (w - sb)) / (w + 1.0f + root);
 }
 
 // Primary-index range [j0, j1) outside which the ray's in-plane taps are all outside the

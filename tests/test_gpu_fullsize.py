@@ -1,6 +1,13 @@
-"""One prior-block iteration of Algorithm 2 at full mMR size (344 x 344 x 127; the launch
-configuration of the benchmark: wavefront prior kernels with two runs per column and
-43 row chunks) against the FP64 oracle's operators applied to the same state.
+"""Single iterations of Algorithm 2 at full mMR size (344 x 344 x 127, sinogram 344 x 252
+x 837; the launch configuration of the benchmark) against the FP64 oracle applied to the
+same state.
+
+Data iteration: the oracle's own Algorithm 2 loop (oracle.spdhg.spdhg, one iteration of
+the drawn subset: forward projection, KL-dual prox, backprojection, z and z-bar, then the
+next iteration's line 3) from the library's state and step sizes.
+
+Prior iterations: one TV and one TGV iteration (both blocks) against the oracle's
+operators:
 
 The state is taken from the library after k iterations (k = the first iteration whose
 SplitMix64 draw is a prior block), the GPU runs iteration k, and the oracle recomputes
@@ -21,6 +28,7 @@ import synth
 from oracle import priors as PR
 from oracle import prox as PX
 from oracle import sampling as SA
+from oracle import spdhg as S
 
 pytestmark = pytest.mark.gpu
 
@@ -142,3 +150,56 @@ def test_mmr_prior_iteration(P, mmr_inputs, prior, m, alpha, alpha1):
             close_step(s1["w"], w, w - tw * (zwn + dzw / pb))
     finally:
         rec.close()
+
+
+def test_mmr_data_iteration(P, mmr_inputs):
+    """One data iteration (12 angles, nnz 3.3e9) of mMR with TV, SPDHG+: y of the subset,
+    z and the next iterate against the oracle's Algorithm 2 loop; every other subset's y
+    is left untouched."""
+    g, b, r, mult, x0 = mmr_inputs
+    m, seed, alpha = 21, 18080720, 2e-3
+    blocks = SA.draw_blocks(seed, SA.balanced(m, 1), 400)
+    # a data iteration after at least one data and one prior iteration
+    k = next(i for i in range(2, 400) if blocks[i] < m and any(v < m for v in blocks[:i])
+             and any(v >= m for v in blocks[:i]))
+    i = blocks[k]
+    print(f"[fullsize] data iteration {k} (subset {i})", flush=True)
+    x = x0.clone()
+    rec = P.Reconstruction(g, P.cparams(m, "tv", "balanced", True, alpha=alpha, seed=seed),
+                           b, r, mult, x)
+    try:
+        rec.iterate(k)
+        s0 = snap(rec, ["y", "z", "T", "sigma", "prior_dual"])
+        x_before = x.cpu().numpy().astype(np.float64)
+        prior_sigma = rec.block_info(m)[0]
+        rec.iterate(1)
+        s1 = snap(rec, ["y", "z"])
+        x_after = x.cpu().numpy().astype(np.float64)
+    finally:
+        rec.close()
+
+    class Given(S.Problem):  # the oracle's problem with the library's step sizes
+        def _setup_steps(self):
+            pass
+
+    prob = Given(g, b.cpu().numpy(), r.cpu().numpy(), mult.cpu().numpy(), n_subsets=m,
+                 prior="tv", alpha=alpha, sampling="balanced", precond=True)
+    prob.sigma = [s0["sigma"][a] for a in prob.angles]
+    prob.prior_sigma = [prior_sigma]
+    prob.norms = [None] * prob.n
+    prob.T = s0["T"][None]
+    st = prob.new_state(x_before)  # z-bar = 0: line 3 returns x_before itself
+    st["y"] = [s0["y"][a] for a in prob.angles]
+    st["yp"] = [s0["prior_dual"]]
+    st["z"] = s0["z"][None]
+    S.spdhg(prob, 1, seed, state=st, blocks=[i])
+    ang = prob.angles[i]
+    # the KL-dual prox is non-expansive, so the new dual inherits the projection's error:
+    # within 1e-5 of the largest sigma * (A_i x) (the projection bar) plus two FP32 ulps
+    sax = prob.sigma[i] * prob.A_data(i, x_before[None])
+    err = np.max(np.abs(s1["y"][ang] - st["y"][i]))
+    assert err <= 1e-5 * np.max(np.abs(sax)) + 2.0 ** -22 * np.max(np.abs(st["y"][i])), err
+    others = np.setdiff1d(np.arange(g.n_ang), ang)
+    np.testing.assert_array_equal(s1["y"][others], s0["y"][others])
+    close_step(s1["z"], s0["z"], st["z"][0])
+    close_step(x_after, x_before, prob.reported(st)[0])
