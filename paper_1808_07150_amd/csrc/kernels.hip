@@ -184,10 +184,13 @@ fwd_wave(FwdArgs P) {
     const int ns = G.n_seg;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    float* Gb = smem + w * (2 * P.gsize + 4 * ns);     // [2][gsize] axial columns
+    // each wavefront's LDS region (floats; even, so the doubles stay 8-byte aligned)
+    const int wstride = max(2 * P.gsize + 8 * ns, 64);
+    float* Gb = smem + w * wstride;                    // [2][gsize] axial columns
     int* segc = (int*)(Gb + 2 * P.gsize);              // [2][ns] axial cell offsets
     float* segf = (float*)(segc + 2 * ns);             // [2][ns] axial fractions
-    float* red = smem + NW * (2 * P.gsize + 4 * ns);   // [NW - 1][RPL][64] partial sums
+    double* segk = (double*)(segf + 2 * ns);           // [ns] ez_dk * kk of the segment
+    double* segj = segk + ns;                          // [ns] ez_dj of the segment
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int ia = bid / G.n_rad;
     const int k = bid - ia * G.n_rad;
@@ -211,6 +214,14 @@ fwd_wave(FwdArgs P) {
         }
     }
     for (int i = lane; i < 2 * P.gsize; i += 64) Gb[i] = 0.0f;
+    // the axial offset of segment g at step j is fma(ez_dj, jj, ez_dk * kk) (ax_offset):
+    // its two step-independent parts are read once, so the step loop loads nothing from
+    // global memory but the image columns (only lane g touches entry g)
+    if (lane < ns) {
+        const SegAngleDev S = G.sa[a * ns + lane];
+        segk[lane] = S.ez_dk * kk;
+        segj[lane] = S.ez_dj;
+    }
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
     if (NW > 1 && j0 < j1) {  // this wavefront's part of the steps
@@ -273,12 +284,12 @@ fwd_wave(FwdArgs P) {
                     if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[f][u], w0 * v0[f][u]);
                 }
             }
+            if (j + FD < j1) issue(f, j + FD);
             if (lane < ns) {
-                const Sample sz = split(ax_offset(G.sa[a * ns + lane], kk, jj));
+                const Sample sz = split(__builtin_fma(segj[lane], jj, segk[lane]));
                 segc[buf * ns + lane] = sz.i0;
                 segf[buf * ns + lane] = sz.fu;
             }
-            if (j + FD < j1) issue(f, j + FD);
             __builtin_amdgcn_wave_barrier();
             const float* Gr = Gb + buf * P.gsize;
 #pragma unroll
@@ -296,17 +307,30 @@ fwd_wave(FwdArgs P) {
         }
     }
     if (NW > 1) {
-        if (w > 0) {
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) red[((w - 1) * RPL + r) * 64 + lane] = acc[r];
-        }
-        __syncthreads();
-        if (w > 0) return;
+        // partial ray sums pass through each wavefront's own LDS region (its axial columns
+        // are no longer needed), `per` rays at a time; wavefront 0 adds them in wavefront
+        // order, so the sum is the same for any number of passes
+        const int per = min(RPL, wstride / 64);
 #pragma unroll 1
-        for (int v = 1; v < NW; ++v) {
+        for (int r0 = 0; r0 < RPL; r0 += per) {
+            __syncthreads();  // the walks (first pass) or wavefront 0's reads are done
+            if (w > 0) {
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) acc[r] += red[((v - 1) * RPL + r) * 64 + lane];
+                for (int r = 0; r < RPL; ++r)
+                    if (r >= r0 && r < r0 + per) Gb[(r - r0) * 64 + lane] = acc[r];
+            }
+            __syncthreads();
+            if (w == 0) {
+#pragma unroll 1
+                for (int v = 1; v < NW; ++v) {
+                    const float* pv = smem + v * wstride;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r)
+                        if (r >= r0 && r < r0 + per) acc[r] += pv[(r - r0) * 64 + lane];
+                }
+            }
         }
+        if (w > 0) return;
     }
 
     // epilogues
@@ -337,6 +361,8 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
     float* Gb = smem;                        // [2][gsize] axial columns
     int* segc = (int*)(Gb + 2 * P.gsize);    // [2][ns] axial cell offsets
     float* segf = (float*)(segc + 2 * ns);   // [2][ns] axial fractions
+    double* segk = (double*)(segf + 2 * ns); // [ns] ez_dk * kk of the segment
+    double* segj = segk + ns;                // [ns] ez_dj of the segment
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int ia = bid / G.n_rad;
     const int k = bid - ia * G.n_rad;
@@ -361,6 +387,11 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
         }
     }
     for (int i = tid; i < 2 * P.gsize; i += 64 * PS) Gb[i] = 0.0f;
+    if (tid < ns) {  // step-independent parts of ax_offset (only thread g touches entry g)
+        const SegAngleDev S = G.sa[a * ns + tid];
+        segk[tid] = S.ez_dk * kk;
+        segj[tid] = S.ez_dj;
+    }
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
     // image columns through a range-checked buffer resource (see fwd_wave)
@@ -407,12 +438,12 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
                 if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[u], w0 * v0[u]);
             }
         }
+        if (j + 1 < j1) issue(j + 1);
         if (tid < ns) {
-            const Sample sz = split(ax_offset(G.sa[a * ns + tid], kk, jj));
+            const Sample sz = split(__builtin_fma(segj[tid], jj, segk[tid]));
             segc[buf * ns + tid] = sz.i0;
             segf[buf * ns + tid] = sz.fu;
         }
-        if (j + 1 < j1) issue(j + 1);
         // the other buffer was last read before this barrier's predecessor
         __syncthreads();
         const float* Gr = Gb + buf * P.gsize;

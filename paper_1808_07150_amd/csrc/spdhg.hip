@@ -275,8 +275,9 @@ int check_kernel_limits(const spdhg_geom* g) {
 // ---------------------------------------------------------------- launch helpers
 template <int MODE, int NW>
 int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
-    const size_t lds = (NW * (2 * (size_t)A.gsize + 4 * (size_t)A.G.n_seg) +
-                        (NW - 1) * (size_t)rpl * 64) * 4;
+    // per wavefront: axial columns and segment tables, also the staging of its partial
+    // ray sums (kernel: wstride)
+    const size_t lds = NW * std::max<size_t>(2 * (size_t)A.gsize + 8 * (size_t)A.G.n_seg, 64) * 4;
     const int nt = 64 * NW;
     switch (rpl) {
         case 1: fwd_wave<1, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
@@ -299,7 +300,7 @@ int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
 // Plane-split forward: PS wavefronts per ray bundle, each with RPL rays per lane.
 template <int MODE, int PS>
 int launch_fwd_ps(const FwdArgs& A, int nblk, hipStream_t st) {
-    const size_t lds = (2 * (size_t)A.gsize + 4 * (size_t)A.G.n_seg) * 4;
+    const size_t lds = (2 * (size_t)A.gsize + 8 * (size_t)A.G.n_seg) * 4;
     const int rpl = rays_per_lane((A.G.n_planes + PS - 1) / PS);
     switch (rpl) {
         case 1: fwd_bundle<1, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
