@@ -514,18 +514,6 @@ __device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, doub
     return t;
 }
 
-// Both taps of voxel z for one (ray, segment) through a buffer resource that spans the
-// segment's N_g planes: the hardware range check returns zero for planes outside the
-// segment (a negative plane index wraps to an offset beyond the range).
-__device__ __forceinline__ float tap_sum_rsrc(__amdgpu_buffer_rsrc_t seg, const TapCoef& t, int z,
-                                              float h) {
-    const int va = (z + t.off) * 4;
-    const float ua = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, va, 0, 0));
-    const float ub = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, va - 4, 0, 0));
-    h = __builtin_fmaf(t.wa, ua, h);
-    return __builtin_fmaf(t.wb, ub, h);
-}
-
 // Both taps of z = lane and z = lane + 64 for one (ray, segment) from two loads: plane
 // p - 1 of z = lane (lane_m1 holds lane - 1) and of z = lane + 64 (lane_63 holds
 // lane + 63).  Plane p of each is plane p - 1 of the next-higher lane (a wavefront shift
@@ -1123,6 +1111,29 @@ __device__ __forceinline__ void vol_st(__amdgpu_buffer_rsrc_t r, uint32_t off, u
 // previous row (a register), and the x-neighbour's is recomputed from its inputs, which
 // the neighbouring column's wavefront reads at about the same time (cache hits).  Each
 // row's loads are issued before the previous row's stores.  Requires nz <= 128.
+// The wavefront march's mapping: wavefront gw (XCD-ordered) takes run h = gw % nh of
+// column (cx, chunk) = (gw / nh) % nx, (gw / nh) / nx; lane covers z = 63 h + lane.
+struct WaveMap {
+    int cx, cz, y0, y1, lane;
+    bool act, own;
+};
+
+__device__ __forceinline__ bool wave_map(int nx, int ny, int nz, int ly, WaveMap& m) {
+    const int nh = nz <= 64 ? 1 : (nz + 61) / 63;  // ceil((nz - 1) / 63)
+    m.lane = threadIdx.x & 63;
+    const int gw = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int h = gw % nh;
+    const int rest = gw / nh;
+    m.cx = rest % nx;
+    m.y0 = (rest / nx) * ly;
+    if (m.y0 >= ny) return false;
+    m.y1 = min(ny, m.y0 + ly);
+    m.cz = 63 * h + m.lane;
+    m.act = m.cz < nz;
+    m.own = m.act && (h == 0 || m.lane > 0);
+    return true;
+}
+
 struct TvRow {
     float xp, xn, xz, y0, y1, y2, z, t;  // x(c + e_x), x(c + e_y), x(c + e_z), y(c), z(c), T(c)
     float lxn, lxz, ly0, ly1, ly2;       // x-neighbour: x(c - e_x + e_y), x(c - e_x + e_z), y
@@ -1177,18 +1188,10 @@ tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__
     const auto ry = vol_rsrc(y_in, 3 * nvb), ryo = vol_rsrc(y_out, 3 * nvb);
     const auto rz = vol_rsrc(z, nvb), rt = vol_rsrc(T, nvb);
     const auto rxi = vol_rsrc(DTV ? xi : x_in, DTV ? 3 * nvb : nvb);
-    const int nh = P.nz <= 64 ? 1 : (P.nz + 61) / 63;  // ceil((nz - 1) / 63)
-    const int lane = threadIdx.x & 63;
-    const int gw = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int h = gw % nh;
-    const int rest = gw / nh;
-    const int cx = rest % P.nx;
-    const int y0 = (rest / P.nx) * ly;
-    if (y0 >= P.ny) return;  // whole wavefront beyond the last chunk
-    const int y1 = min(P.ny, y0 + ly);
-    const int cz = 63 * h + lane;
-    const bool act = cz < P.nz;
-    const bool own = act && (h == 0 || lane > 0);  // writes its voxel
+    WaveMap m;
+    if (!wave_map(P.nx, P.ny, P.nz, ly, m)) return;  // whole wavefront beyond the last chunk
+    const int cx = m.cx, cz = m.cz, y0 = m.y0, y1 = m.y1;
+    const bool act = m.act, own = m.own;  // own: writes its voxel
     const bool hx = cx < P.nx - 1, lx = cx > 0, hz = cz < P.nz - 1;
     int cy = y0 > 0 ? y0 - 1 : y0;
     uint32_t c = 4u * (((uint32_t)cy * P.nx + cx) * P.nz + min(cz, P.nz - 1));
@@ -1545,27 +1548,6 @@ tgv2_iter(TgvArgs P, PriorTile TL, const float* __restrict__ u_in, float* __rest
 // previous row's stores; tgv2_wave, with twice the inputs per row, loads its row when it
 // gets there (the prefetching form needed 103 registers and was no faster).  Every
 // 6-component field stays below 4 GiB (checked by the host).
-struct WaveMap {
-    int cx, cz, y0, y1, lane;
-    bool act, own;
-};
-
-__device__ __forceinline__ bool wave_map(int nx, int ny, int nz, int ly, WaveMap& m) {
-    const int nh = nz <= 64 ? 1 : (nz + 61) / 63;  // ceil((nz - 1) / 63)
-    m.lane = threadIdx.x & 63;
-    const int gw = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int h = gw % nh;
-    const int rest = gw / nh;
-    m.cx = rest % nx;
-    m.y0 = (rest / nx) * ly;
-    if (m.y0 >= ny) return false;
-    m.y1 = min(ny, m.y0 + ly);
-    m.cz = 63 * h + m.lane;
-    m.act = m.cz < nz;
-    m.own = m.act && (h == 0 || m.lane > 0);
-    return true;
-}
-
 struct Tgv1Row {
     float up, un, uz;     // u(c + e_x), u(c + e_y), u(c + e_z)
     float w[3], y[3], zw[3], zu, t;
