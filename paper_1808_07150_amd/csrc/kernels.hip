@@ -700,10 +700,24 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 // accesses execute in order: code-motion barriers separate the phases.
 #define BS_W 16
 
+// N consecutive segments of one ray: all 2N loads, then all sums (in segment order).
+template <int N>
+__device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, const TapCoef* tk,
+                                            int g, int lane_m1, int lane_63, float& h0,
+                                            float& h1) {
+    float v[N][2];
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+        tap_pair_loads(seg_rsrc(G, dk, g + u), tk[g + u], lane_m1, lane_63, v[u][0], v[u][1]);
+#pragma unroll
+    for (int u = 0; u < N; ++u) tap_pair_sum(tk[g + u], v[u][0], v[u][1], h0, h1);
+}
+
 template <int MODE>
-// Eight waves per SIMD (at most 64 VGPRs, a few spilled): the mMR launch of 7568 strips
-// then runs in one round on 256 compute units.
-__global__ void __launch_bounds__(64, 8) bwd_strip(BwdArgs P, int KR, int rowdom,
+// Six waves per SIMD (at most 80 VGPRs): room for the loads of a whole ray (span 11:
+// 22 values) next to the 32 accumulators.  Fewer resident strips (the mMR launch of
+// 7568 takes 1.2 rounds) but one memory round trip per ray instead of three.
+__global__ void __launch_bounds__(64, 6) bwd_strip(BwdArgs P, int KR, int rowdom,
                                                 const float* __restrict__ partial) {
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
@@ -779,22 +793,13 @@ __global__ void __launch_bounds__(64, 8) bwd_strip(BwdArgs P, int KR, int rowdom
                 const float* dk = P.d + dual_row(G, ia, klo + kr);
                 const TapCoef* tk = tc + kr * ns;
                 float h0 = 0.0f, h1 = 0.0f;
-                // segments in fours: all eight loads are issued before the taps are summed
+                // segments in batches of 11 (all of them for span 11), then 4, then 1: every
+                // load of a batch is issued before any tap is summed, so a span-11 ray costs
+                // one memory round trip (batches with per-slot guards lose this overlap)
                 int g = 0;
-                for (; g + 4 <= ns; g += 4) {
-                    float v[4][2];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        tap_pair_loads(seg_rsrc(G, dk, g + u), tk[g + u], lane_m1, lane_63,
-                                       v[u][0], v[u][1]);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) tap_pair_sum(tk[g + u], v[u][0], v[u][1], h0, h1);
-                }
-                for (; g < ns; ++g) {
-                    float b0, b1;
-                    tap_pair_loads(seg_rsrc(G, dk, g), tk[g], lane_m1, lane_63, b0, b1);
-                    tap_pair_sum(tk[g], b0, b1, h0, h1);
-                }
+                for (; g + 11 <= ns; g += 11) strip_batch<11>(G, dk, tk, g, lane_m1, lane_63, h0, h1);
+                for (; g + 4 <= ns; g += 4) strip_batch<4>(G, dk, tk, g, lane_m1, lane_63, h0, h1);
+                for (; g < ns; ++g) strip_batch<1>(G, dk, tk, g, lane_m1, lane_63, h0, h1);
                 if (c >= 0) {
                     acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
                     acc[c][1] = __builtin_fmaf(1.0f - fu, h1, acc[c][1]);
