@@ -6,12 +6,18 @@
 // In these layouts every stream of the hot loop is contiguous across the 64 lanes of a
 // wavefront for both angle classes (row- and column-sampled rays).
 //
-//   fwd_wave   forward projection, one wavefront per (angle, radial bin): at every
-//              primary step the lanes form the in-plane interpolated axial column
+//   fwd_wave   forward projection, one workgroup of 1, 2, 4 or 8 wavefronts per (angle,
+//              radial bin), each walking its share of the primary steps: at every step
+//              the lanes form the in-plane interpolated axial column
 //              G(z) = (1 - fu) x[j][i0][z] + fu x[j][i0 + 1][z] in LDS, then each ray of
 //              the bin (all planes of all segments) adds its axial interpolation of G.
 //              Epilogues: plain output, preconditioner sigma, KL-dual prox (Algorithm 2
 //              line 5), FP64 data term of the objective.
+//   fwd_bundle the same with the planes of a bin split over 2 or 4 wavefronts that
+//              share each step's axial column (an autotuner candidate).
+//   bwd_strip  gather backprojection for 32 <= nz <= 127: one wavefront per strip of 16
+//              voxel columns and angle class, rays' tap tables in LDS, lanes along z
+//              reading the dual change contiguously, accumulators in registers.
 //   bwd_col    gather backprojection, one workgroup per group of voxel columns: the
 //              interpolation coordinates of every candidate ray are computed once per
 //              column and angle (FP64, shared through LDS), lanes run along z and read
