@@ -56,7 +56,7 @@ int spdhg_net_pool2(const int32_t fine[3], int32_t c, int32_t adjoint, const uin
                     uint16_t* dst, void* stream);
 
 /* Nearest 2x upsampling to the fine grid `fine`, or with adjoint != 0 its adjoint (sum of
- * the eight fine voxels of each coarse voxel). */
+ * the eight fine voxels of each coarse voxel); c a multiple of 16 (else -2). */
 int spdhg_net_up2(const int32_t fine[3], int32_t c, int32_t adjoint, const uint16_t* src,
                   uint16_t* dst, void* stream);
 

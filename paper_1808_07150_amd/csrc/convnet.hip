@@ -274,17 +274,20 @@ __global__ void pool2_bwd(Dims F, int C, const uint16_t* __restrict__ dout, uint
 }
 
 // Nearest 2x upsampling and its adjoint (sum of the eight fine voxels).
+// Eight channels (16 bytes) per thread: C is a multiple of 16 and channel-last rows are
+// 16-byte aligned.
 __global__ void up2_fwd(Dims F, int C, const uint16_t* __restrict__ in, uint16_t* __restrict__ out) {
     const Dims Cd{F.ny / 2, F.nx / 2, F.nz / 2};
-    const int64_t n = (int64_t)F.ny * F.nx * F.nz * C;
+    const int C8 = C / 8;
+    const int64_t n = (int64_t)F.ny * F.nx * F.nz * C8;
     const int64_t e = (int64_t)blockIdx.x * NET_BLOCK + threadIdx.x;
     if (e >= n) return;
-    const int c = (int)(e % C);
-    int64_t r = e / C;
+    const int c8 = (int)(e % C8);
+    int64_t r = e / C8;
     const int z = (int)(r % F.nz);
     r /= F.nz;
     const int x = (int)(r % F.nx), y = (int)(r / F.nx);
-    out[e] = in[vox(Cd, y / 2, x / 2, z / 2) * C + c];
+    ((uint4*)out)[e] = ((const uint4*)in)[vox(Cd, y / 2, x / 2, z / 2) * C8 + c8];
 }
 
 __global__ void up2_bwd(Dims F, int C, const uint16_t* __restrict__ dout, uint16_t* __restrict__ din) {
@@ -512,10 +515,11 @@ int spdhg_net_up2(const int32_t fine[3], int32_t c, int32_t adjoint, const uint1
     const Dims F{fine[0], fine[1], fine[2]};
     const int64_t nf = (int64_t)F.ny * F.nx * F.nz * c;
     hipStream_t st = (hipStream_t)stream;
+    if (c <= 0 || c % 16) return net_fail(-2, "channel count must be a multiple of 16");
     if (adjoint)
         up2_bwd<<<nblk(nf / 8), NET_BLOCK, 0, st>>>(F, c, src, dst);
     else
-        up2_fwd<<<nblk(nf), NET_BLOCK, 0, st>>>(F, c, src, dst);
+        up2_fwd<<<nblk(nf / 8), NET_BLOCK, 0, st>>>(F, c, src, dst);
     NET_CHECK();
     return 0;
 }

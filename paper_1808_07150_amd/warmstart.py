@@ -90,9 +90,12 @@ def _dims(shape) -> ctypes.Array:
     return (ctypes.c_int32 * 3)(*[int(v) for v in shape[:3]])
 
 
-def bf16(shape, device) -> torch.Tensor:
-    """A BF16 activation buffer (stored as int16 bit patterns)."""
-    return torch.zeros(shape, dtype=torch.int16, device=device)
+def bf16(shape, device, zero: bool = False) -> torch.Tensor:
+    """A BF16 activation buffer (stored as int16 bit patterns); uninitialised unless
+    `zero` (every kernel that fills one writes all of its elements)."""
+    if zero:
+        return torch.zeros(shape, dtype=torch.int16, device=device)
+    return torch.empty(shape, dtype=torch.int16, device=device)
 
 
 # ---------------------------------------------------------------- single kernels
@@ -269,7 +272,7 @@ class WarmStartNet:
         reverse order with the kernels' adjoints)."""
         nv = img.numel()
         _, a = self.forward(img, scale, keep=True)
-        g_out = bf16(self.shape + (16,), self.device)
+        g_out = bf16(self.shape + (16,), self.device, zero=True)  # mse_grad writes channel 0
         _chk(lib().spdhg_net_mse_grad(nv, 16, _p(a["out"]), _p(img), _p(target), float(scale),
                                       _p(g_out), _p(self.lparts), _s()))
         if part is None:
