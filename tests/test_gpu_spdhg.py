@@ -57,6 +57,16 @@ def deep3d():
     return synth.brain_problem(g, 18080600, 5e5, with_side=True)
 
 
+@pytest.fixture(scope="module")
+def maxnz3d():
+    """nz = 128, the largest the library accepts: three overlapping 64-voxel runs per
+    column in the wavefront prior kernels, and the per-column gather (the strip gather
+    stops at 127 planes)."""
+    g = synth.Geometry(nx=12, ny=13, nz=128, vx=5.0, vy=5.0, vz=5.0, n_rad=16, d_rad=5.0,
+                       n_ang=6, seg_planes=(128, 126, 126), seg_tan=(0.0, 0.2, -0.2))
+    return synth.brain_problem(g, 18080800, 5e5)
+
+
 def run_pair(P, d, n_subsets, prior, epochs, seed, sampling="uniform", precond=True,
              alpha=0.1, side=None, eta=1e-2, alpha1=0.0):
     g = d["geom"]
@@ -214,6 +224,33 @@ def test_deep3d_prior_parity(P, deep3d, prior):
     if prior == "tgv":
         assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
     psi_o = prob.objective(X)
+    assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+@pytest.mark.parametrize("prior", ["tv", "tgv"])
+def test_maxnz_parity(P, maxnz3d, prior):
+    print(f"[spdhg] maxnz (nz=128) {prior}", flush=True)
+    prob, st, rec, x = run_pair(P, maxnz3d, 3, prior, 10, seed=41, sampling="balanced",
+                                alpha=0.05, alpha1=0.025 if prior == "tgv" else 0.0)
+    X = prob.reported(st)
+    assert rel(x.cpu().numpy(), X[0]) <= 1e-3
+    if prior == "tgv":
+        assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
+    psi_o = prob.objective(X)
+    assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+def test_zero_counts(P, small3d):
+    """No counts at all (b = 0): the minimiser is x = 0, which the oracle reaches exactly;
+    the KL-dual prox degenerates to min(w, 1)."""
+    print("[spdhg] small3d zero counts", flush=True)
+    d = dict(small3d)
+    d["b"] = np.zeros_like(small3d["b"])
+    prob, st, rec, x = run_pair(P, d, 6, "tv", 10, seed=43, sampling="balanced", alpha=0.05)
+    xo = prob.reported(st)[0]
+    assert np.max(np.abs(xo)) == 0.0
+    assert np.max(np.abs(x.cpu().numpy())) <= 1e-6 * np.max(np.abs(small3d["x_true"]))
+    psi_o = prob.objective(xo[None])
     assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
 
 
