@@ -231,11 +231,15 @@ def batch_leg(P, torch, steps=3, n_problems=64, seed=18080500):
     return out
 
 
-def run_to_target(P, torch, g, d, prm, x0, psi0, psi_star, target=1e-3, max_epochs=60):
+def run_to_target(P, torch, g, d, prm, x0, psi0, psi_star, target=1e-3, max_epochs=60,
+                  split=0):
     """Iteration time (HIP events) from x0 until (Psi - Psi*) / (Psi0 - Psi*) <= target,
-    objective off the clock every quarter epoch; returns (seconds, epochs, reached)."""
+    objective off the clock every quarter epoch; returns (seconds, epochs, reached).
+    `split` (if not 0) fixes the ray-bundle split."""
     x = x0.clone()
     rec = P.Reconstruction(g, prm, d["b"], d["r"], d["mult"], x)
+    if split:
+        rec.set_tuning(split)
     ipe = rec.iters_per_epoch
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_ms, done = 0.0, 0
@@ -254,6 +258,34 @@ def run_to_target(P, torch, g, d, prm, x0, psi0, psi_star, target=1e-3, max_epoc
         rel = (float(rec.objective()[0].item()) - psi_star) / (psi0 - psi_star)
     rec.close()
     return t_ms * 1e-3, done / ipe, bool(rel <= target)
+
+
+def gamma_sweep_leg(P, torch, g, d, wl, seed, split,
+                    gammas=(0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0)):
+    """Step-size balance gamma of Theorem 2 (S_i = gamma rho / A_i 1, T_i = rho p_i /
+    (gamma A_i^T 1); prior blocks scalar): the paper runs gamma = 1 and leaves its tuning
+    open (Discussion).  Time to 1e-3 relative objective from x^0 = 0 for each gamma on the
+    same data, with Psi(x^0) and Psi* shared (Psi* from 200 epochs at gamma = 1)."""
+    m = wl["m"]
+    dev = d["b"].device
+    base = P.cparams(m, wl["prior"], "balanced", True, alpha=wl["alpha"], alpha1=wl["alpha1"],
+                     seed=seed)
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
+    ref = P.Reconstruction(g, base, d["b"], d["r"], d["mult"], x)
+    psi0 = float(ref.objective()[0].item())
+    ref.epoch(200)
+    psi_star = float(ref.objective()[0].item())
+    ref.close()
+    rows = []
+    for gm in gammas:
+        prm = P.cparams(m, wl["prior"], "balanced", True, alpha=wl["alpha"],
+                        alpha1=wl["alpha1"], gamma=gm, seed=seed)
+        zero = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
+        t, ep, ok = run_to_target(P, torch, g, d, prm, zero, psi0, psi_star, split=split)
+        rows.append({"gamma": gm, "seconds": round(t, 4), "epochs": round(ep, 2), "reached": ok})
+        log(f"gamma {gm}: {t:.4f} s, {ep:.2f} epochs to 1e-3")
+    return {"target_rel_objective": 1e-3, "psi_star_from": "200 epochs at gamma = 1",
+            "per_gamma": rows}
 
 
 def warm_start_leg(P, torch, n_train=200, n_test=20, train_passes=12, seed=18080400):
@@ -354,6 +386,9 @@ def main():
     ap.add_argument("--ws-train", type=int, default=200, help="warm start: training phantoms")
     ap.add_argument("--ws-test", type=int, default=20, help="warm start: held-out phantoms")
     ap.add_argument("--ws-passes", type=int, default=12, help="warm start: training passes")
+    ap.add_argument("--gamma-sweep", action="store_true",
+                    help="also measure the time to 1e-3 for step balances gamma = 0.25 .. 32 "
+                         "(the headline value stays at the paper's gamma = 1)")
     ap.add_argument("--batch", action="store_true",
                     help="also measure batched reconstructions (64 mixed problems); off by "
                          "default: its input generation once faulted inside torch's Poisson "
@@ -511,6 +546,8 @@ def main():
                                                ref_epochs=200 if m <= 21 else 40, split=split)
         log(f"time to 1e-3 relative objective: {out['time_to_target']['seconds']} s "
             f"({out['time_to_target']['epochs']} epochs; measured in {time.time() - t0:.1f} s)")
+    if args.gamma_sweep:
+        out["gamma_sweep"] = gamma_sweep_leg(P, torch, g, d, wl, SEED, split)
     if args.warm_start:
         t0 = time.time()
         out["warm_start"] = warm_start_leg(P, torch, n_train=args.ws_train, n_test=args.ws_test,
