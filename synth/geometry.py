@@ -77,7 +77,7 @@ class Geometry:
         return list(range(i, self.n_ang, n_subsets))
 
 
-def config1_2d() -> Geometry:
+def slice64_2d() -> Geometry:
     """2-D single slice: 64x64 image at 4 mm, 90 angles x 95 radial bins at 4 mm."""
     return Geometry(nx=64, ny=64, nz=1, vx=4.0, vy=4.0, vz=4.0,
                     n_rad=95, d_rad=4.0, n_ang=90)

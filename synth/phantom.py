@@ -214,11 +214,11 @@ def make_data(g: Geometry, seed: int, counts: float, act, att,
                 mult=mult.astype(np.float32), scale=scale)
 
 
-def config1_problem(seed: int = 18080100):
-    """Config 1: 64x64 slice, 8 ellipses, activity 0-4, water attenuation, normalisation
+def slice64_problem(seed: int = 18080100):
+    """The small 2-D problem: 64x64 slice, 8 ellipses, activity 0-4, water attenuation, normalisation
     U(0.8, 1.2), constant background 10% of mean, 1e5 expected counts."""
-    from .geometry import config1_2d
-    g = config1_2d()
+    from .geometry import slice64_2d
+    g = slice64_2d()
     rng = np.random.Generator(np.random.PCG64(seed))
     act, att = phantom_2d(rng, g)
     d = make_data(g, seed + 1, 1e5, act, att, "const10")

@@ -14,6 +14,6 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def config1():
+def slice64():
     import synth
-    return synth.config1_problem()
+    return synth.slice64_problem()

@@ -78,7 +78,7 @@ def test_workspace_bytes(lib):
 
 def test_null_arguments_rejected(lib):
     import paper_1808_07150_amd as P
-    g = P.cgeom(synth.config1_2d())
+    g = P.cgeom(synth.slice64_2d())
     assert lib.spdhg_project(ctypes.byref(g), 10, 0, None, None, None, None) == -1
     assert lib.spdhg_backproject(ctypes.byref(g), 10, 0, None, None, None, None) == -1
     ctx = ctypes.c_void_p()

@@ -33,7 +33,7 @@ def close(gpu, ref, tol=1e-5):
 
 
 GEOMS = {
-    "config1": synth.config1_2d(),
+    "slice64": synth.slice64_2d(),
     "small3d": synth.small_3d(),
     "ragged": synth.Geometry(nx=19, ny=23, nz=7, vx=3.0, vy=2.5, vz=2.0, n_rad=37, d_rad=2.2,
                              n_ang=10, seg_planes=(7, 5, 5, 3, 3),
@@ -159,7 +159,7 @@ def test_mmr_backward_one_subset(P, mmr_case):
 
 
 def test_errors(P):
-    g = GEOMS["config1"]
+    g = GEOMS["slice64"]
     x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
     out = torch.empty(g.n_bins, dtype=torch.float32, device="cuda:0")
     with pytest.raises(ValueError):

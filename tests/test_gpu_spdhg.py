@@ -33,7 +33,7 @@ def rel(a, b):
 
 @pytest.fixture(scope="module")
 def c1():
-    return synth.config1_problem()
+    return synth.slice64_problem()
 
 
 @pytest.fixture(scope="module")
@@ -89,8 +89,8 @@ def run_pair(P, d, n_subsets, prior, epochs, seed, sampling="uniform", precond=T
 @pytest.mark.parametrize("sampling,precond,epochs", [("uniform", True, 50),
                                                      ("balanced", True, 30),
                                                      ("balanced", False, 20)])
-def test_config1_tv_parity(P, c1, sampling, precond, epochs):
-    print(f"[spdhg] config1 TV {sampling} precond={precond} epochs={epochs}", flush=True)
+def test_slice64_tv_parity(P, c1, sampling, precond, epochs):
+    print(f"[spdhg] slice64 TV {sampling} precond={precond} epochs={epochs}", flush=True)
     prob, st, rec, x = run_pair(P, c1, 10, "tv", epochs, seed=1808, sampling=sampling,
                                 precond=precond)
     xo = prob.reported(st)[0]
@@ -105,9 +105,9 @@ def test_config1_tv_parity(P, c1, sampling, precond, epochs):
 
 
 @pytest.mark.parametrize("prior", ["tv", "atv", "none"])
-def test_config1_duality_gap(P, c1, prior):
+def test_slice64_duality_gap(P, c1, prior):
     """GPU duality gap (box U) against the oracle's on the same state after 20 epochs."""
-    print(f"[spdhg] config1 gap {prior}", flush=True)
+    print(f"[spdhg] slice64 gap {prior}", flush=True)
     prob, st, rec, x = run_pair(P, c1, 10, prior, 20, seed=4, sampling="balanced")
     X = prob.reported(st)
     U = 2.0 * float(X[0].max())
@@ -120,7 +120,7 @@ def test_config1_duality_gap(P, c1, prior):
     assert out[0] >= -1e-4 * abs(psi)
 
 
-def test_config1_step_sizes(P, c1):
+def test_slice64_step_sizes(P, c1):
     prob, _, rec, _ = run_pair(P, c1, 10, "tv", 0, seed=1, sampling="balanced")
     T = rec.buffer("T").cpu().numpy().reshape(c1["geom"].image_shape)
     assert rel(T, prob.T[0]) <= 1e-5

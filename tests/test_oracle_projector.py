@@ -17,7 +17,7 @@ def _rand(shape, seed):
     return np.random.default_rng(seed).random(shape)
 
 
-@pytest.mark.parametrize("geom", [synth.config1_2d(), synth.small_3d(),
+@pytest.mark.parametrize("geom", [synth.slice64_2d(), synth.small_3d(),
                                   synth.small_3d(nxy=17, nz=7, n_rad=21, n_ang=10)])
 def test_adjoint_identity(geom):
     x = _rand(geom.image_shape, 1)
