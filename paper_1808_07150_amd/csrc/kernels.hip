@@ -1122,6 +1122,7 @@ __device__ __forceinline__ void vol_st(__amdgpu_buffer_rsrc_t r, uint32_t off, u
 // previous row (a register), and the x-neighbour's is recomputed from its inputs, which
 // the neighbouring column's wavefront reads at about the same time (cache hits).  Each
 // row's loads are issued before the previous row's stores.  Requires nz <= 128.
+
 // The wavefront march's mapping: wavefront gw (XCD-ordered) takes run h = gw % nh of
 // column (cx, chunk) = (gw / nh) % nx, (gw / nh) / nx; lane covers z = 63 h + lane.
 struct WaveMap {
