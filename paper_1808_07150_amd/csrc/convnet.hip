@@ -43,8 +43,9 @@ __device__ __forceinline__ int64_t vox(const Dims& D, int y, int x, int z) {
 // One wavefront per output tile of 16 consecutive z x 4 consecutive x at one y, all COUT
 // channels: four M blocks (one per x) times COUT / 16 N blocks of 16x16 FP32 accumulators.
 // For every tap and 16-channel input chunk, A (16 voxels x 16 input channels) comes
-// straight from the channel-last activations (8 bytes per lane) and B from the packed
-// weights; both are cached reads shared by neighbouring tiles.  Epilogue: + bias, optional
+// straight from the channel-last activations (8 bytes per lane; each input column is read
+// once per (dy, dz) for all three dx) and B from the packed weights; both are cached
+// reads shared by neighbouring tiles.  Epilogue: + bias, optional
 // ReLU, BF16 store.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(NET_BLOCK)
@@ -67,28 +68,37 @@ conv3d_fwd(Dims D, const uint16_t* __restrict__ in, const uint16_t* __restrict__
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int n = 0; n < NB; ++n) acc[s][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < 27; ++t) {
-        const int dy = t / 9 - 1, dx = (t / 3) % 3 - 1, dz = t % 3 - 1;
+    // per (dy, dz): the six input columns x0 - 1 .. x0 + 4 are loaded once and serve the
+    // three dx taps of the four output columns (12 operand uses)
+    for (int dyz = 0; dyz < 9; ++dyz) {
+        const int dy = dyz / 3 - 1, dz = dyz % 3 - 1;
         const int yy = y + dy, zz = z0 + i + dz;
-        const bool oky = yy >= 0 && yy < D.ny;
-        const bool okz = zz >= 0 && zz < D.nz;
+        const bool okyz = yy >= 0 && yy < D.ny && zz >= 0 && zz < D.nz;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-            bf16x4 b[NB];
+            bf16x4 a[6];
 #pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const uint16_t* wp = w + (((int64_t)(t * KC + kc) * COUT + n * 16 + i) * 16 + kq);
-                b[n] = *(const bf16x4*)wp;
+            for (int q = 0; q < 6; ++q) {
+                const int xx = x0 + q - 1;
+                a[q] = bf16x4{0, 0, 0, 0};
+                if (okyz && xx >= 0 && xx < D.nx)
+                    a[q] = *(const bf16x4*)(in + vox(D, yy, xx, zz) * CIN + kc * 16 + kq);
             }
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int xx = x0 + s + dx;
-                bf16x4 a = {0, 0, 0, 0};
-                if (oky && okz && xx >= 0 && xx < D.nx)
-                    a = *(const bf16x4*)(in + vox(D, yy, xx, zz) * CIN + kc * 16 + kq);
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int t = (dy + 1) * 9 + (dx + 1) * 3 + (dz + 1);
+                bf16x4 b[NB];
 #pragma unroll
-                for (int n = 0; n < NB; ++n)
-                    acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[n], acc[s][n], 0, 0, 0);
+                for (int n = 0; n < NB; ++n) {
+                    const uint16_t* wp = w + (((int64_t)(t * KC + kc) * COUT + n * 16 + i) * 16 + kq);
+                    b[n] = *(const bf16x4*)wp;
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n)
+                        acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s + dx + 1], b[n],
+                                                                             acc[s][n], 0, 0, 0);
             }
         }
     }
