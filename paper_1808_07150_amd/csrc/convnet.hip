@@ -39,6 +39,19 @@ __device__ __forceinline__ int64_t vox(const Dims& D, int y, int x, int z) {
     return ((int64_t)y * D.nx + x) * D.nz + z;
 }
 
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+// v moved by one lane within each row of 16 lanes (CTRL 0x101: from the next lane, 0x111:
+// from the previous one); the row's end lane that has no source takes `edge`.
+template <int CTRL>
+__device__ __forceinline__ bf16x4 row_shift(bf16x4 v, bf16x4 edge) {
+    const i32x2 vi = __builtin_bit_cast(i32x2, v), ei = __builtin_bit_cast(i32x2, edge);
+    i32x2 r;
+    r.x = __builtin_amdgcn_update_dpp(ei.x, vi.x, CTRL, 0xF, 0xF, false);
+    r.y = __builtin_amdgcn_update_dpp(ei.y, vi.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(bf16x4, r);
+}
+
 // ---------------------------------------------------------------- convolution forward
 // One wavefront per output tile of 16 consecutive z x 4 consecutive x at one y, all COUT
 // channels: four M blocks (one per x) times COUT / 16 N blocks of 16x16 FP32 accumulators.
@@ -68,37 +81,55 @@ conv3d_fwd(Dims D, const uint16_t* __restrict__ in, const uint16_t* __restrict__
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int n = 0; n < NB; ++n) acc[s][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // per (dy, dz): the six input columns x0 - 1 .. x0 + 4 are loaded once and serve the
-    // three dx taps of the four output columns (12 operand uses)
-    for (int dyz = 0; dyz < 9; ++dyz) {
-        const int dy = dyz / 3 - 1, dz = dyz % 3 - 1;
-        const int yy = y + dy, zz = z0 + i + dz;
-        const bool okyz = yy >= 0 && yy < D.ny && zz >= 0 && zz < D.nz;
+    // per dy: the six input columns x0 - 1 .. x0 + 4 are loaded once (the tile's 16 z,
+    // plus z0 - 1 and z0 + 16 in the first and last lane of each 16-lane row) and serve
+    // all nine (dz, dx) taps of the four output columns: the dz = -1 / +1 operands are the
+    // centre ones moved by one lane within each row (DPP row shifts), whose end lanes take
+    // the extra voxel
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = y + dy;
+        const bool oky = yy >= 0 && yy < D.ny;
+        const int zc = z0 + i;
+        const int ze = i == 0 ? z0 - 1 : z0 + 16;  // used by lanes with i == 0 or i == 15
+        const bool edge = i == 0 || i == 15;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-            bf16x4 a[6];
+            bf16x4 ac[6], ae[6];
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const int xx = x0 + q - 1;
-                a[q] = bf16x4{0, 0, 0, 0};
-                if (okyz && xx >= 0 && xx < D.nx)
-                    a[q] = *(const bf16x4*)(in + vox(D, yy, xx, zz) * CIN + kc * 16 + kq);
+                const bool okx = oky && xx >= 0 && xx < D.nx;
+                ac[q] = bf16x4{0, 0, 0, 0};
+                ae[q] = bf16x4{0, 0, 0, 0};
+                if (okx && zc < D.nz)
+                    ac[q] = *(const bf16x4*)(in + vox(D, yy, xx, zc) * CIN + kc * 16 + kq);
+                if (okx && edge && ze >= 0 && ze < D.nz)
+                    ae[q] = *(const bf16x4*)(in + vox(D, yy, xx, ze) * CIN + kc * 16 + kq);
             }
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int t = (dy + 1) * 9 + (dx + 1) * 3 + (dz + 1);
-                bf16x4 b[NB];
+            for (int dz = -1; dz <= 1; ++dz) {
+                bf16x4 a[6];
 #pragma unroll
-                for (int n = 0; n < NB; ++n) {
-                    const uint16_t* wp = w + (((int64_t)(t * KC + kc) * COUT + n * 16 + i) * 16 + kq);
-                    b[n] = *(const bf16x4*)wp;
+                for (int q = 0; q < 6; ++q)
+                    a[q] = dz == 0 ? ac[q] : dz > 0 ? row_shift<0x101>(ac[q], ae[q])
+                                                    : row_shift<0x111>(ac[q], ae[q]);
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int t = (dy + 1) * 9 + (dx + 1) * 3 + (dz + 1);
+                    bf16x4 b[NB];
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) {
+                        const uint16_t* wp =
+                            w + (((int64_t)(t * KC + kc) * COUT + n * 16 + i) * 16 + kq);
+                        b[n] = *(const bf16x4*)wp;
+                    }
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+#pragma unroll
+                        for (int n = 0; n < NB; ++n)
+                            acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                                a[s + dx + 1], b[n], acc[s][n], 0, 0, 0);
                 }
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int n = 0; n < NB; ++n)
-                        acc[s][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s + dx + 1], b[n],
-                                                                             acc[s][n], 0, 0, 0);
             }
         }
     }
