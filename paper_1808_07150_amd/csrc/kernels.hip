@@ -15,7 +15,7 @@
 //              line 5), FP64 data term of the objective.
 //   fwd_bundle the same with the planes of a bin split over 2 or 4 wavefronts that
 //              share each step's axial column (an autotuner candidate).
-//   bwd_strip  gather backprojection for 32 <= nz <= 127: one wavefront per strip of 16
+//   bwd_strip  gather backprojection for 32 <= nz <= 127: one wavefront per strip of 10
 //              voxel columns and angle class, rays' tap tables in LDS, lanes along z
 //              reading the dual change contiguously, accumulators in registers.
 //   bwd_col    gather backprojection, one workgroup per group of voxel columns: the
@@ -704,7 +704,7 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 // angles of a subset write a partial image that the column-sampled launch adds before its
 // epilogue.  Deterministic, no atomics.  The workgroup is one wavefront, whose LDS
 // accesses execute in order: code-motion barriers separate the phases.
-#define BS_W 16
+#define BS_W 10
 
 // N consecutive segments of one ray: all 2N loads, then all sums (in segment order).
 template <int N>
@@ -720,10 +720,12 @@ __device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, c
 }
 
 template <int MODE>
-// Six waves per SIMD (at most 80 VGPRs): room for the loads of a whole ray (span 11:
-// 22 values) next to the 32 accumulators.  Fewer resident strips (the mMR launch of
-// 7568 takes 1.2 rounds) but one memory round trip per ray instead of three.
-__global__ void __launch_bounds__(64, 6) bwd_strip(BwdArgs P, int KR, int rowdom,
+// Seven waves per SIMD (at most 72 VGPRs): room for the loads of a whole ray (span 11:
+// 22 values) next to the 20 accumulators, so a ray costs one memory round trip.  A wave's
+// time is set by the latency of its rays, so narrow strips (fewer rays per wave, more
+// waves) finish sooner: at 344 x 344 the 12040 strips take 1.7 rounds of the chip's wave
+// slots where 16-column strips took 1.2 rounds of longer waves.
+__global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom,
                                                 const float* __restrict__ partial) {
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
