@@ -100,8 +100,8 @@ const char* spdhg_last_error(void);
 /* Number of bins of a geometry / of subset `subset` of `n_subsets` (-1: all angles). */
 int64_t spdhg_subset_bins(const spdhg_geom* geom, int32_t n_subsets, int32_t subset);
 
-/* y_out = A_i x for subset `subset` of `n_subsets` (Algorithm 2, line 5: the projection
- * of the current image), A_i = diag(mult) G restricted to the subset's rows.
+/* y_out = A_i x for subset `subset` of `n_subsets` (Algorithm 2, dual step: the
+ * projection of the current image), A_i = diag(mult) G restricted to the subset's rows.
  *   x       device, image, read only.
  *   mult    device, FULL sinogram of factors, or NULL for G alone.
  *   y_out   device, packed subset rows ([n_angles_of_subset][planes][radial]); subset -1
@@ -110,7 +110,7 @@ int64_t spdhg_subset_bins(const spdhg_geom* geom, int32_t n_subsets, int32_t sub
 int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
                   const float* mult, const float* x, float* y_out, void* stream);
 
-/* x_out = A_i^T y (Algorithm 2, line 6), the exact transpose of spdhg_project computed
+/* x_out = A_i^T y (Algorithm 2, backprojected dual change), the exact transpose of spdhg_project computed
  * by a voxel-driven gather with the same weights (deterministic, no atomics).
  *   y       device, packed subset rows as produced by spdhg_project, read only.
  *   mult    device, FULL sinogram of factors, or NULL.
@@ -132,7 +132,7 @@ int spdhg_workspace_bytes(const spdhg_geom* geom, const spdhg_params* params, si
  *               mult > 0.  Borrowed: they must stay valid until spdhg_destroy.
  *   side        device image (dTV side information) or NULL.  Borrowed.
  *   x           device image: initial image on entry (negative values are clipped, the
- *               first line 3 with z = 0); the iterate is returned here after every
+ *               first primal step with z = 0); the iterate is returned here after every
  *               spdhg_epoch / spdhg_iterate call.  Borrowed.
  *   ws          device workspace of at least spdhg_workspace_bytes(); owned by the
  *               caller, used by the library until spdhg_destroy.

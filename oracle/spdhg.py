@@ -224,7 +224,7 @@ class Problem:
         return out
 
     def reported(self, st):
-        """Iterate after K iterations: line 3 applied once more (x = prox_g(x - T zbar))."""
+        """Iterate after K iterations: the primal step applied once more (x = prox_g(x - T zbar))."""
         return self.prox_g(st["x"] - self.T * st["zbar"])
 
     def iters_per_epoch(self) -> int:
@@ -239,21 +239,21 @@ def spdhg(prob: Problem, n_iter: int, seed: int, state=None, x0=None, blocks=Non
     seq = draw_blocks(seed, prob.p, n_iter, start=st["k"]) if blocks is None else list(blocks)
     x, z, zbar = st["x"], st["z"], st["zbar"]
     for i in seq:
-        x = prob.prox_g(x - prob.T * zbar)                          # line 3
-        if i < prob.m:                                              # line 4: block i
+        x = prob.prox_g(x - prob.T * zbar)                          # primal step
+        if i < prob.m:                                              # sample block i
             yi = st["y"][i]
             v = yi + prob.sigma[i] * prob.A_data(i, x)
-            y_plus = P.prox_kl_dual(v, prob.sigma[i], prob.sub_b[i], prob.sub_r[i])  # line 5
-            dz = prob.AT_data(i, y_plus - yi)                       # line 6
-            st["y"][i] = y_plus                                     # line 7
+            y_plus = P.prox_kl_dual(v, prob.sigma[i], prob.sub_b[i], prob.sub_r[i])  # dual step
+            dz = prob.AT_data(i, y_plus - yi)                       # backprojected dual change
+            st["y"][i] = y_plus                                     # dual update
         else:
             j = i - prob.m
             yj = st["yp"][j]
             y_plus = prob.prior_dual_prox(j, yj + prob.prior_sigma[j] * prob.A_prior(j, x))
             dz = prob.AT_prior(j, y_plus - yj)
             st["yp"][j] = y_plus
-        z = z + dz                                                  # line 7
-        zbar = z + dz / prob.p[i]                                   # line 8
+        z = z + dz                                                  # z update
+        zbar = z + dz / prob.p[i]                                   # extrapolation
         st["k"] += 1
     st["x"], st["z"], st["zbar"] = x, z, zbar
     return st
@@ -283,23 +283,23 @@ def pdhg(prob: Problem, n_iter: int, state=None, x0=None, tol_gap=None, U=None):
     st = prob.new_state(x0) if state is None else state
     x, z, zbar = st["x"], st["z"], st["zbar"]
     for _ in range(n_iter):
-        x = prob.prox_g(x - prob.T * zbar)                          # line 3
+        x = prob.prox_g(x - prob.T * zbar)                          # primal step
         dz = np.zeros_like(x)
         new_y, new_yp = [], []
-        for i in range(prob.m):                                     # line 4
+        for i in range(prob.m):                                     # dual step, every block
             yi = st["y"][i]
             v = yi + prob.sigma[i] * prob.A_data(i, x)
             new_y.append(P.prox_kl_dual(v, prob.sigma[i], prob.sub_b[i], prob.sub_r[i]))
         for j in range(prob.n_prior):
             yj = st["yp"][j]
             new_yp.append(prob.prior_dual_prox(j, yj + prob.prior_sigma[j] * prob.A_prior(j, x)))
-        for i in range(prob.m):                                     # line 5
+        for i in range(prob.m):                                     # backprojected dual change
             dz = dz + prob.AT_data(i, new_y[i] - st["y"][i])
         for j in range(prob.n_prior):
             dz = dz + prob.AT_prior(j, new_yp[j] - st["yp"][j])
-        z = z + dz                                                  # line 6
+        z = z + dz                                                  # z update
         st["y"], st["yp"] = new_y, new_yp
-        zbar = z + dz                                               # line 7
+        zbar = z + dz                                               # extrapolation
         st["k"] += 1
         st["x"], st["z"], st["zbar"] = x, z, zbar
         if tol_gap is not None and st["k"] % 50 == 0:

@@ -11,8 +11,8 @@
 //              the lanes form the in-plane interpolated axial column
 //              G(z) = (1 - fu) x[j][i0][z] + fu x[j][i0 + 1][z] in LDS, then each ray of
 //              the bin (all planes of all segments) adds its axial interpolation of G.
-//              Epilogues: plain output, preconditioner sigma, KL-dual prox (Algorithm 2
-//              line 5), FP64 data term of the objective.
+//              Epilogues: plain output, preconditioner sigma, KL-dual prox (the dual
+//              step of Algorithm 2), FP64 data term of the objective.
 //   fwd_bundle the same with the planes of a bin split over 2 or 4 wavefronts that
 //              share each step's axial column (an autotuner candidate).
 //   bwd_strip  gather backprojection for 32 <= nz <= 127: one wavefront per strip of 10
@@ -22,7 +22,8 @@
 //              interpolation coordinates of every candidate ray are computed once per
 //              column and angle (FP64, shared through LDS), lanes run along z and read
 //              the dual change d[angle][k][plane] contiguously.  No atomics.  Epilogues:
-//              plain output, running minimum for T, primal epilogue (lines 7-8 and 3).
+//              plain output, running minimum for T, primal epilogue (the z updates, extrapolation
+//              and the next primal step).
 //   tv_wave    TV / dTV prior block (dual ascent, l2-ball projection, adjoint, epilogue),
 //              one wavefront per 64-voxel run of a column marching along y (nz >= 32);
 //   tv_iter    the same on column tiles of one workgroup (thin volumes).
@@ -178,25 +179,33 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, in
 // rounded up).  Wavefront w walks the w-th of NW consecutive parts of the primary steps
 // with its own LDS buffers; the partial ray sums are added in a fixed order by wavefront 0
 // (several wavefronts per ray bundle give small subsets enough parallelism).
-// The iteration's projection (F_DUAL) with up to 16 rays per lane is held to six waves
-// per SIMD (at most 80 VGPRs, no spills): more resident wavefronts hide the image-column
-// loads better than the registers the compiler would otherwise take.  The objective's
-// projection (F_OBJ), which the autotuner times in its place, is held the same way.
+// The iteration's projection (F_DUAL) with up to 16 rays per lane is held to five waves
+// per SIMD (at most 96 VGPRs, no spills): room for the reads of FWD_RG rays in flight
+// together.  The objective's projection (F_OBJ), which the autotuner times in its place,
+// is held the same way.
+constexpr int FWD_RG = 8;  // rays per lane whose LDS reads are issued together
+
+// Per step and segment: byte offset of the axial cell and the axial fraction (one 8-byte
+// LDS read per ray and step).
+struct __align__(8) SegStep {
+    int c4;
+    float fz;
+};
+
 template <int RPL, int MODE, int NW>
-__global__ void __launch_bounds__(64 * NW, ((MODE == F_DUAL || MODE == F_OBJ) && RPL <= 16) ? 6 : 1)
+__global__ void __launch_bounds__(64 * NW, ((MODE == F_DUAL || MODE == F_OBJ) && RPL <= 16) ? 5 : 1)
 fwd_wave(FwdArgs P) {
     extern __shared__ float smem[];
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    // each wavefront's LDS region (floats; even, so the doubles stay 8-byte aligned)
+    // each wavefront's LDS region (floats; even, so the 8-byte entries stay aligned)
     const int wstride = max(2 * P.gsize + 8 * ns, 64);
-    float* Gb = smem + w * wstride;                    // [2][gsize] axial columns
-    int* segc = (int*)(Gb + 2 * P.gsize);              // [2][ns] axial cell offsets
-    float* segf = (float*)(segc + 2 * ns);             // [2][ns] axial fractions
-    double* segk = (double*)(segf + 2 * ns);           // [ns] ez_dk * kk of the segment
-    double* segj = segk + ns;                          // [ns] ez_dj of the segment
+    float* Gb = smem + w * wstride;                        // [gsize] axial column (+ gsize spare)
+    SegStep* segt = (SegStep*)(Gb + 2 * P.gsize);          // [ns] this step's axial samples
+    double* segk = (double*)(Gb + 2 * P.gsize + 4 * ns);   // [ns] ez_dk * kk of the segment
+    double* segj = segk + ns;                              // [ns] ez_dj of the segment
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int ia = bid / G.n_rad;
     const int k = bid - ia * G.n_rad;
@@ -207,19 +216,28 @@ fwd_wave(FwdArgs P) {
     const int64_t s_prim = A.rowdom ? G.nx : 1;
     const int64_t s_sec = A.rowdom ? 1 : G.nx;
 
-    int pinfo[RPL];  // (padded axial base of the plane) << 6 | segment
+    // Per ray of the lane: LDS byte offsets of its segment's entry and of its padded axial
+    // base in the column.  A plane beyond the last takes plane 0's (in range; its sum is
+    // never written), so every step handles all rows without per-lane branches.
+    int toff[RPL], boff[RPL];
     float acc[RPL];
+    {
+        const int g0 = G.plane_seg[0];
+        const int base0 = G.seg_off[g0] - G.seg_base[g0] + P.pad;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int q = lane + 64 * r;
-        acc[r] = 0.0f;
-        pinfo[r] = 0;
-        if (q < G.n_planes) {
-            const int g = G.plane_seg[q];
-            pinfo[r] = ((q - G.seg_base[g] + G.seg_off[g] + P.pad) << 6) | g;
+        for (int r = 0; r < RPL; ++r) {
+            const int q = lane + 64 * r;
+            acc[r] = 0.0f;
+            int g = g0, base = base0;
+            if (q < G.n_planes) {
+                g = G.plane_seg[q];
+                base = q - G.seg_base[g] + G.seg_off[g] + P.pad;
+            }
+            toff[r] = (int)((const char*)(segt + g) - (const char*)smem);
+            boff[r] = (int)((const char*)(Gb + base) - (const char*)smem);
         }
     }
-    for (int i = lane; i < 2 * P.gsize; i += 64) Gb[i] = 0.0f;
+    for (int i = lane; i < P.gsize; i += 64) Gb[i] = 0.0f;
     // the axial offset of segment g at step j is fma(ez_dj, jj, ez_dk * kk) (ax_offset):
     // its two step-independent parts are read once, so the step loop loads nothing from
     // global memory but the image columns (only lane g touches entry g)
@@ -235,25 +253,25 @@ fwd_wave(FwdArgs P) {
         j1 = j0 + (n * (w + 1)) / NW;
         j0 = j0 + (n * w) / NW;
     }
-    // Each wavefront has its own LDS buffers and executes its LDS accesses in order, so a
-    // code-motion barrier is enough between writing and reading the axial column.  The
-    // image columns of steps j + 1 .. j + FD are in flight while the rays consume step j
-    // (loads through a range-checked buffer resource: an offset of 1 GiB or more reads
-    // zero, which covers samples outside the image and z beyond nz without branches).
-    // Deeper prefetch (FD > 1) costs more registers than it hides latency on gfx950.
+    // A wavefront's LDS accesses execute in issue order, so one axial column and one
+    // segment table serve every step: the next step's writes cannot overtake this step's
+    // reads, and code-motion barriers keep the compiler to that order.  The image columns
+    // of step j + 1 are in flight while the rays consume step j (loads through a
+    // range-checked buffer resource: an offset of 1 GiB or more reads zero, which covers
+    // samples outside the image and z beyond nz without branches).  Deeper prefetch costs
+    // more registers than it hides latency on gfx950.
     constexpr int NZL = 2;  // z values per lane (nz <= 128)
-    constexpr int FD = 1;   // prefetch depth in steps
     constexpr int OUT = 1 << 30;
     const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
         (void*)P.x, (short)0, (int)(P.G.nx * (int64_t)P.G.ny * nz * 4), 0x00020000);
     int zoff[NZL];
 #pragma unroll
     for (int u = 0; u < NZL; ++u) zoff[u] = lane + 64 * u < nz ? (lane + 64 * u) * 4 : OUT;
-    float v0[FD][NZL], v1[FD][NZL];
-    Sample sm[FD];
-    auto issue = [&](int slot, int j) {
+    float v0[NZL], v1[NZL];
+    Sample sm;
+    auto issue = [&](int j) {
         const Sample q = split(sec_coord(A, kk, (double)j - A.cj));
-        sm[slot] = q;
+        sm = q;
         if (MODE == F_SENS) return;
         const bool ok0 = (unsigned)q.i0 < (unsigned)A.n_sec;
         const bool ok1 = (unsigned)(q.i0 + 1) < (unsigned)A.n_sec;
@@ -261,56 +279,60 @@ fwd_wave(FwdArgs P) {
         const int c1 = ok1 ? (int)(((int64_t)j * s_prim + (int64_t)(q.i0 + 1) * s_sec) * nz * 4) : OUT;
 #pragma unroll
         for (int u = 0; u < NZL; ++u) {
-            v0[slot][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c0 + zoff[u], 0, 0));
-            v1[slot][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c1 + zoff[u], 0, 0));
+            v0[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c0 + zoff[u], 0, 0));
+            v1[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, c1 + zoff[u], 0, 0));
         }
     };
+    if (j0 < j1) issue(j0);
+    float* Gc = Gb + P.pad;
+    const char* lds = (const char*)smem;
+    for (int j = j0; j < j1; ++j) {
+        const double jj = (double)j - A.cj;
+        const Sample s = sm;
+        const float w0 = 1.0f - s.fu, w1 = s.fu;
+        if (MODE == F_SENS) {
+            const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
+            const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
+            const float v = (ok0 ? w0 : 0.0f) + (ok1 ? w1 : 0.0f);
+            for (int iz = lane; iz < nz; iz += 64) Gc[iz] = v;
+        } else {
 #pragma unroll
-    for (int f = 0; f < FD; ++f)
-        if (j0 + f < j1) issue(f, j0 + f);
-    int buf = 0;
-    for (int jb = j0; jb < j1; jb += FD) {
-#pragma unroll
-        for (int f = 0; f < FD; ++f) {
-            const int j = jb + f;
-            if (j >= j1) break;
-            const double jj = (double)j - A.cj;
-            float* Gc = Gb + buf * P.gsize + P.pad;
-            const Sample s = sm[f];
-            const float w0 = 1.0f - s.fu, w1 = s.fu;
-            if (MODE == F_SENS) {
-                const bool ok0 = (unsigned)s.i0 < (unsigned)A.n_sec;
-                const bool ok1 = (unsigned)(s.i0 + 1) < (unsigned)A.n_sec;
-                const float v = (ok0 ? w0 : 0.0f) + (ok1 ? w1 : 0.0f);
-                for (int iz = lane; iz < nz; iz += 64) Gc[iz] = v;
-            } else {
-#pragma unroll
-                for (int u = 0; u < NZL; ++u) {
-                    const int iz = lane + 64 * u;
-                    if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[f][u], w0 * v0[f][u]);
-                }
+            for (int u = 0; u < NZL; ++u) {
+                const int iz = lane + 64 * u;
+                if (iz < nz) Gc[iz] = __builtin_fmaf(w1, v1[u], w0 * v0[u]);
             }
-            if (j + FD < j1) issue(f, j + FD);
-            if (lane < ns) {
-                const Sample sz = split(__builtin_fma(segj[lane], jj, segk[lane]));
-                segc[buf * ns + lane] = sz.i0;
-                segf[buf * ns + lane] = sz.fu;
-            }
-            __builtin_amdgcn_wave_barrier();
-            const float* Gr = Gb + buf * P.gsize;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                if (lane + 64 * r < G.n_planes) {
-                    const int g = pinfo[r] & 63;
-                    const int idx = (pinfo[r] >> 6) + segc[buf * ns + g];
-                    const float fz = segf[buf * ns + g];
-                    acc[r] = __builtin_fmaf(1.0f - fz, Gr[idx], acc[r]);
-                    acc[r] = __builtin_fmaf(fz, Gr[idx + 1], acc[r]);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            buf ^= 1;
         }
+        if (j + 1 < j1) issue(j + 1);
+        if (lane < ns) {
+            const Sample sz = split(__builtin_fma(segj[lane], jj, segk[lane]));
+            SegStep e;
+            e.c4 = sz.i0 * 4;
+            e.fz = sz.fu;
+            segt[lane] = e;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // rays in groups of RG: the table reads of a group, then its column reads, then
+        // its sums, so a group costs two LDS round trips instead of two per ray
+        constexpr int RG = RPL < FWD_RG ? RPL : FWD_RG;
+#pragma unroll
+        for (int r0 = 0; r0 < RPL; r0 += RG) {
+            SegStep e[RG];
+            float ga[RG], gb[RG];
+#pragma unroll
+            for (int i = 0; i < RG; ++i) e[i] = *(const SegStep*)(lds + toff[r0 + i]);
+#pragma unroll
+            for (int i = 0; i < RG; ++i) {
+                const float* gp = (const float*)(lds + boff[r0 + i] + e[i].c4);
+                ga[i] = gp[0];
+                gb[i] = gp[1];
+            }
+#pragma unroll
+            for (int i = 0; i < RG; ++i) {
+                acc[r0 + i] = __builtin_fmaf(1.0f - e[i].fz, ga[i], acc[r0 + i]);
+                acc[r0 + i] = __builtin_fmaf(e[i].fz, gb[i], acc[r0 + i]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     if (NW > 1) {
         // partial ray sums pass through each wavefront's own LDS region (its axial columns
@@ -344,7 +366,7 @@ fwd_wave(FwdArgs P) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int q = lane + 64 * r;
-        if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, pinfo[r] & 63, acc[r], obj);
+        if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], acc[r], obj);
     }
     if (MODE == F_OBJ) {
         obj = wave_sum(obj);
@@ -568,7 +590,7 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t
     } else if (MODE == B_SENS) {
         if (dz > 0.0f) P.T[t] = fminf(P.T[t], P.scale / dz);
     } else {
-        // Algorithm 2 lines 7-8 and line 3 of the next iteration:
+        // Algorithm 2: dual and z updates, extrapolation and the next iteration's primal step:
         // z += dz;  x = max(x - T (z + dz / p_i), 0)
         const float zn = P.z[t] + dz;
         P.z[t] = zn;
@@ -1048,7 +1070,8 @@ __device__ __forceinline__ bool tile_voxel(const PriorTile& TL, int nx, int ny, 
     return ly < TL.ty && cx < nx && cy < ny;
 }
 
-// Algorithm 2 lines 5-8 for the prior block, fused with line 3 of the next iteration.
+// Algorithm 2 from the dual step to the extrapolation for the prior block, fused with the
+// next iteration's primal step.
 // x and y are read from one buffer and written to the other (a recomputing neighbour
 // reads the old values).
 __global__ void __launch_bounds__(1024)
@@ -1370,7 +1393,8 @@ __device__ __forceinline__ void tgv1_dual_at(const TgvArgs& P, const float* __re
                    q1[c + 2 * S.nv], q, dq);
 }
 
-// Algorithm 2 lines 5-8 for block n-1 fused with line 3 of the next iteration:
+// Algorithm 2 from the dual step to the extrapolation for block n-1, fused with the next
+// iteration's primal step:
 // dz_u = grad^T dq, dz_w = -dq; u, w, q1 ping-pong, z_u and z_w in place.  Column tiles as
 // in tv_iter: the dual changes of the tile's voxels are shared through LDS and only the
 // tile's low faces recompute a neighbour's update.
@@ -1489,7 +1513,8 @@ __device__ __forceinline__ void tgv2_dual_at(const TgvArgs& P, const float* __re
     tgv2_dual_vals(P, e, y, q, dq);
 }
 
-// Algorithm 2 lines 5-8 for block n fused with line 3 of the next iteration:
+// Algorithm 2 from the dual step to the extrapolation for block n, fused with the next
+// iteration's primal step:
 // dz_w = E^T dq (E^T p)_k = sum_l D_l^T of the (k, l) entry, D_l^T p (v) = [v_l > 0]
 // p(v - e_l) - [v_l < N_l - 1] p(v); dz_u = 0, so u = max(u - T_u z_u, 0).  Column tiles
 // with the 6-component dual changes shared through LDS, as in tgv1_iter.
@@ -1805,7 +1830,7 @@ tgv2_wave(TgvArgs P, int ly, const float* __restrict__ u_in, float* __restrict__
     }
 }
 
-// Line 3 for the w component over k data iterations (their dz_w is 0, so z_w is
+// The primal step for the w component over k data iterations (their dz_w is 0, so z_w is
 // unchanged and every one of them subtracts T_w z_w): w -= k T_w z_w.
 __global__ void w_catchup(float* __restrict__ w, const float* __restrict__ zw, int64_t n, float s) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;

@@ -1031,7 +1031,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
         c->masked_phi0 = h[0];
     }
-    // the image: caller layout -> z-fastest, line 3 with z = 0: x = max(x0, 0)
+    // the image: caller layout -> z-fastest, the primal step with z = 0: x = max(x0, 0)
     img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(geom->nx, geom->ny,
                                                                          geom->nz, x, c->xa);
     clip_nonneg<<<nblocks(nv), BLOCK, 0, st>>>(c->xa, nv);
@@ -1238,7 +1238,7 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             if ((rc = launch_bwd<B_ITER>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
                 return rc;
             if ((rc = prof_end(c, st))) return rc;
-            if (c->zw) c->w_pending += 1;  // line 3 for w: w -= T_w z_w (z_w unchanged)
+            if (c->zw) c->w_pending += 1;  // primal step for w: w -= T_w z_w (z_w unchanged)
         } else if (c->zw) {
             const int j = i - c->m;
             if ((rc = settle_w(c, st))) return rc;

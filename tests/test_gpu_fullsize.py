@@ -4,14 +4,14 @@ same state.
 
 Data iteration: the oracle's own Algorithm 2 loop (oracle.spdhg.spdhg, one iteration of
 the drawn subset: forward projection, KL-dual prox, backprojection, z and z-bar, then the
-next iteration's line 3) from the library's state and step sizes.
+next iteration's primal step) from the library's state and step sizes.
 
 Prior iterations: one TV and one TGV iteration (both blocks) against the oracle's
 operators:
 
 The state is taken from the library after k iterations (k = the first iteration whose
 SplitMix64 draw is a prior block), the GPU runs iteration k, and the oracle recomputes
-lines 5-8 of that iteration and line 3 of the next (which the library fuses into the
+the dual step to the extrapolation of that iteration and the primal step of the next (which the library fuses into the
 same launch) from the FP32 snapshot:
 
   TV (Section 4.3, eq. setting TV):  y' = P_alpha(y + sigma grad x),  dz = grad^T (y' - y)
@@ -188,7 +188,7 @@ def test_mmr_data_iteration(P, mmr_inputs):
     prob.prior_sigma = [prior_sigma]
     prob.norms = [None] * prob.n
     prob.T = s0["T"][None]
-    st = prob.new_state(x_before)  # z-bar = 0: line 3 returns x_before itself
+    st = prob.new_state(x_before)  # z-bar = 0: the primal step returns x_before itself
     st["y"] = [s0["y"][a] for a in prob.angles]
     st["yp"] = [s0["prior_dual"]]
     st["z"] = s0["z"][None]
