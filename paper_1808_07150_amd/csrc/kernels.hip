@@ -176,7 +176,7 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, in
 }
 
 // One workgroup of NW wavefronts per (angle, radial bin); RPL = rays per lane (planes / 64,
-// rounded up).  Wavefront w walks the w-th of NW consecutive parts of the primary steps
+// rounded up to a power of two, or 14 for the iteration and the objective).  Wavefront w walks the w-th of NW consecutive parts of the primary steps
 // with its own LDS buffers; the partial ray sums are added in a fixed order by wavefront 0
 // (several wavefronts per ray bundle give small subsets enough parallelism).
 // The iteration's projection (F_DUAL) with up to 16 rays per lane is held to five waves
@@ -319,17 +319,22 @@ fwd_wave(FwdArgs P) {
             SegStep e[RG];
             float ga[RG], gb[RG];
 #pragma unroll
-            for (int i = 0; i < RG; ++i) e[i] = *(const SegStep*)(lds + toff[r0 + i]);
+            for (int i = 0; i < RG; ++i)
+                if (r0 + i < RPL) e[i] = *(const SegStep*)(lds + toff[r0 + i]);
 #pragma unroll
             for (int i = 0; i < RG; ++i) {
-                const float* gp = (const float*)(lds + boff[r0 + i] + e[i].c4);
-                ga[i] = gp[0];
-                gb[i] = gp[1];
+                if (r0 + i < RPL) {
+                    const float* gp = (const float*)(lds + boff[r0 + i] + e[i].c4);
+                    ga[i] = gp[0];
+                    gb[i] = gp[1];
+                }
             }
 #pragma unroll
             for (int i = 0; i < RG; ++i) {
-                acc[r0 + i] = __builtin_fmaf(1.0f - e[i].fz, ga[i], acc[r0 + i]);
-                acc[r0 + i] = __builtin_fmaf(e[i].fz, gb[i], acc[r0 + i]);
+                if (r0 + i < RPL) {
+                    acc[r0 + i] = __builtin_fmaf(1.0f - e[i].fz, ga[i], acc[r0 + i]);
+                    acc[r0 + i] = __builtin_fmaf(e[i].fz, gb[i], acc[r0 + i]);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();

@@ -279,11 +279,19 @@ int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
     // ray sums (kernel: wstride)
     const size_t lds = NW * std::max<size_t>(2 * (size_t)A.gsize + 8 * (size_t)A.G.n_seg, 64) * 4;
     const int nt = 64 * NW;
+    // the iteration and the objective also have a 14-row instance (837 planes of span 11
+    // take 14 rows: no rows past the last plane)
+    constexpr bool hot = MODE == F_DUAL || MODE == F_OBJ;
+    if (hot && rpl == 16 && (A.G.n_planes + 63) / 64 >= 13 && (A.G.n_planes + 63) / 64 <= 14)
+        rpl = 14;
     switch (rpl) {
         case 1: fwd_wave<1, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
         case 2: fwd_wave<2, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
         case 4: fwd_wave<4, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
         case 8: fwd_wave<8, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 14:
+            if constexpr (hot) fwd_wave<14, MODE, NW><<<nblk, nt, lds, st>>>(A);
+            break;
         case 16: fwd_wave<16, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
         case 32:
             if constexpr (NW <= 4) fwd_wave<32, MODE, NW><<<nblk, nt, lds, st>>>(A);
