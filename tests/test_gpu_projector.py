@@ -42,6 +42,10 @@ GEOMS = {
     "tall": synth.Geometry(nx=37, ny=45, nz=41, vx=2.0, vy=2.0, vz=2.0, n_rad=50, d_rad=2.0,
                            n_ang=16, seg_planes=(41, 37, 37, 31, 31),
                            seg_tan=(0.0, 0.1, -0.1, 0.3, -0.3)),
+    # the span-11 segment structure of the mMR (11 segments, 837 planes = 14 rows of 64
+    # lanes, two rows past the last plane in the 16-row forward instance; all 11 segment
+    # loads of a ray in one batch of the strip gather) on a 13 x 13 x 127 image
+    "span11": synth.mmr(nxy=13, vxy=5.0, n_rad=16, n_ang=6),
 }
 
 

@@ -67,6 +67,16 @@ def maxnz3d():
     return synth.brain_problem(g, 18080800, 5e5)
 
 
+@pytest.fixture(scope="module")
+def span11_3d():
+    """The mMR's span-11 segment structure (11 segments, 837 planes) on a 13 x 13 x 127
+    image: the 14-row forward instances of the iteration and the objective, and the strip
+    gather with all 11 segment loads of a ray in one batch, at a size the oracle runs in a
+    second."""
+    g = synth.mmr(nxy=13, vxy=5.0, n_rad=16, n_ang=6)
+    return synth.brain_problem(g, 18080900, 5e5)
+
+
 def run_pair(P, d, n_subsets, prior, epochs, seed, sampling="uniform", precond=True,
              alpha=0.1, side=None, eta=1e-2, alpha1=0.0):
     g = d["geom"]
@@ -231,6 +241,19 @@ def test_deep3d_prior_parity(P, deep3d, prior):
 def test_maxnz_parity(P, maxnz3d, prior):
     print(f"[spdhg] maxnz (nz=128) {prior}", flush=True)
     prob, st, rec, x = run_pair(P, maxnz3d, 3, prior, 10, seed=41, sampling="balanced",
+                                alpha=0.05, alpha1=0.025 if prior == "tgv" else 0.0)
+    X = prob.reported(st)
+    assert rel(x.cpu().numpy(), X[0]) <= 1e-3
+    if prior == "tgv":
+        assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
+    psi_o = prob.objective(X)
+    assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
+
+
+@pytest.mark.parametrize("prior", ["tv", "tgv"])
+def test_span11_parity(P, span11_3d, prior):
+    print(f"[spdhg] span11 (837 planes) {prior}", flush=True)
+    prob, st, rec, x = run_pair(P, span11_3d, 3, prior, 10, seed=43, sampling="balanced",
                                 alpha=0.05, alpha1=0.025 if prior == "tgv" else 0.0)
     X = prob.reported(st)
     assert rel(x.cpu().numpy(), X[0]) <= 1e-3
