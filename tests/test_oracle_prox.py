@@ -120,3 +120,29 @@ def test_nonneg_prox_vs_brute_force():
         res = minimize_scalar(lambda z: 0.5 * (z - xi) ** 2, bounds=(0, 10), method="bounded",
                               options=dict(xatol=1e-12))
         assert P.prox_nonneg(xi) == pytest.approx(res.x, abs=1e-8)
+
+
+def _soft_threshold(v, t):
+    """prox of t ||.||_1: sign(v) max(|v| - t, 0) (the textbook shrinkage)."""
+    return np.sign(v) * np.maximum(np.abs(v) - t, 0.0)
+
+
+def test_linf_ball_projection_vs_brute_force_and_moreau():
+    """aTV's dual prox (Section 4.3): the prox of the conjugate of alpha ||.||_1, i.e. the
+    projection onto the box |p_c| <= alpha, against (a) a bound-constrained minimiser of
+    1/2 ||z - v||^2 and (b) the Moreau identity v = prox_{f*}(v) + prox_f(v) with the
+    soft-thresholding prox of f = alpha ||.||_1."""
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        v = rng.normal(size=3) * 2
+        alpha = rng.uniform(0.1, 3)
+        got = P.clip_linf_ball(v, alpha)
+        res = minimize(lambda z: 0.5 * np.sum((z - v) ** 2), np.zeros(3), method="L-BFGS-B",
+                       bounds=[(-alpha, alpha)] * 3, jac=lambda z: z - v,
+                       options=dict(ftol=1e-15, gtol=1e-12, maxiter=500))
+        np.testing.assert_allclose(got, res.x, atol=1e-7)
+        np.testing.assert_allclose(got + _soft_threshold(v, alpha), v, rtol=0, atol=1e-14)
+    np.testing.assert_array_equal(P.clip_linf_ball(np.array([0.5, -0.25, 0.0]), 1.0),
+                                  [0.5, -0.25, 0.0])
+    np.testing.assert_array_equal(P.clip_linf_ball(np.array([2.0, -3.0, 0.9]), 1.0),
+                                  [1.0, -1.0, 0.9])

@@ -66,6 +66,25 @@ def test_pdhg_gap_tv():
     assert gap <= 1e-8 * pp.objective(xr)
 
 
+def test_pdhg_gap_atv():
+    """aTV (alpha ||grad u||_{1,1}, Section 4.3): PDHG with the box projection as the dual
+    prox closes the gap, whose dual part is the indicator of that same box and whose
+    primal part charges alpha ||grad u||_1.  A dual prox onto any other box leaves a gap
+    of (alpha - alpha') ||grad x*||_1 or an infeasible dual."""
+    g, b, r, mult = tiny_problem()
+    prob = S.Problem(g, b, r, mult, n_subsets=4, prior="atv", alpha=0.5)
+    pp, st = _solve_pdhg(prob, tol=1e-9)
+    xr = pp.reported(st)
+    gap = S.duality_gap(pp, xr, st, 2 * xr.max() + 1)
+    assert gap <= 1e-8 * pp.objective(xr)
+    # the prior dual sits on the box's faces wherever the gradient is non-zero
+    q = st["yp"][0]
+    gr = priors.grad(xr[0])
+    on = np.abs(gr) > 1e-6
+    assert np.any(on)
+    np.testing.assert_allclose(np.abs(q[on]), 0.5, rtol=1e-6)
+
+
 def test_pdhg_gap_ml_interior():
     """High counts on a well-conditioned 4x4 problem (cond(A) ~ 26): the ML solution is
     interior and PDHG converges linearly."""
