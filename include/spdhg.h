@@ -14,7 +14,9 @@
  *
  * Conventions shared by every entry point
  *   - Every pointer argument documented as "device" is device memory on the device that
- *     is current when the call is made; the library never frees caller memory.
+ *     is current when the call is made.  The library allocates no device memory: every
+ *     scratch array lives in a caller-provided workspace (sized by the *_workspace_bytes
+ *     queries, 256-byte aligned), and it never frees caller memory.
  *   - Images are float32 [nz][ny][nx] (x fastest); sinograms are float32
  *     [angle][plane][radial] (radial fastest).  Planes are ordered by segment
  *     0, +1, -1, +2, -2, ... and, inside a segment, by axial position.
@@ -75,6 +77,17 @@ typedef struct spdhg_geom {
 
 #define SPDHG_SAMPLING_UNIFORM 0  /* p_i = 1/n (Section 4.2)                          */
 #define SPDHG_SAMPLING_BALANCED 1 /* data 1/(2m) each, prior 1/2 (Section 4.2)        */
+#define SPDHG_SAMPLING_CUSTOM 2   /* a constant tuned distribution (Discussion): prior
+                                   * blocks together p_prior, data (1 - p_prior)/m each;
+                                   * TGV: block n gets p_tgv_n of p_prior (0: half)    */
+
+#define SPDHG_FLAG_EM 1 /* also set up the EM-type updates of eq. OSEM (spdhg_em_iterate):
+                          * m sensitivity images in the workspace */
+#define SPDHG_FLAG_TGV_SPLIT_T 2 /* TGV: each prior block's scalar step caps only the
+                                  * variables its operator acts on (block n = (0, E): w
+                                  * only), instead of the minimum over all blocks for u and w
+                                  * alike; Theorem 1 bounds ||S_i^1/2 A_i T^1/2|| per block,
+                                  * and T_u does not enter block n's bound */
 
 typedef struct spdhg_params {
     int32_t n_subsets; /* m >= 1                                                      */
@@ -88,8 +101,10 @@ typedef struct spdhg_params {
     double rho;        /* step parameter 0 < rho < 1                                  */
     uint64_t seed;     /* SplitMix64 seed of the block sequence                        */
     int32_t power_iters; /* scalar steps: power iterations for ||A_i|| (e.g. 100)      */
-    int32_t reserved;
+    int32_t flags;       /* SPDHG_FLAG_* (0 for plain SPDHG)                            */
     double alpha1;     /* TGV: weight of ||E w|| (alpha is the weight of ||grad u - w||) */
+    double p_prior;    /* SPDHG_SAMPLING_CUSTOM: total probability of the prior blocks   */
+    double p_tgv_n;    /* SPDHG_SAMPLING_CUSTOM, TGV: probability of block n (0: half)   */
 } spdhg_params;
 
 typedef struct spdhg_ctx spdhg_ctx;
@@ -100,29 +115,55 @@ const char* spdhg_last_error(void);
 /* Number of bins of a geometry / of subset `subset` of `n_subsets` (-1: all angles). */
 int64_t spdhg_subset_bins(const spdhg_geom* geom, int32_t n_subsets, int32_t subset);
 
+/* Bytes of device workspace the stand-alone operator calls below (spdhg_project,
+ * spdhg_backproject, spdhg_nnz, spdhg_normalised_backprojection) need for `geom`, for any
+ * subset: the geometry tables, two z-fastest images, the staging of 16 angles' sinogram
+ * rows and FP64 partials over every bin.  The workspace is the caller's (e.g. a torch
+ * uint8 tensor), 256-byte aligned; a call overwrites it, so calls that share one
+ * workspace must be ordered (the same stream). */
+int spdhg_op_workspace_bytes(const spdhg_geom* geom, size_t* bytes);
+
 /* y_out = A_i x for subset `subset` of `n_subsets` (Algorithm 2, dual step: the
  * projection of the current image), A_i = diag(mult) G restricted to the subset's rows.
  *   x       device, image, read only.
  *   mult    device, FULL sinogram of factors, or NULL for G alone.
  *   y_out   device, packed subset rows ([n_angles_of_subset][planes][radial]); subset -1
  *           means all angles (the full sinogram).  Overwritten.
- * FP32 arithmetic and accumulation.  Errors: SPDHG_E_ARG, SPDHG_E_SHAPE, SPDHG_E_HIP. */
+ *   ws      device workspace of at least spdhg_op_workspace_bytes() bytes.
+ * FP32 arithmetic and accumulation.  Errors: SPDHG_E_ARG, SPDHG_E_SHAPE,
+ * SPDHG_E_WORKSPACE, SPDHG_E_HIP. */
 int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
-                  const float* mult, const float* x, float* y_out, void* stream);
+                  const float* mult, const float* x, float* y_out, void* ws, size_t ws_bytes,
+                  void* stream);
 
-/* x_out = A_i^T y (Algorithm 2, backprojected dual change), the exact transpose of spdhg_project computed
- * by a voxel-driven gather with the same weights (deterministic, no atomics).
+/* x_out = A_i^T y (Algorithm 2, backprojected dual change), the exact transpose of
+ * spdhg_project computed by a voxel-driven gather with the same weights (deterministic,
+ * no atomics).
  *   y       device, packed subset rows as produced by spdhg_project, read only.
  *   mult    device, FULL sinogram of factors, or NULL.
- *   x_out   device, image, overwritten. */
+ *   x_out   device, image, overwritten.
+ *   ws      device workspace of at least spdhg_op_workspace_bytes() bytes. */
 int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
-                      const float* mult, const float* y, float* x_out, void* stream);
+                      const float* mult, const float* y, float* x_out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* The normalised backprojection (A^T b) / (A^T 1) over all angles, 0 where A^T 1 = 0
+ * (A^T 1 is the sensitivity of the EM-type update, eq. MLEM; A^T b / A^T 1 is the first
+ * MLEM iterate from a constant image up to a factor):
+ *   b, mult     device, full sinograms (counts, factors), read only.
+ *   out         device image, overwritten.
+ *   stats_dev   device, 3 doubles: [sum, count, count / sum] of the positive voxels of
+ *               out (the last is the scale that brings their mean to 1; 1 if none).
+ *   ws          device workspace of at least spdhg_op_workspace_bytes() bytes. */
+int spdhg_normalised_backprojection(const spdhg_geom* geom, const float* b, const float* mult,
+                                    float* out, double* stats_dev, void* ws, size_t ws_bytes,
+                                    void* stream);
 
 /* Number of nonzero entries of A_i (taps of the rays of subset `subset` that fall inside
  * the image with a nonzero interpolation weight), written to *out (host).  Measurement
- * helper: allocates a small scratch array, synchronises `stream`. */
+ * helper: uses the operator workspace `ws` and synchronises `stream`. */
 int spdhg_nnz(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, double* out,
-              void* stream);
+              void* ws, size_t ws_bytes, void* stream);
 
 /* Bytes of device workspace a reconstruction needs (duals, z, step sizes, scratch). */
 int spdhg_workspace_bytes(const spdhg_geom* geom, const spdhg_params* params, size_t* bytes);
@@ -180,6 +221,26 @@ int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32
  * *fwd_split and *ms receive the choice and its time per launch. */
 int spdhg_set_tuning(spdhg_ctx* ctx, int32_t fwd_split);
 int spdhg_autotune(spdhg_ctx* ctx, int32_t* fwd_split, double* ms, void* stream);
+
+/* n_iters iterations of deterministic PDHG (Algorithm 1): every block's dual step from the
+ * same x, the backprojected dual changes summed, z += dz, extrapolation z_bar = z + dz and
+ * the primal step max(x - T z_bar, 0).  Needs a context with one data block (n_subsets =
+ * 1, else SPDHG_E_STATE); its step sizes are those of Theorem 2 with the context's block
+ * probabilities in the role of the weights that sum to 1 (1/2 data, 1/2 prior; 1 for ML),
+ * which the convergence condition of PDHG with several blocks needs.  TV, aTV, dTV and
+ * no prior (TGV: SPDHG_E_NOTIMPL).  The reference minimiser of the relative objective
+ * (Section 4: 5,000 PDHG iterations) is computed with it.  Asynchronous on `stream`. */
+int spdhg_pdhg_iterate(spdhg_ctx* ctx, int64_t n_iters, void* stream);
+
+/* EM-type sub-iterations (eq. MLEM; eq. OSEM with the context's m subsets, visited in
+ * the order 0, 1, ..., m - 1, continuing where the previous call stopped): on subset i,
+ *     x = x / (A_i^T 1) * A_i^T (b_i / (A_i x + r_i)),
+ * with b / (.) taken as 0 on bins with b = 0 and x = 0 where A_i^T 1 = 0.  With m = 1 this
+ * is MLEM.  Acts on the context's image only (the SPDHG duals are left as they are); the
+ * image is returned in the caller's x as after spdhg_iterate.  EM keeps zero voxels at
+ * zero, so start it from a positive image.  Needs a context set up with SPDHG_FLAG_EM
+ * (else SPDHG_E_STATE).  Asynchronous on `stream`. */
+int spdhg_em_iterate(spdhg_ctx* ctx, int64_t n_subiters, void* stream);
 
 /* Iterations per epoch and iterations done so far. */
 int spdhg_info(const spdhg_ctx* ctx, int64_t* iters_per_epoch, int64_t* iters_done);

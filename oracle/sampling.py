@@ -58,3 +58,22 @@ def balanced(m: int, n_prior: int):
     if n_prior == 0:
         return uniform(m)
     return [1.0 / (2 * m)] * m + [0.5 / n_prior] * n_prior
+
+
+def prior_share(m: int, n_prior: int, q: float, q_last: float = 0.0):
+    """A constant tuned distribution (Discussion: optimising the sampling): the prior
+    blocks together with probability q, the m data blocks uniformly with 1 - q.  With two
+    prior blocks (TGV) the last gets q_last (0 < q_last < q) and the other q - q_last; q_last
+    = 0 splits q equally.  q = 1/2 is the balanced sampling of Section 4.2."""
+    if n_prior == 0:
+        return uniform(m)
+    if not 0.0 < q < 1.0:
+        raise ValueError("prior share must be in (0, 1)")
+    data = [(1.0 - q) / m] * m
+    if n_prior == 1:
+        return data + [q]
+    if q_last == 0.0:
+        return data + [q / 2.0, q / 2.0]
+    if not 0.0 < q_last < q:
+        raise ValueError("q_last must be in (0, q)")
+    return data + [q - q_last, q_last]

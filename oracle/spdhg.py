@@ -34,7 +34,7 @@ import numpy as np
 from . import priors
 from . import projector as proj
 from . import prox as P
-from .sampling import balanced, draw_blocks, uniform
+from .sampling import balanced, draw_blocks, prior_share, uniform
 
 
 @dataclasses.dataclass
@@ -50,10 +50,13 @@ class Problem:
     side: Optional[np.ndarray] = None
     eta: float = 1e-2
     gamma_d: float = 1.0
-    sampling: str = "uniform"   # 'uniform' | 'balanced'
+    sampling: str = "uniform"   # 'uniform' | 'balanced' | 'custom'
     precond: bool = True
     gamma: float = 1.0
     rho: float = 0.99
+    p_prior: float = 0.5        # 'custom': total probability of the prior blocks
+    p_tgv_n: float = 0.0        # 'custom', TGV: probability of block n (0: half of p_prior)
+    split_T: bool = False       # TGV: each prior block's scalar T caps only its variables
 
     def __post_init__(self):
         g = self.geom
@@ -75,6 +78,8 @@ class Problem:
             self.p = uniform(self.n)
         elif self.sampling == "balanced":
             self.p = balanced(m, self.n_prior)
+        elif self.sampling == "custom":
+            self.p = prior_share(m, self.n_prior, self.p_prior, self.p_tgv_n)
         else:
             raise ValueError(self.sampling)
         if self.prior == "dtv":
@@ -141,8 +146,10 @@ class Problem:
         if self.prior == "tgv" and j == 0:
             return math.sqrt(priors.grad_norm_closed_form(shape) ** 2 + 1.0)
         if self.prior == "tgv":
-            return priors.power_norm(priors.sym_grad, priors.sym_grad_adj,
-                                     priors.checkerboard((3,) + tuple(shape)), iters=200)
+            # block n = (0, E): the closed-form bound ||E|| <= ||grad|| (Frobenius: ||E w||^2
+            # <= sum_k ||grad w_k||^2), so the step condition of Theorem 1 holds for sure; a
+            # truncated power iteration approaches ||E|| from below
+            return priors.grad_norm_closed_form(shape)
         if self.prior == "dtv":
             return priors.power_norm(lambda u: priors.dgrad(u, self.xi, self.gamma_d),
                                      lambda q: priors.dgrad_adj(q, self.xi, self.gamma_d),
@@ -183,7 +190,13 @@ class Problem:
             nrm = self.prior_norm(j)
             self.norms.append(nrm)
             self.prior_sigma.append(gam * rho / nrm)
-            Tmin = np.minimum(Tmin, rho * self.p[self.m + j] / (gam * nrm))
+            tj = rho * self.p[self.m + j] / (gam * nrm)
+            if self.prior == "tgv" and self.split_T and j == 1:
+                # block n is (0, E): it constrains the step of w only (Theorem 1 bounds
+                # ||S_n^1/2 A_n T^1/2||, in which T_u does not appear)
+                Tmin[1:4] = np.minimum(Tmin[1:4], tj)
+            else:
+                Tmin = np.minimum(Tmin, tj)
         self.T = np.where(np.isfinite(Tmin), Tmin, 0.0)
 
     # ------------------------------------------------------------ objective
@@ -365,6 +378,33 @@ def kkt_residual(prob: Problem, X, st) -> float:
     x_fix = prob.prox_g(X - prob.T * ATy)
     res = max(res, float(np.max(np.abs(x_fix - X))))
     return res
+
+
+def osem_step(prob: Problem, u, i: int):
+    """One OSEM sub-iteration on subset i (eq. OSEM): u <- u / (P_i^T 1) * P_i^T(b_i /
+    (P_i u + r_i)), with 0 where P_i^T 1 = 0 and b / (.) taken as 0 on bins with b = 0.
+    The subsets are the problem's (equidistant angles); a full OSEM iteration visits
+    i = 0, 1, ..., m - 1 in order."""
+    g = prob.geom
+    u = np.asarray(u, np.float64).reshape(g.image_shape)
+    ang = prob.angles[i]
+    sens = proj.backward(g, prob.sub_mult[i], ang)
+    pu = prob.sub_mult[i] * proj.forward(g, u, ang)
+    b, r = prob.sub_b[i], prob.sub_r[i]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(b > 0, b / (pu + r), 0.0)
+    back = proj.backward(g, prob.sub_mult[i] * ratio, ang)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(sens > 0, u / sens * back, 0.0)
+
+
+def poisson_loglik(prob: Problem, u) -> float:
+    """sum_j b_j log((P u + r)_j) - (P u + r)_j: the Poisson log-likelihood up to a constant
+    (the negative of the data term of Problem 1 plus that constant)."""
+    g = prob.geom
+    ybar = prob.mult * proj.forward(g, np.asarray(u, np.float64).reshape(g.image_shape)) + prob.r
+    with np.errstate(divide="ignore"):
+        return float(np.sum(np.where(prob.b > 0, prob.b * np.log(ybar), 0.0) - ybar))
 
 
 def mlem_step(prob: Problem, u):

@@ -3,6 +3,7 @@
 The computation lives in libspdhg.so (hand-written HIP kernels for gfx950, C ABI in
 include/spdhg.h); this package is its thin Python binding.
 """
-from .spdhg import (CGeom, CParams, Reconstruction, SpdhgError, batch_epoch,  # noqa: F401
-                    cgeom, cparams, load_library, spdhg_backproject, spdhg_nnz,
+from .spdhg import (CGeom, CParams, Reconstruction, SpdhgError, aligned_workspace,  # noqa: F401
+                    batch_epoch, cgeom, cparams, load_library, normalised_backprojection,
+                    op_workspace, op_workspace_bytes, spdhg_backproject, spdhg_nnz,
                     spdhg_project, subset_bins)

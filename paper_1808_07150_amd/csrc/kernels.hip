@@ -118,7 +118,7 @@ __device__ __forceinline__ void sec_range(const AngleDev& A, double u0, int& j0,
 }
 
 // ---------------------------------------------------------------- forward projection
-enum FwdMode { F_PLAIN_QK = 0, F_POWER = 1, F_SENS = 2, F_DUAL = 3, F_OBJ = 4 };
+enum FwdMode { F_PLAIN_QK = 0, F_POWER = 1, F_SENS = 2, F_DUAL = 3, F_OBJ = 4, F_EM = 5 };
 
 // Row layout of the dual change read by the backprojectors: per (angle of the list,
 // radial bin) the n_planes values of the ray bundle, segment g at planes seg_base[g] ..
@@ -172,6 +172,12 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, in
         P.d[dual_row(G, ia, k) + q] = m * (yn - yo);
     } else if (MODE == F_OBJ) {
         obj += phi64((double)(P.mult[full] * v), (double)P.b[full], (double)P.r[full]);
+    } else if (MODE == F_EM) {
+        // EM-type update (eq. MLEM / OSEM): the ratio b / (A x + r) of the bin, times mult
+        // (the row factor of the backprojection A^T = G^T diag(mult)); 0 where b = 0
+        const float m = P.mult[full];
+        const float b = P.b[full];
+        P.d[dual_row(G, ia, k) + q] = b > 0.0f ? m * (b / __builtin_fmaf(m, v, P.r[full])) : 0.0f;
     }
 }
 
@@ -511,7 +517,7 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
 }
 
 // ---------------------------------------------------------------- gather backprojection
-enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2, B_PARTIAL = 3, B_ACCUM = 4 };
+enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2, B_PARTIAL = 3, B_ACCUM = 4, B_EM = 5 };
 #define BWD_THREADS 128
 #define BWD_KC 4  // candidate radial bins per column and angle
 
@@ -594,6 +600,10 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t
         P.out[t] += dz;
     } else if (MODE == B_SENS) {
         if (dz > 0.0f) P.T[t] = fminf(P.T[t], P.scale / dz);
+    } else if (MODE == B_EM) {
+        // eq. OSEM: x = x / (A_i^T 1) * A_i^T (b / (A_i x + r)); T holds 1 / (A_i^T 1) (0 off
+        // the subset's support)
+        P.x[t] = P.x[t] * (dz * P.T[t]);
     } else {
         // Algorithm 2: dual and z updates, extrapolation and the next iteration's primal step:
         // z += dz;  x = max(x - T (z + dz / p_i), 0)
@@ -983,6 +993,10 @@ struct PriorArgs {
     float gamma_d;
     int dtv;
     int atv;      // anisotropic TV: f_n = alpha ||.||_{1,1}, dual prox = clip to [-alpha, alpha]
+    // PDHG (Algorithm 1): the data blocks' backprojected dual change of the same iteration
+    // (z-fastest image), added to the prior's before the z update and the primal step;
+    // NULL in SPDHG, where each iteration updates one block
+    const float* dz_add;
 };
 
 __device__ __forceinline__ void zf_coords(const PriorArgs& P, int64_t t, int& cx, int& cy,
@@ -1120,6 +1134,7 @@ tv_iter(PriorArgs P, PriorTile TL, const float* __restrict__ x_in, float* __rest
     }
     if (cz > 0) dz += sdq[2][l - 1];
     const int64_t t = ((int64_t)cy * P.nx + cx) * P.nz + cz;
+    if (P.dz_add) dz += P.dz_add[t];
     y_out[t] = q[0];
     y_out[t + nv] = q[1];
     y_out[t + 2 * nv] = q[2];
@@ -1269,6 +1284,7 @@ tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__
             if (lx) dz += dn[0];
             if (cy > 0) dz += dprev;
             if (cz > 0) dz += dzn;
+            if (P.dz_add) dz += vol_ld(vol_rsrc(P.dz_add, nvb), c, 0);
             vol_st(ryo, c, 0, q[0]);
             vol_st(ryo, c, nvb, q[1]);
             vol_st(ryo, c, 2 * nvb, q[2]);
@@ -1876,60 +1892,47 @@ tgv_obj(int nx, int ny, int nz, double alpha0, double alpha1, const float* __res
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Power iteration helpers for ||E||: out6 = E w, out3 = E^T q.
+// ---------------------------------------------------------------- normalised backprojection
+// out = atb / at1 where at1 > 0, else 0 (out may alias atb: each thread reads its element
+// before writing it); FP64 partials per block of the sum of the positive outputs (part_s)
+// and of their count (part_n).
 __global__ void __launch_bounds__(BLOCK)
-sym_grad_apply(int nx, int ny, int nz, const float* __restrict__ w, float* __restrict__ out) {
-    const ZfStrides S = zf_strides(nx, ny, nz);
+ratio_on_support(const float* atb, const float* __restrict__ at1, int64_t n, float* out,
+                 double* __restrict__ part_s, double* __restrict__ part_n) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t >= S.nv) return;
-    const int64_t col = t / nz;
-    const int cz = (int)(t - col * nz);
-    const int cy = (int)(col / nx), cx = (int)(col - (int64_t)cy * nx);
-    float e[6];
-    sym_grad_at(nx, ny, nz, w, cx, cy, cz, e);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) out[t + k * S.nv] = e[k];
-}
-
-__global__ void __launch_bounds__(BLOCK)
-sym_grad_adj(int nx, int ny, int nz, const float* __restrict__ q, float* __restrict__ out) {
-    const ZfStrides S = zf_strides(nx, ny, nz);
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t >= S.nv) return;
-    const int64_t col = t / nz;
-    const int cz = (int)(t - col * nz);
-    const int cy = (int)(col / nx), cx = (int)(col - (int64_t)cy * nx);
-    const int cc[3] = {cx, cy, cz};
-    const int nn[3] = {nx, ny, nz};
-    const int64_t step[3] = {S.sx, S.sy, 1};
-    const int ent[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    for (int k = 0; k < 3; ++k) {
-        float acc = 0.0f;
-        for (int l = 0; l < 3; ++l) {
-            const float* qe = q + ent[k][l] * S.nv;
-            float v = 0.0f;
-            if (cc[l] > 0) v += qe[t - step[l]];
-            if (cc[l] < nn[l] - 1) v -= qe[t];
-            acc = __builtin_fmaf(k == l ? 1.0f : TGV_SQRT_HALF, v, acc);
+    double v = 0.0, c = 0.0;
+    if (t < n) {
+        const float a = at1[t];
+        const float r = a > 0.0f ? atb[t] / a : 0.0f;
+        out[t] = r;
+        if (r > 0.0f) {
+            v = r;
+            c = 1.0;
         }
-        out[t + k * S.nv] = acc;
+    }
+    const double s = block_sum<BLOCK>(v);
+    const double k = block_sum<BLOCK>(c);
+    if (threadIdx.x == 0) {
+        part_s[blockIdx.x] = s;
+        part_n[blockIdx.x] = k;
     }
 }
 
-// (-1)^(k + x + y + z) over a 3-component z-fastest field.
-__global__ void checkerboard3(int nx, int ny, int nz, float* __restrict__ out) {
-    const ZfStrides S = zf_strides(nx, ny, nz);
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t >= 3 * S.nv) return;
-    const int k = (int)(t / S.nv);
-    const int64_t r = t - k * S.nv;
-    const int64_t col = r / nz;
-    const int cz = (int)(r - col * nz);
-    const int cy = (int)(col / nx), cx = (int)(col - (int64_t)cy * nx);
-    out[t] = ((k + cx + cy + cz) & 1) ? -1.0f : 1.0f;
+// stats = [sum, count] of the positive voxels -> [sum, count, count / sum] (1 if none):
+// the scale that brings the mean over the support to one.
+__global__ void support_scale(double* stats) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        stats[2] = (stats[1] > 0.0 && stats[0] > 0.0) ? stats[1] / stats[0] : 1.0;
 }
 
 // ---------------------------------------------------------------- small helpers
+// inv = 1 / s where s > 0, else 0 (the EM update's 1 / (A_i^T 1), zero off the support).
+__global__ void reciprocal_on_support(const float* __restrict__ s, int64_t n,
+                                      float* __restrict__ inv) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t < n) inv[t] = s[t] > 0.0f ? 1.0f / s[t] : 0.0f;
+}
+
 __global__ void fill_f64(double* __restrict__ a, int64_t n, double v) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (t < n) a[t] = v;

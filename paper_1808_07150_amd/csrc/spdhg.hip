@@ -152,47 +152,23 @@ size_t table_bytes(const HostTables& T) {
            align256(T.plane_seg.size() * sizeof(int32_t));
 }
 
-// Copy the tables to `dev` (table_bytes long) and point G at them.  Blocking copy.
-int upload_tables(HostTables& T, char* dev) {
+// Copy the tables to `dev` (table_bytes long, device memory) on `st` and point G at them.
+// The host vectors are pageable memory: each copy returns once HIP has staged the source,
+// so they may be released after the call; the device copies are ordered on `st` before
+// every kernel enqueued after them.
+int upload_tables(HostTables& T, char* dev, hipStream_t st) {
     char* p = dev;
-    HIP_TRY(hipMemcpy(p, T.ang.data(), T.ang.size() * sizeof(AngleDev), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(p, T.ang.data(), T.ang.size() * sizeof(AngleDev),
+                           hipMemcpyHostToDevice, st));
     T.G.ang = (const AngleDev*)p;
     p += align256(T.ang.size() * sizeof(AngleDev));
-    HIP_TRY(hipMemcpy(p, T.sa.data(), T.sa.size() * sizeof(SegAngleDev), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(p, T.sa.data(), T.sa.size() * sizeof(SegAngleDev),
+                           hipMemcpyHostToDevice, st));
     T.G.sa = (const SegAngleDev*)p;
     p += align256(T.sa.size() * sizeof(SegAngleDev));
-    HIP_TRY(hipMemcpy(p, T.plane_seg.data(), T.plane_seg.size() * sizeof(int32_t),
-                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(p, T.plane_seg.data(), T.plane_seg.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
     T.G.plane_seg = (const int32_t*)p;
-    return SPDHG_OK;
-}
-
-// Geometry tables for the stand-alone projector calls, cached per (device, geometry).
-std::mutex g_cache_mu;
-std::map<std::string, GeomDev> g_cache;
-
-int cached_geom(const spdhg_geom* g, GeomDev& out) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    std::string key((const char*)g, sizeof(spdhg_geom));
-    key += std::to_string(dev);
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto it = g_cache.find(key);
-    if (it != g_cache.end()) {
-        out = it->second;
-        return SPDHG_OK;
-    }
-    HostTables T;
-    build_tables(g, T);
-    void* d = nullptr;
-    HIP_TRY(hipMalloc(&d, table_bytes(T)));
-    int rc = upload_tables(T, (char*)d);
-    if (rc) {
-        (void)hipFree(d);
-        return rc;
-    }
-    g_cache[key] = T.G;
-    out = T.G;
     return SPDHG_OK;
 }
 
@@ -490,6 +466,8 @@ struct spdhg_ctx {
     int64_t w_pending = 0;
     double tw = 0.0;
     int fwd_split = 0;  // wavefronts per ray bundle of the subset projection (0: automatic)
+    float* em_inv = nullptr;  // SPDHG_FLAG_EM: 1 / (A_i^T 1) per subset (m images, z-fastest)
+    int64_t em_k = 0;         // EM-type sub-iterations done (subset em_k mod m is next)
     double* part = nullptr;
     double* scal = nullptr;  // 8 doubles of device scalars
     int64_t part_n = 0;
@@ -552,8 +530,8 @@ struct spdhg_ctx {
 namespace {
 
 struct Layout {
-    size_t tables, bp, rp, mp, y, sigma, dscr, xa, xb, z, T, scr, yn, xi, w, zw, q2, part, scal,
-        total;
+    size_t tables, bp, rp, mp, y, sigma, dscr, xa, xb, z, T, scr, yn, xi, w, zw, q2, em, part,
+        scal, total;
     int64_t part_n;
 };
 
@@ -590,6 +568,7 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
     L.w = take(tgv ? 6 * nv * 4 : 0);
     L.zw = take(tgv ? 3 * nv * 4 : 0);
     L.q2 = take(tgv ? 12 * nv * 4 : 0);
+    L.em = take((p->flags & SPDHG_FLAG_EM) ? (size_t)m * nv * 4 : 0);
     const int64_t fwd_blocks = (int64_t)g->n_ang * g->n_rad;
     L.part_n = std::max<int64_t>({(nb + BLOCK - 1) / BLOCK, (3 * nv + BLOCK - 1) / BLOCK,
                                   fwd_blocks, 1}) * 2;
@@ -607,8 +586,15 @@ int check_params(const spdhg_geom* g, const spdhg_params* p) {
         return fail(SPDHG_E_NOTIMPL, "prior not implemented");
     if (p->prior == SPDHG_PRIOR_TGV && !(p->alpha1 >= 0))
         return fail(SPDHG_E_ARG, "TGV weight alpha1 must be >= 0");
-    if (p->sampling != SPDHG_SAMPLING_UNIFORM && p->sampling != SPDHG_SAMPLING_BALANCED)
+    if (p->sampling != SPDHG_SAMPLING_UNIFORM && p->sampling != SPDHG_SAMPLING_BALANCED &&
+        p->sampling != SPDHG_SAMPLING_CUSTOM)
         return fail(SPDHG_E_ARG, "unknown sampling");
+    if (p->sampling == SPDHG_SAMPLING_CUSTOM && p->prior != SPDHG_PRIOR_NONE) {
+        if (!(p->p_prior > 0.0) || !(p->p_prior < 1.0))
+            return fail(SPDHG_E_ARG, "custom sampling needs 0 < p_prior < 1");
+        if (p->prior == SPDHG_PRIOR_TGV && (!(p->p_tgv_n >= 0.0) || !(p->p_tgv_n < p->p_prior)))
+            return fail(SPDHG_E_ARG, "custom sampling needs 0 <= p_tgv_n < p_prior");
+    }
     if (!(p->gamma > 0) || !(p->rho > 0) || !(p->rho < 1))
         return fail(SPDHG_E_ARG, "need gamma > 0 and 0 < rho < 1");
     if (p->prior != SPDHG_PRIOR_NONE && !(p->alpha >= 0))
@@ -616,6 +602,7 @@ int check_params(const spdhg_geom* g, const spdhg_params* p) {
     if (p->prior == SPDHG_PRIOR_DTV && (!(p->eta > 0) || !(p->gamma_d >= 0) || !(p->gamma_d <= 1)))
         return fail(SPDHG_E_ARG, "dTV needs eta > 0 and gamma_d in [0, 1]");
     if (!p->precond && p->power_iters < 1) return fail(SPDHG_E_ARG, "power_iters must be >= 1");
+    if (p->flags & ~(SPDHG_FLAG_EM | SPDHG_FLAG_TGV_SPLIT_T)) return fail(SPDHG_E_ARG, "unknown flags");
     return SPDHG_OK;
 }
 
@@ -691,35 +678,6 @@ int power_norm_dgrad(spdhg_ctx* c, double* out, hipStream_t st) {
     return SPDHG_OK;
 }
 
-// ||E|| of the TGV symmetrised gradient: 200 power iterations from a checkerboard over
-// the three components (constants are in the null space).  Uses w[0], w[1] and q2[0]
-// as scratch (before the TGV state is initialised).
-int power_norm_symgrad(spdhg_ctx* c, double* out, hipStream_t st) {
-    const int64_t nv = c->nv, n3 = 3 * nv;
-    const spdhg_geom& g = c->geom;
-    float* v = c->w[0];
-    float* w = c->w[1];
-    float* pp = c->q2[0];
-    int rc;
-    checkerboard3<<<nblocks(n3), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, v);
-    sumsq<<<nblocks(n3), BLOCK, 0, st>>>(v, n3, c->part);
-    if ((rc = reduce_to(c->part, nblocks(n3), c->scal, 0, 1.0, st))) return rc;
-    scale_by_rnorm<<<nblocks(n3), BLOCK, 0, st>>>(v, v, n3, c->scal);
-    for (int it = 0; it < 200; ++it) {
-        sym_grad_apply<<<nblocks(nv), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, v, pp);
-        sym_grad_adj<<<nblocks(nv), BLOCK, 0, st>>>(g.nx, g.ny, g.nz, pp, w);
-        sumsq<<<nblocks(n3), BLOCK, 0, st>>>(w, n3, c->part);
-        if ((rc = reduce_to(c->part, nblocks(n3), c->scal, 0, 1.0, st))) return rc;
-        scale_by_rnorm<<<nblocks(n3), BLOCK, 0, st>>>(w, v, n3, c->scal);
-    }
-    LAUNCH_CHECK();
-    double h = 0.0;
-    HIP_TRY(hipMemcpyAsync(&h, c->scal, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    *out = std::sqrt(std::sqrt(h));
-    return SPDHG_OK;
-}
-
 // TGV: apply the line-3 updates of w owed by the data iterations since the last use.
 int settle_w(spdhg_ctx* c, hipStream_t st) {
     if (!c->zw || c->w_pending == 0) return SPDHG_OK;
@@ -773,6 +731,118 @@ int prof_end(spdhg_ctx* c, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------- stand-alone operators
+// Workspace of spdhg_project / spdhg_backproject / spdhg_nnz /
+// spdhg_normalised_backprojection (caller memory, 256-byte aligned): the geometry tables,
+// two z-fastest images, the dual_row staging of up to OP_CHUNK angles, and FP64 partials
+// for a reduction over every bin.
+constexpr int OP_CHUNK = 16;
+
+struct OpLayout {
+    size_t tables, img, img2, rows, part, total;
+    size_t project_total;  // what spdhg_project uses: the tables and the first image
+};
+
+OpLayout op_layout(const spdhg_geom* g, const HostTables& T) {
+    OpLayout L{};
+    const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
+    const int64_t np = n_planes(g);
+    const int64_t nb = (int64_t)g->n_ang * np * g->n_rad;
+    const int64_t chunk = std::min(g->n_ang, OP_CHUNK);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.tables = take(table_bytes(T));
+    L.img = take(nv * 4);
+    L.project_total = off;
+    L.img2 = take(nv * 4);
+    L.rows = take(chunk * g->n_rad * np * 4);
+    L.part = take((std::max<int64_t>(nblocks(nb), 2 * nblocks(nv)) + 1) * 8);
+    L.total = off;
+    return L;
+}
+
+struct OpWork {
+    HostTables tab;
+    float *img = nullptr, *img2 = nullptr, *rows = nullptr;
+    double* part = nullptr;
+    int pad = 0;
+    BwdPlan plan;
+};
+
+// Validate the caller's workspace, carve it and upload the geometry tables on `st`
+// (project_only: the workspace need only hold what spdhg_project uses).
+int op_begin(const spdhg_geom* g, void* ws, size_t ws_bytes, hipStream_t st, OpWork& W,
+             bool project_only = false) {
+    if (!ws) return fail(SPDHG_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws) & 255) return fail(SPDHG_E_WORKSPACE, "workspace must be 256-byte aligned");
+    build_tables(g, W.tab);
+    const OpLayout L = op_layout(g, W.tab);
+    const size_t need = project_only ? L.project_total : L.total;
+    if (ws_bytes < need)
+        return fail(SPDHG_E_WORKSPACE, "operator workspace too small: need " + std::to_string(need));
+    char* w = (char*)ws;
+    int rc = upload_tables(W.tab, w + L.tables, st);
+    if (rc) return rc;
+    W.img = (float*)(w + L.img);
+    W.img2 = (float*)(w + L.img2);
+    W.rows = (float*)(w + L.rows);
+    W.part = (double*)(w + L.part);
+    W.pad = axial_pad(W.tab);
+    W.plan = bwd_plan(W.tab);
+    return SPDHG_OK;
+}
+
+// y_out = A x for the angles a0 + i * step (i < cnt), caller layouts; W.img holds the
+// z-fastest copy of x.
+int project_zf_scratch(const spdhg_geom* g, const OpWork& W, const float* mult, const float* x,
+                       float* y_out, int a0, int step, int cnt, hipStream_t st) {
+    img_to_zf<<<img_grid(g->nx, g->ny, g->nz), TT * 8, 0, st>>>(g->nx, g->ny, g->nz, x, W.img);
+    LAUNCH_CHECK();
+    FwdArgs F{};
+    F.G = W.tab.G;
+    F.pad = W.pad;
+    F.gsize = g->nz + 2 * W.pad;
+    F.x = W.img;
+    F.mult = mult;
+    F.out = y_out;
+    return launch_fwd<F_PLAIN_QK>(F, a0, step, cnt, st);
+}
+
+// acc = G^T (mult y) for the angles a0 + i * step (i < cnt) with y packed in the caller's
+// subset layout [i][plane][radial] (mult: full caller sinogram, or NULL); acc is a
+// z-fastest image, cleared first.  Angles go through W.rows OP_CHUNK at a time.
+int backproject_acc(const spdhg_geom* g, const OpWork& W, const float* y, const float* mult,
+                    int a0, int step, int cnt, float* acc, hipStream_t st) {
+    const GeomDev& G = W.tab.G;
+    const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
+    fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(acc, nv, 0.0f);
+    LAUNCH_CHECK();
+    const int chunk = std::min(cnt, OP_CHUNK);
+    for (int c0 = 0; c0 < cnt; c0 += chunk) {
+        const int cc = std::min(chunk, cnt - c0);
+        const int cang0 = a0 + c0 * step;
+        const int64_t nsub = (int64_t)cc * G.n_planes * G.n_rad;
+        to_rows<<<nblocks(nsub), BLOCK, 0, st>>>(G, y + (int64_t)c0 * G.n_planes * G.n_rad, 1,
+                                                   mult, cang0, step, cc, W.rows);
+        LAUNCH_CHECK();
+        BwdArgs B{};
+        B.G = G;
+        B.d = W.rows;
+        B.out = acc;
+        int rc = launch_bwd<B_ACCUM>(B, cang0, step, cc, st, W.plan, W.tab.ang.data(), nullptr);
+        if (rc) return rc;
+    }
+    return SPDHG_OK;
+}
+
+}  // namespace
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -785,115 +855,92 @@ int64_t spdhg_subset_bins(const spdhg_geom* geom, int32_t n_subsets, int32_t sub
     return (int64_t)cnt * n_planes(geom) * geom->n_rad;
 }
 
+int spdhg_op_workspace_bytes(const spdhg_geom* geom, size_t* bytes) {
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    if (!bytes) return fail(SPDHG_E_ARG, "bytes is NULL");
+    HostTables T;
+    build_tables(geom, T);
+    *bytes = op_layout(geom, T).total;
+    return SPDHG_OK;
+}
+
 int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, const float* mult,
-                  const float* x, float* y_out, void* stream) {
+                  const float* x, float* y_out, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_geom(geom);
     if (rc || (rc = check_kernel_limits(geom))) return rc;
     if (!x || !y_out) return fail(SPDHG_E_ARG, "NULL image or output");
     int a0, step, cnt;
     rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
     if (rc) return rc;
-    GeomDev G;
-    rc = cached_geom(geom, G);
-    if (rc) return rc;
-    HostTables T;
-    build_tables(geom, T);
     hipStream_t st = (hipStream_t)stream;
-    const int64_t nv = (int64_t)geom->nx * geom->ny * geom->nz;
-    float* xz = nullptr;  // stream-ordered scratch: the image in the z-fastest layout
-    HIP_TRY(hipMallocAsync((void**)&xz, nv * 4, st));
-    img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(geom->nx, geom->ny,
-                                                                         geom->nz, x, xz);
-    FwdArgs F{};
-    F.G = G;
-    F.pad = axial_pad(T);
-    F.gsize = geom->nz + 2 * F.pad;
-    F.x = xz;
-    F.mult = mult;
-    F.out = y_out;
-    rc = launch_fwd<F_PLAIN_QK>(F, a0, step, cnt, st);
-    hipError_t e = hipFreeAsync(xz, st);
-    if (rc) return rc;
-    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("hipFreeAsync: ") + hipGetErrorString(e));
-    return SPDHG_OK;
+    OpWork W;
+    if ((rc = op_begin(geom, ws, ws_bytes, st, W, true))) return rc;
+    return project_zf_scratch(geom, W, mult, x, y_out, a0, step, cnt, st);
 }
 
 int spdhg_backproject(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
-                      const float* mult, const float* y, float* x_out, void* stream) {
+                      const float* mult, const float* y, float* x_out, void* ws, size_t ws_bytes,
+                      void* stream) {
     int rc = check_geom(geom);
     if (rc || (rc = check_kernel_limits(geom))) return rc;
     if (!y || !x_out) return fail(SPDHG_E_ARG, "NULL sinogram or output");
     int a0, step, cnt;
     rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
     if (rc) return rc;
-    GeomDev G;
-    rc = cached_geom(geom, G);
-    if (rc) return rc;
-    const int64_t nv = (int64_t)geom->nx * geom->ny * geom->nz;
     hipStream_t st = (hipStream_t)stream;
-    HostTables T;
-    build_tables(geom, T);
-    const BwdPlan plan = bwd_plan(T);
-    // angles in chunks: each chunk's rows go to a scratch in the dual_row layout and are
-    // added to the z-fastest image; then one transpose to the caller's layout
-    const int chunk = std::min(cnt, 16);
-    const int64_t npad = (int64_t)chunk * geom->n_rad * G.n_planes;
-    float* dk = nullptr;
-    float* xz = nullptr;
-    HIP_TRY(hipMallocAsync((void**)&dk, npad * 4, st));
-    HIP_TRY(hipMallocAsync((void**)&xz, nv * 4, st));
-    hipError_t e = hipMemsetAsync(xz, 0, nv * 4, st);
-    for (int c0 = 0; c0 < cnt && e == hipSuccess && rc == SPDHG_OK; c0 += chunk) {
-        const int cc = std::min(chunk, cnt - c0);
-        const int cang0 = a0 + c0 * step;
-        const int64_t nsub = (int64_t)cc * G.n_planes * G.n_rad;
-        to_rows<<<nblocks(nsub), BLOCK, 0, st>>>(G, y + (int64_t)c0 * G.n_planes * G.n_rad, 1,
-                                                   mult, cang0, step, cc, dk);
-        e = hipGetLastError();
-        if (e != hipSuccess) break;
-        BwdArgs B{};
-        B.G = G;
-        B.d = dk;
-        B.out = xz;
-        rc = launch_bwd<B_ACCUM>(B, cang0, step, cc, st, plan, T.ang.data(), nullptr);
-    }
-    if (e == hipSuccess && rc == SPDHG_OK) {
-        img_from_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
-            geom->nx, geom->ny, geom->nz, xz, x_out);
-        e = hipGetLastError();
-    }
-    hipError_t e1 = hipFreeAsync(xz, st);
-    hipError_t e2 = hipFreeAsync(dk, st);
-    if (rc) return rc;
-    if (e == hipSuccess) e = e1 ? e1 : e2;
-    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("spdhg_backproject: ") + hipGetErrorString(e));
+    OpWork W;
+    if ((rc = op_begin(geom, ws, ws_bytes, st, W))) return rc;
+    if ((rc = backproject_acc(geom, W, y, mult, a0, step, cnt, W.img, st))) return rc;
+    img_from_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
+        geom->nx, geom->ny, geom->nz, W.img, x_out);
+    LAUNCH_CHECK();
     return SPDHG_OK;
 }
 
-int spdhg_nnz(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, double* out,
-              void* stream) {
+int spdhg_normalised_backprojection(const spdhg_geom* geom, const float* b, const float* mult,
+                                    float* out, double* stats_dev, void* ws, size_t ws_bytes,
+                                    void* stream) {
+    int rc = check_geom(geom);
+    if (rc || (rc = check_kernel_limits(geom))) return rc;
+    if (!b || !mult || !out || !stats_dev) return fail(SPDHG_E_ARG, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    OpWork W;
+    if ((rc = op_begin(geom, ws, ws_bytes, st, W))) return rc;
+    // A^T b = G^T (mult b) into img, A^T 1 = G^T mult into img2 (all angles)
+    if ((rc = backproject_acc(geom, W, b, mult, 0, 1, geom->n_ang, W.img, st))) return rc;
+    if ((rc = backproject_acc(geom, W, mult, nullptr, 0, 1, geom->n_ang, W.img2, st))) return rc;
+    const int64_t nv = (int64_t)geom->nx * geom->ny * geom->nz;
+    const int64_t nbk = nblocks(nv);
+    ratio_on_support<<<nbk, BLOCK, 0, st>>>(W.img, W.img2, nv, W.img, W.part, W.part + nbk);
+    reduce_final<<<1, BLOCK, 0, st>>>(W.part, nbk, stats_dev, 0, 1.0);
+    reduce_final<<<1, BLOCK, 0, st>>>(W.part + nbk, nbk, stats_dev, 1, 1.0);
+    support_scale<<<1, 64, 0, st>>>(stats_dev);
+    img_from_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
+        geom->nx, geom->ny, geom->nz, W.img, out);
+    LAUNCH_CHECK();
+    return SPDHG_OK;
+}
+
+int spdhg_nnz(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, double* out, void* ws,
+              size_t ws_bytes, void* stream) {
     int rc = check_geom(geom);
     if (rc) return rc;
     if (!out) return fail(SPDHG_E_ARG, "out is NULL");
     int a0, step, cnt;
     rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
     if (rc) return rc;
-    GeomDev G;
-    rc = cached_geom(geom, G);
-    if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
+    OpWork W;
+    if ((rc = op_begin(geom, ws, ws_bytes, st, W))) return rc;
+    const GeomDev& G = W.tab.G;
     const int64_t n = (int64_t)cnt * G.n_planes * G.n_rad;
     const int64_t nbk = nblocks(n);
-    double* part = nullptr;
-    HIP_TRY(hipMallocAsync((void**)&part, (nbk + 1) * sizeof(double), st));
-    fwd_count<<<nbk, BLOCK, 0, st>>>(G, a0, step, cnt, part);
-    reduce_final<<<1, BLOCK, 0, st>>>(part, nbk, part + nbk, 0, 1.0);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(out, part + nbk, sizeof(double), hipMemcpyDeviceToHost, st);
-    hipError_t e2 = hipFreeAsync(part, st);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return fail(SPDHG_E_HIP, std::string("spdhg_nnz: ") + hipGetErrorString(e));
+    fwd_count<<<nbk, BLOCK, 0, st>>>(G, a0, step, cnt, W.part);
+    reduce_final<<<1, BLOCK, 0, st>>>(W.part, nbk, W.part + nbk, 0, 1.0);
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(out, W.part + nbk, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return SPDHG_OK;
 }
 
@@ -940,7 +987,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
     }
     char* w = (char*)ws;
-    if ((rc = upload_tables(c->tab, w + L.tables))) return bail(rc);
+    if ((rc = upload_tables(c->tab, w + L.tables, st))) return bail(rc);
     c->pad = axial_pad(c->tab);
     c->gsize = geom->nz + 2 * c->pad;
     c->bplan = bwd_plan(c->tab);
@@ -975,6 +1022,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     }
     c->part = (double*)(w + L.part);
     c->part_n = L.part_n;
+    c->em_inv = (params->flags & SPDHG_FLAG_EM) ? (float*)(w + L.em) : nullptr;
     c->scal = (double*)(w + L.scal);
     c->m = params->n_subsets;
     c->n_prior = tgv ? 2 : (prior ? 1 : 0);
@@ -984,6 +1032,17 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     if (params->sampling == SPDHG_SAMPLING_BALANCED && c->n_prior > 0) {
         for (int i = 0; i < c->m; ++i) c->p[i] = 1.0 / (2.0 * c->m);
         for (int j = 0; j < c->n_prior; ++j) c->p[c->m + j] = 0.5 / c->n_prior;
+    } else if (params->sampling == SPDHG_SAMPLING_CUSTOM && c->n_prior > 0) {
+        const double q = params->p_prior;
+        for (int i = 0; i < c->m; ++i) c->p[i] = (1.0 - q) / c->m;
+        if (c->n_prior == 1) {
+            c->p[c->m] = q;
+        } else if (params->p_tgv_n == 0.0) {
+            c->p[c->m] = c->p[c->m + 1] = q / 2.0;
+        } else {
+            c->p[c->m] = q - params->p_tgv_n;
+            c->p[c->m + 1] = params->p_tgv_n;
+        }
     }
     c->cum.resize(c->n);
     double acc = 0.0;
@@ -1079,17 +1138,21 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     }
     double t_prior = INFINITY;
     if (tgv) {
-        // block n-1: ||(grad, -I)|| = sqrt(||grad||^2 + 1); block n: ||E|| (power iteration)
+        // block n-1: ||(grad, -I)|| = sqrt(||grad||^2 + 1); block n: the bound ||grad||
         const double gn = grad_norm(geom->nx, geom->ny, geom->nz);
         c->prior_norm = std::sqrt(gn * gn + 1.0);
-        double en = 0.0;
-        if ((rc = power_norm_symgrad(c, &en, st))) return bail(rc);
-        c->prior_norm2 = en;
+        // ||E|| <= ||grad|| (||E w||_F^2 <= sum_k ||grad w_k||^2): the closed-form bound keeps
+        // the step condition exact, where a truncated power iteration approaches ||E||
+        // from below
+        c->prior_norm2 = gn;
         c->prior_sigma = gam * rho / c->prior_norm;
         c->prior_sigma2 = gam * rho / c->prior_norm2;
-        t_prior = std::min(rho * c->p[c->m] / (gam * c->prior_norm),
-                           rho * c->p[c->m + 1] / (gam * c->prior_norm2));
-        c->tw = t_prior;
+        const double t1 = rho * c->p[c->m] / (gam * c->prior_norm);
+        const double t2 = rho * c->p[c->m + 1] / (gam * c->prior_norm2);
+        c->tw = std::min(t1, t2);
+        // the minimum over all blocks caps u as well, unless block n (0, E), which does not
+        // act on u, is kept to w
+        t_prior = (params->flags & SPDHG_FLAG_TGV_SPLIT_T) ? t1 : c->tw;
     } else if (prior) {
         if (params->prior == SPDHG_PRIOR_DTV) {
             img_to_zf<<<img_grid(geom->nx, geom->ny, geom->nz), TT * 8, 0, st>>>(
@@ -1106,6 +1169,22 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         t_prior = rho * c->p[c->m] / (gam * c->prior_norm);
     }
     finalize_T<<<nblocks(nv), BLOCK, 0, st>>>(c->T, nv, (float)t_prior);
+    // EM-type updates (eq. OSEM): 1 / (A_i^T 1) of every subset
+    if (c->em_inv) {
+        for (int i = 0; i < c->m; ++i) {
+            int a0, step, cnt;
+            subset_angles(geom, c->m, i, a0, step, cnt);
+            const int64_t nsub = (int64_t)cnt * np * geom->n_rad;
+            to_rows<<<nblocks(nsub), BLOCK, 0, st>>>(c->tab.G, c->mp, 0, nullptr, a0, step, cnt,
+                                                       c->dscr);
+            BwdArgs B = c->bwd_args();
+            B.d = c->dscr;
+            B.out = c->em_inv + (int64_t)i * nv;
+            if ((rc = launch_bwd<B_PLAIN>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
+                return bail(rc);
+            reciprocal_on_support<<<nblocks(nv), BLOCK, 0, st>>>(B.out, nv, B.out);
+        }
+    }
     // y = 0, z = 0, prior duals = 0
     fill_f32<<<nblocks(nb), BLOCK, 0, st>>>(c->y, nb, 0.0f);
     fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->z, nv, 0.0f);
@@ -1355,6 +1434,100 @@ int spdhg_epoch_graph(spdhg_ctx* c, int32_t n_epochs, void* stream) {
     for (hipGraphExec_t x : execs) (void)hipGraphExecDestroy(x);
     if (rc == SPDHG_OK && err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
     return rc;
+}
+
+int spdhg_pdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (n_iters < 0) return fail(SPDHG_E_ARG, "n_iters < 0");
+    if (c->m != 1) return fail(SPDHG_E_STATE, "PDHG needs a context with one data block (m = 1)");
+    if (c->zw) return fail(SPDHG_E_NOTIMPL, "PDHG is not built for TGV");
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    const spdhg_geom& g = c->geom;
+    for (int64_t it = 0; it < n_iters; ++it) {
+        // Algorithm 1: the dual step of every block from the same x ...
+        FwdArgs F = c->fwd_args();
+        F.x = c->xcur();
+        F.mult = c->mp;
+        F.b = c->bp;
+        F.r = c->rp;
+        F.sigma = c->sigma;
+        F.sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[0];
+        F.y = c->y;
+        F.d = c->dscr;
+        F.split = c->fwd_split;
+        if ((rc = launch_fwd<F_DUAL>(F, 0, 1, g.n_ang, st))) return rc;
+        BwdArgs B = c->bwd_args();
+        B.d = c->dscr;
+        if (c->n_prior == 0) {
+            // ... one block: z += dz, x = max(x - T (z + dz), 0)
+            B.inv_p = 1.0f;
+            B.z = c->z;
+            B.x = c->xcur();
+            B.T = c->T;
+            if ((rc = launch_bwd<B_ITER>(B, 0, 1, g.n_ang, st, c->bplan, c->tab.ang.data(), c->scr)))
+                return rc;
+            continue;
+        }
+        // ... with a prior block: the data change dz_data into scr (the other iterate buffer
+        // holds the two-class partial), then the prior kernel adds it to its own change
+        // before z += dz and x = max(x - T (z + dz), 0)
+        B.out = c->scr;
+        if ((rc = launch_bwd<B_PLAIN>(B, 0, 1, g.n_ang, st, c->bplan, c->tab.ang.data(), c->xother())))
+            return rc;
+        PriorArgs P = c->prior_args();
+        P.inv_p = 1.0f;
+        P.dz_add = c->scr;
+        if (prior_use_wave(g, 3)) {
+            const int ly = std::min(TV_WAVE_LY, g.ny);
+            if (P.dtv)
+                tv_wave<true><<<tv_wave_blocks(g, ly), 256, 0, st>>>(
+                    P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
+                    c->T, c->xi);
+            else
+                tv_wave<false><<<tv_wave_blocks(g, ly), 256, 0, st>>>(
+                    P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
+                    c->T, c->xi);
+        } else {
+            const PriorTile TL = prior_tile(g);
+            tv_iter<<<prior_blocks(g, TL), TL.tx * TL.ty * g.nz, 0, st>>>(
+                P, TL, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
+                c->T, c->xi);
+        }
+        LAUNCH_CHECK();
+        c->x_cur ^= 1;
+        c->yn_cur ^= 1;
+    }
+    return export_x(c, st);
+}
+
+int spdhg_em_iterate(spdhg_ctx* c, int64_t n_subiters, void* stream) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (n_subiters < 0) return fail(SPDHG_E_ARG, "n_subiters < 0");
+    if (!c->em_inv) return fail(SPDHG_E_STATE, "the context was set up without SPDHG_FLAG_EM");
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    for (int64_t it = 0; it < n_subiters; ++it) {
+        const int i = (int)(c->em_k % c->m);
+        int a0, step, cnt;
+        subset_angles(&c->geom, c->m, i, a0, step, cnt);
+        FwdArgs F = c->fwd_args();
+        F.x = c->xcur();
+        F.mult = c->mp;
+        F.b = c->bp;
+        F.r = c->rp;
+        F.d = c->dscr;
+        F.split = c->fwd_split;
+        if ((rc = launch_fwd<F_EM>(F, a0, step, cnt, st))) return rc;
+        BwdArgs B = c->bwd_args();
+        B.d = c->dscr;
+        B.x = c->xcur();
+        B.T = c->em_inv + (int64_t)i * c->nv;
+        if ((rc = launch_bwd<B_EM>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
+            return rc;
+        c->em_k += 1;
+    }
+    return export_x(c, st);
 }
 
 int spdhg_info(const spdhg_ctx* c, int64_t* ipe, int64_t* done) {

@@ -6,7 +6,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import torch
 
@@ -19,11 +19,12 @@ ERRORS = {-1: "SPDHG_E_ARG", -2: "SPDHG_E_SHAPE", -3: "SPDHG_E_DOMAIN", -4: "SPD
           -5: "SPDHG_E_WORKSPACE", -6: "SPDHG_E_STATE", -7: "SPDHG_E_NOTIMPL"}
 
 PRIOR = {"none": 0, "tv": 1, "atv": 2, "dtv": 3, "tgv": 4}
-SAMPLING = {"uniform": 0, "balanced": 1}
+SAMPLING = {"uniform": 0, "balanced": 1, "custom": 2}
 
-EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_project", "spdhg_backproject",
-            "spdhg_nnz",
-            "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch", "spdhg_epoch_graph", "spdhg_batch_epoch",
+EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_op_workspace_bytes",
+            "spdhg_project", "spdhg_backproject", "spdhg_normalised_backprojection", "spdhg_nnz",
+            "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch",
+            "spdhg_epoch_graph", "spdhg_batch_epoch", "spdhg_pdhg_iterate", "spdhg_em_iterate",
             "spdhg_set_tuning", "spdhg_autotune", "spdhg_info",
             "spdhg_objective", "spdhg_gap", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
             "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
@@ -52,8 +53,9 @@ class CParams(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("eta", ctypes.c_double),
                 ("gamma_d", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("rho", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("power_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("alpha1", ctypes.c_double)]
+                ("power_iters", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("alpha1", ctypes.c_double), ("p_prior", ctypes.c_double),
+                ("p_tgv_n", ctypes.c_double)]
 
 
 _lib = None
@@ -74,17 +76,22 @@ def load_library() -> ctypes.CDLL:
     lib.spdhg_last_error.argtypes = []
     lib.spdhg_subset_bins.restype = i64
     lib.spdhg_subset_bins.argtypes = [G, i32, i32]
+    lib.spdhg_op_workspace_bytes.argtypes = [G, ctypes.POINTER(ctypes.c_size_t)]
     for name in ("spdhg_project", "spdhg_backproject"):
         f = getattr(lib, name)
         f.restype = ctypes.c_int
-        f.argtypes = [G, i32, i32, vp, vp, vp, vp]
-    lib.spdhg_nnz.argtypes = [G, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
+        f.argtypes = [G, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.spdhg_normalised_backprojection.argtypes = [G, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.spdhg_nnz.argtypes = [G, i32, i32, ctypes.POINTER(ctypes.c_double), vp,
+                              ctypes.c_size_t, vp]
     lib.spdhg_workspace_bytes.argtypes = [G, Pm, ctypes.POINTER(ctypes.c_size_t)]
     lib.spdhg_init.argtypes = [ctypes.POINTER(vp), G, Pm, vp, vp, vp, vp, vp, vp,
                                ctypes.c_size_t, vp]
     lib.spdhg_iterate.argtypes = [vp, i64, vp]
     lib.spdhg_epoch.argtypes = [vp, i32, vp]
     lib.spdhg_epoch_graph.argtypes = [vp, i32, vp]
+    lib.spdhg_em_iterate.argtypes = [vp, i64, vp]
+    lib.spdhg_pdhg_iterate.argtypes = [vp, i64, vp]
     lib.spdhg_batch_epoch.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, vp]
     lib.spdhg_set_tuning.argtypes = [vp, i32]
     lib.spdhg_autotune.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
@@ -129,7 +136,8 @@ def cgeom(g) -> CGeom:
 def cparams(n_subsets: int, prior: str = "tv", sampling: str = "uniform", precond: bool = True,
             alpha: float = 0.1, eta: float = 1e-2, gamma_d: float = 1.0, gamma: float = 1.0,
             rho: float = 0.99, seed: int = 0, power_iters: int = 100,
-            alpha1: float = 0.0) -> CParams:
+            alpha1: float = 0.0, em: bool = False, p_prior: float = 0.5,
+            p_tgv_n: float = 0.0, split_T: bool = False) -> CParams:
     p = CParams()
     p.n_subsets = n_subsets
     p.prior = PRIOR[prior]
@@ -139,6 +147,9 @@ def cparams(n_subsets: int, prior: str = "tv", sampling: str = "uniform", precon
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.power_iters = power_iters
     p.alpha1 = alpha1
+    p.flags = (1 if em else 0) | (2 if split_T else 0)  # SPDHG_FLAG_EM, SPDHG_FLAG_TGV_SPLIT_T
+    p.p_prior = p_prior
+    p.p_tgv_n = p_tgv_n
     return p
 
 
@@ -161,31 +172,78 @@ def subset_bins(g, n_subsets: int, subset: int) -> int:
     return int(load_library().spdhg_subset_bins(ctypes.byref(cgeom(g)), n_subsets, subset))
 
 
+def op_workspace_bytes(g) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().spdhg_op_workspace_bytes(ctypes.byref(cgeom(g)), ctypes.byref(n)))
+    return int(n.value)
+
+
+def aligned_workspace(nbytes: int, device) -> Tuple[torch.Tensor, int, int]:
+    """A torch uint8 tensor holding a 256-byte aligned region of nbytes: (tensor, address,
+    bytes).  Torch owns the memory; keep the tensor alive while the library uses it."""
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    base = t.data_ptr()
+    return t, (base + 255) & ~255, int(nbytes)
+
+
+def op_workspace(g, device) -> Tuple[torch.Tensor, int, int]:
+    """Workspace of the stand-alone operator calls for geometry g."""
+    return aligned_workspace(op_workspace_bytes(g), device)
+
+
+def _ws_args(g, device, ws):
+    if ws is None:
+        ws = op_workspace(g, device)
+    return ws, ctypes.c_void_p(ws[1]), ctypes.c_size_t(ws[2])
+
+
 def spdhg_project(g, n_subsets: int, subset: int, mult: Optional[torch.Tensor],
-                  x: torch.Tensor, y_out: torch.Tensor, stream=None) -> torch.Tensor:
+                  x: torch.Tensor, y_out: torch.Tensor, stream=None, ws=None) -> torch.Tensor:
+    """y_out = A_i x (spdhg_project).  `ws` is an op_workspace(g, device) triple, or None
+    for a fresh one."""
     n = subset_bins(g, n_subsets, subset)
     if y_out.numel() != n or x.numel() != g.nx * g.ny * g.nz:
         raise ValueError("size mismatch")
+    keep, wp, wn = _ws_args(g, x.device, ws)
     _check(load_library().spdhg_project(ctypes.byref(cgeom(g)), n_subsets, subset, _ptr(mult),
-                                        _ptr(x), _ptr(y_out), _stream(stream)))
+                                        _ptr(x), _ptr(y_out), wp, wn, _stream(stream)))
     return y_out
 
 
 def spdhg_backproject(g, n_subsets: int, subset: int, mult: Optional[torch.Tensor],
-                      y: torch.Tensor, x_out: torch.Tensor, stream=None) -> torch.Tensor:
+                      y: torch.Tensor, x_out: torch.Tensor, stream=None, ws=None) -> torch.Tensor:
+    """x_out = A_i^T y (spdhg_backproject)."""
     n = subset_bins(g, n_subsets, subset)
     if y.numel() != n or x_out.numel() != g.nx * g.ny * g.nz:
         raise ValueError("size mismatch")
+    keep, wp, wn = _ws_args(g, y.device, ws)
     _check(load_library().spdhg_backproject(ctypes.byref(cgeom(g)), n_subsets, subset,
-                                            _ptr(mult), _ptr(y), _ptr(x_out), _stream(stream)))
+                                            _ptr(mult), _ptr(y), _ptr(x_out), wp, wn,
+                                            _stream(stream)))
     return x_out
 
 
-def spdhg_nnz(g, n_subsets: int, subset: int, stream=None) -> int:
+def normalised_backprojection(g, b: torch.Tensor, mult: torch.Tensor, out: torch.Tensor,
+                              stats: torch.Tensor, stream=None, ws=None) -> torch.Tensor:
+    """out = (A^T b) / (A^T 1) (0 where A^T 1 = 0); stats (3 float64 on the device) =
+    [sum, count, count / sum] over the positive voxels."""
+    if b.numel() != g.n_bins or mult.numel() != g.n_bins or out.numel() != g.n_vox:
+        raise ValueError("size mismatch")
+    if stats.numel() < 3:
+        raise ValueError("stats needs 3 doubles")
+    keep, wp, wn = _ws_args(g, b.device, ws)
+    _check(load_library().spdhg_normalised_backprojection(
+        ctypes.byref(cgeom(g)), _ptr(b), _ptr(mult), _ptr(out), _ptr(stats, torch.float64), wp,
+        wn, _stream(stream)))
+    return out
+
+
+def spdhg_nnz(g, n_subsets: int, subset: int, stream=None, ws=None, device=None) -> int:
     """Nonzero count of A_i (taps inside the image with nonzero weight)."""
     out = ctypes.c_double()
+    keep, wp, wn = _ws_args(g, device or torch.device("cuda", torch.cuda.current_device()), ws)
     _check(load_library().spdhg_nnz(ctypes.byref(cgeom(g)), n_subsets, subset,
-                                    ctypes.byref(out), _stream(stream)))
+                                    ctypes.byref(out), wp, wn, _stream(stream)))
     return int(out.value)
 
 
@@ -205,9 +263,7 @@ class Reconstruction:
         nbytes = ctypes.c_size_t(0)
         _check(lib.spdhg_workspace_bytes(ctypes.byref(gs), ctypes.byref(params),
                                          ctypes.byref(nbytes)))
-        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=x.device)
-        base = self.ws.data_ptr()
-        aligned = (base + 255) & ~255
+        self.ws, aligned, _ = aligned_workspace(nbytes.value, x.device)
         ctx = ctypes.c_void_p()
         _check(lib.spdhg_init(ctypes.byref(ctx), ctypes.byref(gs), ctypes.byref(params),
                               _ptr(b), _ptr(r), _ptr(mult), _ptr(side), _ptr(x),
@@ -216,6 +272,15 @@ class Reconstruction:
 
     def iterate(self, n_iters: int, stream=None):
         _check(load_library().spdhg_iterate(self.ctx, int(n_iters), _stream(stream)))
+
+    def pdhg_iterate(self, n_iters: int, stream=None):
+        """Deterministic PDHG iterations (Algorithm 1); the context must have one data block."""
+        _check(load_library().spdhg_pdhg_iterate(self.ctx, int(n_iters), _stream(stream)))
+
+    def em_iterate(self, n_subiters: int, stream=None):
+        """EM-type sub-iterations (eq. OSEM on the context's subsets; MLEM with one subset)
+        on the image; needs cparams(..., em=True)."""
+        _check(load_library().spdhg_em_iterate(self.ctx, int(n_subiters), _stream(stream)))
 
     def epoch(self, n_epochs: int = 1, stream=None):
         _check(load_library().spdhg_epoch(self.ctx, int(n_epochs), _stream(stream)))

@@ -331,14 +331,15 @@ def from_net(vol: torch.Tensor, g) -> torch.Tensor:
     return vol[:g.ny, :g.nx, :g.nz].permute(2, 0, 1).contiguous()
 
 
-def normalised_backprojection(g, d) -> torch.Tensor:
-    """(A^T b) / (A^T 1) on the voxels some ray reaches (0 elsewhere): the network input."""
-    from .spdhg import spdhg_backproject
-    atb = torch.empty(g.image_shape, dtype=torch.float32, device=d["b"].device)
-    at1 = torch.empty_like(atb)
-    spdhg_backproject(g, 1, -1, d["mult"], d["b"], atb)
-    spdhg_backproject(g, 1, -1, d["mult"], torch.ones_like(d["b"]), at1)
-    return torch.where(at1 > 0, atb / at1.clamp(min=1e-30), torch.zeros_like(atb))
+def normalised_backprojection(g, d, stats: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """(A^T b) / (A^T 1) on the voxels some ray reaches (0 elsewhere): the network input,
+    computed by the library (spdhg_normalised_backprojection); `stats` (3 float64 on the
+    device, optional) receives [sum, count, count / sum] over the positive voxels."""
+    from .spdhg import normalised_backprojection as nbp
+    out = torch.empty(g.image_shape, dtype=torch.float32, device=d["b"].device)
+    if stats is None:
+        stats = torch.empty(3, dtype=torch.float64, device=d["b"].device)
+    return nbp(g, d["b"], d["mult"], out, stats)
 
 
 def input_scale(nbp: torch.Tensor) -> float:

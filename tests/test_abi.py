@@ -79,10 +79,46 @@ def test_workspace_bytes(lib):
 def test_null_arguments_rejected(lib):
     import paper_1808_07150_amd as P
     g = P.cgeom(synth.slice64_2d())
-    assert lib.spdhg_project(ctypes.byref(g), 10, 0, None, None, None, None) == -1
-    assert lib.spdhg_backproject(ctypes.byref(g), 10, 0, None, None, None, None) == -1
+    assert lib.spdhg_project(ctypes.byref(g), 10, 0, None, None, None, None, 0, None) == -1
+    assert lib.spdhg_backproject(ctypes.byref(g), 10, 0, None, None, None, None, 0,
+                                 None) == -1
+    assert lib.spdhg_normalised_backprojection(ctypes.byref(g), None, None, None, None, None,
+                                               0, None) == -1
     ctx = ctypes.c_void_p()
     assert lib.spdhg_init(ctypes.byref(ctx), ctypes.byref(g),
                           ctypes.byref(P.cparams(10, "tv")), None, None, None, None, None,
                           None, 0, None) == -1
     assert lib.spdhg_iterate(None, 1, None) == -1
+
+
+def test_operator_workspace(lib):
+    """The stand-alone operator calls take their scratch from the caller: the size query,
+    and the NULL / misaligned / too-small workspace errors (raised before any HIP call)."""
+    import paper_1808_07150_amd as P
+    g = synth.mmr()
+    n = P.op_workspace_bytes(g)
+    nv, np_, nb = 344 * 344 * 127, 837, 252 * 837 * 344
+    # two images, 16 angles of rows and the partials, plus the tables
+    assert 4 * (2 * nv + 16 * 344 * np_) + 8 * (nb // 256) <= n
+    assert n < 4 * (2 * nv + 16 * 344 * np_) + 8 * (nb // 256) + (4 << 20)
+    cg = P.cgeom(synth.slice64_2d())
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: the checks fail first
+    for ws, nbytes in ((None, 1 << 20), (ctypes.c_void_p(0x10004), 1 << 30), (fake, 16)):
+        rc = lib.spdhg_project(ctypes.byref(cg), 10, 0, None, fake, fake, ws, nbytes, None)
+        assert rc == -5, lib.spdhg_last_error()
+        rc = lib.spdhg_backproject(ctypes.byref(cg), 10, 0, None, fake, fake, ws, nbytes, None)
+        assert rc == -5, lib.spdhg_last_error()
+        d = ctypes.c_double()
+        rc = lib.spdhg_nnz(ctypes.byref(cg), 10, 0, ctypes.byref(d), ws, nbytes, None)
+        assert rc == -5, lib.spdhg_last_error()
+
+
+def test_library_allocates_no_device_memory():
+    """Device memory belongs to the caller: no allocation or free call in the library's
+    sources (the workspaces come in as arguments)."""
+    csrc = os.path.join(ROOT, "paper_1808_07150_amd", "csrc")
+    banned = re.compile(r"\bhip(Malloc|MallocAsync|MallocManaged|ExtMallocWithFlags|Free|"
+                        r"FreeAsync|HostMalloc|HostFree|MallocPitch|Malloc3D)\s*\(")
+    for name in sorted(os.listdir(csrc)):
+        text = open(os.path.join(csrc, name)).read()
+        assert not banned.search(text), name

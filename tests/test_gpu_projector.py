@@ -149,6 +149,35 @@ def test_mmr_forward_sampled_rays(P, mmr_case):
     assert np.linalg.norm(val - ref) <= 1e-5 * np.linalg.norm(ref)
 
 
+def test_mmr_forward_every_radial_bin(P):
+    """Full mMR geometry, 21 subsets, a random image over the whole volume (so that rays at
+    the edge of the field of view carry values): rays at every radial bin 0 .. 343 (each
+    bin once, random angle of the subset and plane) against the oracle, including the
+    first and last bins and the planes of the outermost segments."""
+    g = synth.mmr()
+    print("[fwd] mMR m=21 subset 0, every radial bin", flush=True)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0, 1, g.image_shape).astype(np.float32)
+    m, i = 21, 0
+    ang = g.subset_angles(m, i)
+    out = torch.empty(len(ang) * g.n_planes * g.n_rad, dtype=torch.float32, device="cuda:0")
+    P.spdhg_project(g, m, i, None, dev(x), out)
+    got = out.cpu().numpy().reshape(len(ang), g.n_planes, g.n_rad)
+    xd = x.astype(np.float64)
+    last_planes = [g.n_planes - 1, g.n_planes - 1 - g.seg_planes[-1]]
+    ref, val = [], []
+    for k in range(g.n_rad):
+        ia = int(rng.integers(len(ang)))
+        q = last_planes[k % 2] if k % 7 == 0 else int(rng.integers(g.n_planes))
+        ref.append(OP.ray(g, xd, ang[ia], q, k))
+        val.append(got[ia, q, k])
+    ref, val = np.array(ref), np.array(val)
+    assert ref[0] > 0 and ref[-1] > 0  # the corner rays cross the image
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(val - ref)) <= 1e-5 * scale
+    assert np.linalg.norm(val - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
 def test_mmr_backward_one_subset(P, mmr_case):
     g, _ = mmr_case
     print("[bwd] mMR, m=252 subset 63 (45 degrees) and subset 100", flush=True)

@@ -169,6 +169,8 @@ def test_small3d_tgv_parity(P, small3d, sampling, precond):
     X = prob.reported(st)
     assert rel(x.cpu().numpy(), X[0]) <= 1e-3
     w = rec.buffer("w").cpu().numpy()
+    print(f"[spdhg] TGV rel err u {rel(x.cpu().numpy(), X[0]):.3e} w {rel(w, X[1:4]):.3e}",
+          flush=True)
     assert rel(w, X[1:4]) <= 2e-3
     psi_o = prob.objective(X)
     assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
@@ -232,7 +234,9 @@ def test_deep3d_prior_parity(P, deep3d, prior):
     X = prob.reported(st)
     assert rel(x.cpu().numpy(), X[0]) <= 1e-3
     if prior == "tgv":
-        assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
+        ew = rel(rec.buffer("w").cpu().numpy(), X[1:4])
+        print(f"[spdhg] TGV rel err u {rel(x.cpu().numpy(), X[0]):.3e} w {ew:.3e}", flush=True)
+        assert ew <= 2e-3
     psi_o = prob.objective(X)
     assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
 
@@ -245,7 +249,9 @@ def test_maxnz_parity(P, maxnz3d, prior):
     X = prob.reported(st)
     assert rel(x.cpu().numpy(), X[0]) <= 1e-3
     if prior == "tgv":
-        assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
+        ew = rel(rec.buffer("w").cpu().numpy(), X[1:4])
+        print(f"[spdhg] TGV rel err u {rel(x.cpu().numpy(), X[0]):.3e} w {ew:.3e}", flush=True)
+        assert ew <= 2e-3
     psi_o = prob.objective(X)
     assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
 
@@ -258,7 +264,9 @@ def test_span11_parity(P, span11_3d, prior):
     X = prob.reported(st)
     assert rel(x.cpu().numpy(), X[0]) <= 1e-3
     if prior == "tgv":
-        assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
+        ew = rel(rec.buffer("w").cpu().numpy(), X[1:4])
+        print(f"[spdhg] TGV rel err u {rel(x.cpu().numpy(), X[0]):.3e} w {ew:.3e}", flush=True)
+        assert ew <= 2e-3
     psi_o = prob.objective(X)
     assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
 
@@ -431,3 +439,36 @@ def test_forward_splits_parity(P, tall3d, split):
     torch.cuda.synchronize()
     xo = prob.reported(st)[0]
     assert rel(x.cpu().numpy(), xo) <= 1e-3
+
+
+@pytest.mark.parametrize("prior,split_T", [("tv", False), ("tgv", False), ("tgv", True)])
+def test_custom_sampling_parity(P, small3d, prior, split_T):
+    """A constant tuned distribution (prior share 0.3; TGV block n 0.05 of it) and, for
+    TGV, steps per variable (block n's scalar step caps w only): same block sequence, step
+    maps and iterates as the oracle."""
+    print(f"[spdhg] small3d custom sampling {prior} split_T={split_T}", flush=True)
+    g = small3d["geom"]
+    kw = dict(p_prior=0.3, p_tgv_n=0.05 if prior == "tgv" else 0.0, split_T=split_T)
+    prob = S.Problem(g, small3d["b"], small3d["r"], small3d["mult"], n_subsets=6, prior=prior,
+                     alpha=0.05, alpha1=0.025, sampling="custom", precond=True, **kw)
+    t = {k: dev(small3d[k]) for k in ("b", "r", "mult")}
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    rec = P.Reconstruction(g, P.cparams(6, prior, "custom", True, alpha=0.05, alpha1=0.025,
+                                        seed=61, **kw), t["b"], t["r"], t["mult"], x)
+    try:
+        assert rec.iters_per_epoch == prob.iters_per_epoch()
+        for i in range(prob.n):
+            assert rec.block_info(i)[1] == prob.p[i]
+        T = rec.buffer("T").cpu().numpy()
+        assert rel(T, prob.T[0]) <= 1e-5
+        st = S.spdhg(prob, 8 * prob.iters_per_epoch(), seed=61)
+        rec.epoch(8)
+        torch.cuda.synchronize()
+        X = prob.reported(st)
+        assert rel(x.cpu().numpy(), X[0]) <= 1e-3
+        if prior == "tgv":
+            assert rel(rec.buffer("w").cpu().numpy(), X[1:4]) <= 2e-3
+        psi_o = prob.objective(X)
+        assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
+    finally:
+        rec.close()

@@ -118,6 +118,14 @@ def test_grad_norm_quoted_values():
     assert R.grad_norm_closed_form((127, 344, 344)) == pytest.approx(3.463989, abs=1e-6)
 
 
+@pytest.mark.parametrize("shape", [(1, 5, 5), (3, 4, 5), (2, 6, 3)])
+def test_sym_grad_norm_below_grad_norm(shape):
+    """||E|| <= ||grad|| (the TGV block-n step bound): dense SVD of E against the closed
+    form, with ||E w||_F^2 <= sum_k ||grad w_k||^2 as the reason."""
+    ME = _dense(R.sym_grad, (3,) + shape)
+    assert np.linalg.norm(ME, 2) <= R.grad_norm_closed_form(shape) * (1 + 1e-12)
+
+
 def test_power_iteration_vs_svd():
     shape = (3, 4, 5)
     ME = _dense(R.sym_grad, (3,) + shape)

@@ -33,3 +33,17 @@ def test_draw_frequencies():
     # counter-based: a stream resumed at k continues exactly
     a = S.draw_blocks(9, p, 100)
     assert S.draw_blocks(9, p, 40, start=60) == a[60:]
+
+
+def test_prior_share_probabilities():
+    """The tuned constant distribution: prior blocks together q, data 1 - q uniformly;
+    q = 1/2 reproduces balanced sampling exactly; the draws follow it."""
+    for m, npr in ((21, 1), (10, 2), (7, 0)):
+        assert S.prior_share(m, npr, 0.5) == S.balanced(m, npr)
+    p = S.prior_share(4, 2, 0.3, 0.05)
+    assert abs(sum(p) - 1) < 1e-15
+    assert p[-1] == 0.05 and abs(p[-2] - 0.25) < 1e-15 and p[0] == 0.7 / 4
+    draws = np.array(S.draw_blocks(77, p, 60000))
+    freq = np.bincount(draws, minlength=len(p)) / len(draws)
+    chi2 = len(draws) * np.sum((freq - np.array(p)) ** 2 / np.array(p))
+    assert chi2 < 25.0  # 5 dof

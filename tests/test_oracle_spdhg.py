@@ -127,11 +127,25 @@ def _dense_op(apply, in_shape):
 
 
 @pytest.mark.parametrize("precond", [True, False])
-@pytest.mark.parametrize("prior", ["tv", "tgv"])
-def test_step_size_condition(precond, prior):
-    g, b, r, mult = tiny_problem(nxy=5, n_ang=6, n_rad=8)
+@pytest.mark.parametrize("prior,sampling,split_T", [
+    ("tv", "balanced", False), ("tgv", "balanced", False),
+    # tuned constant sampling (prior share 0.3, TGV block n with 0.05 of it) and TGV steps
+    # per variable: block n (0, E) caps only the step of w
+    ("tv", "custom", False), ("tgv", "custom", False), ("tgv", "custom", True)])
+def test_step_size_condition(precond, prior, sampling, split_T):
+    # low sensitivities (mult scale 0.5) make the data steps larger than block n's, so that
+    # the TGV split decides T_u
+    g, b, r, mult = tiny_problem(nxy=5, n_ang=6, n_rad=8, scale=0.5 if split_T else 10.0)
     prob = S.Problem(g, b, r, mult, n_subsets=3, prior=prior, alpha=0.5, alpha1=0.25,
-                     sampling="balanced", precond=precond)
+                     sampling=sampling, precond=precond, p_prior=0.3, p_tgv_n=0.05,
+                     split_T=split_T)
+    if split_T:
+        # the split matters here: block n's scalar step is the smallest prior step and
+        # caps w, while u may take the larger step of block n-1
+        t_prev = 0.99 * prob.p[prob.m] / prob.norms[prob.m]
+        t_n = 0.99 * prob.p[prob.m + 1] / prob.norms[prob.m + 1]
+        assert t_n < t_prev
+        assert np.max(prob.T[0]) > t_n and np.max(prob.T[1:4]) <= t_n
     ishape = prob.image_shape()
     Th = np.sqrt(prob.T.ravel())
     for i in range(prob.n):
@@ -210,3 +224,48 @@ def test_epoch_lengths():
     assert S.Problem(g, b, r, mult, n_subsets=4, prior="tv").iters_per_epoch() == 5
     assert S.Problem(g, b, r, mult, n_subsets=4, prior="tv",
                      sampling="balanced").iters_per_epoch() == 8
+
+
+def test_osem_consistent_data_is_a_fixed_point():
+    """With noise-free data b = P x + r every subset update leaves x unchanged (each ratio
+    b / (P_i x + r) is 1, and P_i^T 1 / P_i^T 1 = 1 on the sensitivity's support), eq. OSEM;
+    a wrong subset, factor or ordering breaks it."""
+    g, _, r, mult = tiny_problem(seed=5, nz=3, segs=((3, 1, 1), (0.0, 0.3, -0.3)))
+    rng = np.random.default_rng(9)
+    xt = rng.uniform(0.5, 2.0, g.image_shape)
+    b = mult * proj.forward(g, xt) + r
+    prob = S.Problem(g, b, r, mult, n_subsets=4, prior="none")
+    for i in range(4):
+        np.testing.assert_allclose(S.osem_step(prob, xt, i), xt, rtol=1e-12)
+
+
+def test_osem_subset_count_identity():
+    """sum_v (P_i^T 1)_v x'_v = sum_{j in S_i} b_j (P_i x)_j / (P_i x + r)_j for the update x'
+    of subset i (multiply eq. OSEM by P_i^T 1 and sum over voxels)."""
+    g, b, r, mult = tiny_problem(seed=6)
+    prob = S.Problem(g, b, r, mult, n_subsets=3, prior="none")
+    rng = np.random.default_rng(10)
+    x = rng.uniform(0.2, 3.0, g.image_shape)
+    for i in range(3):
+        ang = prob.angles[i]
+        xn = S.osem_step(prob, x, i)
+        sens = proj.backward(g, prob.sub_mult[i], ang)
+        px = prob.sub_mult[i] * proj.forward(g, x, ang)
+        lhs = float(np.sum(sens * xn))
+        rhs = float(np.sum(prob.sub_b[i] * px / (px + prob.sub_r[i])))
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_mlem_is_osem_with_one_subset_and_increases_likelihood():
+    """OSEM with one subset is MLEM (eq. MLEM); MLEM never decreases the Poisson
+    likelihood (the EM property)."""
+    g, b, r, mult = tiny_problem(seed=7)
+    prob1 = S.Problem(g, b, r, mult, n_subsets=1, prior="none")
+    u = np.ones(g.image_shape)
+    ll = S.poisson_loglik(prob1, u)
+    for _ in range(20):
+        un = S.mlem_step(prob1, u)
+        np.testing.assert_array_equal(S.osem_step(prob1, u, 0), un)
+        ll_new = S.poisson_loglik(prob1, un)
+        assert ll_new >= ll - 1e-9 * abs(ll)
+        u, ll = un, ll_new
