@@ -136,6 +136,19 @@ int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
                   const float* mult, const float* x, float* y_out, void* ws, size_t ws_bytes,
                   void* stream);
 
+/* spdhg_project for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same projection,
+ * bitwise, with its scratch (geometry tables and the z-fastest copy of x) taken from a
+ * fixed array inside the library instead of a caller workspace.  The array holds 64 MiB on
+ * every GPU the library runs on, until the process ends: enough for the 344 x 344 x 127
+ * mMR image; a geometry whose tables and image need more is rejected with
+ * SPDHG_E_WORKSPACE before any GPU work.  The call allocates nothing.  Every call on one
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other streams or host
+ * threads) race; calls ordered on one stream do not.  Arguments and errors as
+ * spdhg_project. */
+int spdhg_project_noalloc(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
+                          const float* mult, const float* x, float* y_out, void* stream);
+
 /* x_out = A_i^T y (Algorithm 2, backprojected dual change), the exact transpose of
  * spdhg_project computed by a voxel-driven gather with the same weights (deterministic,
  * no atomics).

@@ -733,6 +733,39 @@ int prof_end(spdhg_ctx* c, hipStream_t st) {
 
 namespace {
 
+// ---------------------------------------------------------------- fixed scratch
+// Device scratch of spdhg_project_noalloc, for callers that cannot allocate: a fixed
+// array in the code object, one copy per GPU the library runs on, held until the process
+// ends.  Host code never uses the array's name as an address (on the host it names a
+// stand-in, not device memory): scratch_ptr() fetches the device address of the current
+// GPU's copy once per device with hipGetSymbolAddress and keeps it.
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {nullptr};
+
+int scratch_ptr(char** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(SPDHG_E_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SPDHG_E_HIP, "hipGetSymbolAddress returned NULL for the scratch");
+        g_scratch_ptr[dev] = (char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPDHG_OK;
+}
+
 // ---------------------------------------------------------------- stand-alone operators
 // Workspace of spdhg_project / spdhg_backproject / spdhg_nnz /
 // spdhg_normalised_backprojection (caller memory, 256-byte aligned): the geometry tables,
@@ -876,6 +909,33 @@ int spdhg_project(const spdhg_geom* geom, int32_t n_subsets, int32_t subset, con
     hipStream_t st = (hipStream_t)stream;
     OpWork W;
     if ((rc = op_begin(geom, ws, ws_bytes, st, W, true))) return rc;
+    return project_zf_scratch(geom, W, mult, x, y_out, a0, step, cnt, st);
+}
+
+int spdhg_project_noalloc(const spdhg_geom* geom, int32_t n_subsets, int32_t subset,
+                          const float* mult, const float* x, float* y_out, void* stream) {
+    int rc = check_geom(geom);
+    if (rc || (rc = check_kernel_limits(geom))) return rc;
+    if (!x || !y_out) return fail(SPDHG_E_ARG, "NULL image or output");
+    int a0, step, cnt;
+    rc = subset_angles(geom, n_subsets, subset, a0, step, cnt);
+    if (rc) return rc;
+    {
+        HostTables T;
+        build_tables(geom, T);
+        const size_t need = op_layout(geom, T).project_total;
+        if (need > SCRATCH_BYTES)
+            return fail(SPDHG_E_WORKSPACE,
+                        "spdhg_project_noalloc: the geometry needs " + std::to_string(need) +
+                            " bytes of scratch, above the library's fixed " +
+                            std::to_string((size_t)SCRATCH_BYTES) +
+                            " (use spdhg_project with a workspace)");
+    }
+    char* ptr = nullptr;
+    if ((rc = scratch_ptr(&ptr))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    OpWork W;
+    if ((rc = op_begin(geom, ptr, SCRATCH_BYTES, st, W, true))) return rc;
     return project_zf_scratch(geom, W, mult, x, y_out, a0, step, cnt, st);
 }
 

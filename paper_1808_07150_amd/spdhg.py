@@ -22,7 +22,8 @@ PRIOR = {"none": 0, "tv": 1, "atv": 2, "dtv": 3, "tgv": 4}
 SAMPLING = {"uniform": 0, "balanced": 1, "custom": 2}
 
 EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_op_workspace_bytes",
-            "spdhg_project", "spdhg_backproject", "spdhg_normalised_backprojection", "spdhg_nnz",
+            "spdhg_project", "spdhg_project_noalloc", "spdhg_backproject",
+            "spdhg_normalised_backprojection", "spdhg_nnz",
             "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch",
             "spdhg_epoch_graph", "spdhg_batch_epoch", "spdhg_pdhg_iterate", "spdhg_em_iterate",
             "spdhg_set_tuning", "spdhg_autotune", "spdhg_info",
@@ -81,6 +82,7 @@ def load_library() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.restype = ctypes.c_int
         f.argtypes = [G, i32, i32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.spdhg_project_noalloc.argtypes = [G, i32, i32, vp, vp, vp, vp]
     lib.spdhg_normalised_backprojection.argtypes = [G, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.spdhg_nnz.argtypes = [G, i32, i32, ctypes.POINTER(ctypes.c_double), vp,
                               ctypes.c_size_t, vp]
