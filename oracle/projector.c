@@ -12,7 +12,8 @@
  * method (P. M. Joseph, IEEE TMI 1982) for parallel-beam rays with oblique planes:
  *
  *   ray (a, q, k):   phi = a*pi/n_ang,  s = (k - (n_rad-1)/2) d_rad,
- *                    plane q = local plane p of segment g,  z_p = (p - (N_g-1)/2) vz,
+ *                    plane q = local plane p of segment g,
+ *                    z_p = (p - (N_g-1)/2) pitch_g vz  (pitch_g = 1, or 2 for ring pairs),
  *   points           (s cos phi - t sin phi,  s sin phi + t cos phi,  z_p + tau_g t).
  *
  * If |cos phi| >= |sin phi| (decided by the integer test 4a <= n_ang or 4a >= 3 n_ang,
@@ -33,7 +34,7 @@
 #define M_PI 3.14159265358979323846
 #endif
 
-#define ORC_MAX_SEG 64
+#define ORC_MAX_SEG 128
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -44,6 +45,9 @@ typedef struct {
     int32_t n_seg;
     int32_t seg_planes[ORC_MAX_SEG];
     double seg_tan[ORC_MAX_SEG];
+    int32_t seg_pitch[ORC_MAX_SEG]; /* axial spacing of the segment's planes in image planes
+                                     * (0 or 1: every plane; 2: every other plane, the ring
+                                     * pairs of span 1 with a ring pitch of two planes) */
 } orc_geom;
 
 static int32_t n_planes(const orc_geom* G) {
@@ -78,7 +82,8 @@ static sample_t ray_sample(const orc_geom* G, int32_t a, int32_t p, int32_t g,
     double c = cos(phi), s = sin(phi);
     double r = ((double)k - 0.5 * (G->n_rad - 1)) * G->d_rad;
     int32_t Ng = G->seg_planes[g];
-    double zp = ((double)p - 0.5 * (Ng - 1)) * G->vz;
+    int32_t pitch = G->seg_pitch[g] > 1 ? G->seg_pitch[g] : 1;
+    double zp = ((double)p - 0.5 * (Ng - 1)) * pitch * G->vz;
     double tau = G->seg_tan[g];
     sample_t out;
     if (row_dominant(G, a)) {

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "projector.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-MAX_SEG = 64
+MAX_SEG = 128
 
 
 class _Geom(ctypes.Structure):
@@ -26,7 +26,8 @@ class _Geom(ctypes.Structure):
                 ("n_rad", ctypes.c_int32), ("d_rad", ctypes.c_double),
                 ("n_ang", ctypes.c_int32), ("n_seg", ctypes.c_int32),
                 ("seg_planes", ctypes.c_int32 * MAX_SEG),
-                ("seg_tan", ctypes.c_double * MAX_SEG)]
+                ("seg_tan", ctypes.c_double * MAX_SEG),
+                ("seg_pitch", ctypes.c_int32 * MAX_SEG)]
 
 
 def build(force: bool = False) -> str:
@@ -68,9 +69,13 @@ def _geom(g) -> _Geom:
     s.vx, s.vy, s.vz = g.vx, g.vy, g.vz
     s.n_rad, s.d_rad, s.n_ang = g.n_rad, g.d_rad, g.n_ang
     s.n_seg = g.n_seg
-    for i, (n, t) in enumerate(zip(g.seg_planes, g.seg_tan)):
+    if g.n_seg > MAX_SEG:
+        raise ValueError("too many segments")
+    pitch = getattr(g, "seg_pitch", ()) or (1,) * g.n_seg
+    for i, (n, t, pt) in enumerate(zip(g.seg_planes, g.seg_tan, pitch)):
         s.seg_planes[i] = n
         s.seg_tan[i] = t
+        s.seg_pitch[i] = pt
     return s
 
 

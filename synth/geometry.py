@@ -8,8 +8,9 @@ everywhere in this repository is a parallel-beam, ray-driven Joseph model:
 
 * voxel centres ``(i - (n-1)/2) * v`` per axis, image stored ``[z][y][x]``;
 * angle ``phi_a = a * pi / n_ang``, radial position ``s_k = (k - (n_rad-1)/2) * d_rad``;
-* segment ``g`` holds ``N_g`` planes with axial centres ``(p - (N_g-1)/2) * vz`` and a
-  constant axial slope ``tau_g`` (dz per mm of in-plane path);
+* segment ``g`` holds ``N_g`` planes with axial centres ``(p - (N_g-1)/2) * pitch_g * vz``
+  (``pitch_g`` = 1, or 2 for the ring pairs of span 1, whose ring pitch is two image
+  planes) and a constant axial slope ``tau_g`` (dz per mm of in-plane path);
 * sinogram stored ``[angle][plane][radial]``, planes ordered by segment 0, +1, -1, +2, -2 ...
 """
 from __future__ import annotations
@@ -32,13 +33,22 @@ class Geometry:
     n_ang: int
     seg_planes: Tuple[int, ...] = (1,)
     seg_tan: Tuple[float, ...] = (0.0,)
+    seg_pitch: Tuple[int, ...] = ()  # empty: every segment has pitch 1
 
     def __post_init__(self):
         if len(self.seg_planes) != len(self.seg_tan):
             raise ValueError("seg_planes and seg_tan differ in length")
-        for n in self.seg_planes:
-            if n <= 0 or n > self.nz or (self.nz - n) % 2:
-                raise ValueError(f"segment plane count {n} incompatible with nz={self.nz}")
+        if self.seg_pitch and len(self.seg_pitch) != len(self.seg_planes):
+            raise ValueError("seg_pitch and seg_planes differ in length")
+        for n, pt in zip(self.seg_planes, self.pitches):
+            span = 1 + pt * (n - 1)  # image planes from the first plane to the last
+            if pt not in (1, 2) or n <= 0 or span > self.nz or (self.nz - span) % 2:
+                raise ValueError(f"segment of {n} planes at pitch {pt} incompatible with "
+                                 f"nz={self.nz}")
+
+    @property
+    def pitches(self) -> Tuple[int, ...]:
+        return tuple(self.seg_pitch) if self.seg_pitch else (1,) * len(self.seg_planes)
 
     @property
     def n_seg(self) -> int:
@@ -122,6 +132,40 @@ def small_3d(nxy: int = 24, nz: int = 9, n_rad: int = 26, n_ang: int = 12,
     return Geometry(nx=nxy, ny=nxy, nz=nz, vx=v, vy=v, vz=v, n_rad=n_rad, d_rad=v,
                     n_ang=n_ang, seg_planes=(nz, nz - 4, nz - 4),
                     seg_tan=(0.0, tan1, -tan1))
+
+
+def span1_segments(rings: int, max_ring_diff: int, vz: float, ring_radius: float = 328.0):
+    """Span-1 (uncompressed) segments of a scanner with `rings` detector rings at a ring
+    pitch of two image planes (nz = 2 rings - 1): one segment per ring difference d = 0,
+    +1, -1, ..., +D, -D, holding the rings - |d| ring pairs (r, r + d), whose axial centres
+    sit on every other image plane; axial slope d (2 vz) / (2 R)."""
+    planes, tans, pitch = [], [], []
+    for k in range(2 * max_ring_diff + 1):
+        d = (k + 1) // 2 * (1 if k % 2 else -1) if k else 0
+        planes.append(rings - abs(d))
+        tans.append(d * (2.0 * vz) / (2.0 * ring_radius))
+        pitch.append(2)
+    return tuple(planes), tuple(tans), tuple(pitch)
+
+
+def mmr_span1(rings: int = 64, max_ring_diff: int = 60, n_rad: int = 344, n_ang: int = 252,
+              nxy: int = 344, vxy: float = 2.08, vz: float = 2.08) -> Geometry:
+    """mMR-shaped span-1 data: 64 rings, ring differences up to 60 (121 segments, 4084
+    planes), image 344 x 344 x 127 at 2.08 mm, sinogram 344 x 252 x 4084 (354,033,792
+    bins)."""
+    planes, tans, pitch = span1_segments(rings, max_ring_diff, vz)
+    return Geometry(nx=nxy, ny=nxy, nz=2 * rings - 1, vx=vxy, vy=vxy, vz=vz,
+                    n_rad=n_rad, d_rad=vxy, n_ang=n_ang, seg_planes=planes, seg_tan=tans,
+                    seg_pitch=pitch)
+
+
+def slab_span1(rings: int = 8, max_ring_diff: int = 7, nxy: int = 344, v: float = 2.08,
+               n_ang: int = 252) -> Geometry:
+    """Span-1 slab of the mMR: `rings` rings (nz = 2 rings - 1 image planes) with every ring
+    difference up to max_ring_diff, 344 x 344 in-plane, 252 angles."""
+    planes, tans, pitch = span1_segments(rings, max_ring_diff, v)
+    return Geometry(nx=nxy, ny=nxy, nz=2 * rings - 1, vx=v, vy=v, vz=v, n_rad=nxy, d_rad=v,
+                    n_ang=n_ang, seg_planes=planes, seg_tan=tans, seg_pitch=pitch)
 
 
 def slab(nz: int, nxy: int = 344, v: float = 2.08) -> Geometry:

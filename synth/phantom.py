@@ -40,8 +40,8 @@ def _ray_params(g: Geometry, a: int):
     c, s = math.cos(phi), math.sin(phi)
     r = (np.arange(g.n_rad) - 0.5 * (g.n_rad - 1)) * g.d_rad
     zp, tau = [], []
-    for n, t in zip(g.seg_planes, g.seg_tan):
-        zp.append((np.arange(n) - 0.5 * (n - 1)) * g.vz)
+    for n, t, pt in zip(g.seg_planes, g.seg_tan, g.pitches):
+        zp.append((np.arange(n) - 0.5 * (n - 1)) * pt * g.vz)
         tau.append(np.full(n, t))
     zp = np.concatenate(zp)[:, None]
     tau = np.concatenate(tau)[:, None]
@@ -121,6 +121,11 @@ def _non_overlapping(rng, body: Ellipsoid, count: int, rmin: float, rmax: float,
         tries += 1
         ax, ay = rng.uniform(rmin, rmax, size=2)
         az = math.inf if flat else rng.uniform(rmin, rmax)
+        if not flat:
+            # keep the ellipsoid inside the body along z too: in thin slabs (body.az small)
+            # a drawn az could exceed the body, and an inner ellipsoid with a negative
+            # value would make the total activity negative outside the body
+            az = min(az, 0.8 * body.az)
         R = max(ax, ay) if flat else max(ax, ay, az)
         # centre uniformly inside the body's shrunken ellipsoid
         u = rng.uniform(-1, 1, size=3)
@@ -209,6 +214,8 @@ def make_data(g: Geometry, seed: int, counts: float, act, att,
         raise ValueError(background)
     scale = counts / (trues.sum() + rshape.sum())
     ybar = scale * (trues + rshape)
+    if not np.all(np.isfinite(ybar)) or ybar.min() < 0:
+        raise ValueError("negative or non-finite expected counts (activity < 0 somewhere)")
     b = rng.poisson(ybar).astype(np.float32)
     return dict(b=b, r=(scale * rshape).astype(np.float32),
                 mult=mult.astype(np.float32), scale=scale)
@@ -262,8 +269,8 @@ def _torch_chords(torch, g: Geometry, angles, e: Ellipsoid, device):
     c, s = torch.cos(phi), torch.sin(phi)
     r = ((torch.arange(g.n_rad, dtype=f64, device=device) - 0.5 * (g.n_rad - 1))
          * g.d_rad)[None, None, :]
-    zp = torch.cat([(torch.arange(n, dtype=f64, device=device) - 0.5 * (n - 1)) * g.vz
-                    for n in g.seg_planes])[None, :, None]
+    zp = torch.cat([(torch.arange(n, dtype=f64, device=device) - 0.5 * (n - 1)) * pt * g.vz
+                    for n, pt in zip(g.seg_planes, g.pitches)])[None, :, None]
     tau = torch.cat([torch.full((n,), t, dtype=f64, device=device)
                      for n, t in zip(g.seg_planes, g.seg_tan)])[None, :, None]
     ct, st = math.cos(e.theta), math.sin(e.theta)
@@ -326,6 +333,10 @@ def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side
     del scatter
     scale = counts / (trues.sum() + rshape.sum())
     ybar = scale * (trues + rshape)
+    # a Poisson sampler given a negative or NaN rate is undefined (on the device, torch's
+    # sampler faulted the GPU on such rates): check before sampling
+    if not bool(torch.isfinite(ybar).all()) or float(ybar.min()) < 0:
+        raise ValueError("negative or non-finite expected counts (activity < 0 somewhere)")
     if host_poisson:
         hrng = np.random.Generator(np.random.PCG64(seed + 3))
         b = torch.from_numpy(hrng.poisson(ybar.cpu().numpy()).astype(np.float32)).to(device)
