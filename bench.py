@@ -48,6 +48,12 @@ WORKLOADS = {
                        label="mMR 344x344x127 / 344x252x837 span-11, dTV beta=2e-3 eta=1e-2 "
                              "(MR-like side image) + nonneg, 252 single-angle subsets, "
                              "SPDHG+, 3e7 counts"),
+    "mmr-span1-tv21": dict(m=21, prior="tv", counts=1e8, alpha=2e-3, alpha1=0.0, prior_bpv=44,
+                           geometry="span1",
+                           label="mMR span-1 344x344x127 / 344x252x4084 (64 rings, ring "
+                                 "differences up to 60: 121 segments, 354M bins), TV "
+                                 "beta=2e-3 + nonneg, 21 subsets, SPDHG+ (balanced, "
+                                 "preconditioned), 1e8 counts"),
 }
 HBM_PEAK_GBS = 8000.0
 # MI355X's published FP32 vector peak (256 CUs at 2.4 GHz, packed FP32 FMA); the kernels
@@ -497,8 +503,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration(torch, dev)
-    g = synth.mmr()
     wl = WORKLOADS[args.workload]
+    g = synth.mmr_span1() if wl.get("geometry") == "span1" else synth.mmr()
     m = wl["m"]
     t0 = time.time()
     if args.inputs == "phantom":

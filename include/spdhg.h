@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define SPDHG_MAX_SEG 64
+#define SPDHG_MAX_SEG 128
 
 #define SPDHG_OK 0
 #define SPDHG_E_ARG (-1)       /* invalid argument (null pointer, out-of-range value)   */
@@ -53,10 +53,13 @@ extern "C" {
 /* Scanner / image geometry (a reading: the paper leaves the geometry to its projector
  * package).  Voxel centres (i - (n-1)/2) v per axis; angle a has phi = a pi / n_ang;
  * radial bin k sits at s = (k - (n_rad-1)/2) d_rad; segment g holds seg_planes[g] planes
- * with axial centres (p - (N_g-1)/2) vz and axial slope seg_tan[g] (mm of z per mm of
- * in-plane path); nz - seg_planes[g] must be even.  A ray is sampled at every image row
- * when 4a <= n_ang or 4a >= 3 n_ang, else at every column, and the image is interpolated
- * bilinearly (zero outside) in the other in-plane axis and z. */
+ * with axial centres (p - (N_g-1)/2) pitch_g vz and axial slope seg_tan[g] (mm of z per
+ * mm of in-plane path), where pitch_g = seg_pitch[g] is 1 (0 means 1: consecutive image
+ * planes, e.g. span-11 data) or 2 (every other image plane: the ring pairs of span-1 data,
+ * whose ring pitch is two image planes); nz - 1 - pitch_g (N_g - 1) must be even and
+ * >= 0.  A ray is sampled at every image row when 4a <= n_ang or 4a >= 3 n_ang, else at
+ * every column, and the image is interpolated bilinearly (zero outside) in the other
+ * in-plane axis and z. */
 typedef struct spdhg_geom {
     int32_t nx, ny, nz;
     double vx, vy, vz;
@@ -66,6 +69,7 @@ typedef struct spdhg_geom {
     int32_t n_seg;
     int32_t seg_planes[SPDHG_MAX_SEG];
     double seg_tan[SPDHG_MAX_SEG];
+    int32_t seg_pitch[SPDHG_MAX_SEG];
 } spdhg_geom;
 
 #define SPDHG_PRIOR_NONE 0 /* ML: n = m blocks                                        */
@@ -209,20 +213,34 @@ int spdhg_iterate(spdhg_ctx* ctx, int64_t n_iters, void* stream);
  * iterations that in expectation use all data once). */
 int spdhg_epoch(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
 
-/* The same iterations as spdhg_epoch (bitwise the same result), with each epoch's
- * launches recorded by stream capture into one HIP graph and launched as a graph (the
- * epoch is a fixed sequence of kernels once its random blocks are drawn).  Returns after
- * the stream has run the graphs (the graphs are then released).  Not with per-kernel
- * profiling on (SPDHG_E_STATE). */
+/* The same iterations as spdhg_epoch (bitwise the same result), launched as a persistent
+ * HIP graph: the context's own spdhg_graph (below), built on the first call and kept until
+ * spdhg_destroy or a change of the tuning.  Returns after the stream has run the epochs.
+ * Not with per-kernel profiling on (SPDHG_E_STATE). */
 int spdhg_epoch_graph(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
+
+/* Persistent epoch graph of one or more problems (Algorithm 2's epochs of independent
+ * reconstructions, of any sizes and subset counts, in one HIP graph): per problem a chain
+ * of kernel nodes, one group per iteration slot of an epoch, each group holding every
+ * kernel an iteration of any block could launch in that slot (then the end of the epoch).
+ * The graph is instantiated once.  spdhg_graph_epoch draws each problem's blocks on the
+ * host exactly as spdhg_epoch does, writes the arguments of the resulting launches into the
+ * matching nodes, disables the others and launches the graph on `stream`: every problem
+ * advances one epoch per graph launch, bitwise as in a solo spdhg_epoch.  The contexts must
+ * outlive the graph; an eager call on a context between graph epochs is ordered by the
+ * stream like any other.  Not with per-kernel profiling on (SPDHG_E_STATE). */
+typedef struct spdhg_graph spdhg_graph;
+int spdhg_graph_create(spdhg_ctx* const* ctxs, int32_t n, spdhg_graph** out);
+int spdhg_graph_epoch(spdhg_graph* graph, int32_t n_epochs, void* stream);
+int spdhg_graph_destroy(spdhg_graph* graph);
 
 /* Batched reconstructions: n independent problems (contexts from spdhg_init, each with
  * its own geometry, subsets, prior and workspace) each advance n_epochs of their own
  * epochs.  Problem i runs on worker stream i mod n_streams (at most 8, default priority)
  * forked from and joined back to `stream`, so the problems overlap on the GPU; every
  * problem's launches are exactly those of a solo spdhg_epoch (bitwise the same result).
- * use_graph != 0 records the whole forked batch epoch with stream capture into one HIP
- * graph and launches it (needs a non-default `stream`; returns after it has run);
+ * use_graph != 0 runs the n_epochs batch epochs as one persistent spdhg_graph over the
+ * problems (built, launched n_epochs times, released; returns after it has run);
  * otherwise the call is asynchronous on `stream`.  A context may appear once. */
 int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32_t n_streams,
                       int32_t use_graph, void* stream);
@@ -234,6 +252,14 @@ int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32
  * *fwd_split and *ms receive the choice and its time per launch. */
 int spdhg_set_tuning(spdhg_ctx* ctx, int32_t fwd_split);
 int spdhg_autotune(spdhg_ctx* ctx, int32_t* fwd_split, double* ms, void* stream);
+
+/* Tiling of the gather backprojection: 1 = strips of 10 voxel columns along the secondary
+ * axis (for 32 <= nz <= 127, one plane pitch and tap tables within one workgroup's LDS),
+ * 2 = groups of whole voxel columns (any geometry), 0 = the automatic choice (strips where
+ * they apply).  spdhg_autotune also times both on the subset-0 backprojection and keeps
+ * the faster; spdhg_get_tuning reports the split and the gather in use (1 or 2). */
+int spdhg_set_gather(spdhg_ctx* ctx, int32_t gather);
+int spdhg_get_tuning(const spdhg_ctx* ctx, int32_t* fwd_split, int32_t* gather);
 
 /* n_iters iterations of deterministic PDHG (Algorithm 1): every block's dual step from the
  * same x, the backprojected dual changes summed, z += dz, extrapolation z_bar = z + dz and
@@ -260,8 +286,10 @@ int spdhg_info(const spdhg_ctx* ctx, int64_t* iters_per_epoch, int64_t* iters_do
 
 /* FP64 objective of an image (Problem 1): out_dev[0] = Psi, [1] = data term
  * sum_j phi_j((A x)_j) over all bins, [2] = prior term alpha R(x) (infinite if x has a
- * negative entry), [3] = reserved (0).  x = NULL means the current iterate.  out_dev
- * is device memory for 4 doubles.  Deterministic (fixed reduction order). */
+ * negative entry), [3] = the failure flag: the number of non-finite voxels of x (for the
+ * current TGV iterate, of u and w), 0 for a healthy iterate.  x = NULL means the current
+ * iterate.  out_dev is device memory for 4 doubles.  Deterministic (fixed reduction
+ * order). */
 int spdhg_objective(spdhg_ctx* ctx, const float* x, double* out_dev, void* stream);
 
 /* Duality gap of the current state (x, y) for the problem with g = indicator of [0, U]

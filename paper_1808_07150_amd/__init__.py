@@ -3,7 +3,8 @@
 The computation lives in libspdhg.so (hand-written HIP kernels for gfx950, C ABI in
 include/spdhg.h); this package is its thin Python binding.
 """
-from .spdhg import (CGeom, CParams, Reconstruction, SpdhgError, aligned_workspace,  # noqa: F401
+from .spdhg import (CGeom, CParams, EpochGraph, Reconstruction, SpdhgError,  # noqa: F401
+                    aligned_workspace,
                     batch_epoch, cgeom, cparams, load_library, normalised_backprojection,
                     op_workspace, op_workspace_bytes, spdhg_backproject, spdhg_nnz,
                     spdhg_project, subset_bins)

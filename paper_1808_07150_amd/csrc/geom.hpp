@@ -7,7 +7,7 @@
 //
 //   u = du_dj * jj + (du_dk * kk + cu)       secondary in-plane index (fma, fma)
 //   e = ez_dj[g] * jj + ez_dk[g] * kk        axial offset in voxels from the plane centre
-//   z index = p + off_g + e,  off_g = (nz - N_g) / 2
+//   z index = off_g + pitch_g p + e,  off_g = (nz - 1 - pitch_g (N_g - 1)) / 2
 //
 // Bilinear interpolation in (u, z) with zero padding; each sample carries the 3-D path
 // length L_g = v_prim / |cos or sin| * sqrt(1 + tau_g^2).  The coordinates are evaluated
@@ -20,7 +20,7 @@
 
 #include <stdint.h>
 
-#define SPDHG_DEV_MAX_SEG 64
+#define SPDHG_DEV_MAX_SEG 128
 
 struct AngleDev {
     double du_dk;  // secondary index per radial bin
@@ -46,7 +46,8 @@ struct GeomDev {
     double ck;  // (n_rad - 1) / 2
     int32_t seg_planes[SPDHG_DEV_MAX_SEG];
     int32_t seg_base[SPDHG_DEV_MAX_SEG];  // first sinogram plane of the segment
-    int32_t seg_off[SPDHG_DEV_MAX_SEG];   // (nz - N_g) / 2
+    int32_t seg_off[SPDHG_DEV_MAX_SEG];   // image plane of the first plane: (nz - 1 - pitch (N_g - 1)) / 2
+    int32_t seg_pitch[SPDHG_DEV_MAX_SEG]; // image planes between consecutive planes (1 or 2)
     const AngleDev* ang;                  // [n_ang]
     const SegAngleDev* sa;                // [n_ang][n_seg]
     const int32_t* plane_seg;             // [n_planes] segment of each plane

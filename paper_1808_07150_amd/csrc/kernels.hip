@@ -229,7 +229,7 @@ fwd_wave(FwdArgs P) {
     float acc[RPL];
     {
         const int g0 = G.plane_seg[0];
-        const int base0 = G.seg_off[g0] - G.seg_base[g0] + P.pad;
+        const int base0 = G.seg_off[g0] - G.seg_pitch[g0] * G.seg_base[g0] + P.pad;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int q = lane + 64 * r;
@@ -237,7 +237,7 @@ fwd_wave(FwdArgs P) {
             int g = g0, base = base0;
             if (q < G.n_planes) {
                 g = G.plane_seg[q];
-                base = q - G.seg_base[g] + G.seg_off[g] + P.pad;
+                base = G.seg_pitch[g] * (q - G.seg_base[g]) + G.seg_off[g] + P.pad;
             }
             toff[r] = (int)((const char*)(segt + g) - (const char*)smem);
             boff[r] = (int)((const char*)(Gb + base) - (const char*)smem);
@@ -246,11 +246,11 @@ fwd_wave(FwdArgs P) {
     for (int i = lane; i < P.gsize; i += 64) Gb[i] = 0.0f;
     // the axial offset of segment g at step j is fma(ez_dj, jj, ez_dk * kk) (ax_offset):
     // its two step-independent parts are read once, so the step loop loads nothing from
-    // global memory but the image columns (only lane g touches entry g)
-    if (lane < ns) {
-        const SegAngleDev S = G.sa[a * ns + lane];
-        segk[lane] = S.ez_dk * kk;
-        segj[lane] = S.ez_dj;
+    // global memory but the image columns (only lane g % 64 touches entry g)
+    for (int sg = lane; sg < ns; sg += 64) {
+        const SegAngleDev S = G.sa[a * ns + sg];
+        segk[sg] = S.ez_dk * kk;
+        segj[sg] = S.ez_dj;
     }
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
@@ -309,12 +309,12 @@ fwd_wave(FwdArgs P) {
             }
         }
         if (j + 1 < j1) issue(j + 1);
-        if (lane < ns) {
-            const Sample sz = split(__builtin_fma(segj[lane], jj, segk[lane]));
+        for (int sg = lane; sg < ns; sg += 64) {
+            const Sample sz = split(__builtin_fma(segj[sg], jj, segk[sg]));
             SegStep e;
             e.c4 = sz.i0 * 4;
             e.fz = sz.fu;
-            segt[lane] = e;
+            segt[sg] = e;
         }
         __builtin_amdgcn_wave_barrier();
         // rays in groups of RG: the table reads of a group, then its column reads, then
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
     const int64_t s_sec = A.rowdom ? 1 : G.nx;
     const int q0 = w * 64 * RPL;  // first plane of this wavefront
 
-    int pinfo[RPL];  // (padded axial base of the plane) << 6 | segment
+    int pinfo[RPL];  // (padded axial base of the plane) << 7 | segment
     float acc[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
@@ -422,14 +422,15 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
         pinfo[r] = 0;
         if (q < G.n_planes) {
             const int g = G.plane_seg[q];
-            pinfo[r] = ((q - G.seg_base[g] + G.seg_off[g] + P.pad) << 6) | g;
+            pinfo[r] = ((G.seg_pitch[g] * (q - G.seg_base[g]) + G.seg_off[g] + P.pad) << 7) | g;
         }
     }
     for (int i = tid; i < 2 * P.gsize; i += 64 * PS) Gb[i] = 0.0f;
-    if (tid < ns) {  // step-independent parts of ax_offset (only thread g touches entry g)
-        const SegAngleDev S = G.sa[a * ns + tid];
-        segk[tid] = S.ez_dk * kk;
-        segj[tid] = S.ez_dj;
+    // step-independent parts of ax_offset (only one thread touches entry g)
+    for (int sg = tid; sg < ns; sg += 64 * PS) {
+        const SegAngleDev S = G.sa[a * ns + sg];
+        segk[sg] = S.ez_dk * kk;
+        segj[sg] = S.ez_dj;
     }
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
@@ -478,10 +479,10 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
             }
         }
         if (j + 1 < j1) issue(j + 1);
-        if (tid < ns) {
-            const Sample sz = split(__builtin_fma(segj[tid], jj, segk[tid]));
-            segc[buf * ns + tid] = sz.i0;
-            segf[buf * ns + tid] = sz.fu;
+        for (int sg = tid; sg < ns; sg += 64 * PS) {
+            const Sample sz = split(__builtin_fma(segj[sg], jj, segk[sg]));
+            segc[buf * ns + sg] = sz.i0;
+            segf[buf * ns + sg] = sz.fu;
         }
         // the other buffer was last read before this barrier's predecessor
         __syncthreads();
@@ -489,8 +490,8 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             if (q0 + lane + 64 * r < G.n_planes) {
-                const int g = pinfo[r] & 63;
-                const int idx = (pinfo[r] >> 6) + segc[buf * ns + g];
+                const int g = pinfo[r] & 127;
+                const int idx = (pinfo[r] >> 7) + segc[buf * ns + g];
                 const float fz = segf[buf * ns + g];
                 acc[r] = __builtin_fmaf(1.0f - fz, Gr[idx], acc[r]);
                 acc[r] = __builtin_fmaf(fz, Gr[idx + 1], acc[r]);
@@ -502,7 +503,7 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int q = q0 + lane + 64 * r;
-        if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, pinfo[r] & 63, acc[r], obj);
+        if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, pinfo[r] & 127, acc[r], obj);
     }
     if (MODE == F_OBJ) {
         obj = wave_sum(obj);
@@ -577,10 +578,19 @@ __device__ __forceinline__ void tap_pair_sum(const TapCoef& t, float b0, float b
     h1 = __builtin_fmaf(t.wb, b1, h1);
 }
 
-// The same with explicit bounds (per-lane rays).
-__device__ __forceinline__ float tap_sum_masked(const float* __restrict__ seg, int n,
+// The same with explicit bounds (per-lane rays).  Pitch 1: voxel z takes plane
+// p = z + off (weight wa) and p - 1 (wb).  Pitch 2 (a segment on every other image plane):
+// with u = z + off, plane p sits at image plane off_g + 2p + i0 (weight wa) and reaches the
+// next one with weight wb, so voxel z takes one plane, u / 2 with wa if u is even, else
+// (u - 1) / 2 with wb (u >> 1 in both cases).
+__device__ __forceinline__ float tap_sum_masked(const float* __restrict__ seg, int n, int pitch,
                                                 const TapCoef& t, int z, float h) {
     const int p = z + t.off;
+    if (pitch == 2) {
+        const int pp = p >> 1;
+        if ((unsigned)pp < (unsigned)n) h = __builtin_fmaf((p & 1) ? t.wb : t.wa, seg[pp], h);
+        return h;
+    }
     if ((unsigned)p < (unsigned)n) h = __builtin_fmaf(t.wa, seg[p], h);
     if ((unsigned)(p - 1) < (unsigned)n) h = __builtin_fmaf(t.wb, seg[p - 1], h);
     return h;
@@ -708,7 +718,8 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
                 if (iz >= nz) break;
                 float h = 0.0f;
                 for (int g = 0; g < ns; ++g)
-                    h = tap_sum_masked(dk + G.seg_base[g], G.seg_planes[g], tk[g], iz, h);
+                    h = tap_sum_masked(dk + G.seg_base[g], G.seg_planes[g], G.seg_pitch[g], tk[g],
+                                       iz, h);
                 acc[zz] = __builtin_fmaf(o.wx, h, acc[zz]);
             }
         }
@@ -742,21 +753,44 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 // epilogue.  Deterministic, no atomics.  The workgroup is one wavefront, whose LDS
 // accesses execute in order: code-motion barriers separate the phases.
 #define BS_W 10
+#define SEG_CHUNK 11  // segments whose tap tables the strip gather holds at a time
 
 // N consecutive segments of one ray: all 2N loads, then all sums (in segment order).
-template <int N>
+// PITCH 1 (consecutive planes): la, lb = lane - 1, lane + 63, and each plane is loaded once,
+// the second tap coming from the next lane (tap_pair_*).  PITCH 2 (planes on every other
+// image plane): la, lb = lane, lane + 64; each voxel takes one plane of the segment,
+// u >> 1 with u = z + off, weighted wa (u even) or wb (u odd), so neighbouring lanes load
+// the same plane.
+template <int N, int PITCH>
 __device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, const TapCoef* tk,
-                                            int g, int lane_m1, int lane_63, float& h0,
-                                            float& h1) {
+                                            int g, int la, int lb, float& h0, float& h1) {
     float v[N][2];
+    if constexpr (PITCH == 1) {
 #pragma unroll
-    for (int u = 0; u < N; ++u)
-        tap_pair_loads(seg_rsrc(G, dk, g + u), tk[g + u], lane_m1, lane_63, v[u][0], v[u][1]);
+        for (int u = 0; u < N; ++u)
+            tap_pair_loads(seg_rsrc(G, dk, g + u), tk[g + u], la, lb, v[u][0], v[u][1]);
 #pragma unroll
-    for (int u = 0; u < N; ++u) tap_pair_sum(tk[g + u], v[u][0], v[u][1], h0, h1);
+        for (int u = 0; u < N; ++u) tap_pair_sum(tk[g + u], v[u][0], v[u][1], h0, h1);
+    } else {
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g + u);
+            const int off = tk[g + u].off;
+            v[u][0] = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(rs, ((la + off) >> 1) * 4, 0, 0));
+            v[u][1] = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(rs, ((lb + off) >> 1) * 4, 0, 0));
+        }
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const TapCoef& t = tk[g + u];
+            h0 = __builtin_fmaf(((la + t.off) & 1) ? t.wb : t.wa, v[u][0], h0);
+            h1 = __builtin_fmaf(((lb + t.off) & 1) ? t.wb : t.wa, v[u][1], h1);
+        }
+    }
 }
 
-template <int MODE>
+template <int MODE, int PITCH>
 // Seven waves per SIMD (at most 72 VGPRs): room for the loads of a whole ray (span 11:
 // 22 values) next to the 20 accumulators, so a ray costs one memory round trip.  A wave's
 // time is set by the latency of its rays, so narrow strips (fewer rays per wave, more
@@ -772,7 +806,8 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
     float* rfu = (float*)(ri0 + KR);          // [KR] in-plane fraction
     int* cfirst = (int*)(rfu + KR);           // [BS_W + 1] first ray of cell c (index c + 1)
     int* clast = cfirst + (BS_W + 1);         // [BS_W + 1] last ray of cell c
-    TapCoef* tc = (TapCoef*)(clast + (BS_W + 1));  // [KR][ns]
+    TapCoef* tc = (TapCoef*)(clast + (BS_W + 1));  // [KR][sc]: one chunk of segments
+    const int sc = min(ns, SEG_CHUNK);  // the table's entries per ray (host: bwd_plan)
 
     const int lane = threadIdx.x;
     const int n_sec = rowdom ? G.nx : G.ny;
@@ -783,11 +818,12 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
     const int sidx = blk / n_prim;
     const int j = blk - sidx * n_prim;
     const int s0 = sidx * BS_W;
-    // lane - 1 and lane + 63 through register copies the compiler cannot fold into an
-    // immediate buffer offset (the hardware range check must see the whole offset)
-    int lane_m1, lane_63;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_m1) : "v"(lane - 1));
-    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_63) : "v"(lane + 63));
+    // the lane offsets of strip_batch (lane - 1 and lane + 63, or lane and lane + 64)
+    // through register copies the compiler cannot fold into an immediate buffer offset
+    // (the hardware range check must see the whole offset)
+    int lane_a, lane_b;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_a) : "v"(PITCH == 1 ? lane - 1 : lane));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_b) : "v"(PITCH == 1 ? lane + 63 : lane + 64));
     float acc[BS_W][2];
 #pragma unroll
     for (int c = 0; c < BS_W; ++c) acc[c][0] = acc[c][1] = 0.0f;
@@ -814,10 +850,6 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
             cfirst[lane] = 0;
             clast[lane] = -1;
         }
-        for (int t = lane; t < nr * ns; t += 64) {
-            const int kr = t / ns, g = t - kr * ns;
-            tc[t] = tap_coef(G, a, g, (double)(klo + kr) - G.ck, jj);
-        }
         __builtin_amdgcn_wave_barrier();
         for (int kr = lane; kr < nr; kr += 64) {
             const int ci = ri0[kr];
@@ -826,32 +858,46 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
                 if (kr == nr - 1 || ri0[kr + 1] != ci) clast[ci + 1] = kr;
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        // 2. axial gather of the rays of each cell, added to the cell's two columns
+        // 2. per chunk of up to SEG_CHUNK segments (all of them for span 11): the chunk's
+        // tap coefficients of every ray, then the axial gather of the rays of each cell,
+        // added to the cell's two columns
+        for (int gc = 0; gc < ns; gc += SEG_CHUNK) {
+            const int nsc = min(SEG_CHUNK, ns - gc);
+            __builtin_amdgcn_wave_barrier();  // the previous chunk's taps are consumed
+            for (int t = lane; t < nr * nsc; t += 64) {
+                const int kr = t / nsc, gl = t - kr * nsc;
+                tc[kr * sc + gl] = tap_coef(G, a, gc + gl, (double)(klo + kr) - G.ck, jj);
+            }
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int c = -1; c < BS_W; ++c) {
-            const int r0 = __builtin_amdgcn_readfirstlane(cfirst[c + 1]);
-            const int r1 = __builtin_amdgcn_readfirstlane(clast[c + 1]);
-            for (int kr = r0; kr <= r1; ++kr) {
-                const float fu =
-                    __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rfu[kr])));
-                const float* dk = P.d + dual_row(G, ia, klo + kr);
-                const TapCoef* tk = tc + kr * ns;
-                float h0 = 0.0f, h1 = 0.0f;
-                // segments in batches of 11 (all of them for span 11), then 4, then 1: every
-                // load of a batch is issued before any tap is summed, so a span-11 ray costs
-                // one memory round trip (batches with per-slot guards lose this overlap)
-                int g = 0;
-                for (; g + 11 <= ns; g += 11) strip_batch<11>(G, dk, tk, g, lane_m1, lane_63, h0, h1);
-                for (; g + 4 <= ns; g += 4) strip_batch<4>(G, dk, tk, g, lane_m1, lane_63, h0, h1);
-                for (; g < ns; ++g) strip_batch<1>(G, dk, tk, g, lane_m1, lane_63, h0, h1);
-                if (c >= 0) {
-                    acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
-                    acc[c][1] = __builtin_fmaf(1.0f - fu, h1, acc[c][1]);
-                }
-                if (c + 1 < BS_W) {
-                    acc[c + 1][0] = __builtin_fmaf(fu, h0, acc[c + 1][0]);
-                    acc[c + 1][1] = __builtin_fmaf(fu, h1, acc[c + 1][1]);
+            for (int c = -1; c < BS_W; ++c) {
+                const int r0 = __builtin_amdgcn_readfirstlane(cfirst[c + 1]);
+                const int r1 = __builtin_amdgcn_readfirstlane(clast[c + 1]);
+                for (int kr = r0; kr <= r1; ++kr) {
+                    const float fu =
+                        __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rfu[kr])));
+                    const float* dk = P.d + dual_row(G, ia, klo + kr);
+                    const TapCoef* tk = tc + kr * sc - gc;  // tk[g]: segment g of the chunk
+                    float h0 = 0.0f, h1 = 0.0f;
+                    // segments in batches of 11, then 4, then 1: every load of a batch is
+                    // issued before any tap is summed, so a span-11 ray costs one memory
+                    // round trip (batches with per-slot guards lose this overlap)
+                    int g = gc;
+                    const int ge = gc + nsc;
+                    for (; g + 11 <= ge; g += 11)
+                        strip_batch<11, PITCH>(G, dk, tk, g, lane_a, lane_b, h0, h1);
+                    for (; g + 4 <= ge; g += 4)
+                        strip_batch<4, PITCH>(G, dk, tk, g, lane_a, lane_b, h0, h1);
+                    for (; g < ge; ++g)
+                        strip_batch<1, PITCH>(G, dk, tk, g, lane_a, lane_b, h0, h1);
+                    if (c >= 0) {
+                        acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
+                        acc[c][1] = __builtin_fmaf(1.0f - fu, h1, acc[c][1]);
+                    }
+                    if (c + 1 < BS_W) {
+                        acc[c + 1][0] = __builtin_fmaf(fu, h0, acc[c + 1][0]);
+                        acc[c + 1][1] = __builtin_fmaf(fu, h1, acc[c + 1][1]);
+                    }
                 }
             }
         }
@@ -978,10 +1024,17 @@ reduce_final(const double* __restrict__ part, int64_t n, double* __restrict__ ou
 }
 
 __global__ void combine_objective(double* out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        out[0] = out[1] + out[2];
-        out[3] = 0.0;
-    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = out[1] + out[2];
+}
+
+// FP64 partials of the number of non-finite entries of a (the failure flag of the
+// objective: an iterate stays finite unless an input or a step overflowed).
+__global__ void __launch_bounds__(BLOCK)
+count_nonfinite(const float* __restrict__ a, int64_t n, double* __restrict__ part) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const double v = (t < n && !isfinite(a[t])) ? 1.0 : 0.0;
+    const double s = block_sum<BLOCK>(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------- TV / dTV prior block
@@ -2077,7 +2130,7 @@ __device__ double ray_taps(const GeomDev& G, int a, int q, int k) {
     const int p = q - G.seg_base[g];
     const SegAngleDev S = G.sa[a * G.n_seg + g];
     const double kk = (double)k - G.ck;
-    const int zb = p + G.seg_off[g];
+    const int zb = G.seg_pitch[g] * p + G.seg_off[g];
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
     double n = 0.0;

@@ -8,9 +8,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/spdhg.h"
@@ -43,6 +47,55 @@ int fail(int code, const std::string& msg) {
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
+// ---------------------------------------------------------------- recordable launches
+// The kernels of the SPDHG iteration are launched through klaunch, which either enqueues
+// the launch or, while a Recorder is installed on the calling thread, records it (kernel,
+// launch shape and a copy of the argument values) for a persistent epoch graph, whose
+// nodes then receive exactly the arguments an eager run would launch with.
+struct LaunchRec {
+    const void* func = nullptr;
+    dim3 grid, block;
+    unsigned lds = 0;
+    std::shared_ptr<void> vals;  // a std::tuple of the kernel's parameter values
+    std::vector<void*> ptrs;     // pointers to its elements (kernel node parameters)
+};
+
+struct Recorder {
+    std::vector<LaunchRec> recs;
+    std::vector<size_t> marks;  // recs.size() at the start of each iteration
+};
+
+thread_local Recorder* g_rec = nullptr;
+
+template <typename Tup, size_t... I>
+void tuple_ptrs(Tup& t, void** out, std::index_sequence<I...>) {
+    ((out[I] = (void*)&std::get<I>(t)), ...);
+}
+
+template <typename... KP, typename... A>
+int klaunch(void (*k)(KP...), dim3 grid, dim3 block, size_t lds, hipStream_t st, A&&... a) {
+    static_assert(sizeof...(KP) == sizeof...(A), "kernel argument count");
+    using Tup = std::tuple<std::decay_t<KP>...>;
+    if (g_rec) {
+        auto t = std::make_shared<Tup>(std::forward<A>(a)...);
+        LaunchRec r;
+        r.func = (const void*)k;
+        r.grid = grid;
+        r.block = block;
+        r.lds = (unsigned)lds;
+        r.ptrs.resize(sizeof...(KP));
+        tuple_ptrs(*t, r.ptrs.data(), std::index_sequence_for<KP...>{});
+        r.vals = t;
+        g_rec->recs.push_back(std::move(r));
+        return SPDHG_OK;
+    }
+    Tup t(std::forward<A>(a)...);
+    std::array<void*, sizeof...(KP)> p;
+    tuple_ptrs(t, p.data(), std::index_sequence_for<KP...>{});
+    HIP_TRY(hipLaunchKernel((const void*)k, grid, block, p.data(), lds, st));
+    return SPDHG_OK;
+}
+
 int64_t n_planes(const spdhg_geom* g) {
     int64_t n = 0;
     for (int i = 0; i < g->n_seg; ++i) n += g->seg_planes[i];
@@ -58,9 +111,13 @@ int check_geom(const spdhg_geom* g) {
     if (g->n_seg <= 0 || g->n_seg > SPDHG_MAX_SEG)
         return fail(SPDHG_E_SHAPE, "n_seg out of range");
     for (int i = 0; i < g->n_seg; ++i) {
-        if (g->seg_planes[i] <= 0 || g->seg_planes[i] > g->nz ||
-            ((g->nz - g->seg_planes[i]) & 1))
-            return fail(SPDHG_E_SHAPE, "segment plane count must be in [1, nz] with nz - N even");
+        const int pitch = g->seg_pitch[i] == 0 ? 1 : g->seg_pitch[i];
+        if (pitch != 1 && pitch != 2) return fail(SPDHG_E_SHAPE, "segment pitch must be 1 or 2");
+        const int64_t span = 1 + (int64_t)pitch * ((int64_t)g->seg_planes[i] - 1);
+        if (g->seg_planes[i] <= 0 || span > g->nz || ((g->nz - span) & 1))
+            return fail(SPDHG_E_SHAPE,
+                        "segment plane count N must be >= 1 with nz - 1 - pitch (N - 1) even "
+                        "and >= 0");
         if (!std::isfinite(g->seg_tan[i])) return fail(SPDHG_E_SHAPE, "segment slope not finite");
     }
     const double nv = (double)g->nx * g->ny * g->nz;
@@ -136,9 +193,11 @@ void build_tables(const spdhg_geom* g, HostTables& T) {
     G.ck = 0.5 * (g->n_rad - 1);
     int base = 0;
     for (int sg = 0; sg < ns; ++sg) {
+        const int pitch = g->seg_pitch[sg] == 0 ? 1 : g->seg_pitch[sg];
         G.seg_planes[sg] = g->seg_planes[sg];
         G.seg_base[sg] = base;
-        G.seg_off[sg] = (g->nz - g->seg_planes[sg]) / 2;
+        G.seg_pitch[sg] = pitch;
+        G.seg_off[sg] = (g->nz - 1 - pitch * (g->seg_planes[sg] - 1)) / 2;
         for (int p = 0; p < g->seg_planes[sg]; ++p) T.plane_seg.push_back(sg);
         base += g->seg_planes[sg];
     }
@@ -260,25 +319,25 @@ int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
     constexpr bool hot = MODE == F_DUAL || MODE == F_OBJ;
     if (hot && rpl == 16 && (A.G.n_planes + 63) / 64 >= 13 && (A.G.n_planes + 63) / 64 <= 14)
         rpl = 14;
+    int rc = SPDHG_OK;
     switch (rpl) {
-        case 1: fwd_wave<1, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
-        case 2: fwd_wave<2, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
-        case 4: fwd_wave<4, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
-        case 8: fwd_wave<8, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 1: rc = klaunch(fwd_wave<1, MODE, NW>, nblk, nt, lds, st, A); break;
+        case 2: rc = klaunch(fwd_wave<2, MODE, NW>, nblk, nt, lds, st, A); break;
+        case 4: rc = klaunch(fwd_wave<4, MODE, NW>, nblk, nt, lds, st, A); break;
+        case 8: rc = klaunch(fwd_wave<8, MODE, NW>, nblk, nt, lds, st, A); break;
         case 14:
-            if constexpr (hot) fwd_wave<14, MODE, NW><<<nblk, nt, lds, st>>>(A);
+            if constexpr (hot) rc = klaunch(fwd_wave<14, MODE, NW>, nblk, nt, lds, st, A);
             break;
-        case 16: fwd_wave<16, MODE, NW><<<nblk, nt, lds, st>>>(A); break;
+        case 16: rc = klaunch(fwd_wave<16, MODE, NW>, nblk, nt, lds, st, A); break;
         case 32:
-            if constexpr (NW <= 4) fwd_wave<32, MODE, NW><<<nblk, nt, lds, st>>>(A);
+            if constexpr (NW <= 4) rc = klaunch(fwd_wave<32, MODE, NW>, nblk, nt, lds, st, A);
             break;
         case 64:
-            if constexpr (NW <= 4) fwd_wave<64, MODE, NW><<<nblk, nt, lds, st>>>(A);
+            if constexpr (NW <= 4) rc = klaunch(fwd_wave<64, MODE, NW>, nblk, nt, lds, st, A);
             break;
         default: return fail(SPDHG_E_SHAPE, "unsupported plane count");
     }
-    LAUNCH_CHECK();
-    return SPDHG_OK;
+    return rc;
 }
 
 // Plane-split forward: PS wavefronts per ray bundle, each with RPL rays per lane.
@@ -287,15 +346,13 @@ int launch_fwd_ps(const FwdArgs& A, int nblk, hipStream_t st) {
     const size_t lds = (2 * (size_t)A.gsize + 8 * (size_t)A.G.n_seg) * 4;
     const int rpl = rays_per_lane((A.G.n_planes + PS - 1) / PS);
     switch (rpl) {
-        case 1: fwd_bundle<1, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
-        case 2: fwd_bundle<2, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
-        case 4: fwd_bundle<4, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
-        case 8: fwd_bundle<8, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
-        case 16: fwd_bundle<16, MODE, PS><<<nblk, 64 * PS, lds, st>>>(A); break;
+        case 1: return klaunch(fwd_bundle<1, MODE, PS>, nblk, 64 * PS, lds, st, A);
+        case 2: return klaunch(fwd_bundle<2, MODE, PS>, nblk, 64 * PS, lds, st, A);
+        case 4: return klaunch(fwd_bundle<4, MODE, PS>, nblk, 64 * PS, lds, st, A);
+        case 8: return klaunch(fwd_bundle<8, MODE, PS>, nblk, 64 * PS, lds, st, A);
+        case 16: return klaunch(fwd_bundle<16, MODE, PS>, nblk, 64 * PS, lds, st, A);
         default: return fail(SPDHG_E_SHAPE, "unsupported plane count for the plane split");
     }
-    LAUNCH_CHECK();
-    return SPDHG_OK;
 }
 
 // One block per (angle of the list, radial bin); launches with few blocks split every ray
@@ -332,6 +389,7 @@ int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }
 struct BwdPlan {
     bool strip = false;
     int KR = 0;
+    int pitch = 1;  // the plane pitch every segment shares (the strip kernel's instance)
     size_t lds = 0;
 };
 
@@ -341,10 +399,15 @@ BwdPlan bwd_plan(const HostTables& T) {
     double min_du = 1e30;
     for (const AngleDev& A : T.ang) min_du = std::min(min_du, std::fabs(A.du_dk));
     if (nz < 32 || nz > 127 || !(min_du >= 0.5)) return pl;
+    for (int g = 1; g < ns; ++g)
+        if (T.G.seg_pitch[g] != T.G.seg_pitch[0]) return pl;  // mixed pitches: per column
     const int KR = (int)std::ceil((BS_W + 1) / min_du) + 6;
-    const size_t floats = 2 * (size_t)KR + 2 * (BS_W + 1) + (sizeof(TapCoef) / 4) * (size_t)KR * ns;
+    const size_t floats = 2 * (size_t)KR + 2 * (BS_W + 1) +
+                          (sizeof(TapCoef) / 4) * (size_t)KR * std::min(ns, SEG_CHUNK);
+    if (floats * 4 > 64 * 1024) return pl;  // one workgroup's LDS
     pl.strip = true;
     pl.KR = KR;
+    pl.pitch = T.G.seg_pitch[0];
     pl.lds = floats * 4;
     return pl;
 }
@@ -353,44 +416,50 @@ BwdPlan bwd_plan(const HostTables& T) {
 // A.d holds their dual change in the dual_row layout.  With the strip kernel the
 // row-sampled and column-sampled angles run as two launches; when both classes occur and
 // the epilogue needs the whole sum, the first writes its partial image to `partial`.
+// The strip gather of the angles ang0 + i * step (i < cnt) (see launch_bwd).
+template <int MODE, int PITCH>
+int launch_strip(const BwdArgs& A, int cnt, int ang0, int step, hipStream_t st,
+                 const BwdPlan& plan, const AngleDev* host_ang, float* partial) {
+    bool has[2] = {false, false};
+    for (int i = 0; i < cnt; ++i) has[host_ang[ang0 + i * step].rowdom] = true;
+    const int nstr_r = ((A.G.nx + BS_W - 1) / BS_W) * A.G.ny;  // rows: strips along x
+    const int nstr_c = ((A.G.ny + BS_W - 1) / BS_W) * A.G.nx;  // columns: strips along y
+    const float* none = nullptr;
+    if (has[1] && has[0]) {
+        if (MODE == B_ACCUM) {
+            int rc = klaunch(bwd_strip<B_ACCUM, PITCH>, nstr_r, 64, plan.lds, st, A, plan.KR, 1, none);
+            if (rc) return rc;
+            return klaunch(bwd_strip<B_ACCUM, PITCH>, nstr_c, 64, plan.lds, st, A, plan.KR, 0, none);
+        }
+        BwdArgs Pp = A;
+        Pp.out = partial;
+        int rc = klaunch(bwd_strip<B_PARTIAL, PITCH>, nstr_r, 64, plan.lds, st, Pp, plan.KR, 1, none);
+        if (rc) return rc;
+        return klaunch(bwd_strip<MODE, PITCH>, nstr_c, 64, plan.lds, st, A, plan.KR, 0,
+                       (const float*)partial);
+    }
+    if (has[1]) return klaunch(bwd_strip<MODE, PITCH>, nstr_r, 64, plan.lds, st, A, plan.KR, 1, none);
+    if (has[0]) return klaunch(bwd_strip<MODE, PITCH>, nstr_c, 64, plan.lds, st, A, plan.KR, 0, none);
+    return SPDHG_OK;
+}
+
 template <int MODE>
 int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st, const BwdPlan& plan,
                const AngleDev* host_ang, float* partial) {
     A.ang0 = ang0;
     A.ang_step = step;
     A.n_ang_sub = cnt;
-    if (plan.strip) {
-        bool has[2] = {false, false};
-        for (int i = 0; i < cnt; ++i) has[host_ang[ang0 + i * step].rowdom] = true;
-        const int nstr_r = ((A.G.nx + BS_W - 1) / BS_W) * A.G.ny;  // rows: strips along x
-        const int nstr_c = ((A.G.ny + BS_W - 1) / BS_W) * A.G.nx;  // columns: strips along y
-        if (has[1] && has[0]) {
-            if (MODE == B_ACCUM) {
-                bwd_strip<B_ACCUM><<<nstr_r, 64, plan.lds, st>>>(A, plan.KR, 1, nullptr);
-                LAUNCH_CHECK();
-                bwd_strip<B_ACCUM><<<nstr_c, 64, plan.lds, st>>>(A, plan.KR, 0, nullptr);
-            } else {
-                BwdArgs Pp = A;
-                Pp.out = partial;
-                bwd_strip<B_PARTIAL><<<nstr_r, 64, plan.lds, st>>>(Pp, plan.KR, 1, nullptr);
-                LAUNCH_CHECK();
-                bwd_strip<MODE><<<nstr_c, 64, plan.lds, st>>>(A, plan.KR, 0, partial);
-            }
-        } else if (has[1]) {
-            bwd_strip<MODE><<<nstr_r, 64, plan.lds, st>>>(A, plan.KR, 1, nullptr);
-        } else if (has[0]) {
-            bwd_strip<MODE><<<nstr_c, 64, plan.lds, st>>>(A, plan.KR, 0, nullptr);
-        }
-        LAUNCH_CHECK();
-        return SPDHG_OK;
-    }
-    A.cols = bwd_cols(A.G.nz);
+    if (plan.strip && plan.pitch == 2)
+        return launch_strip<MODE, 2>(A, cnt, ang0, step, st, plan, host_ang, partial);
+    if (plan.strip)
+        return launch_strip<MODE, 1>(A, cnt, ang0, step, st, plan, host_ang, partial);
+    // columns per workgroup: as many as the threads cover, within one workgroup's LDS
+    const size_t per_col = (size_t)BWD_KC * (sizeof(ColCoord) + sizeof(TapCoef) * A.G.n_seg);
+    A.cols = std::max(1, std::min<int>(bwd_cols(A.G.nz), (int)((64 * 1024) / per_col)));
     const int64_t ncol = (int64_t)A.G.nx * A.G.ny;
     const int64_t nblk = (ncol + A.cols - 1) / A.cols;
-    const size_t lds = (size_t)A.cols * BWD_KC * (sizeof(ColCoord) + sizeof(TapCoef) * A.G.n_seg);
-    bwd_col<MODE><<<(unsigned)nblk, BWD_THREADS, lds, st>>>(A, nullptr);
-    LAUNCH_CHECK();
-    return SPDHG_OK;
+    const size_t lds = (size_t)A.cols * per_col;
+    return klaunch(bwd_col<MODE>, (unsigned)nblk, BWD_THREADS, lds, st, A, (const float*)nullptr);
 }
 
 dim3 img_grid(int nx, int ny, int nz) { return dim3((nx + TT - 1) / TT, (nz + TT - 1) / TT, ny); }
@@ -466,6 +535,9 @@ struct spdhg_ctx {
     int64_t w_pending = 0;
     double tw = 0.0;
     int fwd_split = 0;  // wavefronts per ray bundle of the subset projection (0: automatic)
+    int gather = 0;     // backprojection tiling: 0 automatic (strips where they apply), 2 columns
+    BwdPlan bplan_auto; // the automatic plan (bplan is it, or the per-column gather)
+    spdhg_graph* graph = nullptr;  // persistent epoch graph of spdhg_epoch_graph (owned)
     float* em_inv = nullptr;  // SPDHG_FLAG_EM: 1 / (A_i^T 1) per subset (m images, z-fastest)
     int64_t em_k = 0;         // EM-type sub-iterations done (subset em_k mod m is next)
     double* part = nullptr;
@@ -682,20 +754,17 @@ int power_norm_dgrad(spdhg_ctx* c, double* out, hipStream_t st) {
 int settle_w(spdhg_ctx* c, hipStream_t st) {
     if (!c->zw || c->w_pending == 0) return SPDHG_OK;
     const int64_t n3 = 3 * c->nv;
-    w_catchup<<<nblocks(n3), BLOCK, 0, st>>>(c->w[c->w_cur], c->zw, n3,
-                                              (float)((double)c->w_pending * c->tw));
-    LAUNCH_CHECK();
+    int rc = klaunch(w_catchup, nblocks(n3), BLOCK, 0, st, c->w[c->w_cur], (const float*)c->zw, n3,
+                     (float)((double)c->w_pending * c->tw));
     c->w_pending = 0;
-    return SPDHG_OK;
+    return rc;
 }
 
 // Copy the internal iterate out to the caller's image.
 int export_x(spdhg_ctx* c, hipStream_t st) {
     const spdhg_geom& g = c->geom;
-    img_from_zf<<<img_grid(g.nx, g.ny, g.nz), TT * 8, 0, st>>>(g.nx, g.ny, g.nz, c->xcur(),
-                                                               c->x_user);
-    LAUNCH_CHECK();
-    return SPDHG_OK;
+    return klaunch(img_from_zf, img_grid(g.nx, g.ny, g.nz), TT * 8, 0, st, g.nx, g.ny, g.nz,
+                   (const float*)c->xcur(), c->x_user);
 }
 
 // Per-kernel timing (events around launches; collected on demand).
@@ -1051,6 +1120,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     c->pad = axial_pad(c->tab);
     c->gsize = geom->nz + 2 * c->pad;
     c->bplan = bwd_plan(c->tab);
+    c->bplan_auto = c->bplan;
     c->side = side;
     c->x_user = x;
     c->bp = (float*)(w + L.bp);
@@ -1306,12 +1376,369 @@ int objective_into(spdhg_ctx* c, const float* x, double* out_dev, hipStream_t st
                                               c->prm.prior != SPDHG_PRIOR_NONE);
     }
     reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv), out_dev, 2, 1.0);
+    // failure flag: non-finite voxels of the image (and of w for TGV)
+    count_nonfinite<<<nblocks(nv), BLOCK, 0, st>>>(xx, nv, c->part);
+    if (c->zw && !x)
+        count_nonfinite<<<nblocks(3 * nv), BLOCK, 0, st>>>(c->w[c->w_cur], 3 * nv,
+                                                           c->part + nblocks(nv));
+    reduce_final<<<1, BLOCK, 0, st>>>(c->part, nblocks(nv) + ((c->zw && !x) ? nblocks(3 * nv) : 0),
+                                      out_dev, 3, 1.0);
     combine_objective<<<1, 64, 0, st>>>(out_dev);
     LAUNCH_CHECK();
     return SPDHG_OK;
 }
 
 }  // namespace
+
+namespace {
+
+// Block of the context's next iteration (Algorithm 2, block sampling): SplitMix64 output k
+// mapped through the cumulative probabilities.
+int draw_block(const spdhg_ctx* c) {
+    const uint64_t zr = splitmix64(c->prm.seed, (uint64_t)c->k);
+    const double u = (double)(zr >> 11) * (1.0 / 9007199254740992.0);
+    int i = 0;
+    while (!(u < c->cum[i])) ++i;
+    return i;
+}
+
+// One iteration of Algorithm 2 on block i: dual step, backprojected dual change, z update,
+// extrapolation and the next primal step (fused), then the state's buffer parities.
+int one_iteration(spdhg_ctx* c, int i, hipStream_t st) {
+    const float inv_p = (float)(1.0 / c->p[i]);
+    int rc;
+    if (i < c->m) {
+        int a0, step, cnt;
+        subset_angles(&c->geom, c->m, i, a0, step, cnt);
+        FwdArgs F = c->fwd_args();
+        F.x = c->xcur();
+        F.mult = c->mp;
+        F.b = c->bp;
+        F.r = c->rp;
+        F.sigma = c->sigma;
+        F.sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[i];
+        F.y = c->y;
+        F.d = c->dscr;
+        F.split = c->fwd_split;
+        if ((rc = prof_begin(c, SPDHG_PROF_FWD, st))) return rc;
+        if ((rc = launch_fwd<F_DUAL>(F, a0, step, cnt, st))) return rc;
+        if ((rc = prof_end(c, st))) return rc;
+        BwdArgs B = c->bwd_args();
+        B.d = c->dscr;
+        B.inv_p = inv_p;
+        B.z = c->z;
+        B.x = c->xcur();
+        B.T = c->T;
+        if ((rc = prof_begin(c, SPDHG_PROF_BWD, st))) return rc;
+        if ((rc = launch_bwd<B_ITER>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
+            return rc;
+        if ((rc = prof_end(c, st))) return rc;
+        if (c->zw) c->w_pending += 1;  // primal step for w: w -= T_w z_w (z_w unchanged)
+    } else if (c->zw) {
+        const int j = i - c->m;
+        if ((rc = settle_w(c, st))) return rc;
+        TgvArgs A = c->tgv_args(j);
+        A.inv_p = inv_p;
+        if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
+        const PriorTile TL = prior_tile(c->geom);
+        const int nb_t = prior_blocks(c->geom, TL), nt_t = TL.tx * TL.ty * c->geom.nz;
+        const int ly = std::min(TV_WAVE_LY, c->geom.ny);
+        const float* xin = c->xcur();
+        const float* win = c->w[c->w_cur];
+        float* const* dual = j == 0 ? c->yn : c->q2;
+        const int dcur = j == 0 ? c->yn_cur : c->q2_cur;
+        const float* qin = dual[dcur];
+        float* wout = c->w[1 - c->w_cur];
+        const float* T = c->T;
+        if (prior_use_wave(c->geom, 6)) {
+            const unsigned nbw = tv_wave_blocks(c->geom, ly);
+            rc = j == 0 ? klaunch(tgv1_wave, nbw, 256, 0, st, A, ly, xin, c->xother(), win, wout,
+                                  qin, dual[1 - dcur], c->z, c->zw, T)
+                        : klaunch(tgv2_wave, nbw, 256, 0, st, A, ly, xin, c->xother(), win, wout,
+                                  qin, dual[1 - dcur], (const float*)c->z, c->zw, T);
+        } else {
+            rc = j == 0 ? klaunch(tgv1_iter, nb_t, nt_t, 0, st, A, TL, xin, c->xother(), win,
+                                  wout, qin, dual[1 - dcur], c->z, c->zw, T)
+                        : klaunch(tgv2_iter, nb_t, nt_t, 0, st, A, TL, xin, c->xother(), win,
+                                  wout, qin, dual[1 - dcur], (const float*)c->z, c->zw, T);
+        }
+        if (rc) return rc;
+        if (j == 0)
+            c->yn_cur ^= 1;
+        else
+            c->q2_cur ^= 1;
+        if ((rc = prof_end(c, st))) return rc;
+        c->x_cur ^= 1;
+        c->w_cur ^= 1;
+    } else {
+        PriorArgs P = c->prior_args();
+        P.inv_p = inv_p;
+        if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
+        const float* xin = c->xcur();
+        const float* yin = c->yn[c->yn_cur];
+        if (prior_use_wave(c->geom, 3)) {
+            const int ly = std::min(TV_WAVE_LY, c->geom.ny);
+            rc = klaunch(P.dtv ? tv_wave<true> : tv_wave<false>, tv_wave_blocks(c->geom, ly), 256,
+                         0, st, P, ly, xin, c->xother(), yin, c->yn[1 - c->yn_cur], c->z,
+                         (const float*)c->T, (const float*)c->xi);
+        } else {
+            const PriorTile TL = prior_tile(c->geom);
+            rc = klaunch(tv_iter, prior_blocks(c->geom, TL), TL.tx * TL.ty * c->geom.nz, 0, st, P,
+                         TL, xin, c->xother(), yin, c->yn[1 - c->yn_cur], c->z,
+                         (const float*)c->T, (const float*)c->xi);
+        }
+        if (rc) return rc;
+        if ((rc = prof_end(c, st))) return rc;
+        c->x_cur ^= 1;
+        c->yn_cur ^= 1;
+    }
+    c->k += 1;
+    return SPDHG_OK;
+}
+
+}  // namespace
+
+// ====================================================================== persistent epoch graphs
+// One HIP graph holds an epoch of every problem of a batch: per problem a chain of kernel
+// nodes, one group per iteration slot (then the end of the epoch: the owed w steps and the
+// export of the iterate), where each group holds every kernel that an iteration of any
+// block could launch in that slot.  The graph is instantiated once (twice: two executable
+// copies alternate, so one can be updated while the other runs).  Before each epoch the
+// blocks are drawn on the host exactly as in spdhg_iterate, whose launches are recorded;
+// the recorded arguments are written into the matching nodes and the other nodes of each
+// group are disabled.  The kernels and their arguments are those of an eager run, so the
+// result is bitwise the same.
+struct GraphSlot {
+    std::vector<hipGraphNode_t> nodes;
+    std::vector<const void*> funcs;
+};
+
+struct GraphProblem {
+    spdhg_ctx* c = nullptr;
+    std::vector<GraphSlot> slots;  // iters_per_epoch iteration slots, then the end slot
+};
+
+struct spdhg_graph {
+    std::vector<GraphProblem> probs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
+    int next = 0;
+    std::vector<std::shared_ptr<void>> keep[2];  // argument storage of the last update
+};
+
+namespace {
+
+struct CtxState {
+    int64_t k, w_pending;
+    int x_cur, yn_cur, w_cur, q2_cur;
+};
+
+CtxState ctx_state(const spdhg_ctx* c) {
+    return {c->k, c->w_pending, c->x_cur, c->yn_cur, c->w_cur, c->q2_cur};
+}
+
+void set_ctx_state(spdhg_ctx* c, const CtxState& s) {
+    c->k = s.k;
+    c->w_pending = s.w_pending;
+    c->x_cur = s.x_cur;
+    c->yn_cur = s.yn_cur;
+    c->w_cur = s.w_cur;
+    c->q2_cur = s.q2_cur;
+}
+
+// Make `into` a supersequence of `seq` (kernels in launch order).
+void merge_seq(std::vector<const void*>& into, const std::vector<const void*>& seq) {
+    size_t pos = 0;
+    for (const void* f : seq) {
+        size_t k = pos;
+        while (k < into.size() && into[k] != f) ++k;
+        if (k < into.size()) {
+            pos = k + 1;
+        } else {
+            into.insert(into.begin() + pos, f);
+            ++pos;
+        }
+    }
+}
+
+// Launches of one iteration on block i (end = -1: the end of an epoch), recorded without
+// changing the context's state.  pending: TGV owes w steps first.
+int record_block(spdhg_ctx* c, int i, bool pending, Recorder& r) {
+    const CtxState s0 = ctx_state(c);
+    if (pending && c->zw) c->w_pending = 1;
+    g_rec = &r;
+    int rc = SPDHG_OK;
+    if (i >= 0) {
+        rc = one_iteration(c, i, nullptr);
+    } else if ((rc = settle_w(c, nullptr)) == SPDHG_OK) {
+        rc = export_x(c, nullptr);
+    }
+    g_rec = nullptr;
+    set_ctx_state(c, s0);
+    return rc;
+}
+
+hipKernelNodeParams node_params(const LaunchRec& r) {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(r.func);
+    kp.gridDim = r.grid;
+    kp.blockDim = r.block;
+    kp.sharedMemBytes = r.lds;
+    kp.kernelParams = const_cast<void**>(r.ptrs.data());
+    kp.extra = nullptr;
+    return kp;
+}
+
+int graph_build(spdhg_graph* G) {
+    HIP_TRY(hipGraphCreate(&G->graph, 0));
+    for (GraphProblem& P : G->probs) {
+        spdhg_ctx* c = P.c;
+        // the kernels any block can launch in an iteration slot, and at the end
+        std::vector<const void*> it_funcs, end_funcs;
+        std::map<const void*, LaunchRec> proto;
+        auto absorb = [&](Recorder& r, std::vector<const void*>& into) {
+            std::vector<const void*> seq;
+            for (LaunchRec& x : r.recs) {
+                seq.push_back(x.func);
+                proto.emplace(x.func, x);
+            }
+            merge_seq(into, seq);
+        };
+        for (int i = 0; i < c->n; ++i)
+            for (int pend = 0; pend < (c->zw ? 2 : 1); ++pend) {
+                Recorder r;
+                int rc = record_block(c, i, pend != 0, r);
+                if (rc) return rc;
+                absorb(r, it_funcs);
+            }
+        for (int pend = 0; pend < (c->zw ? 2 : 1); ++pend) {
+            Recorder r;
+            int rc = record_block(c, -1, pend != 0, r);
+            if (rc) return rc;
+            absorb(r, end_funcs);
+        }
+        const int64_t L = c->iters_per_epoch;
+        P.slots.resize((size_t)L + 1);
+        hipGraphNode_t prev = nullptr;
+        for (int64_t sl = 0; sl <= L; ++sl) {
+            GraphSlot& S = P.slots[(size_t)sl];
+            S.funcs = sl < L ? it_funcs : end_funcs;
+            for (const void* f : S.funcs) {
+                hipKernelNodeParams kp = node_params(proto.at(f));
+                hipGraphNode_t node = nullptr;
+                HIP_TRY(hipGraphAddKernelNode(&node, G->graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                              &kp));
+                S.nodes.push_back(node);
+                prev = node;
+            }
+        }
+    }
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipGraphInstantiate(&G->exec[b], G->graph, nullptr, nullptr, 0));
+        HIP_TRY(hipEventCreateWithFlags(&G->done[b], hipEventDisableTiming));
+    }
+    return SPDHG_OK;
+}
+
+// Draw the next epoch of every problem (advancing the contexts as spdhg_iterate does) and
+// write its launches into executable copy b.
+int graph_update(spdhg_graph* G, int b) {
+    G->keep[b].clear();
+    hipGraphExec_t ex = G->exec[b];
+    for (GraphProblem& P : G->probs) {
+        spdhg_ctx* c = P.c;
+        Recorder r;
+        g_rec = &r;
+        int rc = spdhg_iterate(c, c->iters_per_epoch, nullptr);
+        g_rec = nullptr;
+        if (rc) return rc;
+        const size_t L = P.slots.size() - 1;
+        if (r.marks.size() != L + 1) return fail(SPDHG_E_STATE, "epoch graph: slot count changed");
+        for (size_t sl = 0; sl <= L; ++sl) {
+            size_t idx = r.marks[sl];
+            const size_t end = sl < L ? r.marks[sl + 1] : r.recs.size();
+            GraphSlot& S = P.slots[sl];
+            for (size_t n = 0; n < S.nodes.size(); ++n) {
+                if (idx < end && r.recs[idx].func == S.funcs[n]) {
+                    hipKernelNodeParams kp = node_params(r.recs[idx]);
+                    HIP_TRY(hipGraphExecKernelNodeSetParams(ex, S.nodes[n], &kp));
+                    HIP_TRY(hipGraphNodeSetEnabled(ex, S.nodes[n], 1));
+                    ++idx;
+                } else {
+                    HIP_TRY(hipGraphNodeSetEnabled(ex, S.nodes[n], 0));
+                }
+            }
+            if (idx != end)
+                return fail(SPDHG_E_STATE, "epoch graph: a launch has no node in its slot");
+        }
+        for (LaunchRec& x : r.recs) G->keep[b].push_back(x.vals);
+    }
+    return SPDHG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spdhg_graph_create(spdhg_ctx* const* ctxs, int32_t n, spdhg_graph** out) {
+    if (!out) return fail(SPDHG_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n <= 0) return fail(SPDHG_E_ARG, "bad context list");
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(SPDHG_E_ARG, "NULL context in the graph");
+        if (ctxs[i]->prof) return fail(SPDHG_E_STATE, "per-kernel profiling is not recorded in graphs");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(SPDHG_E_ARG, "a context appears twice");
+    }
+    spdhg_graph* G = new spdhg_graph();
+    for (int i = 0; i < n; ++i) {
+        GraphProblem P;
+        P.c = ctxs[i];
+        G->probs.push_back(P);
+    }
+    int rc = graph_build(G);
+    if (rc) {
+        spdhg_graph_destroy(G);
+        return rc;
+    }
+    *out = G;
+    return SPDHG_OK;
+}
+
+int spdhg_graph_epoch(spdhg_graph* G, int32_t n_epochs, void* stream) {
+    if (!G) return fail(SPDHG_E_ARG, "graph is NULL");
+    if (n_epochs < 0) return fail(SPDHG_E_ARG, "n_epochs < 0");
+    hipStream_t st = (hipStream_t)stream;
+    for (GraphProblem& P : G->probs)
+        if (P.c->prof) return fail(SPDHG_E_STATE, "per-kernel profiling is not recorded in graphs");
+    for (int e = 0; e < n_epochs; ++e) {
+        const int b = G->next;
+        if (G->used[b]) HIP_TRY(hipEventSynchronize(G->done[b]));  // its previous run is over
+        int rc = graph_update(G, b);
+        if (rc) return rc;
+        HIP_TRY(hipGraphLaunch(G->exec[b], st));
+        HIP_TRY(hipEventRecord(G->done[b], st));
+        G->used[b] = true;
+        G->next ^= 1;
+    }
+    return SPDHG_OK;
+}
+
+int spdhg_graph_destroy(spdhg_graph* G) {
+    if (!G) return SPDHG_OK;
+    for (int b = 0; b < 2; ++b) {
+        if (G->used[b] && G->done[b]) (void)hipEventSynchronize(G->done[b]);
+        if (G->exec[b]) (void)hipGraphExecDestroy(G->exec[b]);
+        if (G->done[b]) (void)hipEventDestroy(G->done[b]);
+    }
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return SPDHG_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 
@@ -1350,104 +1777,12 @@ int spdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
     if (n_iters < 0) return fail(SPDHG_E_ARG, "n_iters < 0");
     hipStream_t st = (hipStream_t)stream;
-    const int64_t nv = c->nv;
-    PriorArgs P = c->prior_args();
     int rc;
     for (int64_t it = 0; it < n_iters; ++it) {
-        const uint64_t zr = splitmix64(c->prm.seed, (uint64_t)c->k);
-        const double u = (double)(zr >> 11) * (1.0 / 9007199254740992.0);
-        int i = 0;
-        while (!(u < c->cum[i])) ++i;
-        const float inv_p = (float)(1.0 / c->p[i]);
-        if (i < c->m) {
-            int a0, step, cnt;
-            subset_angles(&c->geom, c->m, i, a0, step, cnt);
-            FwdArgs F = c->fwd_args();
-            F.x = c->xcur();
-            F.mult = c->mp;
-            F.b = c->bp;
-            F.r = c->rp;
-            F.sigma = c->sigma;
-            F.sig_s = c->prm.precond ? 0.0f : (float)c->data_sigma[i];
-            F.y = c->y;
-            F.d = c->dscr;
-            F.split = c->fwd_split;
-            if ((rc = prof_begin(c, SPDHG_PROF_FWD, st))) return rc;
-            if ((rc = launch_fwd<F_DUAL>(F, a0, step, cnt, st))) return rc;
-            if ((rc = prof_end(c, st))) return rc;
-            BwdArgs B = c->bwd_args();
-            B.d = c->dscr;
-            B.inv_p = inv_p;
-            B.z = c->z;
-            B.x = c->xcur();
-            B.T = c->T;
-            if ((rc = prof_begin(c, SPDHG_PROF_BWD, st))) return rc;
-            if ((rc = launch_bwd<B_ITER>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
-                return rc;
-            if ((rc = prof_end(c, st))) return rc;
-            if (c->zw) c->w_pending += 1;  // primal step for w: w -= T_w z_w (z_w unchanged)
-        } else if (c->zw) {
-            const int j = i - c->m;
-            if ((rc = settle_w(c, st))) return rc;
-            TgvArgs A = c->tgv_args(j);
-            A.inv_p = inv_p;
-            if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
-            const PriorTile TL = prior_tile(c->geom);
-            const int nb_t = prior_blocks(c->geom, TL), nt_t = TL.tx * TL.ty * c->geom.nz;
-            const int ly = std::min(TV_WAVE_LY, c->geom.ny);
-            if (prior_use_wave(c->geom, 6)) {
-                if (j == 0) {
-                    tgv1_wave<<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
-                        A, ly, c->xcur(), c->xother(), c->w[c->w_cur], c->w[1 - c->w_cur],
-                        c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z, c->zw, c->T);
-                    c->yn_cur ^= 1;
-                } else {
-                    tgv2_wave<<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
-                        A, ly, c->xcur(), c->xother(), c->w[c->w_cur], c->w[1 - c->w_cur],
-                        c->q2[c->q2_cur], c->q2[1 - c->q2_cur], c->z, c->zw, c->T);
-                    c->q2_cur ^= 1;
-                }
-            } else if (j == 0) {
-                tgv1_iter<<<nb_t, nt_t, 0, st>>>(A, TL, c->xcur(), c->xother(), c->w[c->w_cur],
-                                                 c->w[1 - c->w_cur], c->yn[c->yn_cur],
-                                                 c->yn[1 - c->yn_cur], c->z, c->zw, c->T);
-                c->yn_cur ^= 1;
-            } else {
-                tgv2_iter<<<nb_t, nt_t, 0, st>>>(A, TL, c->xcur(), c->xother(), c->w[c->w_cur],
-                                                 c->w[1 - c->w_cur], c->q2[c->q2_cur],
-                                                 c->q2[1 - c->q2_cur], c->z, c->zw, c->T);
-                c->q2_cur ^= 1;
-            }
-            LAUNCH_CHECK();
-            if ((rc = prof_end(c, st))) return rc;
-            c->x_cur ^= 1;
-            c->w_cur ^= 1;
-        } else {
-            P.inv_p = inv_p;
-            if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
-            if (prior_use_wave(c->geom, 3)) {
-                const int ly = std::min(TV_WAVE_LY, c->geom.ny);
-                if (P.dtv)
-                    tv_wave<true><<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
-                        P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur],
-                        c->z, c->T, c->xi);
-                else
-                    tv_wave<false><<<tv_wave_blocks(c->geom, ly), 256, 0, st>>>(
-                        P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur],
-                        c->z, c->T, c->xi);
-            } else {
-                const PriorTile TL = prior_tile(c->geom);
-                tv_iter<<<prior_blocks(c->geom, TL), TL.tx * TL.ty * c->geom.nz, 0, st>>>(
-                    P, TL, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
-                    c->T, c->xi);
-            }
-            LAUNCH_CHECK();
-            if ((rc = prof_end(c, st))) return rc;
-            c->x_cur ^= 1;
-            c->yn_cur ^= 1;
-        }
-        c->k += 1;
+        if (g_rec) g_rec->marks.push_back(g_rec->recs.size());
+        if ((rc = one_iteration(c, draw_block(c), st))) return rc;
     }
+    if (g_rec) g_rec->marks.push_back(g_rec->recs.size());
     if ((rc = settle_w(c, st))) return rc;
     return export_x(c, st);
 }
@@ -1462,38 +1797,15 @@ int spdhg_epoch_graph(spdhg_ctx* c, int32_t n_epochs, void* stream) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
     if (n_epochs < 0) return fail(SPDHG_E_ARG, "n_epochs < 0");
     if (c->prof) return fail(SPDHG_E_STATE, "per-kernel profiling is not recorded in graphs");
-    hipStream_t st = (hipStream_t)stream;
-    std::vector<hipGraphExec_t> execs;
-    int rc = SPDHG_OK;
-    for (int e = 0; e < n_epochs && rc == SPDHG_OK; ++e) {
-        hipGraph_t graph = nullptr;
-        hipError_t err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-        if (err != hipSuccess) {
-            rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
-            break;
-        }
-        const int rc_it = spdhg_iterate(c, c->iters_per_epoch, stream);
-        err = hipStreamEndCapture(st, &graph);
-        if (rc_it != SPDHG_OK) {
-            rc = rc_it;
-        } else if (err != hipSuccess) {
-            rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
-        } else {
-            hipGraphExec_t exec = nullptr;
-            err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (err == hipSuccess) {
-                execs.push_back(exec);
-                err = hipGraphLaunch(exec, st);
-            }
-            if (err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
-        }
-        if (graph) (void)hipGraphDestroy(graph);
+    if (!c->graph) {
+        spdhg_ctx* one[1] = {c};
+        int rc = spdhg_graph_create(one, 1, &c->graph);
+        if (rc) return rc;
     }
-    // the executable graphs are released once the stream has run them
-    const hipError_t err = hipStreamSynchronize(st);
-    for (hipGraphExec_t x : execs) (void)hipGraphExecDestroy(x);
-    if (rc == SPDHG_OK && err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
-    return rc;
+    int rc = spdhg_graph_epoch(c->graph, n_epochs, stream);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return SPDHG_OK;
 }
 
 int spdhg_pdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
@@ -1748,6 +2060,31 @@ int spdhg_set_tuning(spdhg_ctx* c, int32_t fwd_split) {
         fwd_split != 20 && fwd_split != 40)
         return fail(SPDHG_E_ARG, "fwd_split must be 0, 1, 2, 4, 8, 20 or 40");
     c->fwd_split = fwd_split;
+    if (c->graph) {  // its kernels may change: rebuilt on the next graph epoch
+        spdhg_graph_destroy(c->graph);
+        c->graph = nullptr;
+    }
+    return SPDHG_OK;
+}
+
+int spdhg_set_gather(spdhg_ctx* c, int32_t gather) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (gather != 0 && gather != 1 && gather != 2) return fail(SPDHG_E_ARG, "gather must be 0, 1 or 2");
+    if (gather == 1 && !c->bplan_auto.strip)
+        return fail(SPDHG_E_ARG, "the strip gather does not apply to this geometry");
+    c->gather = gather;
+    c->bplan = gather == 2 ? BwdPlan{} : c->bplan_auto;
+    if (c->graph) {  // its kernels change: rebuilt on the next graph epoch
+        spdhg_graph_destroy(c->graph);
+        c->graph = nullptr;
+    }
+    return SPDHG_OK;
+}
+
+int spdhg_get_tuning(const spdhg_ctx* c, int32_t* fwd_split, int32_t* gather) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (fwd_split) *fwd_split = c->fwd_split;
+    if (gather) *gather = c->bplan.strip ? 1 : 2;
     return SPDHG_OK;
 }
 
@@ -1787,10 +2124,40 @@ int spdhg_autotune(spdhg_ctx* c, int32_t* fwd_split, double* ms, void* stream) {
             best = cand[ci];
         }
     }
+    // the gather's tiling: strips of BS_W columns (where they apply) against groups of whole
+    // columns, timed on the subset-0 backprojection of the stale dual change into the
+    // scratch image (the other iterate buffer takes the two-class partial: the next prior
+    // iteration overwrites all of it)
+    int best_gather = c->bplan_auto.strip ? 1 : 2;
+    double bms[2] = {INFINITY, INFINITY};
+    for (int gi = 0; gi < 2 && rc == SPDHG_OK && c->bplan_auto.strip; ++gi) {
+        const BwdPlan plan = gi == 0 ? c->bplan_auto : BwdPlan{};
+        BwdArgs B = c->bwd_args();
+        B.d = c->dscr;
+        B.out = c->scr;
+        if ((rc = launch_bwd<B_PLAIN>(B, a0, step, cnt, st, plan, c->tab.ang.data(), c->xother())))
+            break;  // warm-up
+        hipError_t err = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && rc == SPDHG_OK; ++r)
+            rc = launch_bwd<B_PLAIN>(B, a0, step, cnt, st, plan, c->tab.ang.data(), c->xother());
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+        bms[gi] = t / 3.0;
+    }
+    if (c->bplan_auto.strip && rc == SPDHG_OK) best_gather = bms[1] < bms[0] ? 2 : 1;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     c->fwd_split = best;
+    c->gather = best_gather;
+    c->bplan = best_gather == 2 ? BwdPlan{} : c->bplan_auto;
+    if (c->graph) {
+        spdhg_graph_destroy(c->graph);
+        c->graph = nullptr;
+    }
     if (fwd_split) *fwd_split = best;
     if (ms) *ms = best_ms;
     return SPDHG_OK;
@@ -1807,7 +2174,17 @@ int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32
     }
     if (n == 0 || n_epochs == 0) return SPDHG_OK;
     hipStream_t st = (hipStream_t)stream;
-    if (use_graph && st == nullptr) return fail(SPDHG_E_ARG, "graph batches need a non-default stream");
+    if (use_graph) {
+        // one persistent graph for the n_epochs batch epochs
+        spdhg_graph* G = nullptr;
+        int rc = spdhg_graph_create(ctxs, n, &G);
+        if (rc) return rc;
+        rc = spdhg_graph_epoch(G, n_epochs, stream);
+        const hipError_t err = hipStreamSynchronize(st);
+        spdhg_graph_destroy(G);
+        if (rc == SPDHG_OK && err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
+        return rc;
+    }
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     const int ns = std::max(1, std::min<int>(std::min(n_streams, 8), n));
@@ -1817,28 +2194,16 @@ int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32
     std::vector<hipEvent_t> ev(ns + 1, nullptr);
     for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     int rc = SPDHG_OK;
-    hipGraph_t graph = nullptr;
     hipError_t err = hipSuccess;
-    if (use_graph) err = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     // fork: every worker stream waits for the caller's stream; problem i runs on worker
     // i mod ns (its iterations in order, exactly as a solo run); join back
-    if (err == hipSuccess) err = hipEventRecord(ev[ns], st);
+    err = hipEventRecord(ev[ns], st);
     for (int w = 0; w < ns && err == hipSuccess; ++w) err = hipStreamWaitEvent(pool[w], ev[ns], 0);
     for (int i = 0; i < n && err == hipSuccess && rc == SPDHG_OK; ++i)
         rc = spdhg_iterate(ctxs[i], (int64_t)n_epochs * ctxs[i]->iters_per_epoch, pool[i % ns]);
     for (int w = 0; w < ns && err == hipSuccess; ++w) {
         err = hipEventRecord(ev[w], pool[w]);
         if (err == hipSuccess) err = hipStreamWaitEvent(st, ev[w], 0);
-    }
-    if (use_graph) {
-        const hipError_t e2 = hipStreamEndCapture(st, &graph);
-        if (err == hipSuccess) err = e2;
-        hipGraphExec_t exec = nullptr;
-        if (err == hipSuccess && rc == SPDHG_OK) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (err == hipSuccess && rc == SPDHG_OK) err = hipGraphLaunch(exec, st);
-        if (err == hipSuccess && rc == SPDHG_OK) err = hipStreamSynchronize(st);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc == SPDHG_OK && err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
@@ -1847,6 +2212,7 @@ int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32
 
 int spdhg_destroy(spdhg_ctx* c) {
     if (!c) return SPDHG_OK;
+    if (c->graph) spdhg_graph_destroy(c->graph);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     delete c;
     return SPDHG_OK;

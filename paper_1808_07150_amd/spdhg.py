@@ -12,7 +12,7 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspdhg.so")
-MAX_SEG = 64
+MAX_SEG = 128
 
 SPDHG_OK = 0
 ERRORS = {-1: "SPDHG_E_ARG", -2: "SPDHG_E_SHAPE", -3: "SPDHG_E_DOMAIN", -4: "SPDHG_E_HIP",
@@ -25,8 +25,10 @@ EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_op_workspace_bytes",
             "spdhg_project", "spdhg_project_noalloc", "spdhg_backproject",
             "spdhg_normalised_backprojection", "spdhg_nnz",
             "spdhg_workspace_bytes", "spdhg_init", "spdhg_iterate", "spdhg_epoch",
-            "spdhg_epoch_graph", "spdhg_batch_epoch", "spdhg_pdhg_iterate", "spdhg_em_iterate",
-            "spdhg_set_tuning", "spdhg_autotune", "spdhg_info",
+            "spdhg_epoch_graph", "spdhg_graph_create", "spdhg_graph_epoch",
+            "spdhg_graph_destroy", "spdhg_batch_epoch", "spdhg_pdhg_iterate", "spdhg_em_iterate",
+            "spdhg_set_tuning", "spdhg_autotune", "spdhg_set_gather", "spdhg_get_tuning",
+            "spdhg_info",
             "spdhg_objective", "spdhg_gap", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
             "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
             "spdhg_destroy"]
@@ -45,7 +47,8 @@ class CGeom(ctypes.Structure):
                 ("n_rad", ctypes.c_int32), ("d_rad", ctypes.c_double),
                 ("n_ang", ctypes.c_int32), ("n_seg", ctypes.c_int32),
                 ("seg_planes", ctypes.c_int32 * MAX_SEG),
-                ("seg_tan", ctypes.c_double * MAX_SEG)]
+                ("seg_tan", ctypes.c_double * MAX_SEG),
+                ("seg_pitch", ctypes.c_int32 * MAX_SEG)]
 
 
 class CParams(ctypes.Structure):
@@ -95,8 +98,13 @@ def load_library() -> ctypes.CDLL:
     lib.spdhg_em_iterate.argtypes = [vp, i64, vp]
     lib.spdhg_pdhg_iterate.argtypes = [vp, i64, vp]
     lib.spdhg_batch_epoch.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, vp]
+    lib.spdhg_graph_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    lib.spdhg_graph_epoch.argtypes = [vp, i32, vp]
+    lib.spdhg_graph_destroy.argtypes = [vp]
     lib.spdhg_set_tuning.argtypes = [vp, i32]
     lib.spdhg_autotune.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
+    lib.spdhg_set_gather.argtypes = [vp, i32]
+    lib.spdhg_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.spdhg_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.spdhg_objective.argtypes = [vp, vp, vp, vp]
     lib.spdhg_gap.argtypes = [vp, ctypes.c_double, vp, vp]
@@ -129,9 +137,13 @@ def cgeom(g) -> CGeom:
     s.vx, s.vy, s.vz = g.vx, g.vy, g.vz
     s.n_rad, s.d_rad, s.n_ang = g.n_rad, g.d_rad, g.n_ang
     s.n_seg = len(g.seg_planes)
-    for i, (n, t) in enumerate(zip(g.seg_planes, g.seg_tan)):
+    if s.n_seg > MAX_SEG:
+        raise ValueError(f"at most {MAX_SEG} segments")
+    pitch = getattr(g, "seg_pitch", ()) or (1,) * s.n_seg
+    for i, (n, t, pt) in enumerate(zip(g.seg_planes, g.seg_tan, pitch)):
         s.seg_planes[i] = n
         s.seg_tan[i] = t
+        s.seg_pitch[i] = pt
     return s
 
 
@@ -301,9 +313,19 @@ class Reconstruction:
     def set_tuning(self, fwd_split: int):
         _check(load_library().spdhg_set_tuning(self.ctx, int(fwd_split)))
 
+    def set_gather(self, gather: int):
+        """Gather tiling: 0 automatic, 1 strips of 10 columns, 2 whole columns."""
+        _check(load_library().spdhg_set_gather(self.ctx, int(gather)))
+
+    def tuning(self):
+        """(ray-bundle split, gather tiling) in use."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().spdhg_get_tuning(self.ctx, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
     def autotune(self, stream=None):
-        """Time the ray-bundle splits of the subset projection and keep the fastest;
-        returns (split, ms per launch)."""
+        """Time the ray-bundle splits of the subset projection and the gather tilings of
+        the backprojection and keep the fastest; returns (split, ms per projection)."""
         s, ms = ctypes.c_int32(), ctypes.c_double()
         _check(load_library().spdhg_autotune(self.ctx, ctypes.byref(s), ctypes.byref(ms),
                                              _stream(stream)))
@@ -435,3 +457,39 @@ def batch_epoch(recs, n_epochs: int = 1, n_streams: int = 4, graph: bool = False
     else:
         _check(lib.spdhg_batch_epoch(arr, len(recs), int(n_epochs), int(n_streams), 0,
                                      ctypes.c_void_p(cur.cuda_stream)))
+
+
+class EpochGraph:
+    """Persistent epoch graph (spdhg_graph_create) over Reconstructions of any shapes: one
+    HIP graph, instantiated once; epoch(n) advances every problem n epochs, bitwise as solo
+    spdhg_epoch calls.  Launched on a side stream (the default stream cannot run graphs
+    captured elsewhere) that the current stream then waits for."""
+
+    def __init__(self, recs):
+        lib = load_library()
+        self.recs = list(recs)
+        arr = (ctypes.c_void_p * len(self.recs))(*[r.ctx for r in self.recs])
+        g = ctypes.c_void_p()
+        _check(lib.spdhg_graph_create(arr, len(self.recs), ctypes.byref(g)))
+        self.g = g
+        self.dev = self.recs[0].x.device
+        self.side = torch.cuda.Stream(device=self.dev)
+
+    def epoch(self, n_epochs: int = 1):
+        cur = torch.cuda.current_stream(self.dev)
+        self.side.wait_stream(cur)
+        _check(load_library().spdhg_graph_epoch(self.g, int(n_epochs),
+                                                ctypes.c_void_p(self.side.cuda_stream)))
+        cur.wait_stream(self.side)
+
+    def close(self):
+        if getattr(self, "g", None):
+            torch.cuda.synchronize(self.dev)
+            load_library().spdhg_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

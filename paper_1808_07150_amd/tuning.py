@@ -1,5 +1,7 @@
-"""Ray-bundle tiling choices of the subset projection, found by timing on the GPU
-(spdhg_autotune) and kept in a JSON cache keyed by the problem's shape class."""
+"""Tiling choices of the projector pair (the ray-bundle split of the subset projection:
+primary steps or planes per wavefront; the gather backprojection: strips of columns or
+whole columns), found by timing on the GPU (spdhg_autotune) and kept in a JSON cache keyed
+by the problem's shape class."""
 from __future__ import annotations
 
 import json
@@ -37,8 +39,10 @@ def autotune(recs: Iterable, cache_path: Optional[str] = None) -> Dict[str, dict
         key = shape_key(rec.g, rec.params.n_subsets)
         if key in cache:
             rec.set_tuning(int(cache[key]["fwd_split"]))
+            rec.set_gather(int(cache[key].get("gather", 0)))
         else:
             split, ms = rec.autotune()
-            cache[key] = {"fwd_split": split, "ms_per_projection": round(ms, 4)}
+            cache[key] = {"fwd_split": split, "gather": rec.tuning()[1],
+                          "ms_per_projection": round(ms, 4)}
     save_cache(cache_path, cache)
     return cache

@@ -472,3 +472,92 @@ def test_custom_sampling_parity(P, small3d, prior, split_T):
         assert abs(rec.objective().cpu().numpy()[0] - psi_o) <= 1e-4 * abs(psi_o)
     finally:
         rec.close()
+
+
+def test_objective_failure_flag(P, c1):
+    """The objective's failure flag counts non-finite voxels: 0 for a healthy iterate; a
+    checkpoint whose image carries a NaN and an Inf, loaded back, raises it to 2 (and the
+    objective itself is no longer finite)."""
+    g = c1["geom"]
+    t = {k: dev(c1[k]) for k in ("b", "r", "mult")}
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    rec = P.Reconstruction(g, P.cparams(10, "tv", "balanced", seed=3), t["b"], t["r"],
+                           t["mult"], x)
+    try:
+        rec.epoch(2)
+        out = rec.objective().cpu().numpy()
+        assert out[3] == 0.0 and np.isfinite(out[0])
+        buf = rec.save_state()
+        img = buf[:4 * g.n_vox].view(torch.float32)  # the image is the first array
+        img[5] = float("nan")
+        img[17] = float("inf")
+        rec.load_state(buf)
+        out = rec.objective().cpu().numpy()
+        assert out[3] == 2.0 and not np.isfinite(out[0])
+    finally:
+        rec.close()
+
+
+def test_persistent_graph_mixed_batch(P):
+    """One persistent epoch graph (instantiated once) over problems of different shapes,
+    subset counts and priors (TV, no prior, TGV): three graph epochs, with eager objective
+    evaluations and synchronisations between them, equal solo epochs bitwise; a fourth
+    epoch eager afterwards continues exactly."""
+    probs = _batch_problems()[:4]
+    specs = [(g, m, prior if j != 2 else "tgv", d, seed) for j, (g, m, prior, d, seed)
+             in enumerate(probs)]
+
+    def make(g, m, prior, d, seed):
+        t = {k: dev(d[k]) for k in ("b", "r", "mult")}
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, P.cparams(m, prior, "balanced", alpha=0.05, alpha1=0.025,
+                                            seed=seed), t["b"], t["r"], t["mult"], x)
+        return rec, x
+
+    solo = []
+    for sp in specs:
+        rec, x = make(*sp)
+        rec.epoch(4)
+        torch.cuda.synchronize()
+        solo.append(x.cpu().numpy())
+        rec.close()
+    made = [make(*sp) for sp in specs]
+    graph = P.EpochGraph([r for r, _ in made])
+    try:
+        for _ in range(3):
+            graph.epoch(1)
+            torch.cuda.synchronize()
+            for r, _ in made:
+                _ = r.objective().cpu()
+    finally:
+        graph.close()
+    for (r, x), a in zip(made, solo):
+        r.epoch(1)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(x.cpu().numpy(), a)
+        r.close()
+
+
+@pytest.mark.parametrize("gather", [1, 2])
+def test_gather_tilings_parity(P, tall3d, gather):
+    """Both tilings of the gather backprojection (strips of 10 columns, whole columns)
+    reproduce the oracle's iterates; the autotuner picks one of them."""
+    print(f"[spdhg] tall3d TV gather={gather}", flush=True)
+    g = tall3d["geom"]
+    prob = S.Problem(g, tall3d["b"], tall3d["r"], tall3d["mult"], n_subsets=4, prior="tv",
+                     alpha=0.05, sampling="balanced", precond=True)
+    t = {k: dev(tall3d[k]) for k in ("b", "r", "mult")}
+    x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+    rec = P.Reconstruction(g, P.cparams(4, "tv", "balanced", True, alpha=0.05, seed=19),
+                           t["b"], t["r"], t["mult"], x)
+    try:
+        rec.set_gather(gather)
+        assert rec.tuning()[1] == gather
+        st = S.spdhg(prob, 6 * prob.iters_per_epoch(), seed=19)
+        rec.epoch(6)
+        torch.cuda.synchronize()
+        assert rel(x.cpu().numpy(), prob.reported(st)[0]) <= 1e-3
+        split, ms = rec.autotune()
+        assert rec.tuning() in ((split, 1), (split, 2)) and ms > 0
+    finally:
+        rec.close()
