@@ -554,31 +554,7 @@ __device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, doub
     return t;
 }
 
-// Both taps of z = lane and z = lane + 64 for one (ray, segment) from two loads: plane
-// p - 1 of z = lane (lane_m1 holds lane - 1) and of z = lane + 64 (lane_63 holds
-// lane + 63).  Plane p of each is plane p - 1 of the next-higher lane (a wavefront shift
-// by one lane); for lane 63 of the lower half it is lane 0 of the upper half.  The upper
-// half's lane 63 (z = 127) gets no valid value.
-__device__ __forceinline__ void tap_pair_loads(__amdgpu_buffer_rsrc_t seg, const TapCoef& t,
-                                               int lane_m1, int lane_63, float& b0, float& b1) {
-    b0 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, (lane_m1 + t.off) * 4, 0, 0));
-    b1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(seg, (lane_63 + t.off) * 4, 0, 0));
-}
-
-__device__ __forceinline__ void tap_pair_sum(const TapCoef& t, float b0, float b1, float& h0,
-                                             float& h1) {
-    const int top = __builtin_amdgcn_readlane(__float_as_int(b1), 0);
-    const float a0 = __int_as_float(
-        __builtin_amdgcn_update_dpp(top, __float_as_int(b0), 0x130 /* wave_shl:1 */, 0xF, 0xF, false));
-    const float a1 = __int_as_float(
-        __builtin_amdgcn_update_dpp(0, __float_as_int(b1), 0x130 /* wave_shl:1 */, 0xF, 0xF, false));
-    h0 = __builtin_fmaf(t.wa, a0, h0);
-    h0 = __builtin_fmaf(t.wb, b0, h0);
-    h1 = __builtin_fmaf(t.wa, a1, h1);
-    h1 = __builtin_fmaf(t.wb, b1, h1);
-}
-
-// The same with explicit bounds (per-lane rays).  Pitch 1: voxel z takes plane
+// Per-lane bounds (per-column gather).  Pitch 1: voxel z takes plane
 // p = z + off (weight wa) and p - 1 (wb).  Pitch 2 (a segment on every other image plane):
 // with u = z + off, plane p sits at image plane off_g + 2p + i0 (weight wa) and reaches the
 // next one with weight wb, so voxel z takes one plane, u / 2 with wa if u is even, else
@@ -599,7 +575,7 @@ __device__ __forceinline__ float tap_sum_masked(const float* __restrict__ seg, i
 // Buffer resource over segment g of a dual-change row (raw, byte offsets, range checked).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const GeomDev& G, const float* row,
                                                            int g) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)(row + G.seg_base[g]), (short)0,
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(row + (uint32_t)G.seg_base[g]), (short)0,
                                              G.seg_planes[g] * 4, 0x00020000);
 }
 
@@ -756,21 +732,33 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 #define SEG_CHUNK 11  // segments whose tap tables the strip gather holds at a time
 
 // N consecutive segments of one ray: all 2N loads, then all sums (in segment order).
-// PITCH 1 (consecutive planes): la, lb = lane - 1, lane + 63, and each plane is loaded once,
-// the second tap coming from the next lane (tap_pair_*).  PITCH 2 (planes on every other
-// image plane): la, lb = lane, lane + 64; each voxel takes one plane of the segment,
-// u >> 1 with u = z + off, weighted wa (u even) or wb (u odd), so neighbouring lanes load
-// the same plane.
+// PITCH 1 (consecutive planes): lanes hold z = lane - 1 and z = lane + 63 and load
+// c(z) = d(z + off) of each segment.  With h(z) = sum_g wa_g d(z + off_g) + wb_g d(z - 1 +
+// off_g) = A(z) + B(z - 1), A = sum wa c and B = sum wb c, every lane uses only its own
+// loaded value; the one-voxel shift of B is taken once per ray (ray_sum).  PITCH 2 (planes
+// on every other image plane): la, lb = lane, lane + 64; each voxel takes one plane of
+// the segment, u >> 1 with u = z + off, weighted wa (u even) or wb (u odd), so
+// neighbouring lanes load the same plane; s[0] and s[2] are the two halves' sums.
 template <int N, int PITCH>
 __device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, const TapCoef* tk,
-                                            int g, int la, int lb, float& h0, float& h1) {
+                                            int g, int la, int lb, float (&s)[4]) {
     float v[N][2];
     if constexpr (PITCH == 1) {
 #pragma unroll
-        for (int u = 0; u < N; ++u)
-            tap_pair_loads(seg_rsrc(G, dk, g + u), tk[g + u], la, lb, v[u][0], v[u][1]);
+        for (int u = 0; u < N; ++u) {
+            const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g + u);
+            const int off = tk[g + u].off;
+            v[u][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (la + off) * 4, 0, 0));
+            v[u][1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (lb + off) * 4, 0, 0));
+        }
 #pragma unroll
-        for (int u = 0; u < N; ++u) tap_pair_sum(tk[g + u], v[u][0], v[u][1], h0, h1);
+        for (int u = 0; u < N; ++u) {
+            const TapCoef& t = tk[g + u];
+            s[0] = __builtin_fmaf(t.wa, v[u][0], s[0]);
+            s[1] = __builtin_fmaf(t.wb, v[u][0], s[1]);
+            s[2] = __builtin_fmaf(t.wa, v[u][1], s[2]);
+            s[3] = __builtin_fmaf(t.wb, v[u][1], s[3]);
+        }
     } else {
 #pragma unroll
         for (int u = 0; u < N; ++u) {
@@ -784,13 +772,35 @@ __device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, c
 #pragma unroll
         for (int u = 0; u < N; ++u) {
             const TapCoef& t = tk[g + u];
-            h0 = __builtin_fmaf(((la + t.off) & 1) ? t.wb : t.wa, v[u][0], h0);
-            h1 = __builtin_fmaf(((lb + t.off) & 1) ? t.wb : t.wa, v[u][1], h1);
+            s[0] = __builtin_fmaf(((la + t.off) & 1) ? t.wb : t.wa, v[u][0], s[0]);
+            s[2] = __builtin_fmaf(((lb + t.off) & 1) ? t.wb : t.wa, v[u][1], s[2]);
         }
     }
 }
 
-template <int MODE, int PITCH>
+// The axial gathers of the two halves from the sums of strip_batch.  PITCH 1: h(z) = A(z)
+// + B(z - 1); B(z - 1) is the previous lane's value (wavefront shift right by one lane,
+// checked on the GPU like the left shift), and for the upper half's lane 0 (z = 63) the
+// lower half's lane 63 (z = 62).  The lower half's lane 0 (z = -1) is never written out.
+template <int PITCH>
+__device__ __forceinline__ void ray_sum(const float (&s)[4], float& h0, float& h1) {
+    if constexpr (PITCH == 1) {
+        const int top = __builtin_amdgcn_readlane(__float_as_int(s[1]), 63);
+        const float b0 = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(s[1]), 0x138 /* wave_shr:1 */, 0xF, 0xF, false));
+        const float b1 = __int_as_float(
+            __builtin_amdgcn_update_dpp(top, __float_as_int(s[3]), 0x138 /* wave_shr:1 */, 0xF, 0xF, false));
+        h0 = s[0] + b0;
+        h1 = s[2] + b1;
+    } else {
+        h0 = s[0];
+        h1 = s[2];
+    }
+}
+
+// NS = 11: every launch has exactly 11 segments (span 11), so the segment table's entries
+// are compile-time indices the compiler keeps in scalar registers; NS = 0: any count.
+template <int MODE, int PITCH, int NS>
 // Seven waves per SIMD (at most 72 VGPRs): room for the loads of a whole ray (span 11:
 // 22 values) next to the 20 accumulators, so a ray costs one memory round trip.  A wave's
 // time is set by the latency of its rays, so narrow strips (fewer rays per wave, more
@@ -807,7 +817,7 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
     int* cfirst = (int*)(rfu + KR);           // [BS_W + 1] first ray of cell c (index c + 1)
     int* clast = cfirst + (BS_W + 1);         // [BS_W + 1] last ray of cell c
     TapCoef* tc = (TapCoef*)(clast + (BS_W + 1));  // [KR][sc]: one chunk of segments
-    const int sc = min(ns, SEG_CHUNK);  // the table's entries per ray (host: bwd_plan)
+    const int sc = NS ? NS : min(ns, SEG_CHUNK);  // the table's entries per ray (host: bwd_plan)
 
     const int lane = threadIdx.x;
     const int n_sec = rowdom ? G.nx : G.ny;
@@ -818,9 +828,10 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
     const int sidx = blk / n_prim;
     const int j = blk - sidx * n_prim;
     const int s0 = sidx * BS_W;
-    // the lane offsets of strip_batch (lane - 1 and lane + 63, or lane and lane + 64)
-    // through register copies the compiler cannot fold into an immediate buffer offset
-    // (the hardware range check must see the whole offset)
+    // the lane offsets of strip_batch (lane - 1 and lane + 63, or lane and lane + 64: the
+    // z of the lane's two halves) through register copies the compiler cannot fold into an
+    // immediate buffer offset (the hardware range check must see the whole offset)
+    const int zl = PITCH == 1 ? lane - 1 : lane;
     int lane_a, lane_b;
     asm volatile("v_mov_b32 %0, %1" : "=v"(lane_a) : "v"(PITCH == 1 ? lane - 1 : lane));
     asm volatile("v_mov_b32 %0, %1" : "=v"(lane_b) : "v"(PITCH == 1 ? lane + 63 : lane + 64));
@@ -862,7 +873,7 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
         // tap coefficients of every ray, then the axial gather of the rays of each cell,
         // added to the cell's two columns
         for (int gc = 0; gc < ns; gc += SEG_CHUNK) {
-            const int nsc = min(SEG_CHUNK, ns - gc);
+            const int nsc = NS ? NS : min(SEG_CHUNK, ns - gc);
             __builtin_amdgcn_wave_barrier();  // the previous chunk's taps are consumed
             for (int t = lane; t < nr * nsc; t += 64) {
                 const int kr = t / nsc, gl = t - kr * nsc;
@@ -878,18 +889,24 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rfu[kr])));
                     const float* dk = P.d + dual_row(G, ia, klo + kr);
                     const TapCoef* tk = tc + kr * sc - gc;  // tk[g]: segment g of the chunk
-                    float h0 = 0.0f, h1 = 0.0f;
+                    float sm[4] = {0.0f, 0.0f, 0.0f, 0.0f};
                     // segments in batches of 11, then 4, then 1: every load of a batch is
                     // issued before any tap is summed, so a span-11 ray costs one memory
                     // round trip (batches with per-slot guards lose this overlap)
-                    int g = gc;
-                    const int ge = gc + nsc;
-                    for (; g + 11 <= ge; g += 11)
-                        strip_batch<11, PITCH>(G, dk, tk, g, lane_a, lane_b, h0, h1);
-                    for (; g + 4 <= ge; g += 4)
-                        strip_batch<4, PITCH>(G, dk, tk, g, lane_a, lane_b, h0, h1);
-                    for (; g < ge; ++g)
-                        strip_batch<1, PITCH>(G, dk, tk, g, lane_a, lane_b, h0, h1);
+                    if constexpr (NS == 11) {
+                        strip_batch<11, PITCH>(G, dk, tk, 0, lane_a, lane_b, sm);
+                    } else {
+                        int g = gc;
+                        const int ge = gc + nsc;
+                        for (; g + 11 <= ge; g += 11)
+                            strip_batch<11, PITCH>(G, dk, tk, g, lane_a, lane_b, sm);
+                        for (; g + 4 <= ge; g += 4)
+                            strip_batch<4, PITCH>(G, dk, tk, g, lane_a, lane_b, sm);
+                        for (; g < ge; ++g)
+                            strip_batch<1, PITCH>(G, dk, tk, g, lane_a, lane_b, sm);
+                    }
+                    float h0, h1;
+                    ray_sum<PITCH>(sm, h0, h1);
                     if (c >= 0) {
                         acc[c][0] = __builtin_fmaf(1.0f - fu, h0, acc[c][0]);
                         acc[c][1] = __builtin_fmaf(1.0f - fu, h1, acc[c][1]);
@@ -909,8 +926,8 @@ __global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom
         const int ix = rowdom ? sec : j, iy = rowdom ? j : sec;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
-            const int iz = lane + 64 * hh;
-            if (iz >= nz) continue;
+            const int iz = zl + 64 * hh;
+            if (iz < 0 || iz >= nz) continue;
             const int64_t t = ((int64_t)iy * G.nx + ix) * nz + iz;
             bwd_epilogue(P, MODE, t, acc[c][hh] + (partial ? partial[t] : 0.0f));
         }
