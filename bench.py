@@ -532,7 +532,8 @@ def main():
         log(f"ray-bundle split fixed at {split}")
     else:
         split, split_ms = rec.autotune()
-        log(f"autotuned ray-bundle split: {split} wavefronts ({split_ms:.3f} ms per subset projection)")
+        log(f"autotuned ray-bundle split: {split} wavefronts ({split_ms:.3f} ms per subset "
+            f"projection); gather tiling {rec.tuning()[1]}")
     obj = rec.objective()
     psi0 = float(obj[0].item())
 

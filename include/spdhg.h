@@ -255,9 +255,12 @@ int spdhg_autotune(spdhg_ctx* ctx, int32_t* fwd_split, double* ms, void* stream)
 
 /* Tiling of the gather backprojection: 1 = strips of 10 voxel columns along the secondary
  * axis (for 32 <= nz <= 127, one plane pitch and tap tables within one workgroup's LDS),
- * 2 = groups of whole voxel columns (any geometry), 0 = the automatic choice (strips where
- * they apply).  spdhg_autotune also times both on the subset-0 backprojection and keeps
- * the faster; spdhg_get_tuning reports the split and the gather in use (1 or 2). */
+ * one strip per workgroup; 3 = the same strips, those of four consecutive primary indices
+ * in one workgroup (they read nearly the same rays through one L1); 2 = groups of whole
+ * voxel columns (any geometry); 0 = the automatic choice (strips where they apply).
+ * Tilings 1 and 3 give bitwise identical results.  spdhg_autotune also times each on the
+ * subset-0 backprojection and keeps the fastest; spdhg_get_tuning reports the split and
+ * the gather in use (1, 2 or 3). */
 int spdhg_set_gather(spdhg_ctx* ctx, int32_t gather);
 int spdhg_get_tuning(const spdhg_ctx* ctx, int32_t* fwd_split, int32_t* gather);
 

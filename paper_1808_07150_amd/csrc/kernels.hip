@@ -806,27 +806,37 @@ template <int MODE, int PITCH, int NS>
 // time is set by the latency of its rays, so narrow strips (fewer rays per wave, more
 // waves) finish sooner: at 344 x 344 the 12040 strips take 1.7 rounds of the chip's wave
 // slots where 16-column strips took 1.2 rounds of longer waves.
-__global__ void __launch_bounds__(64, 7) bwd_strip(BwdArgs P, int KR, int rowdom,
+//
+// A workgroup holds wj = blockDim.x / 64 wavefronts (1 or 4), the strips of wj consecutive
+// primary indices at one strip position: they read nearly the same rays, which the
+// workgroup's shared L1 then serves.  Each wavefront has its own LDS tables; there is no
+// workgroup barrier.
+__global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdom,
                                                 const float* __restrict__ partial) {
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
     const int nz = G.nz;
+    const int sc = NS ? NS : min(ns, SEG_CHUNK);  // the table's entries per ray (host: bwd_plan)
     extern __shared__ float smem[];
-    int* ri0 = (int*)smem;                    // [KR] in-plane cell relative to the strip
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    float* wsm = smem + wv * (2 * KR + 2 * (BS_W + 1) + 3 * KR * sc);
+    int* ri0 = (int*)wsm;                     // [KR] in-plane cell relative to the strip
     float* rfu = (float*)(ri0 + KR);          // [KR] in-plane fraction
     int* cfirst = (int*)(rfu + KR);           // [BS_W + 1] first ray of cell c (index c + 1)
     int* clast = cfirst + (BS_W + 1);         // [BS_W + 1] last ray of cell c
     TapCoef* tc = (TapCoef*)(clast + (BS_W + 1));  // [KR][sc]: one chunk of segments
-    const int sc = NS ? NS : min(ns, SEG_CHUNK);  // the table's entries per ray (host: bwd_plan)
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wj = blockDim.x >> 6;
     const int n_sec = rowdom ? G.nx : G.ny;
     const int n_prim = rowdom ? G.ny : G.nx;
     // consecutive blocks (one XCD's share) walk along the primary axis at one strip
     // position: neighbouring strips read nearly the same rays
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int sidx = blk / n_prim;
-    const int j = blk - sidx * n_prim;
+    const int njb = (n_prim + wj - 1) / wj;
+    const int sidx = blk / njb;
+    const int j = (blk - sidx * njb) * wj + wv;
+    if (j >= n_prim) return;
     const int s0 = sidx * BS_W;
     // the lane offsets of strip_batch (lane - 1 and lane + 63, or lane and lane + 64: the
     // z of the lane's two halves) through register copies the compiler cannot fold into an

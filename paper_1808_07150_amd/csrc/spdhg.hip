@@ -390,7 +390,8 @@ struct BwdPlan {
     bool strip = false;
     int KR = 0;
     int pitch = 1;  // the plane pitch every segment shares (the strip kernel's instance)
-    size_t lds = 0;
+    int wj = 1;     // strips of consecutive primary indices per workgroup (1 or 4)
+    size_t lds = 0; // per wavefront
 };
 
 BwdPlan bwd_plan(const HostTables& T) {
@@ -422,24 +423,28 @@ int launch_strip(const BwdArgs& A, int cnt, int ang0, int step, hipStream_t st,
                  const BwdPlan& plan, const AngleDev* host_ang, float* partial) {
     bool has[2] = {false, false};
     for (int i = 0; i < cnt; ++i) has[host_ang[ang0 + i * step].rowdom] = true;
-    const int nstr_r = ((A.G.nx + BS_W - 1) / BS_W) * A.G.ny;  // rows: strips along x
-    const int nstr_c = ((A.G.ny + BS_W - 1) / BS_W) * A.G.nx;  // columns: strips along y
+    const int wj = plan.wj;
+    // rows: strips along x, wj rows per workgroup; columns: strips along y
+    const int nstr_r = ((A.G.nx + BS_W - 1) / BS_W) * ((A.G.ny + wj - 1) / wj);
+    const int nstr_c = ((A.G.ny + BS_W - 1) / BS_W) * ((A.G.nx + wj - 1) / wj);
+    const unsigned nt = 64 * wj;
+    const size_t lds = plan.lds * wj;
     const float* none = nullptr;
     if (has[1] && has[0]) {
         if (MODE == B_ACCUM) {
-            int rc = klaunch(bwd_strip<B_ACCUM, PITCH, NS>, nstr_r, 64, plan.lds, st, A, plan.KR, 1, none);
+            int rc = klaunch(bwd_strip<B_ACCUM, PITCH, NS>, nstr_r, nt, lds, st, A, plan.KR, 1, none);
             if (rc) return rc;
-            return klaunch(bwd_strip<B_ACCUM, PITCH, NS>, nstr_c, 64, plan.lds, st, A, plan.KR, 0, none);
+            return klaunch(bwd_strip<B_ACCUM, PITCH, NS>, nstr_c, nt, lds, st, A, plan.KR, 0, none);
         }
         BwdArgs Pp = A;
         Pp.out = partial;
-        int rc = klaunch(bwd_strip<B_PARTIAL, PITCH, NS>, nstr_r, 64, plan.lds, st, Pp, plan.KR, 1, none);
+        int rc = klaunch(bwd_strip<B_PARTIAL, PITCH, NS>, nstr_r, nt, lds, st, Pp, plan.KR, 1, none);
         if (rc) return rc;
-        return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_c, 64, plan.lds, st, A, plan.KR, 0,
+        return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_c, nt, lds, st, A, plan.KR, 0,
                        (const float*)partial);
     }
-    if (has[1]) return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_r, 64, plan.lds, st, A, plan.KR, 1, none);
-    if (has[0]) return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_c, 64, plan.lds, st, A, plan.KR, 0, none);
+    if (has[1]) return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_r, nt, lds, st, A, plan.KR, 1, none);
+    if (has[0]) return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_c, nt, lds, st, A, plan.KR, 0, none);
     return SPDHG_OK;
 }
 
@@ -2069,13 +2074,31 @@ int spdhg_set_tuning(spdhg_ctx* c, int32_t fwd_split) {
     return SPDHG_OK;
 }
 
+// The backprojection plan of a gather tiling (1: strips, one per workgroup; 3: strips of
+// four consecutive primary indices per workgroup; 2: groups of whole columns); false if
+// the tiling does not apply.
+static bool gather_plan(const spdhg_ctx* c, int gather, BwdPlan& out) {
+    if (gather == 2) {
+        out = BwdPlan{};
+        return true;
+    }
+    if (!c->bplan_auto.strip) return false;
+    out = c->bplan_auto;
+    if (gather == 3) {
+        out.wj = 4;
+        if (out.lds * out.wj > 64 * 1024) return false;
+    }
+    return true;
+}
+
 int spdhg_set_gather(spdhg_ctx* c, int32_t gather) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
-    if (gather != 0 && gather != 1 && gather != 2) return fail(SPDHG_E_ARG, "gather must be 0, 1 or 2");
-    if (gather == 1 && !c->bplan_auto.strip)
+    if (gather < 0 || gather > 3) return fail(SPDHG_E_ARG, "gather must be 0, 1, 2 or 3");
+    BwdPlan plan = c->bplan_auto;
+    if (gather != 0 && !gather_plan(c, gather, plan))
         return fail(SPDHG_E_ARG, "the strip gather does not apply to this geometry");
     c->gather = gather;
-    c->bplan = gather == 2 ? BwdPlan{} : c->bplan_auto;
+    c->bplan = plan;
     if (c->graph) {  // its kernels change: rebuilt on the next graph epoch
         spdhg_graph_destroy(c->graph);
         c->graph = nullptr;
@@ -2086,7 +2109,7 @@ int spdhg_set_gather(spdhg_ctx* c, int32_t gather) {
 int spdhg_get_tuning(const spdhg_ctx* c, int32_t* fwd_split, int32_t* gather) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
     if (fwd_split) *fwd_split = c->fwd_split;
-    if (gather) *gather = c->bplan.strip ? 1 : 2;
+    if (gather) *gather = !c->bplan.strip ? 2 : c->bplan.wj > 1 ? 3 : 1;
     return SPDHG_OK;
 }
 
@@ -2131,9 +2154,11 @@ int spdhg_autotune(spdhg_ctx* c, int32_t* fwd_split, double* ms, void* stream) {
     // scratch image (the other iterate buffer takes the two-class partial: the next prior
     // iteration overwrites all of it)
     int best_gather = c->bplan_auto.strip ? 1 : 2;
-    double bms[2] = {INFINITY, INFINITY};
-    for (int gi = 0; gi < 2 && rc == SPDHG_OK && c->bplan_auto.strip; ++gi) {
-        const BwdPlan plan = gi == 0 ? c->bplan_auto : BwdPlan{};
+    double best_bms = INFINITY;
+    const int gcand[3] = {1, 3, 2};
+    for (int gi = 0; gi < 3 && rc == SPDHG_OK && c->bplan_auto.strip; ++gi) {
+        BwdPlan plan;
+        if (!gather_plan(c, gcand[gi], plan)) continue;
         BwdArgs B = c->bwd_args();
         B.d = c->dscr;
         B.out = c->scr;
@@ -2147,15 +2172,17 @@ int spdhg_autotune(spdhg_ctx* c, int32_t* fwd_split, double* ms, void* stream) {
         float t = 0.f;
         if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
         if (err != hipSuccess) rc = fail(SPDHG_E_HIP, hipGetErrorString(err));
-        bms[gi] = t / 3.0;
+        if (rc == SPDHG_OK && t / 3.0 < best_bms) {
+            best_bms = t / 3.0;
+            best_gather = gcand[gi];
+        }
     }
-    if (c->bplan_auto.strip && rc == SPDHG_OK) best_gather = bms[1] < bms[0] ? 2 : 1;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     c->fwd_split = best;
     c->gather = best_gather;
-    c->bplan = best_gather == 2 ? BwdPlan{} : c->bplan_auto;
+    gather_plan(c, best_gather, c->bplan);
     if (c->graph) {
         spdhg_graph_destroy(c->graph);
         c->graph = nullptr;

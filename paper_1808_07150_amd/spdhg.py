@@ -314,7 +314,8 @@ class Reconstruction:
         _check(load_library().spdhg_set_tuning(self.ctx, int(fwd_split)))
 
     def set_gather(self, gather: int):
-        """Gather tiling: 0 automatic, 1 strips of 10 columns, 2 whole columns."""
+        """Gather tiling: 0 automatic, 1 strips of 10 columns, 2 whole columns, 3 strips
+        of 10 columns at four consecutive primary indices per workgroup."""
         _check(load_library().spdhg_set_gather(self.ctx, int(gather)))
 
     def tuning(self):

@@ -538,10 +538,11 @@ def test_persistent_graph_mixed_batch(P):
         r.close()
 
 
-@pytest.mark.parametrize("gather", [1, 2])
+@pytest.mark.parametrize("gather", [1, 2, 3])
 def test_gather_tilings_parity(P, tall3d, gather):
-    """Both tilings of the gather backprojection (strips of 10 columns, whole columns)
-    reproduce the oracle's iterates; the autotuner picks one of them."""
+    """Every tiling of the gather backprojection (strips of 10 columns, one or four
+    primary indices per workgroup (13 rows: a ragged last group), whole columns)
+    reproduces the oracle's iterates; the autotuner picks one of them."""
     print(f"[spdhg] tall3d TV gather={gather}", flush=True)
     g = tall3d["geom"]
     prob = S.Problem(g, tall3d["b"], tall3d["r"], tall3d["mult"], n_subsets=4, prior="tv",
@@ -558,6 +559,27 @@ def test_gather_tilings_parity(P, tall3d, gather):
         torch.cuda.synchronize()
         assert rel(x.cpu().numpy(), prob.reported(st)[0]) <= 1e-3
         split, ms = rec.autotune()
-        assert rec.tuning() in ((split, 1), (split, 2)) and ms > 0
+        assert rec.tuning() in ((split, 1), (split, 2), (split, 3)) and ms > 0
     finally:
         rec.close()
+
+
+def test_strip_workgroup_rows_bitwise(P, tall3d):
+    """Strips grouped four primary indices to a workgroup compute exactly what one strip
+    per workgroup computes (same arithmetic per strip): iterates bitwise equal."""
+    g = tall3d["geom"]
+    t = {k: dev(tall3d[k]) for k in ("b", "r", "mult")}
+    out = []
+    for gather in (1, 3):
+        print(f"[spdhg] tall3d TV strips, gather={gather}", flush=True)
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, P.cparams(4, "tv", "balanced", True, alpha=0.05, seed=5),
+                               t["b"], t["r"], t["mult"], x)
+        try:
+            rec.set_gather(gather)
+            rec.epoch(3)
+            torch.cuda.synchronize()
+            out.append(x.cpu().numpy())
+        finally:
+            rec.close()
+    np.testing.assert_array_equal(out[0], out[1])
