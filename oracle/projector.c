@@ -16,6 +16,11 @@
  *                    z_p = (p - (N_g-1)/2) pitch_g vz  (pitch_g = 1, or 2 for ring pairs),
  *   points           (s cos phi - t sin phi,  s sin phi + t cos phi,  z_p + tau_g t).
  *
+ * Scanner model (a ring of radius R): with `nonarc` the radial bins are equal steps of
+ * the angle on the ring, s = R sin((k - (n_rad-1)/2) d_rad / R); with `oblique_s` a line
+ * of response between two rings spans the chord 2 sqrt(R^2 - s^2) between its detectors,
+ * so its slope is tau_g R / sqrt(R^2 - s^2) (tau_g: the slope at s = 0).
+ *
  * If |cos phi| >= |sin phi| (decided by the integer test 4a <= n_ang or 4a >= 3 n_ang,
  * ties go to rows) the ray is sampled at every image row y_j; otherwise at every column
  * x_i.  At each sample the image slice is interpolated bilinearly in the two remaining
@@ -48,6 +53,9 @@ typedef struct {
     int32_t seg_pitch[ORC_MAX_SEG]; /* axial spacing of the segment's planes in image planes
                                      * (0 or 1: every plane; 2: every other plane, the ring
                                      * pairs of span 1 with a ring pitch of two planes) */
+    double det_radius;              /* scanner model: detector ring radius R (mm) */
+    int32_t nonarc;                 /* radial bins at R sin(...) instead of equal steps */
+    int32_t oblique_s;              /* slope tau_g R / sqrt(R^2 - s^2) */
 } orc_geom;
 
 static int32_t n_planes(const orc_geom* G) {
@@ -76,15 +84,31 @@ typedef struct {
     double u, w;
 } sample_t;
 
+/* Radial position (mm) of bin k. */
+static double radial_pos(const orc_geom* G, int32_t k) {
+    double t = ((double)k - 0.5 * (G->n_rad - 1)) * G->d_rad;
+    return G->nonarc ? G->det_radius * sin(t / G->det_radius) : t;
+}
+
+/* Axial slope of the rays of segment g in radial bin k. */
+static double ray_slope(const orc_geom* G, int32_t g, int32_t k) {
+    double tau = G->seg_tan[g];
+    if (G->oblique_s) {
+        double r = radial_pos(G, k), R = G->det_radius;
+        tau *= R / sqrt(R * R - r * r);
+    }
+    return tau;
+}
+
 static sample_t ray_sample(const orc_geom* G, int32_t a, int32_t p, int32_t g,
                            int32_t k, int32_t prim) {
     double phi = M_PI * (double)a / (double)G->n_ang;
     double c = cos(phi), s = sin(phi);
-    double r = ((double)k - 0.5 * (G->n_rad - 1)) * G->d_rad;
+    double r = radial_pos(G, k);
     int32_t Ng = G->seg_planes[g];
     int32_t pitch = G->seg_pitch[g] > 1 ? G->seg_pitch[g] : 1;
     double zp = ((double)p - 0.5 * (Ng - 1)) * pitch * G->vz;
-    double tau = G->seg_tan[g];
+    double tau = ray_slope(G, g, k);
     sample_t out;
     if (row_dominant(G, a)) {
         double Y = ((double)prim - 0.5 * (G->ny - 1)) * G->vy;
@@ -104,9 +128,9 @@ static sample_t ray_sample(const orc_geom* G, int32_t a, int32_t p, int32_t g,
     return out;
 }
 
-static double step_length(const orc_geom* G, int32_t a, int32_t g) {
+static double step_length(const orc_geom* G, int32_t a, int32_t g, int32_t k) {
     double phi = M_PI * (double)a / (double)G->n_ang;
-    double tau = G->seg_tan[g];
+    double tau = ray_slope(G, g, k);
     if (row_dominant(G, a)) return G->vy / fabs(cos(phi)) * sqrt(1.0 + tau * tau);
     return G->vx / fabs(sin(phi)) * sqrt(1.0 + tau * tau);
 }
@@ -150,7 +174,7 @@ static double ray_sum(const orc_geom* G, const double* img, int32_t a, int32_t q
         acc += (1 - fu) * (1 - fw) * v00 + fu * (1 - fw) * v10 + (1 - fu) * fw * v01 +
                fu * fw * v11;
     }
-    return acc * step_length(G, a, g);
+    return acc * step_length(G, a, g, k);
 }
 
 /* out[ia][q][k] = (G img)[angles[ia]][q][k]: the rows of the listed angles, packed. */
@@ -190,11 +214,10 @@ void orc_backward(const orc_geom* G, const int32_t* angles, int32_t n_angles,
             for (int32_t q = 0; q < np_; q++) {
                 int32_t g, p;
                 plane_seg(G, q, &g, &p);
-                double L = step_length(G, a, g);
                 for (int32_t k = 0; k < G->n_rad; k++) {
                     double val = y[ia * per_angle + (int64_t)q * G->n_rad + k];
                     if (val == 0.0) continue;
-                    val *= L;
+                    val *= step_length(G, a, g, k);
                     sample_t sm = ray_sample(G, a, p, g, k, j);
                     double u0 = floor(sm.u), w0 = floor(sm.w);
                     double fu = sm.u - u0, fw = sm.w - w0;

@@ -4,6 +4,10 @@
 [len(angles)][plane][radial]; ``backward(geom, y, angles)`` takes y packed the same way
 and returns the image G^T y.  ``angles=None`` means all angles in order.  The operator of
 the paper is A = diag(mult) G; the multiplicative factors are applied by the callers.
+
+With span compression (the scanner model's data planes, see ``compression``) G = C G1:
+G1 projects every ring pair (the C projector's planes) and C sums the ring pairs of each
+data plane; G^T = G1^T C^T.
 """
 from __future__ import annotations
 
@@ -27,7 +31,9 @@ class _Geom(ctypes.Structure):
                 ("n_ang", ctypes.c_int32), ("n_seg", ctypes.c_int32),
                 ("seg_planes", ctypes.c_int32 * MAX_SEG),
                 ("seg_tan", ctypes.c_double * MAX_SEG),
-                ("seg_pitch", ctypes.c_int32 * MAX_SEG)]
+                ("seg_pitch", ctypes.c_int32 * MAX_SEG),
+                ("det_radius", ctypes.c_double), ("nonarc", ctypes.c_int32),
+                ("oblique_s", ctypes.c_int32)]
 
 
 def build(force: bool = False) -> str:
@@ -76,7 +82,76 @@ def _geom(g) -> _Geom:
         s.seg_planes[i] = n
         s.seg_tan[i] = t
         s.seg_pitch[i] = pt
+    s.det_radius = getattr(g, "det_radius", 0.0)
+    s.nonarc = int(bool(getattr(g, "nonarc", False)))
+    s.oblique_s = int(bool(getattr(g, "oblique_s", False)))
     return s
+
+
+def _order(d: int) -> int:
+    """Position of ring difference (or data segment) d in the order 0, +1, -1, +2, -2, ..."""
+    return 0 if d == 0 else (2 * d - 1 if d > 0 else -2 * d)
+
+
+def compression(g):
+    """(map, data plane counts) of span compression, or None without it.
+
+    Built from the ring pairs (r1, r2) of rings = (nz + 1) / 2 rings: the pair's ring-pair
+    plane is plane min(r1, r2) of the segment of ring difference d = r2 - r1; its data
+    segment is G = round(|d| / span) with the sign of d (|d| <= (span-1)/2: segment 0),
+    and within that segment its plane is the ring sum r1 + r2 minus the segment's smallest
+    ring sum, G span - (span-1)/2 (0 for segment 0).  map[q] is the data plane of ring-pair
+    plane q."""
+    span = getattr(g, "span", 0)
+    if not span:
+        return None
+    rings = (g.nz + 1) // 2
+    h = (span - 1) // 2
+    dmax = max(((i + 1) // 2) for i in range(g.n_seg))
+    seg_start = np.concatenate([[0], np.cumsum(g.seg_planes)[:-1]])
+    pairs = []  # (ring-pair plane, data segment order, local data plane)
+    for r1 in range(rings):
+        for r2 in range(rings):
+            d = r2 - r1
+            if abs(d) > dmax:
+                continue
+            q = seg_start[_order(d)] + min(r1, r2)
+            grp = (abs(d) + h) // span
+            smin = 0 if grp == 0 else grp * span - h
+            pairs.append((q, _order(grp if d >= 0 else -grp), r1 + r2 - smin))
+    n_dseg = max(p[1] for p in pairs) + 1
+    counts = np.zeros(n_dseg, dtype=np.int64)
+    for _, ds, loc in pairs:
+        counts[ds] = max(counts[ds], loc + 1)
+    dstart = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    m = np.full(g.n_planes, -1, dtype=np.int64)
+    for q, ds, loc in pairs:
+        m[q] = dstart[ds] + loc
+    if (m < 0).any():
+        raise ValueError("ring-pair planes without a ring pair")
+    return m, counts
+
+
+def n_data_planes(g) -> int:
+    c = compression(g)
+    return g.n_planes if c is None else int(c[1].sum())
+
+
+def compress(g, y1: np.ndarray) -> np.ndarray:
+    """C y1: ring-pair rows [..][ring-pair plane][radial] -> data rows (sums)."""
+    c = compression(g)
+    if c is None:
+        return y1
+    m, counts = c
+    out = np.zeros(y1.shape[:-2] + (int(counts.sum()), y1.shape[-1]), dtype=y1.dtype)
+    np.add.at(out, (Ellipsis, m, slice(None)), y1)
+    return out
+
+
+def expand(g, y: np.ndarray) -> np.ndarray:
+    """C^T y: data rows -> ring-pair rows (each ring pair takes its data plane's value)."""
+    c = compression(g)
+    return y if c is None else y[..., c[0], :]
 
 
 def _dptr(a: np.ndarray):
@@ -90,7 +165,7 @@ def _angles(g, angles: Optional[Iterable[int]]):
 
 
 def forward(g, x: np.ndarray, angles=None) -> np.ndarray:
-    """Rows of G x for the listed angles, packed [len(angles)][plane][radial]."""
+    """Rows of G x for the listed angles, packed [len(angles)][data plane][radial]."""
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(g.image_shape)
     ang = _angles(g, angles)
@@ -98,14 +173,15 @@ def forward(g, x: np.ndarray, angles=None) -> np.ndarray:
     gs = _geom(g)
     lib.orc_forward(ctypes.byref(gs), ang.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                     len(ang), _dptr(x), _dptr(out))
-    return out
+    return compress(g, out)
 
 
 def backward(g, y: np.ndarray, angles=None) -> np.ndarray:
-    """G^T y for y packed [len(angles)][plane][radial] over the listed angles."""
+    """G^T y for y packed [len(angles)][data plane][radial] over the listed angles."""
     lib = _load()
     ang = _angles(g, angles)
-    y = np.ascontiguousarray(y, dtype=np.float64).reshape(len(ang), g.n_planes, g.n_rad)
+    y = np.asarray(y, dtype=np.float64).reshape(len(ang), n_data_planes(g), g.n_rad)
+    y = np.ascontiguousarray(expand(g, y))
     out = np.zeros(g.image_shape, dtype=np.float64)
     gs = _geom(g)
     lib.orc_backward(ctypes.byref(gs), ang.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -114,8 +190,13 @@ def backward(g, y: np.ndarray, angles=None) -> np.ndarray:
 
 
 def ray(g, x: np.ndarray, a: int, q: int, k: int) -> float:
-    """Single ray sum (G x)[a, q, k]."""
+    """Single data bin (G x)[a, q, k]: the ray sum, or with span compression the sum of the
+    ray sums of the data plane's ring pairs."""
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(g.image_shape)
     gs = _geom(g)
-    return lib.orc_ray(ctypes.byref(gs), _dptr(x), a, q, k)
+    c = compression(g)
+    if c is None:
+        return lib.orc_ray(ctypes.byref(gs), _dptr(x), a, q, k)
+    return float(sum(lib.orc_ray(ctypes.byref(gs), _dptr(x), a, int(q1), k)
+                     for q1 in np.nonzero(c[0] == q)[0]))

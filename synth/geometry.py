@@ -12,6 +12,20 @@ everywhere in this repository is a parallel-beam, ray-driven Joseph model:
   (``pitch_g`` = 1, or 2 for the ring pairs of span 1, whose ring pitch is two image
   planes) and a constant axial slope ``tau_g`` (dz per mm of in-plane path);
 * sinogram stored ``[angle][plane][radial]``, planes ordered by segment 0, +1, -1, +2, -2 ...
+
+Scanner model (optional, the closer model of a ring scanner with detector radius ``R``):
+
+* ``nonarc``: radial bins are not arc-corrected; bin ``k`` sits at
+  ``s_k = R sin((k - (n_rad-1)/2) d_rad / R)`` (equal steps of the angle on the ring);
+* ``oblique_s``: a line of response between two rings at radial position ``s`` spans the
+  chord ``2 sqrt(R^2 - s^2)``, so its axial slope is ``tau_g R / sqrt(R^2 - s^2)`` rather
+  than the constant ``tau_g``;
+* ``span`` (odd, >= 3; 0 = off): the data planes are sums of the projector's ring-pair
+  planes (segments of single ring differences ``d = 0, +1, -1, ...`` at pitch 2): ring
+  differences ``|d| <= (span-1)/2`` form data segment 0, ``d`` in ``+-[g span - (span-1)/2,
+  g span + (span-1)/2]`` data segment ``+-g``, and within a data segment the ring pairs
+  with the same ring sum form one plane (the axial compression of PET scanners);
+* detector gaps are bins of zero efficiency, i.e. zeros of ``mult`` (see ``synth.gaps``).
 """
 from __future__ import annotations
 
@@ -34,6 +48,10 @@ class Geometry:
     seg_planes: Tuple[int, ...] = (1,)
     seg_tan: Tuple[float, ...] = (0.0,)
     seg_pitch: Tuple[int, ...] = ()  # empty: every segment has pitch 1
+    det_radius: float = 0.0  # detector ring radius R (mm) of the scanner model
+    nonarc: bool = False     # radial bins at R sin((k - c) d_rad / R)
+    oblique_s: bool = False  # axial slope tau_g R / sqrt(R^2 - s^2)
+    span: int = 0            # data planes: 0 the projector's; odd >= 3 ring-sum compression
 
     def __post_init__(self):
         if len(self.seg_planes) != len(self.seg_tan):
@@ -45,6 +63,22 @@ class Geometry:
             if pt not in (1, 2) or n <= 0 or span > self.nz or (self.nz - span) % 2:
                 raise ValueError(f"segment of {n} planes at pitch {pt} incompatible with "
                                  f"nz={self.nz}")
+        if self.nonarc or self.oblique_s:
+            if not self.det_radius > 0:
+                raise ValueError("the scanner model needs det_radius > 0")
+            half = 0.5 * (self.n_rad - 1) * self.d_rad
+            if (self.nonarc and half / self.det_radius >= 0.5 * math.pi) or \
+                    (not self.nonarc and half >= self.det_radius):
+                raise ValueError("radial bins beyond the detector ring")
+        if self.span:
+            if self.span < 3 or self.span % 2 == 0:
+                raise ValueError("span must be odd and >= 3")
+            rings = self.seg_planes[0]
+            if self.nz != 2 * rings - 1:
+                raise ValueError("span compression needs nz = 2 rings - 1")
+            for n, pt, d in zip(self.seg_planes, self.pitches, self.ring_diffs):
+                if pt != 2 or n != rings - abs(d):
+                    raise ValueError("span compression needs ring-pair segments 0, +1, -1, ...")
 
     @property
     def pitches(self) -> Tuple[int, ...]:
@@ -59,12 +93,37 @@ class Geometry:
         return int(sum(self.seg_planes))
 
     @property
+    def ring_diffs(self) -> Tuple[int, ...]:
+        """Ring difference of each segment in the order 0, +1, -1, +2, -2, ..."""
+        return tuple(((i + 1) // 2) * (1 if i % 2 else -1) if i else 0
+                     for i in range(self.n_seg))
+
+    @property
+    def data_seg_planes(self) -> Tuple[int, ...]:
+        """Plane counts of the data segments (the projector's segments when span is 0)."""
+        if not self.span:
+            return tuple(self.seg_planes)
+        h = (self.span - 1) // 2
+        dmax = max(abs(d) for d in self.ring_diffs)
+        out = [self.nz]  # data segment 0: every ring sum 0 .. 2 (rings - 1)
+        g = 1
+        while g * self.span - h <= dmax:
+            n = self.nz - 2 * (g * self.span - h)
+            out += [n, n]
+            g += 1
+        return tuple(out)
+
+    @property
+    def n_data_planes(self) -> int:
+        return int(sum(self.data_seg_planes))
+
+    @property
     def image_shape(self) -> Tuple[int, int, int]:
         return (self.nz, self.ny, self.nx)
 
     @property
     def sino_shape(self) -> Tuple[int, int, int]:
-        return (self.n_ang, self.n_planes, self.n_rad)
+        return (self.n_ang, self.n_data_planes, self.n_rad)
 
     @property
     def n_vox(self) -> int:
@@ -72,7 +131,7 @@ class Geometry:
 
     @property
     def n_bins(self) -> int:
-        return self.n_ang * self.n_planes * self.n_rad
+        return self.n_ang * self.n_data_planes * self.n_rad
 
     def plane_segment(self, q: int) -> Tuple[int, int]:
         """Return (segment, local plane index) of sinogram plane q."""
@@ -166,6 +225,30 @@ def slab_span1(rings: int = 8, max_ring_diff: int = 7, nxy: int = 344, v: float 
     planes, tans, pitch = span1_segments(rings, max_ring_diff, v)
     return Geometry(nx=nxy, ny=nxy, nz=2 * rings - 1, vx=v, vy=v, vz=v, n_rad=nxy, d_rad=v,
                     n_ang=n_ang, seg_planes=planes, seg_tan=tans, seg_pitch=pitch)
+
+
+def mmr_scanner(rings: int = 64, max_ring_diff: int = 60, span: int = 11, n_rad: int = 344,
+                n_ang: int = 252, nxy: int = 344, vxy: float = 2.08, vz: float = 2.08,
+                det_radius: float = 328.0) -> Geometry:
+    """mMR-shaped closer scanner model: the span-11 data (344 x 252 x 837) as sums of the
+    4084 ring-pair planes of 64 rings (ring differences up to 60), non-arc-corrected radial
+    bins and s-dependent obliquity on a 328 mm detector ring; image 344 x 344 x 127."""
+    planes, tans, pitch = span1_segments(rings, max_ring_diff, vz, det_radius)
+    return Geometry(nx=nxy, ny=nxy, nz=2 * rings - 1, vx=vxy, vy=vxy, vz=vz,
+                    n_rad=n_rad, d_rad=vxy, n_ang=n_ang, seg_planes=planes, seg_tan=tans,
+                    seg_pitch=pitch, det_radius=det_radius, nonarc=True, oblique_s=True,
+                    span=span)
+
+
+def scanner_small(rings: int = 8, max_ring_diff: int = 7, span: int = 3, nxy: int = 24,
+                  n_rad: int = 26, n_ang: int = 12, v: float = 4.0,
+                  det_radius: float = 60.0) -> Geometry:
+    """Small scanner-model geometry with strong effects: a 60 mm ring (radial bins up to
+    50 mm from the axis, s-dependent slopes up to 2.4 times the central one), span 3."""
+    planes, tans, pitch = span1_segments(rings, max_ring_diff, v, det_radius)
+    return Geometry(nx=nxy, ny=nxy, nz=2 * rings - 1, vx=v, vy=v, vz=v, n_rad=n_rad,
+                    d_rad=v, n_ang=n_ang, seg_planes=planes, seg_tan=tans, seg_pitch=pitch,
+                    det_radius=det_radius, nonarc=True, oblique_s=True, span=span)
 
 
 def slab(nz: int, nxy: int = 344, v: float = 2.08) -> Geometry:

@@ -34,22 +34,54 @@ class Ellipsoid:
     value: float
 
 
+def radial_positions(g: Geometry) -> np.ndarray:
+    """Radial position (mm) of every bin: equal steps, or with the scanner model's
+    non-arc-corrected sampling R sin((k - c) d_rad / R)."""
+    t = (np.arange(g.n_rad) - 0.5 * (g.n_rad - 1)) * g.d_rad
+    return g.det_radius * np.sin(t / g.det_radius) if g.nonarc else t
+
+
+def lor_data_plane(g: Geometry) -> np.ndarray:
+    """Data plane of every projector plane: the identity, or with span compression the
+    plane of the ring pair's data segment and ring sum."""
+    if not g.span:
+        return np.arange(g.n_planes)
+    h = (g.span - 1) // 2
+    counts = g.data_seg_planes
+    base = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    out = []
+    for n, d in zip(g.seg_planes, g.ring_diffs):
+        grp = (abs(d) + h) // g.span
+        seg = 0 if grp == 0 else (2 * grp - 1 if d > 0 else 2 * grp)
+        smin = 0 if grp == 0 else grp * g.span - h
+        ring_sum = 2 * np.arange(n) + abs(d)
+        out.append(base[seg] + ring_sum - smin)
+    return np.concatenate(out)
+
+
+def _ray_slopes(g: Geometry, r: np.ndarray) -> np.ndarray:
+    """Axial slope of every projector plane (rows) at radial positions r (columns)."""
+    tau = np.concatenate([np.full(n, t) for n, t in zip(g.seg_planes, g.seg_tan)])[:, None]
+    if g.oblique_s:
+        tau = tau * (g.det_radius / np.sqrt(g.det_radius ** 2 - r ** 2))[None, :]
+    return np.broadcast_to(tau, (g.n_planes, g.n_rad))
+
+
 def _ray_params(g: Geometry, a: int):
-    """Per-ray start points and direction for angle a (all planes x radial bins)."""
+    """Per-ray start points and direction for angle a (all projector planes x radial
+    bins)."""
     phi = math.pi * a / g.n_ang
     c, s = math.cos(phi), math.sin(phi)
-    r = (np.arange(g.n_rad) - 0.5 * (g.n_rad - 1)) * g.d_rad
-    zp, tau = [], []
-    for n, t, pt in zip(g.seg_planes, g.seg_tan, g.pitches):
+    r = radial_positions(g)
+    zp = []
+    for n, pt in zip(g.seg_planes, g.pitches):
         zp.append((np.arange(n) - 0.5 * (n - 1)) * pt * g.vz)
-        tau.append(np.full(n, t))
     zp = np.concatenate(zp)[:, None]
-    tau = np.concatenate(tau)[:, None]
     px = np.broadcast_to(r * c, (g.n_planes, g.n_rad))
     py = np.broadcast_to(r * s, (g.n_planes, g.n_rad))
     pz = np.broadcast_to(zp, (g.n_planes, g.n_rad))
     dx, dy = -s, c
-    dz = np.broadcast_to(tau, (g.n_planes, g.n_rad))
+    dz = _ray_slopes(g, r)
     return px, py, pz, dx, dy, dz
 
 
@@ -75,12 +107,19 @@ def chord_lengths(g: Geometry, a: int, e: Ellipsoid) -> np.ndarray:
     return dt * np.sqrt(1.0 + dz * dz)
 
 
-def line_integrals(g: Geometry, ells: List[Ellipsoid]) -> np.ndarray:
+def line_integrals(g: Geometry, ells: List[Ellipsoid], mean: bool = False) -> np.ndarray:
+    """Line integrals of the phantom per data bin: with span compression the sum over the
+    bin's lines of response (or, with mean, their average)."""
     out = np.zeros(g.sino_shape, dtype=np.float64)
+    dp = lor_data_plane(g)
+    cnt = np.bincount(dp, minlength=g.n_data_planes).astype(np.float64)[:, None]
     for a in range(g.n_ang):
-        acc = out[a]
+        acc = np.zeros((g.n_planes, g.n_rad))
         for e in ells:
             acc += e.value * chord_lengths(g, a, e)
+        np.add.at(out[a], dp, acc)
+        if mean:
+            out[a] /= cnt
     return out
 
 
@@ -199,7 +238,8 @@ def make_data(g: Geometry, seed: int, counts: float, act, att,
     The activity is scaled so that the expected total count equals `counts`."""
     rng = np.random.Generator(np.random.PCG64(seed))
     norm = rng.uniform(0.8, 1.2, size=g.sino_shape)
-    att_int = line_integrals(g, att)
+    # attenuation of a compressed bin: that of its mean line of response
+    att_int = line_integrals(g, att, mean=True)
     mult = norm * np.exp(-att_int)
     geo = line_integrals(g, act)
     trues = mult * geo
@@ -247,11 +287,18 @@ def side_image(rng, g: Geometry, labels, noise: float = 0.05) -> np.ndarray:
     return img.astype(np.float32)
 
 
-def brain_problem(g: Geometry, seed: int, counts: float, with_side: bool = False):
-    """Brain-like 3-D problem with randoms + scatter at 30% of trues."""
+def brain_problem(g: Geometry, seed: int, counts: float, with_side: bool = False,
+                  gaps: bool = False):
+    """Brain-like 3-D problem with randoms + scatter at 30% of trues; with gaps, the bins
+    of gap detectors (synth.gaps) have zero efficiency, background and counts."""
     rng = np.random.Generator(np.random.PCG64(seed))
     act, att, labels = phantom_brain(rng, g)
     d = make_data(g, seed + 1, counts, act, att, "rs30")
+    if gaps:
+        from .gaps import gap_mask
+        mk = gap_mask(g)[:, None, :].astype(np.float32)
+        for key in ("b", "r", "mult"):
+            d[key] = d[key] * mk
     d["x_true"] = (d["scale"] * voxelise(g, act, supersample=1)).astype(np.float32)
     d["geom"] = g
     if with_side:
@@ -267,12 +314,11 @@ def _torch_chords(torch, g: Geometry, angles, e: Ellipsoid, device):
     a = torch.as_tensor(angles, dtype=f64, device=device)[:, None, None]
     phi = math.pi * a / g.n_ang
     c, s = torch.cos(phi), torch.sin(phi)
-    r = ((torch.arange(g.n_rad, dtype=f64, device=device) - 0.5 * (g.n_rad - 1))
-         * g.d_rad)[None, None, :]
+    r = torch.as_tensor(radial_positions(g), dtype=f64, device=device)[None, None, :]
     zp = torch.cat([(torch.arange(n, dtype=f64, device=device) - 0.5 * (n - 1)) * pt * g.vz
                     for n, pt in zip(g.seg_planes, g.pitches)])[None, :, None]
-    tau = torch.cat([torch.full((n,), t, dtype=f64, device=device)
-                     for n, t in zip(g.seg_planes, g.seg_tan)])[None, :, None]
+    tau = torch.as_tensor(np.ascontiguousarray(_ray_slopes(g, radial_positions(g))),
+                          dtype=f64, device=device)[None, :, :]
     ct, st = math.cos(e.theta), math.sin(e.theta)
     ox, oy, oz = r * c - e.cx, r * s - e.cy, zp - e.cz
     ux, uy, uz = ct * ox + st * oy, -st * ox + ct * oy, oz
@@ -289,20 +335,28 @@ def _torch_chords(torch, g: Geometry, angles, e: Ellipsoid, device):
     return dt * torch.sqrt(1.0 + tau * tau)
 
 
-def line_integrals_torch(g: Geometry, ells, device, batch: int = 12):
+def line_integrals_torch(g: Geometry, ells, device, batch: int = 12, mean: bool = False):
+    """line_integrals on a torch device (FP64)."""
     import torch
-    out = torch.empty(g.sino_shape, dtype=torch.float64, device=device)
+    out = torch.zeros(g.sino_shape, dtype=torch.float64, device=device)
+    dp = torch.as_tensor(lor_data_plane(g), device=device)
+    cnt = torch.bincount(dp, minlength=g.n_data_planes).to(torch.float64)[None, :, None]
     for a0 in range(0, g.n_ang, batch):
         ang = list(range(a0, min(a0 + batch, g.n_ang)))
         acc = torch.zeros((len(ang), g.n_planes, g.n_rad), dtype=torch.float64, device=device)
         for e in ells:
             acc += e.value * _torch_chords(torch, g, ang, e, device)
+        if g.span:
+            red = torch.zeros((len(ang), g.n_data_planes, g.n_rad), dtype=torch.float64,
+                              device=device)
+            red.index_add_(1, dp, acc)
+            acc = red / cnt if mean else red
         out[a0:a0 + len(ang)] = acc
     return out
 
 
 def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side=False,
-                        host_poisson=False):
+                        host_poisson=False, gaps=False):
     """The brain-like 3-D problem generated on a torch device (float32 outputs): same
     phantom parameters as brain_problem, analytic data in FP64, randoms + scatter at 30%
     of trues, normalisation U(0.8, 1.2), Poisson counts (torch generator seeded, or with
@@ -313,7 +367,7 @@ def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side
     gen = torch.Generator(device=device)
     gen.manual_seed(seed + 1)
     norm = torch.rand(g.sino_shape, generator=gen, device=device, dtype=torch.float64) * 0.4 + 0.8
-    mult = norm * torch.exp(-line_integrals_torch(g, att, device))
+    mult = norm * torch.exp(-line_integrals_torch(g, att, device, mean=True))
     del norm
     trues = mult * line_integrals_torch(g, act, device)
     sigma = 50.0 / g.d_rad
@@ -345,6 +399,11 @@ def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side
     del ybar, trues
     d = dict(b=b, r=(scale * rshape).to(torch.float32), mult=mult.to(torch.float32),
              scale=float(scale), geom=g, ellipsoids=act)
+    if gaps:
+        from .gaps import gap_mask
+        mk = torch.as_tensor(gap_mask(g), dtype=torch.float32, device=device)[:, None, :]
+        for key in ("b", "r", "mult"):
+            d[key] = d[key] * mk
     if with_side:
         d["side"] = torch.from_numpy(
             side_image(np.random.Generator(np.random.PCG64(seed + 2)), g, labels)).to(device)

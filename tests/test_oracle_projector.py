@@ -2,6 +2,7 @@
 analytic line integrals of ellipses/ellipsoids, exact chord lengths, the 90-degree
 rotation covariance of the parallel-beam model, column sums at phi = 0, and the
 adjoint identity between the ray-driven forward and the independent scatter adjoint."""
+import ctypes
 import math
 
 import numpy as np
@@ -203,3 +204,110 @@ def test_span1_against_analytic_ellipsoids():
         assert abs(est.sum() / ref.sum() - 1) < 0.02
     assert errs[-1] < 0.09
     assert errs[1] < 0.6 * errs[0]
+
+
+# ---------------------------------------------------------------- scanner model
+def _scanner_2d(nonarc=True):
+    """One image plane, 32 x 32 at 4 mm, 41 radial bins of 4 mm on a 60 mm ring."""
+    return Geometry(nx=32, ny=32, nz=1, vx=4.0, vy=4.0, vz=4.0, n_rad=41, d_rad=4.0,
+                    n_ang=8, det_radius=60.0, nonarc=nonarc)
+
+
+@pytest.mark.parametrize("nonarc", [True, False])
+def test_scanner_radial_profile_of_a_hot_column(nonarc):
+    """phi = 0 rays run along y at x = s_k; one hot voxel column at x index i0 gives the
+    radial profile v_y max(0, 1 - |s_k / v_x + (n_x - 1) / 2 - i0|) exactly, with s_k =
+    R sin(t_k / R) for non-arc-corrected bins (t_k = (k - 20) 4 mm) and s_k = t_k else."""
+    g = _scanner_2d(nonarc)
+    x = np.zeros(g.image_shape)
+    i0 = 28  # x = 50 mm from the axis: bins 2-3 apart between the two samplings
+    x[0, 17, i0] = 1.0
+    prof = proj.forward(g, x, [0])[0, 0]
+    t = (np.arange(g.n_rad) - 20) * 4.0
+    s = 60.0 * np.sin(t / 60.0) if nonarc else t
+    want = 4.0 * np.maximum(0.0, 1.0 - np.abs(s / 4.0 + 15.5 - i0))
+    np.testing.assert_allclose(prof, want, rtol=0, atol=1e-12)
+    assert prof.max() > 0
+
+
+def test_scanner_slope_depends_on_radial_position():
+    """A uniform image: the phi = 0 ray of a ring-difference-1 plane crosses every row
+    inside the image, so its sum is n_y v_y sqrt(1 + tau(s)^2) with tau(s) = tau_1 R /
+    sqrt(R^2 - s^2), s = R sin(t / R); tau_1 = 1 (2 v_z) / (2 R)."""
+    rings, R, v = 16, 60.0, 4.0
+    planes, tans, pitch = synth.span1_segments(rings, 1, v, R)
+    g = Geometry(nx=32, ny=32, nz=2 * rings - 1, vx=v, vy=v, vz=v, n_rad=41, d_rad=v,
+                 n_ang=8, seg_planes=planes, seg_tan=tans, seg_pitch=pitch, det_radius=R,
+                 nonarc=True, oblique_s=True)
+    assert tans[1] == pytest.approx(2 * v / (2 * R))
+    x = np.ones(g.image_shape)
+    q = planes[0] + 7  # segment +1 (d = 1), its central ring pair (7, 8)
+    for k in (20, 26, 31, 35):
+        t = (k - 20) * v
+        s = R * math.sin(t / R)
+        if abs(s / v + 15.5) > 31 or s / v + 15.5 < 0:
+            continue
+        tau = tans[1] * R / math.sqrt(R * R - s * s)
+        want = 32 * v * math.sqrt(1.0 + tau * tau)
+        assert proj.ray(g, x, 0, q, k) == pytest.approx(want, rel=1e-12)
+    # a constant slope would give the same sum for every bin
+    assert proj.ray(g, x, 0, q, 35) > proj.ray(g, x, 0, q, 20) * 1.002
+
+
+def test_scanner_compression_counts():
+    """Span-11 data plane of ring sum S in segment 0 sums the ring pairs with |d| <= 5,
+    d = S mod 2 and both rings among the 64: #{d : |d| <= min(5, S, 126 - S), d = S mod 2};
+    in segment +1 (d = 6 .. 16) its first plane (S = 6) holds the pair (0, 6) only.  Every
+    ring pair sits in one data plane: 4084 pairs in 837 planes."""
+    g = synth.mmr_scanner()
+    m, counts = proj.compression(g)
+    assert tuple(counts) == (127, 115, 115, 93, 93, 71, 71, 49, 49, 27, 27)
+    per = np.bincount(m, minlength=int(counts.sum()))
+    assert per.sum() == 4084 == g.n_planes
+    for S in range(127):
+        lim = min(5, S, 126 - S)
+        want = sum(1 for d in range(-lim, lim + 1) if (d - S) % 2 == 0)
+        assert per[S] == want
+    # segment +1 (d = 6 .. 16): its first planes S = 6, 7 hold (0, 6) and (0, 7); S = 8
+    # holds (1, 7) and (0, 8); its last plane S = 120 holds (57, 63) only
+    assert per[127] == 1 and per[128] == 1 and per[129] == 2
+    assert per[127 + 115 - 1] == 1
+
+
+def test_scanner_bins_are_sums_of_single_rays():
+    """Data bin (a, q, k) of the scanner model equals the sum of the single ray sums of
+    the ring pairs (r1, r2) found by direct search (|r2 - r1| in the data segment's range,
+    r1 + r2 = the plane's ring sum), each ray evaluated on its own."""
+    g = synth.scanner_small()
+    x = _rand(g.image_shape, 11)
+    full = proj.forward(g, x, [3])[0]
+    lib = proj._load()
+    gs = proj._geom(g)
+    rings, span, h = 8, 3, 1
+    seg_start = np.concatenate([[0], np.cumsum(g.seg_planes)[:-1]])
+    order = lambda d: 0 if d == 0 else (2 * d - 1 if d > 0 else -2 * d)  # noqa: E731
+    dstart = np.concatenate([[0], np.cumsum(g.data_seg_planes)[:-1]])
+    for (dseg, sgn, lo, hi, smin) in [(0, 0, -1, 1, 0), (1, 1, 2, 4, 2), (2, -1, -4, -2, 2),
+                                      (3, 1, 5, 7, 5), (4, -1, -7, -5, 5)]:
+        for loc in range(g.data_seg_planes[dseg]):
+            S = loc + smin
+            for k in (3, 13, 22):
+                want = 0.0
+                for r1 in range(rings):
+                    r2 = S - r1
+                    if not 0 <= r2 < rings or not lo <= r2 - r1 <= hi:
+                        continue
+                    d = r2 - r1
+                    q1 = int(seg_start[order(d)] + min(r1, r2))
+                    want += lib.orc_ray(ctypes.byref(gs), proj._dptr(np.ascontiguousarray(x)),
+                                        3, q1, k)
+                assert full[dstart[dseg] + loc, k] == pytest.approx(want, rel=1e-13, abs=1e-13)
+
+
+def test_scanner_adjoint_identity():
+    g = synth.scanner_small()
+    x = _rand(g.image_shape, 12)
+    y = _rand(g.sino_shape, 13)
+    lhs = np.vdot(proj.forward(g, x), y)
+    rhs = np.vdot(x, proj.backward(g, y))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
