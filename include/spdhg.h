@@ -44,7 +44,7 @@ extern "C" {
 #define SPDHG_OK 0
 #define SPDHG_E_ARG (-1)       /* invalid argument (null pointer, out-of-range value)   */
 #define SPDHG_E_SHAPE (-2)     /* inconsistent geometry / sizes                          */
-#define SPDHG_E_DOMAIN (-3)    /* data outside the model's domain (b<0, r<0, mult<=0 ...) */
+#define SPDHG_E_DOMAIN (-3)    /* data outside the model's domain (b<0, r<0, mult<0 ...)  */
 #define SPDHG_E_HIP (-4)       /* HIP runtime error                                      */
 #define SPDHG_E_WORKSPACE (-5) /* workspace missing or too small                        */
 #define SPDHG_E_STATE (-6)     /* call made on a context in the wrong state              */
@@ -59,7 +59,23 @@ extern "C" {
  * whose ring pitch is two image planes); nz - 1 - pitch_g (N_g - 1) must be even and
  * >= 0.  A ray is sampled at every image row when 4a <= n_ang or 4a >= 3 n_ang, else at
  * every column, and the image is interpolated bilinearly (zero outside) in the other
- * in-plane axis and z. */
+ * in-plane axis and z.
+ *
+ * Scanner model (Section 1.2: the system matrix "includes geometric factors"; all fields
+ * zero = off).  det_radius: detector ring radius R (mm).  nonarc: radial bin k sits at
+ * s = R sin((k - (n_rad-1)/2) d_rad / R) (bins not arc-corrected).  oblique_s: the slope
+ * of segment g at radial position s is seg_tan[g] R / sqrt(R^2 - s^2) (a line of response
+ * spans the chord between its two detectors), and so is its step length's.  span (odd,
+ * >= 3): the segments must be the ring-pair segments of rings = (nz + 1) / 2 rings, ring
+ * difference d = 0, +1, -1, +2, -2, ... with rings - |d| planes at pitch 2, and every
+ * sinogram the library reads or writes (b, r, mult, subset and caller layouts) holds the
+ * span-compressed data planes instead: data segment 0 takes |d| <= (span-1)/2, data
+ * segment +-G the d in +-[G span - (span-1)/2, G span + (span-1)/2]; its plane of ring
+ * sum S (from the segment's smallest ring sum G span - (span-1)/2, 0 for segment 0, up
+ * to 2 (rings - 1) minus that) is the sum of the rays of the ring pairs (r1, r2) with
+ * r1 + r2 = S, so G = C G1 with G1 the ring-pair projector and C the 0/1 sum.  The data
+ * planes are ordered like segments (0, +1, -1, ...) and inside a segment by ring sum.
+ * Detector gaps are zeros of mult (and of b, r). */
 typedef struct spdhg_geom {
     int32_t nx, ny, nz;
     double vx, vy, vz;
@@ -70,6 +86,10 @@ typedef struct spdhg_geom {
     int32_t seg_planes[SPDHG_MAX_SEG];
     double seg_tan[SPDHG_MAX_SEG];
     int32_t seg_pitch[SPDHG_MAX_SEG];
+    double det_radius; /* scanner model (see above): ring radius R, mm                 */
+    int32_t nonarc;    /* 1: radial bins at R sin(...)                                  */
+    int32_t oblique_s; /* 1: slopes seg_tan R / sqrt(R^2 - s^2)                         */
+    int32_t span;      /* 0: data planes = the segments' planes; odd >= 3: compression  */
 } spdhg_geom;
 
 #define SPDHG_PRIOR_NONE 0 /* ML: n = m blocks                                        */
@@ -187,7 +207,8 @@ int spdhg_workspace_bytes(const spdhg_geom* geom, const spdhg_params* params, si
 
 /* Set up a reconstruction (Algorithm 2, inputs and initialisation):
  *   b, r, mult  device, full sinograms: counts b >= 0, background r >= 0, factors
- *               mult > 0.  Borrowed: they must stay valid until spdhg_destroy.
+ *               mult >= 0 (0: a bin of zero efficiency, e.g. a detector gap, whose row of
+ *               A is zero).  Borrowed: they must stay valid until spdhg_destroy.
  *   side        device image (dTV side information) or NULL.  Borrowed.
  *   x           device image: initial image on entry (negative values are clipped, the
  *               first primal step with z = 0); the iterate is returned here after every
@@ -197,8 +218,8 @@ int spdhg_workspace_bytes(const spdhg_geom* geom, const spdhg_params* params, si
  * Computes the step sizes of Theorem 2 (sensitivities A_i 1, A_i^T 1 or power
  * iterations), sets y = 0, z = 0.  Synchronises `stream` once (domain checks and norm
  * estimates come back to the host).  Errors: SPDHG_E_ARG, SPDHG_E_SHAPE,
- * SPDHG_E_DOMAIN (b < 0, r < 0, mult <= 0, or a bin with b > 0 and r = 0 that no voxel
- * reaches, whose objective term is infinite), SPDHG_E_WORKSPACE, SPDHG_E_HIP. */
+ * SPDHG_E_DOMAIN (b < 0, r < 0, mult < 0, or a bin with b > 0 and r = 0 that no voxel
+ * reaches (or with mult = 0), whose objective term is infinite), SPDHG_E_WORKSPACE, SPDHG_E_HIP. */
 int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* params,
                const float* b, const float* r, const float* mult, const float* side,
                float* x, void* ws, size_t ws_bytes, void* stream);

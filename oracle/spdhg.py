@@ -63,8 +63,10 @@ class Problem:
         self.b = np.asarray(self.b, dtype=np.float64).reshape(g.sino_shape)
         self.r = np.asarray(self.r, dtype=np.float64).reshape(g.sino_shape)
         self.mult = np.asarray(self.mult, dtype=np.float64).reshape(g.sino_shape)
-        if np.any(self.b < 0) or np.any(self.r < 0) or np.any(self.mult <= 0):
-            raise ValueError("domain: need b >= 0, r >= 0, mult > 0")
+        # mult = 0 (a bin of zero efficiency, e.g. a detector gap) gives the bin a zero
+        # row of A, like a ray that misses the image
+        if np.any(self.b < 0) or np.any(self.r < 0) or np.any(self.mult < 0):
+            raise ValueError("domain: need b >= 0, r >= 0, mult >= 0")
         m = self.n_subsets
         self.m = m
         self.n_prior = {"none": 0, "tv": 1, "atv": 1, "dtv": 1, "tgv": 2}[self.prior]

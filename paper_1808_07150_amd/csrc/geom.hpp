@@ -10,7 +10,14 @@
 //   z index = off_g + pitch_g p + e,  off_g = (nz - 1 - pitch_g (N_g - 1)) / 2
 //
 // Bilinear interpolation in (u, z) with zero padding; each sample carries the 3-D path
-// length L_g = v_prim / |cos or sin| * sqrt(1 + tau_g^2).  The coordinates are evaluated
+// length L_g = v_prim / |cos or sin| * sqrt(1 + tau_g^2).
+//
+// Scanner model (tables, NULL when off): radial bin k sits at the centred coordinate
+// kpos[k] = s_k / d_rad instead of k - (n_rad-1)/2 (non-arc-corrected bins, s_k = R sin(..)),
+// and the slope of every segment at s_k is scaled by kobl[k] = R / sqrt(R^2 - s_k^2), so
+// both axial coefficients take that factor and the step length the factor
+// kL[g][k] = sqrt(1 + tau_g^2 kobl^2) / sqrt(1 + tau_g^2).  u and e stay affine in the
+// centred radial coordinate, so every formula below reads kk = kappa(G, k).  The coordinates are evaluated
 // in FP64 from FP64 coefficients (an FP32 index near 300 would carry ~2e-5 absolute
 // error) and only the interpolation fractions are rounded to FP32.  The forward walk and
 // the gather backprojector call the same inline functions below with the same integer
@@ -42,15 +49,24 @@ struct SegAngleDev {  // per (angle, segment)
 
 struct GeomDev {
     int32_t nx, ny, nz;
-    int32_t n_rad, n_ang, n_seg, n_planes;
-    double ck;  // (n_rad - 1) / 2
+    int32_t n_rad, n_ang, n_seg, n_planes;  // n_planes: the projector's (ray) planes
+    int32_t n_dplanes;  // planes of a data (sinogram) row: n_planes, or the span-compressed count
+    int32_t dstride;    // data elements between consecutive planes of a segment (1; 2 compressed)
+    double ck;          // (n_rad - 1) / 2
+    double krho;        // non-arc-corrected bins: R / d_rad (0: equal steps)
     int32_t seg_planes[SPDHG_DEV_MAX_SEG];
-    int32_t seg_base[SPDHG_DEV_MAX_SEG];  // first sinogram plane of the segment
+    int32_t seg_base[SPDHG_DEV_MAX_SEG];  // first projector plane of the segment
     int32_t seg_off[SPDHG_DEV_MAX_SEG];   // image plane of the first plane: (nz - 1 - pitch (N_g - 1)) / 2
     int32_t seg_pitch[SPDHG_DEV_MAX_SEG]; // image planes between consecutive planes (1 or 2)
+    int32_t seg_dbase[SPDHG_DEV_MAX_SEG]; // data element of the segment's plane 0 in a data row
     const AngleDev* ang;                  // [n_ang]
     const SegAngleDev* sa;                // [n_ang][n_seg]
     const int32_t* plane_seg;             // [n_planes] segment of each plane
+    const double* kpos;                   // [n_rad] centred radial coordinate (NULL: k - ck)
+    const double* kobl;                   // [n_rad] slope factor (NULL: 1)
+    const float* kL;                      // [n_seg][n_rad] step-length factor (NULL: 1)
+    const int32_t* cstart;                // [n_dplanes + 1] span compression: the ring-pair
+    const int32_t* clist;                 // planes clist[cstart[q] ..] of data plane q (NULL: none)
 };
 
 struct Sample {
@@ -72,7 +88,35 @@ __device__ __forceinline__ Sample split(double u) {
     return s;
 }
 
-// Axial offset (in voxels) of the ray of radial bin kk at primary index jj.
-__device__ __forceinline__ double ax_offset(const SegAngleDev& S, double kk, double jj) {
-    return __builtin_fma(S.ez_dj, jj, S.ez_dk * kk);
+// Centred radial coordinate of bin k.
+__device__ __forceinline__ double kappa(const GeomDev& G, int k) {
+    return G.kpos ? G.kpos[k] : (double)k - G.ck;
+}
+
+// Continuous radial bin of the centred coordinate kk (inverse of kappa; for ray ranges).
+__device__ __forceinline__ double bin_of(const GeomDev& G, double kk) {
+    if (G.krho > 0.0) return G.ck + G.krho * asin(fmin(fmax(kk / G.krho, -1.0), 1.0));
+    return kk + G.ck;
+}
+
+// Axial coefficients and step length of the rays of segment g, angle a, radial bin k
+// (centred coordinate kk): axial offset fma(ezj, jj, ezk) voxels at primary index jj.
+struct SegRay {
+    double ezj, ezk;
+    float L;
+};
+
+__device__ __forceinline__ SegRay seg_ray(const GeomDev& G, int a, int g, int k, double kk) {
+    const SegAngleDev S = G.sa[a * G.n_seg + g];
+    SegRay r;
+    if (G.kobl) {
+        const double f = G.kobl[k];
+        r.ezj = S.ez_dj * f;
+        r.ezk = (S.ez_dk * f) * kk;
+    } else {
+        r.ezj = S.ez_dj;
+        r.ezk = S.ez_dk * kk;
+    }
+    r.L = G.kL ? S.L * G.kL[g * G.n_rad + k] : S.L;
+    return r;
 }

@@ -121,10 +121,11 @@ __device__ __forceinline__ void sec_range(const AngleDev& A, double u0, int& j0,
 enum FwdMode { F_PLAIN_QK = 0, F_POWER = 1, F_SENS = 2, F_DUAL = 3, F_OBJ = 4, F_EM = 5 };
 
 // Row layout of the dual change read by the backprojectors: per (angle of the list,
-// radial bin) the n_planes values of the ray bundle, segment g at planes seg_base[g] ..
-// seg_base[g] + N_g - 1.
+// radial bin) the n_dplanes values of the data bins; projector segment g's plane p at
+// element seg_dbase[g] + dstride p (without span compression: the ray bundle's planes,
+// segment g at seg_base[g] ..).
 __device__ __forceinline__ int64_t dual_row(const GeomDev& G, int ia, int k) {
-    return ((int64_t)ia * G.n_rad + k) * G.n_planes;
+    return ((int64_t)ia * G.n_rad + k) * G.n_dplanes;
 }
 
 struct FwdArgs {
@@ -143,18 +144,22 @@ struct FwdArgs {
     double* part;        // F_OBJ partials (one per block)
     float gr;            // F_SENS: gamma * rho
     int split;           // host only: wavefronts per ray bundle (0: chosen from the size)
+    float* raw;          // span compression: ray sums [angle of the chunk][k][ray plane]
+    int raw_kq;          // 1: the walk writes its ray sums times L to raw (no epilogue)
+    int ia0;             // index of the launch's first angle in the output lists
+    int raw_angles;      // host only: angles the raw buffer holds
 };
 
-// Per-ray epilogue of the forward walk (sum acc of ray (a, k, plane q) in segment g).
+// Epilogue of one data bin (a, k, data plane q) with geometric projection v; ia indexes
+// the launch's list of angles.
 template <int MODE>
-__device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, int k, int q, int g,
-                                             float acc, double& obj) {
+__device__ __forceinline__ void fwd_bin(const FwdArgs& P, int a, int ia, int k, int q, float v,
+                                        double& obj) {
     const GeomDev& G = P.G;
-    const float v = acc * G.sa[a * G.n_seg + g].L;
-    const int64_t full = ((int64_t)a * G.n_rad + k) * G.n_planes + q;
+    const int64_t full = ((int64_t)a * G.n_rad + k) * G.n_dplanes + q;
     if (MODE == F_PLAIN_QK) {
-        const float m = P.mult ? P.mult[((int64_t)a * G.n_planes + q) * G.n_rad + k] : 1.0f;
-        P.out[((int64_t)ia * G.n_planes + q) * G.n_rad + k] = v * m;
+        const float m = P.mult ? P.mult[((int64_t)a * G.n_dplanes + q) * G.n_rad + k] : 1.0f;
+        P.out[((int64_t)ia * G.n_dplanes + q) * G.n_rad + k] = v * m;
     } else if (MODE == F_POWER) {
         // A_i^T A_i needs mult (G x) times mult again: write mult^2 G x
         const float m = P.mult[full];
@@ -178,6 +183,46 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, in
         const float m = P.mult[full];
         const float b = P.b[full];
         P.d[dual_row(G, ia, k) + q] = b > 0.0f ? m * (b / __builtin_fmaf(m, v, P.r[full])) : 0.0f;
+    }
+}
+
+// Per-ray epilogue of the forward walk (sum acc of ray (a, k, plane q) in segment g): the
+// data bin's epilogue, or with span compression (raw_kq) the ray's sum times its step
+// length into the raw rows, which fwd_compress adds up per data bin.
+template <int MODE>
+__device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, int k, int q, int g,
+                                             float acc, double& obj) {
+    const GeomDev& G = P.G;
+    const float L = G.kL ? G.sa[a * G.n_seg + g].L * G.kL[g * G.n_rad + k] : G.sa[a * G.n_seg + g].L;
+    const float v = acc * L;
+    if (P.raw_kq) {
+        P.raw[((int64_t)ia * G.n_rad + k) * G.n_planes + q] = v;
+        return;
+    }
+    fwd_bin<MODE>(P, a, ia, k, q, v, obj);
+}
+
+// Span compression (eq. of the forward model with the scanner's data planes): every data
+// bin of the chunk's angles is the sum of its ring-pair rays (clist order, fixed), then
+// the mode's epilogue.  One block per (angle of the chunk, radial bin), so the objective's
+// partial of bin row (ia0 + ia, k) lands where the walks put theirs.
+template <int MODE>
+__global__ void __launch_bounds__(256) fwd_compress(FwdArgs P) {
+    const GeomDev& G = P.G;
+    const int bid = blockIdx.x;
+    const int ia = bid / G.n_rad;
+    const int k = bid - ia * G.n_rad;
+    const int a = P.ang0 + ia * P.ang_step;
+    const float* raw = P.raw + (int64_t)bid * G.n_planes;
+    double obj = 0.0;
+    for (int q = threadIdx.x; q < G.n_dplanes; q += 256) {
+        float v = 0.0f;
+        for (int i = G.cstart[q]; i < G.cstart[q + 1]; ++i) v += raw[G.clist[i]];
+        fwd_bin<MODE>(P, a, P.ia0 + ia, k, q, v, obj);
+    }
+    if (MODE == F_OBJ) {
+        const double t = block_sum<256>(obj);
+        if (threadIdx.x == 0) P.part[(int64_t)(P.ia0 + ia) * G.n_rad + k] = t;
     }
 }
 
@@ -217,7 +262,7 @@ fwd_wave(FwdArgs P) {
     const int k = bid - ia * G.n_rad;
     const int a = P.ang0 + ia * P.ang_step;
     const AngleDev A = G.ang[a];
-    const double kk = (double)k - G.ck;
+    const double kk = kappa(G, k);
     const int nz = G.nz;
     const int64_t s_prim = A.rowdom ? G.nx : 1;
     const int64_t s_sec = A.rowdom ? 1 : G.nx;
@@ -244,13 +289,13 @@ fwd_wave(FwdArgs P) {
         }
     }
     for (int i = lane; i < P.gsize; i += 64) Gb[i] = 0.0f;
-    // the axial offset of segment g at step j is fma(ez_dj, jj, ez_dk * kk) (ax_offset):
+    // the axial offset of segment g at step j is fma(ezj, jj, ezk) (seg_ray):
     // its two step-independent parts are read once, so the step loop loads nothing from
     // global memory but the image columns (only lane g % 64 touches entry g)
     for (int sg = lane; sg < ns; sg += 64) {
-        const SegAngleDev S = G.sa[a * ns + sg];
-        segk[sg] = S.ez_dk * kk;
-        segj[sg] = S.ez_dj;
+        const SegRay S = seg_ray(G, a, sg, k, kk);
+        segk[sg] = S.ezk;
+        segj[sg] = S.ezj;
     }
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
@@ -379,7 +424,7 @@ fwd_wave(FwdArgs P) {
         const int q = lane + 64 * r;
         if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], acc[r], obj);
     }
-    if (MODE == F_OBJ) {
+    if (MODE == F_OBJ && !P.raw_kq) {  // raw rows: fwd_compress writes the partials
         obj = wave_sum(obj);
         if (lane == 0) P.part[bid] = obj;
     }
@@ -407,7 +452,7 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
     const int k = bid - ia * G.n_rad;
     const int a = P.ang0 + ia * P.ang_step;
     const AngleDev A = G.ang[a];
-    const double kk = (double)k - G.ck;
+    const double kk = kappa(G, k);
     const int nz = G.nz;
     const int64_t s_prim = A.rowdom ? G.nx : 1;
     const int64_t s_sec = A.rowdom ? 1 : G.nx;
@@ -426,11 +471,11 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
         }
     }
     for (int i = tid; i < 2 * P.gsize; i += 64 * PS) Gb[i] = 0.0f;
-    // step-independent parts of ax_offset (only one thread touches entry g)
+    // step-independent parts of the axial offset (seg_ray; only one thread touches entry g)
     for (int sg = tid; sg < ns; sg += 64 * PS) {
-        const SegAngleDev S = G.sa[a * ns + sg];
-        segk[sg] = S.ez_dk * kk;
-        segj[sg] = S.ez_dj;
+        const SegRay S = seg_ray(G, a, sg, k, kk);
+        segk[sg] = S.ezk;
+        segj[sg] = S.ezj;
     }
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
@@ -505,7 +550,7 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
         const int q = q0 + lane + 64 * r;
         if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, pinfo[r] & 127, acc[r], obj);
     }
-    if (MODE == F_OBJ) {
+    if (MODE == F_OBJ && !P.raw_kq) {  // raw rows: fwd_compress writes the partials
         obj = wave_sum(obj);
         if (lane == 0) wsum[w] = obj;
         __syncthreads();
@@ -543,10 +588,10 @@ struct TapCoef {
     float wa, wb;
 };
 
-__device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, double kk,
+__device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, int k, double kk,
                                             double jj) {
-    const SegAngleDev S = G.sa[a * G.n_seg + g];
-    const Sample sz = split(ax_offset(S, kk, jj));
+    const SegRay S = seg_ray(G, a, g, k, kk);
+    const Sample sz = split(__builtin_fma(S.ezj, jj, S.ezk));
     TapCoef t;
     t.off = -(G.seg_off[g] + sz.i0);
     t.wa = S.L * (1.0f - sz.fu);
@@ -558,13 +603,14 @@ __device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, doub
 // p = z + off (weight wa) and p - 1 (wb).  Pitch 2 (a segment on every other image plane):
 // with u = z + off, plane p sits at image plane off_g + 2p + i0 (weight wa) and reaches the
 // next one with weight wb, so voxel z takes one plane, u / 2 with wa if u is even, else
-// (u - 1) / 2 with wb (u >> 1 in both cases).
+// (u - 1) / 2 with wb (u >> 1 in both cases).  Plane pp is data element pp * ds (ds = 2:
+// a span-compressed data row).
 __device__ __forceinline__ float tap_sum_masked(const float* __restrict__ seg, int n, int pitch,
-                                                const TapCoef& t, int z, float h) {
+                                                int ds, const TapCoef& t, int z, float h) {
     const int p = z + t.off;
     if (pitch == 2) {
         const int pp = p >> 1;
-        if ((unsigned)pp < (unsigned)n) h = __builtin_fmaf((p & 1) ? t.wb : t.wa, seg[pp], h);
+        if ((unsigned)pp < (unsigned)n) h = __builtin_fmaf((p & 1) ? t.wb : t.wa, seg[pp * ds], h);
         return h;
     }
     if ((unsigned)p < (unsigned)n) h = __builtin_fmaf(t.wa, seg[p], h);
@@ -572,11 +618,13 @@ __device__ __forceinline__ float tap_sum_masked(const float* __restrict__ seg, i
     return h;
 }
 
-// Buffer resource over segment g of a dual-change row (raw, byte offsets, range checked).
+// Buffer resource over segment g of a dual-change row (raw, byte offsets, range checked):
+// its planes at elements 0, ds, .., (N_g - 1) ds (ds = dstride).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const GeomDev& G, const float* row,
                                                            int g) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)(row + (uint32_t)G.seg_base[g]), (short)0,
-                                             G.seg_planes[g] * 4, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(row + (uint32_t)G.seg_dbase[g]), (short)0,
+                                             ((G.seg_planes[g] - 1) * G.dstride + 1) * 4,
+                                             0x00020000);
 }
 
 __device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t t, float dz) {
@@ -644,13 +692,13 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
                 const int isec = A.rowdom ? qx : qy;
                 const double jj = (double)j - A.cj;
                 const double base = __builtin_fma(A.du_dj, jj, A.cu);
-                const double ka = ((double)(isec - 1) - base) / A.du_dk + G.ck;
-                const double kb = ((double)(isec + 1) - base) / A.du_dk + G.ck;
+                const double ka = bin_of(G, ((double)(isec - 1) - base) / A.du_dk);
+                const double kb = bin_of(G, ((double)(isec + 1) - base) / A.du_dk);
                 const int klo = max(0, (int)__builtin_floor(fmin(ka, kb)) - 1);
                 const int khi = min(G.n_rad - 1, (int)__builtin_ceil(fmax(ka, kb)) + 1);
                 int found = 0;
                 for (int k = klo; k <= khi; ++k) {
-                    const Sample sm = split(sec_coord(A, (double)k - G.ck, jj));
+                    const Sample sm = split(sec_coord(A, kappa(G, k), jj));
                     float w = -1.0f;
                     if (sm.i0 == isec)
                         w = 1.0f - sm.fu;
@@ -678,7 +726,7 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
             if (cq < ncol && o.wx != 0.0f) {
                 const int qy = cq / G.nx, qx = cq - qy * G.nx;
                 const int j = A.rowdom ? qy : qx;
-                v = tap_coef(G, a, g, (double)o.k - G.ck, (double)j - A.cj);
+                v = tap_coef(G, a, g, o.k, kappa(G, o.k), (double)j - A.cj);
             }
             tc[t] = v;
         }
@@ -694,8 +742,8 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
                 if (iz >= nz) break;
                 float h = 0.0f;
                 for (int g = 0; g < ns; ++g)
-                    h = tap_sum_masked(dk + G.seg_base[g], G.seg_planes[g], G.seg_pitch[g], tk[g],
-                                       iz, h);
+                    h = tap_sum_masked(dk + G.seg_dbase[g], G.seg_planes[g], G.seg_pitch[g],
+                                       G.dstride, tk[g], iz, h);
                 acc[zz] = __builtin_fmaf(o.wx, h, acc[zz]);
             }
         }
@@ -760,14 +808,15 @@ __device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, c
             s[3] = __builtin_fmaf(t.wb, v[u][1], s[3]);
         }
     } else {
+        const int sh = G.dstride == 2 ? 3 : 2;  // bytes per plane: 4 dstride
 #pragma unroll
         for (int u = 0; u < N; ++u) {
             const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g + u);
             const int off = tk[g + u].off;
             v[u][0] = __uint_as_float(
-                __builtin_amdgcn_raw_buffer_load_b32(rs, ((la + off) >> 1) * 4, 0, 0));
+                __builtin_amdgcn_raw_buffer_load_b32(rs, ((la + off) >> 1) << sh, 0, 0));
             v[u][1] = __uint_as_float(
-                __builtin_amdgcn_raw_buffer_load_b32(rs, ((lb + off) >> 1) * 4, 0, 0));
+                __builtin_amdgcn_raw_buffer_load_b32(rs, ((lb + off) >> 1) << sh, 0, 0));
         }
 #pragma unroll
         for (int u = 0; u < N; ++u) {
@@ -856,14 +905,14 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
         const double jj = (double)j - A.cj;
         // 1. rays touching the strip: u in [s0 - 1, s0 + BS_W)  (wave-uniform)
         const double base = __builtin_fma(A.du_dj, jj, A.cu);
-        const double ka = ((double)(s0 - 1) - base) / A.du_dk + G.ck;
-        const double kb = ((double)(s0 + BS_W) - base) / A.du_dk + G.ck;
+        const double ka = bin_of(G, ((double)(s0 - 1) - base) / A.du_dk);
+        const double kb = bin_of(G, ((double)(s0 + BS_W) - base) / A.du_dk);
         const int klo = max(0, (int)__builtin_floor(fmin(ka, kb)) - 1);
         const int khi = min(G.n_rad - 1, (int)__builtin_ceil(fmax(ka, kb)) + 1);
         const int nr = min(max(khi - klo + 1, 0), KR);
         __builtin_amdgcn_wave_barrier();  // the previous angle's tables are consumed
         for (int kr = lane; kr < nr; kr += 64) {
-            const Sample sm = split(sec_coord(A, (double)(klo + kr) - G.ck, jj));
+            const Sample sm = split(sec_coord(A, kappa(G, klo + kr), jj));
             ri0[kr] = sm.i0 - s0;
             rfu[kr] = sm.fu;
         }
@@ -887,7 +936,7 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
             __builtin_amdgcn_wave_barrier();  // the previous chunk's taps are consumed
             for (int t = lane; t < nr * nsc; t += 64) {
                 const int kr = t / nsc, gl = t - kr * nsc;
-                tc[kr * sc + gl] = tap_coef(G, a, gc + gl, (double)(klo + kr) - G.ck, jj);
+                tc[kr * sc + gl] = tap_coef(G, a, gc + gl, klo + kr, kappa(G, klo + kr), jj);
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -950,7 +999,7 @@ __global__ void __launch_bounds__(BLOCK)
 to_rows(GeomDev G, const float* __restrict__ src, int caller, const float* __restrict__ mult,
         int ang0, int step, int n_ang_sub, float* __restrict__ dst) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t per = (int64_t)G.n_planes * G.n_rad;
+    const int64_t per = (int64_t)G.n_dplanes * G.n_rad;
     if (t >= per * n_ang_sub) return;
     const int ia = (int)(t / per);
     const int64_t rem = t - ia * per;
@@ -2036,9 +2085,10 @@ __global__ void finalize_T(float* __restrict__ T, int64_t n, float t_prior) {
     T[t] = isinf(v) ? 0.0f : v;
 }
 
-// Domain check partials: counts of bins with b < 0 or r < 0 or mult <= 0 or non-finite
+// Domain check partials: counts of bins with b < 0 or r < 0 or mult < 0 or non-finite
 // values (slot 0), and of bins whose objective term is infinite for every image:
-// b > 0, r = 0 and no voxel reaches the bin (a1 = 0 there) (slot 1).
+// b > 0, r = 0 and no voxel reaches the bin (a1 = 0 there, also where mult = 0: a bin of
+// zero efficiency such as a detector gap has a zero row of A) (slot 1).
 __global__ void __launch_bounds__(BLOCK)
 domain_check(const float* __restrict__ b, const float* __restrict__ r,
              const float* __restrict__ mult, const float* __restrict__ a1, int64_t n,
@@ -2047,7 +2097,7 @@ domain_check(const float* __restrict__ b, const float* __restrict__ r,
     double bad = 0.0, inf = 0.0;
     if (t < n) {
         const float bb = b[t], rr = r[t], mm = mult[t];
-        if (!(bb >= 0.0f) || !(rr >= 0.0f) || !(mm > 0.0f) || isinf(bb) || isinf(rr) ||
+        if (!(bb >= 0.0f) || !(rr >= 0.0f) || !(mm >= 0.0f) || isinf(bb) || isinf(rr) ||
             isinf(mm))
             bad = 1.0;
         if (bb > 0.0f && rr == 0.0f && !(a1[t] > 0.0f)) inf = 1.0;
@@ -2155,8 +2205,8 @@ __device__ double ray_taps(const GeomDev& G, int a, int q, int k) {
     const AngleDev A = G.ang[a];
     const int g = G.plane_seg[q];
     const int p = q - G.seg_base[g];
-    const SegAngleDev S = G.sa[a * G.n_seg + g];
-    const double kk = (double)k - G.ck;
+    const double kk = kappa(G, k);
+    const SegRay S = seg_ray(G, a, g, k, kk);
     const int zb = G.seg_pitch[g] * p + G.seg_off[g];
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
@@ -2164,7 +2214,7 @@ __device__ double ray_taps(const GeomDev& G, int a, int q, int k) {
     for (int j = j0; j < j1; ++j) {
         const double jj = (double)j - A.cj;
         const Sample s = split(sec_coord(A, kk, jj));
-        const Sample sz = split(ax_offset(S, kk, jj));
+        const Sample sz = split(__builtin_fma(S.ezj, jj, S.ezk));
         const int iz = zb + sz.i0;
         const float wx[2] = {1.0f - s.fu, s.fu};
         const float wz[2] = {1.0f - sz.fu, sz.fu};

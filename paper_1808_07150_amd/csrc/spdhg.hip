@@ -102,6 +102,25 @@ int64_t n_planes(const spdhg_geom* g) {
     return n;
 }
 
+// Ring difference of segment i in the order 0, +1, -1, +2, -2, ...
+int ring_diff(int i) { return i == 0 ? 0 : ((i + 1) / 2) * (i % 2 ? 1 : -1); }
+
+// Data planes of a sinogram row: the segments' planes, or with span compression the
+// planes of the data segments 0, +-1, .. (data segment G: ring sums from G span -
+// (span-1)/2 to 2 (rings - 1) minus that; it exists while that smallest |d| is present).
+int64_t n_data_planes(const spdhg_geom* g) {
+    if (g->span == 0) return n_planes(g);
+    const int h = (g->span - 1) / 2;
+    int dmax = 0;
+    for (int i = 0; i < g->n_seg; ++i) dmax = std::max(dmax, std::abs(ring_diff(i)));
+    int64_t n = g->nz;
+    for (int G = 1; G * g->span - h <= dmax; ++G) n += 2 * (g->nz - 2 * (G * g->span - h));
+    return n;
+}
+
+// Largest |bin angle| of the non-arc-corrected sampling, (n_rad - 1) / 2 d_rad / R.
+double max_bin_angle(const spdhg_geom* g) { return 0.5 * (g->n_rad - 1) * g->d_rad / g->det_radius; }
+
 int check_geom(const spdhg_geom* g) {
     if (!g) return fail(SPDHG_E_ARG, "geometry is NULL");
     if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || g->n_rad <= 0 || g->n_ang <= 0)
@@ -120,8 +139,25 @@ int check_geom(const spdhg_geom* g) {
                         "and >= 0");
         if (!std::isfinite(g->seg_tan[i])) return fail(SPDHG_E_SHAPE, "segment slope not finite");
     }
+    if (g->nonarc || g->oblique_s) {
+        if (!(g->det_radius > 0) || !std::isfinite(g->det_radius))
+            return fail(SPDHG_E_SHAPE, "the scanner model needs det_radius > 0");
+        if (g->nonarc ? !(max_bin_angle(g) < 1.5) : !(0.5 * (g->n_rad - 1) * g->d_rad < g->det_radius * 0.997))
+            return fail(SPDHG_E_SHAPE, "radial bins reach the detector ring");
+    }
+    if (g->span != 0) {
+        if (g->span < 3 || !(g->span & 1)) return fail(SPDHG_E_SHAPE, "span must be odd and >= 3");
+        const int rings = g->seg_planes[0];
+        if (g->nz != 2 * rings - 1) return fail(SPDHG_E_SHAPE, "span compression needs nz = 2 rings - 1");
+        for (int i = 0; i < g->n_seg; ++i) {
+            const int pitch = g->seg_pitch[i] == 0 ? 1 : g->seg_pitch[i];
+            if (pitch != 2 || g->seg_planes[i] != rings - std::abs(ring_diff(i)))
+                return fail(SPDHG_E_SHAPE,
+                            "span compression needs the ring-pair segments 0, +1, -1, ... at pitch 2");
+        }
+    }
     const double nv = (double)g->nx * g->ny * g->nz;
-    const double nb = (double)g->n_ang * (double)n_planes(g) * g->n_rad;
+    const double nb = (double)g->n_ang * (double)n_data_planes(g) * g->n_rad;
     if (nv > 4.0e9 || nb > 8.0e9) return fail(SPDHG_E_SHAPE, "problem too large");
     if (g->nx > 16384 || g->ny > 16384 || g->nz > 16384 || g->n_rad > 1 << 20)
         return fail(SPDHG_E_SHAPE, "dimension too large for FP32 index arithmetic");
@@ -134,6 +170,9 @@ struct HostTables {
     std::vector<AngleDev> ang;
     std::vector<SegAngleDev> sa;
     std::vector<int32_t> plane_seg;
+    std::vector<double> kpos, kobl;     // scanner model (empty when off)
+    std::vector<float> kL;
+    std::vector<int32_t> cstart, clist; // span compression (empty when off)
     GeomDev G;
 };
 
@@ -202,13 +241,83 @@ void build_tables(const spdhg_geom* g, HostTables& T) {
         base += g->seg_planes[sg];
     }
     G.n_planes = base;
+    G.n_dplanes = base;
+    G.dstride = 1;
+    for (int sg = 0; sg < ns; ++sg) G.seg_dbase[sg] = G.seg_base[sg];
+
+    // scanner model: centred radial coordinates s_k / d_rad, slope factors R / sqrt(R^2 -
+    // s_k^2), step-length factors sqrt(1 + tau^2 f^2) / sqrt(1 + tau^2)
+    if (g->nonarc || g->oblique_s) {
+        const double R = g->det_radius;
+        T.kpos.resize(g->n_rad);
+        T.kobl.assign(g->n_rad, 1.0);
+        for (int k = 0; k < g->n_rad; ++k) {
+            const double t = ((double)k - G.ck) * g->d_rad;
+            const double sk = g->nonarc ? R * std::sin(t / R) : t;
+            T.kpos[k] = sk / g->d_rad;
+            if (g->oblique_s) T.kobl[k] = R / std::sqrt(R * R - sk * sk);
+        }
+        if (g->oblique_s) {
+            T.kL.resize((size_t)ns * g->n_rad);
+            for (int sg = 0; sg < ns; ++sg)
+                for (int k = 0; k < g->n_rad; ++k) {
+                    const double tau = g->seg_tan[sg], f = T.kobl[k];
+                    T.kL[(size_t)sg * g->n_rad + k] =
+                        (float)(std::sqrt(1.0 + tau * tau * f * f) / std::sqrt(1.0 + tau * tau));
+                }
+        } else {
+            T.kobl.clear();
+        }
+        if (g->nonarc) G.krho = R / g->d_rad;
+    }
+
+    // span compression: ring-pair plane p of segment i (ring difference d, rings
+    // (p, p + |d|) in some order, ring sum 2p + |d|) belongs to data segment G = (|d| + h)
+    // / span (sign of d; h = (span - 1) / 2) at its ring sum minus the segment's smallest,
+    // G span - h (0 for G = 0): data element dbase_i + 2p
+    if (g->span != 0) {
+        const int h = (g->span - 1) / 2;
+        const int64_t nd = n_data_planes(g);
+        std::vector<int> dstart;  // first data plane of data segment j (order 0, +1, -1, ..)
+        int64_t acc = 0;
+        for (int Gs = 0; acc < nd; ++Gs) {
+            const int n = g->nz - 2 * (Gs == 0 ? 0 : Gs * g->span - h);
+            dstart.push_back((int)acc);
+            acc += n;
+            if (Gs > 0) {
+                dstart.push_back((int)acc);
+                acc += n;
+            }
+        }
+        std::vector<int32_t> owner(base);
+        for (int sg = 0; sg < ns; ++sg) {
+            const int d = ring_diff(sg), ad = std::abs(d);
+            const int Gs = (ad + h) / g->span;
+            const int j = Gs == 0 ? 0 : (d > 0 ? 2 * Gs - 1 : 2 * Gs);
+            const int smin = Gs == 0 ? 0 : Gs * g->span - h;
+            G.seg_dbase[sg] = dstart[j] + ad - smin;
+            for (int p = 0; p < g->seg_planes[sg]; ++p)
+                owner[G.seg_base[sg] + p] = G.seg_dbase[sg] + 2 * p;
+        }
+        G.n_dplanes = (int32_t)nd;
+        G.dstride = 2;
+        // CSR: the ring-pair planes of each data plane, in increasing ring-pair plane order
+        T.cstart.assign(nd + 1, 0);
+        for (int q = 0; q < base; ++q) T.cstart[owner[q] + 1] += 1;
+        for (int64_t q = 0; q < nd; ++q) T.cstart[q + 1] += T.cstart[q];
+        T.clist.resize(base);
+        std::vector<int32_t> fill(T.cstart.begin(), T.cstart.end() - 1);
+        for (int q = 0; q < base; ++q) T.clist[fill[owner[q]]++] = q;
+    }
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 size_t table_bytes(const HostTables& T) {
     return align256(T.ang.size() * sizeof(AngleDev)) + align256(T.sa.size() * sizeof(SegAngleDev)) +
-           align256(T.plane_seg.size() * sizeof(int32_t));
+           align256(T.plane_seg.size() * sizeof(int32_t)) + align256(T.kpos.size() * 8) +
+           align256(T.kobl.size() * 8) + align256(T.kL.size() * 4) + align256(T.cstart.size() * 4) +
+           align256(T.clist.size() * 4);
 }
 
 // Copy the tables to `dev` (table_bytes long, device memory) on `st` and point G at them.
@@ -228,6 +337,23 @@ int upload_tables(HostTables& T, char* dev, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(p, T.plane_seg.data(), T.plane_seg.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, st));
     T.G.plane_seg = (const int32_t*)p;
+    p += align256(T.plane_seg.size() * sizeof(int32_t));
+    // optional tables (scanner model, span compression): NULL when empty
+    auto put = [&](const void* src, size_t bytes) -> const void* {
+        if (bytes == 0) return nullptr;
+        void* dst = p;
+        p += align256(bytes);
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess
+                   ? dst : (const void*)-1;
+    };
+    T.G.kpos = (const double*)put(T.kpos.data(), T.kpos.size() * 8);
+    T.G.kobl = (const double*)put(T.kobl.data(), T.kobl.size() * 8);
+    T.G.kL = (const float*)put(T.kL.data(), T.kL.size() * 4);
+    T.G.cstart = (const int32_t*)put(T.cstart.data(), T.cstart.size() * 4);
+    T.G.clist = (const int32_t*)put(T.clist.data(), T.clist.size() * 4);
+    for (const void* q : {(const void*)T.G.kpos, (const void*)T.G.kobl, (const void*)T.G.kL,
+                          (const void*)T.G.cstart, (const void*)T.G.clist})
+        if (q == (const void*)-1) return fail(SPDHG_E_HIP, "copying the scanner tables failed");
     return SPDHG_OK;
 }
 
@@ -282,7 +408,10 @@ int axial_pad(const HostTables& T) {
             const SegAngleDev& S = T.sa[a * ns + g];
             m = std::max(m, std::fabs(S.ez_dj) * T.ang[a].cj + std::fabs(S.ez_dk) * T.G.ck);
         }
-    return (int)std::ceil(m) + 2;
+    // scanner model: |kpos| <= ck (|sin x| <= |x|), both coefficients scaled by kobl
+    double f = 1.0;
+    for (double v : T.kobl) f = std::max(f, v);
+    return (int)std::ceil(m * f) + 2;
 }
 
 // Rays per lane of the forward kernel: smallest supported power of two >= planes / 64.
@@ -359,7 +488,7 @@ int launch_fwd_ps(const FwdArgs& A, int nblk, hipStream_t st) {
 // walk over 2, 4 or 8 wavefronts (a single angle has only n_rad ray bundles), unless
 // A.split fixes the split (the autotuner's choice).
 template <int MODE>
-int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
+int launch_walk(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     A.ang0 = ang0;
     A.ang_step = step;
     A.n_ang_sub = cnt;
@@ -381,6 +510,30 @@ int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
     }
 }
 
+// The forward projection of the angles ang0 + i * step (i < cnt) with the epilogue MODE.
+// With span compression the walk writes ray sums to A.raw (A.raw_angles angles at a time)
+// and fwd_compress adds each data bin's ring-pair rays before the epilogue.
+template <int MODE>
+int launch_fwd(FwdArgs A, int ang0, int step, int cnt, hipStream_t st) {
+    if (!A.G.cstart) return launch_walk<MODE>(A, ang0, step, cnt, st);
+    if (!A.raw || A.raw_angles <= 0)
+        return fail(SPDHG_E_WORKSPACE, "no ray-sum rows for the span-compressed projection");
+    for (int c0 = 0; c0 < cnt; c0 += A.raw_angles) {
+        const int cc = std::min(A.raw_angles, cnt - c0);
+        FwdArgs R = A;
+        R.raw_kq = 1;
+        int rc = launch_walk<MODE>(R, ang0 + c0 * step, step, cc, st);
+        if (rc) return rc;
+        FwdArgs C = A;
+        C.ang0 = ang0 + c0 * step;
+        C.ang_step = step;
+        C.n_ang_sub = cc;
+        C.ia0 = A.ia0 + c0;
+        if ((rc = klaunch(fwd_compress<MODE>, cc * A.G.n_rad, 256, 0, st, C))) return rc;
+    }
+    return SPDHG_OK;
+}
+
 int bwd_cols(int nz) { return nz < BWD_THREADS ? BWD_THREADS / nz : 1; }
 
 // Backprojection kernel choice: the strip gather for 32 <= nz <= 127; else the per-column
@@ -394,12 +547,30 @@ struct BwdPlan {
     size_t lds = 0; // per wavefront
 };
 
+// Smallest distance of neighbouring radial bins in secondary voxel units (non-arc-corrected
+// bins are closer towards the edge of the field of view).
+double min_bin_spacing(const HostTables& T) {
+    double min_du = 1e30;
+    for (const AngleDev& A : T.ang) min_du = std::min(min_du, std::fabs(A.du_dk));
+    double dk = 1.0;
+    for (size_t k = 1; k < T.kpos.size(); ++k) dk = std::min(dk, T.kpos[k] - T.kpos[k - 1]);
+    return min_du * dk;
+}
+
+// The per-column gather keeps BWD_KC candidate bins per column and angle: bins at least
+// half a voxel apart.
+int check_column_gather(const HostTables& T) {
+    if (!(min_bin_spacing(T) >= 0.5))
+        return fail(SPDHG_E_SHAPE, "radial bins closer than half a voxel: only the strip gather "
+                                   "(32 <= nz <= 127, one plane pitch) handles them");
+    return SPDHG_OK;
+}
+
 BwdPlan bwd_plan(const HostTables& T) {
     BwdPlan pl;
     const int nz = T.G.nz, ns = T.G.n_seg;
-    double min_du = 1e30;
-    for (const AngleDev& A : T.ang) min_du = std::min(min_du, std::fabs(A.du_dk));
-    if (nz < 32 || nz > 127 || !(min_du >= 0.5)) return pl;
+    const double min_du = min_bin_spacing(T);
+    if (nz < 32 || nz > 127 || !(min_du >= 0.25)) return pl;
     for (int g = 1; g < ns; ++g)
         if (T.G.seg_pitch[g] != T.G.seg_pitch[0]) return pl;  // mixed pitches: per column
     const int KR = (int)std::ceil((BS_W + 1) / min_du) + 6;
@@ -533,6 +704,8 @@ struct spdhg_ctx {
     // workspace regions (internal layouts: images z-fastest, sinograms [a][k][q])
     float *bp = nullptr, *rp = nullptr, *mp = nullptr;  // private b, r, mult
     float *y = nullptr, *sigma = nullptr, *dscr = nullptr;
+    float* raw = nullptr;  // span compression: ray sums before the data bins are summed
+    int raw_angles = 0;
     float *xa = nullptr, *xb = nullptr, *z = nullptr, *T = nullptr, *scr = nullptr;
     float *yn[2] = {nullptr, nullptr}, *xi = nullptr;
     // TGV: w (ping-pong), z_w, q2 (ping-pong); data iterations owe w the line-3 steps
@@ -575,6 +748,8 @@ struct spdhg_ctx {
         A.G = tab.G;
         A.pad = pad;
         A.gsize = gsize;
+        A.raw = raw;
+        A.raw_angles = raw_angles;
         return A;
     }
     BwdArgs bwd_args() const {
@@ -609,19 +784,22 @@ struct spdhg_ctx {
 namespace {
 
 struct Layout {
-    size_t tables, bp, rp, mp, y, sigma, dscr, xa, xb, z, T, scr, yn, xi, w, zw, q2, em, part,
-        scal, total;
-    int64_t part_n;
+    size_t tables, bp, rp, mp, y, sigma, dscr, raw, xa, xb, z, T, scr, yn, xi, w, zw, q2, em,
+        part, scal, total;
+    int64_t part_n, raw_angles;
 };
 
 Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab) {
     Layout L{};
     const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
-    const int64_t np = n_planes(g);
+    const int64_t np = n_data_planes(g);
     const int64_t nb = (int64_t)g->n_ang * np * g->n_rad;
     const int m = std::max(1, p->n_subsets);
     // dual change of the largest subset (see dual_row)
     const int64_t max_sub = (int64_t)((g->n_ang + m - 1) / m) * g->n_rad * np;
+    // span compression: ray sums of the largest subset's angles (longer launches, such as
+    // the objective's, go through in chunks of that many angles)
+    L.raw_angles = g->span ? (g->n_ang + m - 1) / m : 0;
     const bool prior = p->prior != SPDHG_PRIOR_NONE;
     const bool tgv = p->prior == SPDHG_PRIOR_TGV;
     size_t off = 0;
@@ -637,6 +815,7 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
     L.y = take(nb * 4);
     L.sigma = take(p->precond ? nb * 4 : 0);
     L.dscr = take(max_sub * 4);
+    L.raw = take(L.raw_angles * g->n_rad * n_planes(g) * 4);
     L.xa = take(nv * 4);
     L.xb = take(nv * 4);
     L.z = take(nv * 4);
@@ -850,14 +1029,14 @@ int scratch_ptr(char** out) {
 constexpr int OP_CHUNK = 16;
 
 struct OpLayout {
-    size_t tables, img, img2, rows, part, total;
-    size_t project_total;  // what spdhg_project uses: the tables and the first image
+    size_t tables, img, raw, img2, rows, part, total;
+    size_t project_total;  // what spdhg_project uses: the tables, the first image, raw rows
 };
 
 OpLayout op_layout(const spdhg_geom* g, const HostTables& T) {
     OpLayout L{};
     const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
-    const int64_t np = n_planes(g);
+    const int64_t np = n_data_planes(g);
     const int64_t nb = (int64_t)g->n_ang * np * g->n_rad;
     const int64_t chunk = std::min(g->n_ang, OP_CHUNK);
     size_t off = 0;
@@ -868,6 +1047,8 @@ OpLayout op_layout(const spdhg_geom* g, const HostTables& T) {
     };
     L.tables = take(table_bytes(T));
     L.img = take(nv * 4);
+    // span compression: the ray sums of OP_CHUNK angles before their data bins are summed
+    L.raw = take(g->span ? chunk * g->n_rad * n_planes(g) * 4 : 0);
     L.project_total = off;
     L.img2 = take(nv * 4);
     L.rows = take(chunk * g->n_rad * np * 4);
@@ -878,7 +1059,7 @@ OpLayout op_layout(const spdhg_geom* g, const HostTables& T) {
 
 struct OpWork {
     HostTables tab;
-    float *img = nullptr, *img2 = nullptr, *rows = nullptr;
+    float *img = nullptr, *img2 = nullptr, *rows = nullptr, *raw = nullptr;
     double* part = nullptr;
     int pad = 0;
     BwdPlan plan;
@@ -899,11 +1080,13 @@ int op_begin(const spdhg_geom* g, void* ws, size_t ws_bytes, hipStream_t st, OpW
     int rc = upload_tables(W.tab, w + L.tables, st);
     if (rc) return rc;
     W.img = (float*)(w + L.img);
+    W.raw = g->span ? (float*)(w + L.raw) : nullptr;
     W.img2 = (float*)(w + L.img2);
     W.rows = (float*)(w + L.rows);
     W.part = (double*)(w + L.part);
     W.pad = axial_pad(W.tab);
     W.plan = bwd_plan(W.tab);
+    if (!W.plan.strip && (rc = check_column_gather(W.tab))) return rc;
     return SPDHG_OK;
 }
 
@@ -920,6 +1103,8 @@ int project_zf_scratch(const spdhg_geom* g, const OpWork& W, const float* mult, 
     F.x = W.img;
     F.mult = mult;
     F.out = y_out;
+    F.raw = W.raw;
+    F.raw_angles = std::min(g->n_ang, OP_CHUNK);
     return launch_fwd<F_PLAIN_QK>(F, a0, step, cnt, st);
 }
 
@@ -936,8 +1121,8 @@ int backproject_acc(const spdhg_geom* g, const OpWork& W, const float* y, const 
     for (int c0 = 0; c0 < cnt; c0 += chunk) {
         const int cc = std::min(chunk, cnt - c0);
         const int cang0 = a0 + c0 * step;
-        const int64_t nsub = (int64_t)cc * G.n_planes * G.n_rad;
-        to_rows<<<nblocks(nsub), BLOCK, 0, st>>>(G, y + (int64_t)c0 * G.n_planes * G.n_rad, 1,
+        const int64_t nsub = (int64_t)cc * G.n_dplanes * G.n_rad;
+        to_rows<<<nblocks(nsub), BLOCK, 0, st>>>(G, y + (int64_t)c0 * G.n_dplanes * G.n_rad, 1,
                                                    mult, cang0, step, cc, W.rows);
         LAUNCH_CHECK();
         BwdArgs B{};
@@ -961,7 +1146,7 @@ int64_t spdhg_subset_bins(const spdhg_geom* geom, int32_t n_subsets, int32_t sub
     if (check_geom(geom)) return -1;
     int a0, st, cnt;
     if (subset_angles(geom, n_subsets, subset, a0, st, cnt)) return -1;
-    return (int64_t)cnt * n_planes(geom) * geom->n_rad;
+    return (int64_t)cnt * n_data_planes(geom) * geom->n_rad;
 }
 
 int spdhg_op_workspace_bytes(const spdhg_geom* geom, size_t* bytes) {
@@ -1128,6 +1313,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     c->gsize = geom->nz + 2 * c->pad;
     c->bplan = bwd_plan(c->tab);
     c->bplan_auto = c->bplan;
+    if (!c->bplan.strip && (rc = check_column_gather(c->tab))) return bail(rc);
     c->side = side;
     c->x_user = x;
     c->bp = (float*)(w + L.bp);
@@ -1136,6 +1322,8 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     c->y = (float*)(w + L.y);
     c->sigma = params->precond ? (float*)(w + L.sigma) : nullptr;
     c->dscr = (float*)(w + L.dscr);
+    c->raw = L.raw_angles ? (float*)(w + L.raw) : nullptr;
+    c->raw_angles = (int)L.raw_angles;
     c->xa = (float*)(w + L.xa);
     c->xb = (float*)(w + L.xb);
     c->z = (float*)(w + L.z);
@@ -1143,7 +1331,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     c->scr = (float*)(w + L.scr);
     const bool prior = params->prior != SPDHG_PRIOR_NONE;
     c->nv = (int64_t)geom->nx * geom->ny * geom->nz;
-    c->nb = (int64_t)geom->n_ang * c->tab.G.n_planes * geom->n_rad;
+    c->nb = (int64_t)geom->n_ang * c->tab.G.n_dplanes * geom->n_rad;
     if (prior) {
         c->yn[0] = (float*)(w + L.yn);
         c->yn[1] = c->yn[0] + 3 * c->nv;
@@ -1193,7 +1381,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     c->iters_per_epoch = (int64_t)std::llround(c->m / pdata);
     const int64_t nv = c->nv, nb = c->nb;
     const double gam = params->gamma, rho = params->rho;
-    const int np = c->tab.G.n_planes;
+    const int np = c->tab.G.n_dplanes;
 
     // private copies of b, r, mult in the [a][k][q] layout
     {
@@ -1223,7 +1411,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return bail(fail(SPDHG_E_HIP, hipGetErrorString(e)));
         if (h[0] > 0)
-            return bail(fail(SPDHG_E_DOMAIN, "b < 0, r < 0, mult <= 0 or non-finite data in " +
+            return bail(fail(SPDHG_E_DOMAIN, "b < 0, r < 0, mult < 0 or non-finite data in " +
                                                  std::to_string((long long)h[0]) + " bins"));
         if (h[1] > 0)
             return bail(fail(SPDHG_E_DOMAIN, std::to_string((long long)h[1]) +
@@ -2080,7 +2268,7 @@ int spdhg_set_tuning(spdhg_ctx* c, int32_t fwd_split) {
 static bool gather_plan(const spdhg_ctx* c, int gather, BwdPlan& out) {
     if (gather == 2) {
         out = BwdPlan{};
-        return true;
+        return min_bin_spacing(c->tab) >= 0.5;
     }
     if (!c->bplan_auto.strip) return false;
     out = c->bplan_auto;

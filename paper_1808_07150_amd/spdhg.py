@@ -48,7 +48,9 @@ class CGeom(ctypes.Structure):
                 ("n_ang", ctypes.c_int32), ("n_seg", ctypes.c_int32),
                 ("seg_planes", ctypes.c_int32 * MAX_SEG),
                 ("seg_tan", ctypes.c_double * MAX_SEG),
-                ("seg_pitch", ctypes.c_int32 * MAX_SEG)]
+                ("seg_pitch", ctypes.c_int32 * MAX_SEG),
+                ("det_radius", ctypes.c_double), ("nonarc", ctypes.c_int32),
+                ("oblique_s", ctypes.c_int32), ("span", ctypes.c_int32)]
 
 
 class CParams(ctypes.Structure):
@@ -144,6 +146,10 @@ def cgeom(g) -> CGeom:
         s.seg_planes[i] = n
         s.seg_tan[i] = t
         s.seg_pitch[i] = pt
+    s.det_radius = float(getattr(g, "det_radius", 0.0))
+    s.nonarc = int(bool(getattr(g, "nonarc", False)))
+    s.oblique_s = int(bool(getattr(g, "oblique_s", False)))
+    s.span = int(getattr(g, "span", 0))
     return s
 
 
@@ -373,7 +379,7 @@ class Reconstruction:
         if not caller_layout:
             return out
         g = self.g
-        n_planes = sum(g.seg_planes)
+        n_planes = g.sino_shape[1] if hasattr(g, "sino_shape") else sum(g.seg_planes)
         if name in ("y", "sigma"):
             return out.view(g.n_ang, g.n_rad, n_planes).permute(0, 2, 1).contiguous()
         if name in ("prior_dual", "w", "q2", "zw"):

@@ -11,8 +11,11 @@ from typing import Dict, Iterable, Optional
 
 def shape_key(g, n_subsets: int) -> str:
     """Problems with equal keys launch identically shaped projections."""
+    scanner = (f"-R{g.det_radius:g}-na{int(g.nonarc)}-os{int(g.oblique_s)}-span{g.span}"
+               if getattr(g, "nonarc", False) or getattr(g, "oblique_s", False)
+               or getattr(g, "span", 0) else "")
     return (f"img{g.nx}x{g.ny}x{g.nz}-sino{g.n_rad}x{g.n_ang}x{sum(g.seg_planes)}"
-            f"-seg{len(g.seg_planes)}-m{n_subsets}")
+            f"-seg{len(g.seg_planes)}-m{n_subsets}{scanner}")
 
 
 def load_cache(path: Optional[str]) -> Dict[str, dict]:

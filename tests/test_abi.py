@@ -122,3 +122,31 @@ def test_library_allocates_no_device_memory():
     for name in sorted(os.listdir(csrc)):
         text = open(os.path.join(csrc, name)).read()
         assert not banned.search(text), name
+
+
+def test_scanner_model_geometry_on_the_host(lib):
+    """The library's own count of span-compressed data planes (host code) matches the
+    mMR's 837 (and the oracle's count on a small geometry); invalid scanner geometries are
+    rejected with a shape error before anything reaches a GPU."""
+    import dataclasses
+
+    import paper_1808_07150_amd as P
+    from oracle import projector as OP
+    g = synth.mmr_scanner()
+    assert P.subset_bins(g, 21, 0) == 12 * 837 * 344
+    assert P.subset_bins(g, 21, -1) == 252 * 837 * 344
+    small = synth.scanner_small()
+    assert P.subset_bins(small, 1, -1) == small.n_ang * OP.n_data_planes(small) * small.n_rad
+    span1 = dataclasses.replace(small, span=0)
+    assert P.subset_bins(span1, 1, -1) == small.n_ang * small.n_planes * small.n_rad
+    for bad in (dict(span=4), dict(span=1), dict(det_radius=0.0),
+                dict(det_radius=30.0)):  # bin angles past 1.5 rad
+        c = P.cgeom(small)
+        for k, v in bad.items():
+            setattr(c, k, v)
+        assert lib.spdhg_subset_bins(ctypes.byref(c), 1, 0) == -1, bad
+    # span compression needs the ring-pair segments
+    c = P.cgeom(synth.small_3d())
+    c.span = 3
+    assert lib.spdhg_subset_bins(ctypes.byref(c), 1, 0) == -1
+    assert P.op_workspace_bytes(g) > 0

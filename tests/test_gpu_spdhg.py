@@ -359,6 +359,22 @@ def test_domain_errors(P, c1):
     with pytest.raises(SpdhgError) as e:
         P.Reconstruction(g, P.cparams(10, "tv"), dev(b), dev(r), dev(c1["mult"]), x)
     assert e.value.code == -3
+    # mult < 0 is outside the model; mult = 0 (zero efficiency, e.g. a detector gap) is a
+    # zero row of A: rejected only where b > 0 and r = 0 make the objective infinite
+    mult = c1["mult"].copy()
+    mult[2, 0, 30] = -0.5
+    with pytest.raises(SpdhgError) as e:
+        P.Reconstruction(g, P.cparams(10, "tv"), dev(c1["b"]), dev(c1["r"]), dev(mult), x)
+    assert e.value.code == -3
+    mult = c1["mult"].copy()
+    b, r = c1["b"].copy(), c1["r"].copy()
+    mult[2, 0, 30] = 0.0
+    b[2, 0, 30], r[2, 0, 30] = 4.0, 0.0
+    with pytest.raises(SpdhgError) as e:
+        P.Reconstruction(g, P.cparams(10, "tv"), dev(b), dev(r), dev(mult), x)
+    assert e.value.code == -3
+    b[2, 0, 30] = 0.0
+    P.Reconstruction(g, P.cparams(10, "tv"), dev(b), dev(r), dev(mult), x).close()
 
 
 def _batch_problems():

@@ -269,3 +269,29 @@ def test_mlem_is_osem_with_one_subset_and_increases_likelihood():
         ll_new = S.poisson_loglik(prob1, un)
         assert ll_new >= ll - 1e-9 * abs(ll)
         u, ll = un, ll_new
+
+
+@pytest.mark.parametrize("precond", [True, False])
+def test_zero_efficiency_bins_drop_out(precond):
+    """A bin with mult = 0 (a detector gap) has a zero row of A: its term phi_j(0) is a
+    constant, its dual never moves, and the iterates do not depend on its data.  Two
+    problems that differ only in b, r on such bins (b = 0, r = 0 against b = 0, r = 5)
+    give bitwise equal iterates; negative mult is rejected."""
+    g, b, r, mult = tiny_problem(seed=9)
+    gap = np.zeros(g.sino_shape, dtype=bool)
+    gap[:, :, 2] = True
+    gap[3::4, :, 7] = True
+    mult = np.where(gap, 0.0, mult)
+    b = np.where(gap, 0.0, b)
+    out = []
+    for rv in (0.0, 5.0):
+        rr = np.where(gap, rv, r)
+        prob = S.Problem(g, b, rr, mult, n_subsets=4, prior="tv", alpha=0.05,
+                         sampling="balanced", precond=precond)
+        st = S.spdhg(prob, 3 * prob.iters_per_epoch(), seed=4)
+        x = prob.reported(st)[0]
+        assert np.all(np.isfinite(x))
+        out.append(x)
+    np.testing.assert_array_equal(out[0], out[1])
+    with pytest.raises(ValueError):
+        S.Problem(g, b, r, np.where(gap, -1.0, mult), n_subsets=4, prior="tv", alpha=0.05)
