@@ -54,6 +54,14 @@ WORKLOADS = {
                                  "differences up to 60: 121 segments, 354M bins), TV "
                                  "beta=2e-3 + nonneg, 21 subsets, SPDHG+ (balanced, "
                                  "preconditioned), 1e8 counts"),
+    "mmr-scanner-tv21": dict(m=21, prior="tv", counts=1e8, alpha=2e-3, alpha1=0.0, prior_bpv=44,
+                             geometry="scanner",
+                             label="mMR closer scanner model: span-11 data 344x252x837 as sums "
+                                   "of the 4084 ring-pair planes (64 rings, ring differences up "
+                                   "to 60), non-arc-corrected radial bins and s-dependent "
+                                   "slopes on a 328 mm ring, detector gaps (1 in 9), image "
+                                   "344x344x127, TV beta=2e-3 + nonneg, 21 subsets, SPDHG+, 1e8 "
+                                   "counts"),
 }
 HBM_PEAK_GBS = 8000.0
 # MI355X's published FP32 vector peak (256 CUs at 2.4 GHz, packed FP32 FMA); the kernels
@@ -504,11 +512,13 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch, dev)
     wl = WORKLOADS[args.workload]
-    g = synth.mmr_span1() if wl.get("geometry") == "span1" else synth.mmr()
+    g = {"span1": synth.mmr_span1, "scanner": synth.mmr_scanner}.get(wl.get("geometry"),
+                                                                      synth.mmr)()
     m = wl["m"]
     t0 = time.time()
     if args.inputs == "phantom":
-        d = brain_problem_torch(g, SEED, wl["counts"], dev, with_side=wl["prior"] == "dtv")
+        d = brain_problem_torch(g, SEED, wl["counts"], dev, with_side=wl["prior"] == "dtv",
+                                gaps=wl.get("geometry") == "scanner")
     else:
         torch.manual_seed(SEED)
         mean = wl["counts"] / g.n_bins

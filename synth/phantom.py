@@ -317,7 +317,7 @@ def _torch_chords(torch, g: Geometry, angles, e: Ellipsoid, device):
     r = torch.as_tensor(radial_positions(g), dtype=f64, device=device)[None, None, :]
     zp = torch.cat([(torch.arange(n, dtype=f64, device=device) - 0.5 * (n - 1)) * pt * g.vz
                     for n, pt in zip(g.seg_planes, g.pitches)])[None, :, None]
-    tau = torch.as_tensor(np.ascontiguousarray(_ray_slopes(g, radial_positions(g))),
+    tau = torch.as_tensor(np.array(_ray_slopes(g, radial_positions(g)), dtype=np.float64),
                           dtype=f64, device=device)[None, :, :]
     ct, st = math.cos(e.theta), math.sin(e.theta)
     ox, oy, oz = r * c - e.cx, r * s - e.cy, zp - e.cz
