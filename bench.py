@@ -353,32 +353,29 @@ def run_to_target(P, torch, g, d, prm, x0, psi0, psi_star, target=1e-3, max_epoc
     return t_ms * 1e-3, done / ipe, bool(rel <= target)
 
 
-def gamma_sweep_leg(P, torch, g, d, wl, seed, split,
-                    gammas=(0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0)):
-    """Step-size balance gamma of Theorem 2 (S_i = gamma rho / A_i 1, T_i = rho p_i /
-    (gamma A_i^T 1); prior blocks scalar): the paper runs gamma = 1 and leaves its tuning
-    open (Discussion).  Time to 1e-3 relative objective from x^0 = 0 for each gamma on the
-    same data, with Psi(x^0) and Psi* shared (Psi* from 200 epochs at gamma = 1)."""
+def sweep_leg(P, torch, g, d, wl, seed, split, psi0, psi_star, ref_info, kind, values):
+    """Time to 1e-3 relative objective from x^0 = 0 on the same data for each value of a
+    step or sampling parameter, with Psi(x^0) and Psi* shared (the reference minimum of
+    the headline measurement).  kind "gamma": the step-size balance of Theorem 2 (S_i =
+    gamma rho / A_i 1, T_i = rho p_i / (gamma A_i^T 1); the paper runs gamma = 1 and leaves
+    its tuning open, Discussion); kind "p_prior": a constant tuned sampling (Discussion) in
+    which the prior block is drawn with probability p_prior and each of the m data blocks
+    with (1 - p_prior) / m (balanced sampling is p_prior = 1/2)."""
     m = wl["m"]
     dev = d["b"].device
-    base = P.cparams(m, wl["prior"], "balanced", True, alpha=wl["alpha"], alpha1=wl["alpha1"],
-                     seed=seed)
-    x = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
-    ref = P.Reconstruction(g, base, d["b"], d["r"], d["mult"], x)
-    psi0 = float(ref.objective()[0].item())
-    ref.epoch(200)
-    psi_star = float(ref.objective()[0].item())
-    ref.close()
     rows = []
-    for gm in gammas:
-        prm = P.cparams(m, wl["prior"], "balanced", True, alpha=wl["alpha"],
-                        alpha1=wl["alpha1"], gamma=gm, seed=seed)
+    for v in values:
+        kw = dict(alpha=wl["alpha"], alpha1=wl["alpha1"], seed=seed)
+        if kind == "gamma":
+            prm = P.cparams(m, wl["prior"], "balanced", True, gamma=v, **kw)
+        else:
+            prm = P.cparams(m, wl["prior"], "custom", True, p_prior=v, **kw)
         zero = torch.zeros(g.image_shape, dtype=torch.float32, device=dev)
         t, ep, ok = run_to_target(P, torch, g, d, prm, zero, psi0, psi_star, split=split)
-        rows.append({"gamma": gm, "seconds": round(t, 4), "epochs": round(ep, 2), "reached": ok})
-        log(f"gamma {gm}: {t:.4f} s, {ep:.2f} epochs to 1e-3")
-    return {"target_rel_objective": 1e-3, "psi_star_from": "200 epochs at gamma = 1",
-            "per_gamma": rows}
+        rows.append({kind: v, "seconds": round(t, 4), "epochs": round(ep, 2), "reached": ok})
+        log(f"{kind} {v}: {t:.4f} s, {ep:.2f} epochs to 1e-3")
+    return {"target_rel_objective": 1e-3, "psi_star_from": ref_info.get("psi_star_from"),
+            "rows": rows}
 
 
 def warm_start_leg(P, torch, n_train=200, n_test=20, train_passes=12, seed=18080400):
@@ -482,6 +479,9 @@ def main():
     ap.add_argument("--gamma-sweep", action="store_true",
                     help="also measure the time to 1e-3 for step balances gamma = 0.25 .. 32 "
                          "(the headline value stays at the paper's gamma = 1)")
+    ap.add_argument("--p-sweep", action="store_true",
+                    help="also measure the time to 1e-3 for a tuned constant sampling: prior "
+                         "block probability p_prior = 0.1 .. 0.8 (balanced is 0.5)")
     ap.add_argument("--batch", action="store_true",
                     help="also measure batched reconstructions (64 mixed problems, inputs "
                          "generated on the host)")
@@ -653,8 +653,19 @@ def main():
                                                ref_info, split=split)
         log(f"time to 1e-3 relative objective: {out['time_to_target']['seconds']} s "
             f"({out['time_to_target']['epochs']} epochs; measured in {time.time() - t0:.1f} s)")
-    if args.gamma_sweep:
-        out["gamma_sweep"] = gamma_sweep_leg(P, torch, g, d, wl, SEED, split)
+    if args.gamma_sweep or args.p_sweep:
+        if args.no_time_to_target:
+            psi0_ref, psi_star, ref_info = reference_minimum(
+                P, torch, g, d, wl, SEED, ref_epochs=200 if m <= 21 else 40,
+                pdhg_iters=args.pdhg_iters, split=split)
+        if args.gamma_sweep:
+            out["gamma_sweep"] = sweep_leg(P, torch, g, d, wl, SEED, split, psi0_ref, psi_star,
+                                           ref_info, "gamma",
+                                           (0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0))
+        if args.p_sweep:
+            out["p_prior_sweep"] = sweep_leg(P, torch, g, d, wl, SEED, split, psi0_ref,
+                                             psi_star, ref_info, "p_prior",
+                                             (0.1, 0.2, 0.35, 0.5, 0.65, 0.8))
     if args.warm_start:
         t0 = time.time()
         out["warm_start"] = warm_start_leg(P, torch, n_train=args.ws_train, n_test=args.ws_test,
