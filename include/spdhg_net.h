@@ -2,9 +2,10 @@
  *
  * Not part of the paper's method: a small 3-D convolutional encoder-decoder maps the
  * normalised backprojection of the data to an initial image for SPDHG (Algorithm 2 then
- * runs from it unchanged).  These entry points are its building blocks; the network,
- * its training on SPDHG MAP solutions and the warm-started reconstruction are assembled
- * from them by the Python binding (paper_1808_07150_amd/warmstart.py).
+ * runs from it unchanged).  spdhg_ws_infer / spdhg_ws_gradients / spdhg_ws_train_step
+ * run the whole network (forward, backpropagation, Adam) from parameter blobs and a
+ * caller-owned workspace; the single-kernel entry points below them are its building
+ * blocks.  The input image comes from spdhg_normalised_backprojection (spdhg.h).
  *
  * Conventions.  All pointers are device pointers on the current HIP device; nothing is
  * allocated and nothing is freed.  Volumes are dims = {ny, nx, nz}.  Activations are
@@ -81,6 +82,49 @@ int spdhg_net_adam(int64_t n, float lr, float b1, float b2, float eps, int64_t s
 
 /* FP32 weights [tap][co][ci] -> packed BF16 [tap][ci / 16][co][16]. */
 int spdhg_net_pack_weights(int32_t cin, int32_t cout, const float* w32, uint16_t* w16, void* stream);
+
+/* ---- the whole network ------------------------------------------------------------
+ * Layers c1 .. c11 (cin -> cout, ReLU): 16->16, 16->16 (ReLU, full resolution, e1);
+ * 16->32, 32->32 (half, e2); 32->64, 64->64 (quarter, b); 64->32 after nearest 2x up,
+ * then + e2, 32->32 (half, d2); 32->16 after up, then + e1, 16->16 (full, d1); 16->16
+ * linear (c11).  Pooling is 2x2x2 averaging.  Output image = input + channel 0 of c11
+ * (divided by scale).  Volumes dims = {ny, nx, nz}, each a positive multiple of 4; images
+ * are FP32 [ny][nx][nz].
+ * Parameters: an FP32 blob of n32 values (per layer in order: weights [27][cout][cin],
+ * then bias [cout]) and a packed BF16 blob of n16 values (per layer: the weights packed as
+ * by spdhg_net_pack_weights); spdhg_ws_param_offsets gives layer l's offsets (elements). */
+int spdhg_ws_param_count(int64_t* n32, int64_t* n16);
+int spdhg_ws_param_offsets(int32_t layer, int64_t* w32, int64_t* b32, int64_t* w16);
+
+/* The packed BF16 blob from the FP32 blob (every layer). */
+int spdhg_ws_pack(const float* p32, uint16_t* w16, void* stream);
+
+/* Bytes of device workspace for a volume: train = 0 for spdhg_ws_infer (activations),
+ * 1 for spdhg_ws_gradients / spdhg_ws_train_step (also gradients and partials).  -2 if
+ * dims are not positive multiples of 4. */
+int spdhg_ws_workspace_bytes(const int32_t dims[3], int32_t train, size_t* bytes);
+
+/* out = network(img) (scale: brings img to order one, e.g. 1 / its mean over the
+ * support).  ws: device workspace (256-byte aligned, at least the train = 0 size), owned
+ * by the caller, nothing allocated; -5 if too small. */
+int spdhg_ws_infer(const int32_t dims[3], const float* p32, const uint16_t* w16, float scale,
+                   const float* img, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Loss 0.5 sum_v (net(img)_v - target_v)^2 scale^2 (FP64, device scalar *loss, or NULL)
+ * and its gradient with respect to every parameter (grads: n32 FP32, blob layout).  BF16
+ * activations and gradients, FP32 accumulation; deterministic.  ws: at least the
+ * train = 1 size. */
+int spdhg_ws_gradients(const int32_t dims[3], const float* p32, const uint16_t* w16, float scale,
+                       const float* img, const float* target, float* grads, double* loss,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* One training step: spdhg_ws_gradients, one Adam step (lr, beta 0.9 / 0.999, eps 1e-8,
+ * bias-corrected at `step` >= 1) on p32 with moments adam_m, adam_v (n32 each), and the
+ * new packed w16. */
+int spdhg_ws_train_step(const int32_t dims[3], float* p32, uint16_t* w16, float* adam_m,
+                        float* adam_v, int64_t step, float lr, float scale, const float* img,
+                        const float* target, double* loss, void* ws, size_t ws_bytes,
+                        void* stream);
 
 #ifdef __cplusplus
 }

@@ -445,6 +445,27 @@ __global__ void pack_weights(int cin, int cout, const float* __restrict__ w32, u
     w16[(((int64_t)t * (cin / 16) + ci / 16) * cout + co) * 16 + ci % 16] = f2bf(w32[e]);
 }
 
+// Zero fill of n 16-bit values (a kernel rather than a memset node: safe under graph capture).
+__global__ void fill_zero_u16(int64_t n, uint16_t* __restrict__ a) {
+    const int64_t t = (int64_t)blockIdx.x * NET_BLOCK + threadIdx.x;
+    if (t < n) a[t] = 0;
+}
+
+// out[0] = sum of n FP64 partials in a fixed order (one block: strided per-thread sums,
+// then the threads' sums in index order).
+__global__ void sum_parts(const double* __restrict__ part, int64_t n, double* __restrict__ out) {
+    __shared__ double s[256];
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) v += part[i];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 256; ++i) t += s[i];
+        out[0] = t;
+    }
+}
+
 }  // namespace wsnet
 
 // ====================================================================== C ABI
@@ -644,6 +665,303 @@ int spdhg_net_pack_weights(int32_t cin, int32_t cout, const float* w32, uint16_t
     pack_weights<<<nblk(27LL * cin * cout), NET_BLOCK, 0, (hipStream_t)stream>>>(cin, cout, w32, w16);
     NET_CHECK();
     return 0;
+}
+
+// ---------------------------------------------------------------- the network as a whole
+// Encoder-decoder of 11 3x3x3 convolutions (channels 16/32/64, three resolutions):
+//   e1 = relu(c2(relu(c1(in))));  e2 = relu(c4(relu(c3(pool e1))));
+//   b = relu(c6(relu(c5(pool e2))));  d2 = relu(c8(relu(c7(up b)) + e2));
+//   d1 = relu(c10(relu(c9(up d2)) + e1));  image = in + channel 0 of c11(d1) (linear).
+static const int WS_CI[11] = {16, 16, 16, 32, 32, 64, 64, 32, 32, 16, 16};
+static const int WS_CO[11] = {16, 16, 32, 32, 64, 64, 32, 32, 16, 16, 16};
+static const int WS_RELU[11] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 0};
+static const int WS_LEVEL[11] = {0, 0, 1, 1, 2, 2, 1, 1, 0, 0, 0};  // resolution of the layer's input
+constexpr int WS_CHUNK = 4096;  // voxel chunk of the weight-gradient partials
+
+}  // extern "C"
+
+namespace {
+
+// Offsets (in elements) of layer l's FP32 weights [27][co][ci] and bias [co] in the FP32
+// parameter blob, and of its packed BF16 weights in the BF16 blob.
+struct WsParams {
+    int64_t w32[11], b32[11], w16[11], n32 = 0, n16 = 0;
+    WsParams() {
+        for (int l = 0; l < 11; ++l) {
+            const int64_t nw = 27LL * WS_CI[l] * WS_CO[l];
+            w32[l] = n32;
+            b32[l] = n32 + nw;
+            n32 += nw + WS_CO[l];
+            w16[l] = n16;
+            n16 += nw;
+        }
+    }
+};
+
+// Workspace carving: activations (and with train, gradients and partials), 256-byte aligned.
+struct WsLayout {
+    // activations: in c1 e1 p1 c3 e2 p2 c5 b u2 c7 s2 d2 u1 c9 s1 d1 out
+    size_t act[18];
+    // gradients
+    size_t gout, g10, g9in, g9, g9u, g8, g7in, g7, g7u, g6, g5, g5p, g5s, g4, g3, g3p, g3s, g2;
+    size_t wt, part, grads, lparts, total;
+    int64_t part_floats, nv;
+    int32_t dims[3][3];  // per level: ny, nx, nz
+};
+
+int ws_dims_ok(const int32_t d[3]) {
+    return d && d[0] >= 4 && d[1] >= 4 && d[2] >= 4 && d[0] % 4 == 0 && d[1] % 4 == 0 &&
+           d[2] % 4 == 0;
+}
+
+WsLayout ws_layout(const int32_t dims[3], bool train) {
+    WsLayout L{};
+    for (int lv = 0; lv < 3; ++lv)
+        for (int a = 0; a < 3; ++a) L.dims[lv][a] = dims[a] >> lv;
+    const int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
+    L.nv = nv;
+    const int64_t n[3] = {nv, nv / 8, nv / 64};
+    size_t off = 0;
+    auto take = [&](int64_t elems, int bytes_each) {
+        const size_t o = off;
+        off += ((size_t)elems * bytes_each + 255) & ~(size_t)255;
+        return o;
+    };
+    // level and channels of each activation, in the order of the comment above
+    const int lvl[18] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 1, 1, 0, 0, 0, 0, 0};
+    const int ch[18] = {16, 16, 16, 16, 32, 32, 32, 64, 64, 64, 32, 32, 32, 32, 16, 16, 16, 16};
+    for (int i = 0; i < 18; ++i) L.act[i] = take(n[lvl[i]] * ch[i], 2);
+    if (train) {
+        L.gout = take(n[0] * 16, 2);
+        L.g10 = take(n[0] * 16, 2);
+        L.g9in = take(n[0] * 16, 2);
+        L.g9 = take(n[0] * 32, 2);
+        L.g9u = take(n[1] * 32, 2);
+        L.g8 = take(n[1] * 32, 2);
+        L.g7in = take(n[1] * 32, 2);
+        L.g7 = take(n[1] * 64, 2);
+        L.g7u = take(n[2] * 64, 2);
+        L.g6 = take(n[2] * 64, 2);
+        L.g5 = take(n[2] * 32, 2);
+        L.g5p = take(n[1] * 32, 2);
+        L.g5s = take(n[1] * 32, 2);
+        L.g4 = take(n[1] * 32, 2);
+        L.g3 = take(n[1] * 16, 2);
+        L.g3p = take(n[0] * 16, 2);
+        L.g3s = take(n[0] * 16, 2);
+        L.g2 = take(n[0] * 16, 2);
+        L.wt = take(27LL * 64 * 64, 2);
+        int64_t pf = 0;
+        for (int l = 0; l < 11; ++l) {
+            const int64_t nvl = n[WS_LEVEL[l]];
+            pf = std::max<int64_t>(pf, std::max<int64_t>((nvl + WS_CHUNK - 1) / WS_CHUNK * 27 *
+                                                             WS_CI[l] * WS_CO[l],
+                                                         (nvl + 1023) / 1024 * WS_CO[l]));
+        }
+        L.part_floats = pf;
+        L.part = take(pf, 4);
+        L.grads = take(WsParams().n32, 4);
+        L.lparts = take((nv + 255) / 256, 8);
+    }
+    L.total = off;
+    return L;
+}
+
+#define WS_TRY(call)                \
+    do {                            \
+        const int rc_ = (call);     \
+        if (rc_ != 0) return rc_;   \
+    } while (0)
+
+// The forward pass into the workspace's activations (A[i] as in WsLayout::act).
+int ws_forward(const WsLayout& L, char* w, const uint16_t* w16, const float* p32, float scale,
+               const float* img, float* out, hipStream_t st) {
+    static const WsParams PR;
+    uint16_t* A[18];
+    for (int i = 0; i < 18; ++i) A[i] = (uint16_t*)(w + L.act[i]);
+    const int32_t* D0 = L.dims[0];
+    const int32_t* D1 = L.dims[1];
+    const int32_t* D2 = L.dims[2];
+    auto conv = [&](int l, const int32_t* D, const uint16_t* in, uint16_t* o) {
+        return spdhg_conv3d_fwd(D, WS_CI[l], WS_CO[l], in, w16 + PR.w16[l], p32 + PR.b32[l],
+                                WS_RELU[l], o, st);
+    };
+    WS_TRY(spdhg_net_image_to_act(L.nv, scale, img, A[0], st));
+    WS_TRY(conv(0, D0, A[0], A[1]));
+    WS_TRY(conv(1, D0, A[1], A[2]));
+    WS_TRY(spdhg_net_pool2(D0, 16, 0, A[2], A[3], st));
+    WS_TRY(conv(2, D1, A[3], A[4]));
+    WS_TRY(conv(3, D1, A[4], A[5]));
+    WS_TRY(spdhg_net_pool2(D1, 32, 0, A[5], A[6], st));
+    WS_TRY(conv(4, D2, A[6], A[7]));
+    WS_TRY(conv(5, D2, A[7], A[8]));
+    WS_TRY(spdhg_net_up2(D1, 64, 0, A[8], A[9], st));
+    WS_TRY(conv(6, D1, A[9], A[10]));
+    WS_TRY(spdhg_net_add(L.nv / 8 * 32, A[10], A[5], A[11], st));
+    WS_TRY(conv(7, D1, A[11], A[12]));
+    WS_TRY(spdhg_net_up2(D0, 32, 0, A[12], A[13], st));
+    WS_TRY(conv(8, D0, A[13], A[14]));
+    WS_TRY(spdhg_net_add(L.nv * 16, A[14], A[2], A[15], st));
+    WS_TRY(conv(9, D0, A[15], A[16]));
+    WS_TRY(conv(10, D0, A[16], A[17]));
+    if (out) WS_TRY(spdhg_net_act_to_image(L.nv, scale, A[17], 16, img, out, st));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spdhg_ws_param_count(int64_t* n32, int64_t* n16) {
+    if (!n32 || !n16) return net_fail(-1, "NULL argument");
+    static const WsParams PR;
+    *n32 = PR.n32;
+    *n16 = PR.n16;
+    return 0;
+}
+
+int spdhg_ws_param_offsets(int32_t layer, int64_t* w32, int64_t* b32, int64_t* w16) {
+    if (layer < 0 || layer > 10 || !w32 || !b32 || !w16) return net_fail(-1, "bad argument");
+    static const WsParams PR;
+    *w32 = PR.w32[layer];
+    *b32 = PR.b32[layer];
+    *w16 = PR.w16[layer];
+    return 0;
+}
+
+int spdhg_ws_workspace_bytes(const int32_t dims[3], int32_t train, size_t* bytes) {
+    if (!bytes) return net_fail(-1, "NULL argument");
+    if (!ws_dims_ok(dims)) return net_fail(-2, "volume sizes must be positive multiples of 4");
+    *bytes = ws_layout(dims, train != 0).total;
+    return 0;
+}
+
+int spdhg_ws_pack(const float* p32, uint16_t* w16, void* stream) {
+    if (!p32 || !w16) return net_fail(-1, "NULL argument");
+    static const WsParams PR;
+    for (int l = 0; l < 11; ++l)
+        WS_TRY(spdhg_net_pack_weights(WS_CI[l], WS_CO[l], p32 + PR.w32[l], w16 + PR.w16[l], stream));
+    return 0;
+}
+
+int spdhg_ws_infer(const int32_t dims[3], const float* p32, const uint16_t* w16, float scale,
+                   const float* img, float* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!p32 || !w16 || !img || !out || !ws) return net_fail(-1, "NULL argument");
+    if (!ws_dims_ok(dims)) return net_fail(-2, "volume sizes must be positive multiples of 4");
+    if (!(scale > 0)) return net_fail(-1, "scale must be positive");
+    if ((uintptr_t)ws & 255) return net_fail(-1, "workspace must be 256-byte aligned");
+    const WsLayout L = ws_layout(dims, false);
+    if (ws_bytes < L.total) return net_fail(-5, "workspace too small");
+    return ws_forward(L, (char*)ws, w16, p32, scale, img, out, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Loss 0.5 |net(img) - scale target|^2 (into loss, if not NULL) and its gradient with
+// respect to every parameter (FP32 blob layout, into grads): the forward pass, then
+// backpropagation through the layers in reverse order with the kernels' adjoints.
+int ws_grads(const WsLayout& L, char* w, const float* p32, const uint16_t* w16, float scale,
+             const float* img, const float* target, float* grads, double* loss, hipStream_t st) {
+    static const WsParams PR;
+    WS_TRY(ws_forward(L, w, w16, p32, scale, img, nullptr, st));
+    uint16_t* A[18];
+    for (int i = 0; i < 18; ++i) A[i] = (uint16_t*)(w + L.act[i]);
+    auto G = [&](size_t o) { return (uint16_t*)(w + o); };
+    float* part = (float*)(w + L.part);
+    uint16_t* wt = G(L.wt);
+    const int32_t* D[3] = {L.dims[0], L.dims[1], L.dims[2]};
+    const int64_t nv = L.nv;
+    // loss and its gradient in channel 0 of the output (the other channels zero)
+    wsnet::fill_zero_u16<<<nblk(nv * 16), NET_BLOCK, 0, st>>>(nv * 16, G(L.gout));
+    NET_CHECK();
+    WS_TRY(spdhg_net_mse_grad(nv, 16, A[17], img, target, scale, G(L.gout),
+                              (double*)(w + L.lparts), st));
+    // back(l): relu derivative (from the layer's output), weight and bias gradients, and
+    // the input gradient through the adjoint convolution (not needed for the first layer)
+    auto back = [&](int l, const uint16_t* in, const uint16_t* outp, uint16_t* gout,
+                    uint16_t* gin) -> int {
+        const int32_t* Dl = D[WS_LEVEL[l]];
+        const int64_t nvl = (int64_t)Dl[0] * Dl[1] * Dl[2];
+        if (WS_RELU[l]) WS_TRY(spdhg_net_relu_bwd(nvl * WS_CO[l], outp, gout, st));
+        WS_TRY(spdhg_conv3d_wgrad(Dl, WS_CI[l], WS_CO[l], in, gout, WS_CHUNK, part, L.part_floats,
+                                  grads + PR.w32[l], grads + PR.b32[l], st));
+        if (!gin) return 0;
+        WS_TRY(spdhg_conv3d_adjoint_weights(WS_CI[l], WS_CO[l], w16 + PR.w16[l], wt, st));
+        return spdhg_conv3d_fwd(Dl, WS_CO[l], WS_CI[l], gout, wt, nullptr, 0, gin, st);
+    };
+    auto copy = [&](uint16_t* dst, const uint16_t* src, int64_t n) -> int {
+        const hipError_t e = hipMemcpyAsync(dst, src, n * 2, hipMemcpyDeviceToDevice, st);
+        return e == hipSuccess ? 0 : net_fail(-4, hipGetErrorString(e));
+    };
+    WS_TRY(back(10, A[16], A[17], G(L.gout), G(L.g10)));          // c11: d1 -> out
+    WS_TRY(back(9, A[15], A[16], G(L.g10), G(L.g9in)));           // c10: s1 -> d1
+    WS_TRY(copy(G(L.g2), G(L.g9in), nv * 16));                    // d s1 / d e1: the skip
+    WS_TRY(back(8, A[13], A[14], G(L.g9in), G(L.g9)));            // c9: u1 -> c9
+    WS_TRY(spdhg_net_up2(D[0], 32, 1, G(L.g9), G(L.g9u), st));    // up(d2) adjoint
+    WS_TRY(back(7, A[11], A[12], G(L.g9u), G(L.g8)));             // c8: s2 -> d2
+    WS_TRY(copy(G(L.g7in), G(L.g8), nv / 8 * 32));                // d s2 / d e2: the skip
+    WS_TRY(back(6, A[9], A[10], G(L.g7in), G(L.g7)));             // c7: u2 -> c7
+    WS_TRY(spdhg_net_up2(D[1], 64, 1, G(L.g7), G(L.g7u), st));    // up(b) adjoint
+    WS_TRY(back(5, A[7], A[8], G(L.g7u), G(L.g6)));               // c6: c5 -> b
+    WS_TRY(back(4, A[6], A[7], G(L.g6), G(L.g5)));                // c5: p2 -> c5
+    WS_TRY(spdhg_net_pool2(D[1], 32, 1, G(L.g5), G(L.g5p), st));  // pool(e2) adjoint
+    WS_TRY(spdhg_net_add(nv / 8 * 32, G(L.g5p), G(L.g8), G(L.g5s), st));
+    WS_TRY(back(3, A[4], A[5], G(L.g5s), G(L.g4)));               // c4: c3 -> e2
+    WS_TRY(back(2, A[3], A[4], G(L.g4), G(L.g3)));                // c3: p1 -> c3
+    WS_TRY(spdhg_net_pool2(D[0], 16, 1, G(L.g3), G(L.g3p), st));  // pool(e1) adjoint
+    WS_TRY(spdhg_net_add(nv * 16, G(L.g3p), G(L.g2), G(L.g3s), st));
+    WS_TRY(back(1, A[1], A[2], G(L.g3s), G(L.g9in)));             // c2: c1 -> e1
+    WS_TRY(back(0, A[0], A[1], G(L.g9in), nullptr));              // c1: in -> c1
+    if (loss) {
+        wsnet::sum_parts<<<1, 256, 0, st>>>((const double*)(w + L.lparts), (nv + 255) / 256, loss);
+        NET_CHECK();
+    }
+    return 0;
+}
+
+int ws_train_checks(const int32_t dims[3], float scale, const void* ws, size_t ws_bytes,
+                    WsLayout& L) {
+    if (!ws_dims_ok(dims)) return net_fail(-2, "volume sizes must be positive multiples of 4");
+    if (!(scale > 0)) return net_fail(-1, "scale must be positive");
+    if ((uintptr_t)ws & 255) return net_fail(-1, "workspace must be 256-byte aligned");
+    L = ws_layout(dims, true);
+    if (ws_bytes < L.total) return net_fail(-5, "workspace too small");
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spdhg_ws_gradients(const int32_t dims[3], const float* p32, const uint16_t* w16, float scale,
+                       const float* img, const float* target, float* grads, double* loss,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!p32 || !w16 || !img || !target || !grads || !ws) return net_fail(-1, "NULL argument");
+    WsLayout L;
+    WS_TRY(ws_train_checks(dims, scale, ws, ws_bytes, L));
+    return ws_grads(L, (char*)ws, p32, w16, scale, img, target, grads, loss, (hipStream_t)stream);
+}
+
+int spdhg_ws_train_step(const int32_t dims[3], float* p32, uint16_t* w16, float* adam_m,
+                        float* adam_v, int64_t step, float lr, float scale, const float* img,
+                        const float* target, double* loss, void* ws, size_t ws_bytes,
+                        void* stream) {
+    if (!p32 || !w16 || !adam_m || !adam_v || !img || !target || !ws)
+        return net_fail(-1, "NULL argument");
+    if (step < 1) return net_fail(-1, "step must be >= 1");
+    WsLayout L;
+    WS_TRY(ws_train_checks(dims, scale, ws, ws_bytes, L));
+    static const WsParams PR;
+    hipStream_t st = (hipStream_t)stream;
+    float* grads = (float*)((char*)ws + L.grads);
+    WS_TRY(ws_grads(L, (char*)ws, p32, w16, scale, img, target, grads, loss, st));
+    // one Adam step over the whole blob (elementwise: the same as a step per tensor), then
+    // the packed BF16 copies of the new weights
+    WS_TRY(spdhg_net_adam(PR.n32, lr, 0.9f, 0.999f, 1e-8f, step, p32, adam_m, adam_v, grads,
+                          nullptr, st));
+    return spdhg_ws_pack(p32, w16, st);
 }
 
 }  // extern "C"

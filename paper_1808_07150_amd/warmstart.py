@@ -3,9 +3,10 @@
 A 3-level 3-D convolutional encoder-decoder (channels 16/32/64, 3x3x3 kernels, BF16
 weights and activations with FP32 accumulation on the MFMA units) maps the normalised
 backprojection (A^T b) / (A^T 1) of the data to an initial image; SPDHG (Algorithm 2)
-then runs from that image unchanged.  Every numerical step runs in libspdhg.so
-(include/spdhg_net.h); this module holds the parameters in torch tensors (device memory
-only) and sequences the calls.
+then runs from that image unchanged.  The network runs in libspdhg.so (include/
+spdhg_net.h: spdhg_ws_infer, spdhg_ws_gradients, spdhg_ws_train_step sequence its
+layers, backpropagation and Adam); this module holds the parameter blobs and
+workspaces in torch tensors (device memory only) and marshals the calls.
 
 Architecture (channel-last activations [y][x][z][C], sizes divisible by 4):
     e1 = relu(c2(relu(c1(in))))                  16 ch, full resolution
@@ -28,7 +29,10 @@ from .spdhg import load_library
 NET_EXPORTED = ["spdhg_net_last_error", "spdhg_conv3d_fwd", "spdhg_conv3d_adjoint_weights",
                 "spdhg_conv3d_wgrad", "spdhg_net_relu_bwd", "spdhg_net_add", "spdhg_net_pool2",
                 "spdhg_net_up2", "spdhg_net_image_to_act", "spdhg_net_act_to_image",
-                "spdhg_net_mse_grad", "spdhg_net_adam", "spdhg_net_pack_weights"]
+                "spdhg_net_mse_grad", "spdhg_net_adam", "spdhg_net_pack_weights",
+                "spdhg_ws_param_count", "spdhg_ws_param_offsets", "spdhg_ws_pack",
+                "spdhg_ws_workspace_bytes", "spdhg_ws_infer", "spdhg_ws_gradients",
+                "spdhg_ws_train_step"]
 
 # (name, cin, cout, relu)
 LAYERS = [("c1", 16, 16, 1), ("c2", 16, 16, 1), ("c3", 16, 32, 1), ("c4", 32, 32, 1),
@@ -64,6 +68,15 @@ def lib():
     L.spdhg_net_mse_grad.argtypes = [i64, i32, vp, vp, vp, f32, vp, vp, vp]
     L.spdhg_net_adam.argtypes = [i64, f32, f32, f32, f32, i64, vp, vp, vp, vp, vp, vp]
     L.spdhg_net_pack_weights.argtypes = [i32, i32, vp, vp, vp]
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.spdhg_ws_param_count.argtypes = [i64p, i64p]
+    L.spdhg_ws_param_offsets.argtypes = [i32, i64p, i64p, i64p]
+    L.spdhg_ws_pack.argtypes = [vp, vp, vp]
+    L.spdhg_ws_workspace_bytes.argtypes = [dims, i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.spdhg_ws_infer.argtypes = [dims, vp, vp, f32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.spdhg_ws_gradients.argtypes = [dims, vp, vp, f32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.spdhg_ws_train_step.argtypes = [dims, vp, vp, vp, vp, i64, f32, f32, vp, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
     for n in NET_EXPORTED[1:]:
         getattr(L, n).restype = ctypes.c_int
     _net = L
@@ -185,130 +198,104 @@ def from_float(t: torch.Tensor) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------- the network
+def param_layout():
+    """(n32, n16, {layer: (w32 offset, b32 offset, w16 offset)}) of the parameter blobs."""
+    n32, n16 = ctypes.c_int64(), ctypes.c_int64()
+    _chk(lib().spdhg_ws_param_count(ctypes.byref(n32), ctypes.byref(n16)))
+    offs = {}
+    for l, (name, *_) in enumerate(LAYERS):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _chk(lib().spdhg_ws_param_offsets(l, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        offs[name] = (a.value, b.value, c.value)
+    return n32.value, n16.value, offs
+
+
 class WarmStartNet:
-    """Parameters (FP32 masters, packed BF16 copies, Adam moments) and the forward /
-    backward sequence of the encoder-decoder on one volume size."""
+    """Parameter blobs (FP32 masters with per-layer views, packed BF16 copies, Adam
+    moments) and workspaces of the encoder-decoder on one volume size; the library runs
+    the network (spdhg_ws_infer, spdhg_ws_gradients, spdhg_ws_train_step)."""
 
     def __init__(self, shape: Tuple[int, int, int], device, seed: int = 0):
         ny, nx, nz = shape
         if ny % 4 or nx % 4 or nz % 4:
             raise ValueError("volume sizes must be divisible by 4 (two poolings)")
         self.shape, self.device = tuple(shape), device
-        g = torch.Generator(device="cpu")
-        g.manual_seed(seed)
+        n32, n16, offs = param_layout()
+        self.p32 = torch.zeros(n32, dtype=torch.float32, device=device)
+        self.w16blob = torch.zeros(n16, dtype=torch.int16, device=device)
         self.w32: Dict[str, torch.Tensor] = {}
         self.b32: Dict[str, torch.Tensor] = {}
+        self.w16: Dict[str, torch.Tensor] = {}
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed)
         for name, ci, co, relu in LAYERS:
+            ow, ob, o16 = offs[name]
+            nw = 27 * ci * co
+            self.w32[name] = self.p32[ow:ow + nw].view(27, co, ci)
+            self.b32[name] = self.p32[ob:ob + co]
+            self.w16[name] = self.w16blob[o16:o16 + nw]
             # He initialisation for ReLU layers; the last (linear) layer starts at zero so
             # the untrained network returns its input image
             std = math.sqrt(2.0 / (27 * ci)) if relu else 0.0
-            self.w32[name] = (torch.randn((27, co, ci), generator=g) * std).to(device)
-            self.b32[name] = torch.zeros(co, device=device)
-        self.w16 = {n: pack(self.w32[n], ci, co) for n, ci, co, _ in LAYERS}
-        self.m = {k: torch.zeros_like(v) for k, v in list(self._params().items())}
-        self.v = {k: torch.zeros_like(v) for k, v in list(self._params().items())}
+            self.w32[name].copy_(torch.randn((27, co, ci), generator=g) * std)
+        self.pack()
+        self.m = torch.zeros_like(self.p32)
+        self.v = torch.zeros_like(self.p32)
         self.step = 0
-        self.lparts = torch.zeros(-(-ny * nx * nz // 256), dtype=torch.float64, device=device)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=device)
+        self._ws = {}
 
-    def _params(self) -> Dict[str, torch.Tensor]:
-        d = {f"{n}.w": self.w32[n] for n, *_ in LAYERS}
-        d.update({f"{n}.b": self.b32[n] for n, *_ in LAYERS})
-        return d
+    def _dims(self):
+        return (ctypes.c_int32 * 3)(*self.shape)
 
-    def forward(self, img: torch.Tensor, scale: float, keep: bool = False):
+    def _workspace(self, train: bool):
+        if train not in self._ws:
+            from .spdhg import aligned_workspace
+            nb = ctypes.c_size_t()
+            _chk(lib().spdhg_ws_workspace_bytes(self._dims(), int(train), ctypes.byref(nb)))
+            self._ws[train] = aligned_workspace(nb.value, self.device)
+        return self._ws[train]
+
+    def pack(self):
+        """Packed BF16 weights from the FP32 masters (after editing w32 directly)."""
+        _chk(lib().spdhg_ws_pack(_p(self.p32), _p(self.w16blob), _s()))
+
+    def forward(self, img: torch.Tensor, scale: float) -> torch.Tensor:
         """Network output image from `img` ([ny][nx][nz] FP32, z fastest) scaled by
-        `scale` into the network's range; with keep the activations are returned too."""
-        nv = img.numel()
-        spec = {n: (ci, co, relu) for n, ci, co, relu in LAYERS}
-        a: Dict[str, torch.Tensor] = {}
-        x = bf16(self.shape + (16,), self.device)
-        _chk(lib().spdhg_net_image_to_act(nv, float(scale), _p(img), _p(x), _s()))
-        a["in"] = x
-
-        def conv(name, inp):
-            ci, co, relu = spec[name]
-            return conv_fwd(inp, self.w16[name], self.b32[name], bool(relu), co)
-
-        a["c1"] = conv("c1", a["in"])
-        a["e1"] = conv("c2", a["c1"])
-        a["p1"] = pool2(a["e1"])
-        a["c3"] = conv("c3", a["p1"])
-        a["e2"] = conv("c4", a["c3"])
-        a["p2"] = pool2(a["e2"])
-        a["c5"] = conv("c5", a["p2"])
-        a["b"] = conv("c6", a["c5"])
-        a["u2"] = up2(a["b"])
-        a["c7"] = conv("c7", a["u2"])
-        a["s2"] = add(a["c7"], a["e2"])
-        a["d2"] = conv("c8", a["s2"])
-        a["u1"] = up2(a["d2"])
-        a["c9"] = conv("c9", a["u1"])
-        a["s1"] = add(a["c9"], a["e1"])
-        a["d1"] = conv("c10", a["s1"])
-        a["out"] = conv("c11", a["d1"])
+        `scale` into the network's range."""
         out = torch.empty_like(img)
-        _chk(lib().spdhg_net_act_to_image(nv, float(scale), _p(a["out"]), 16, _p(img), _p(out), _s()))
-        return (out, a) if keep else out
+        _, addr, nb = self._workspace(False)
+        _chk(lib().spdhg_ws_infer(self._dims(), _p(self.p32), _p(self.w16blob), float(scale),
+                                  _p(img), _p(out), ctypes.c_void_p(addr), nb, _s()))
+        return out
 
-    def train_step(self, img: torch.Tensor, target: torch.Tensor, scale: float, lr: float = 1e-3,
-                   part: Optional[torch.Tensor] = None) -> float:
-        """One Adam step on 0.5 |net(img) - target|^2 (in the scaled range); returns the loss."""
-        loss, grads = self.gradients(img, target, scale, part)
-        self.step += 1
-        for name, ci, co, _ in LAYERS:
-            for kind in ("w", "b"):
-                key = f"{name}.{kind}"
-                p = self.w32[name] if kind == "w" else self.b32[name]
-                _chk(lib().spdhg_net_adam(p.numel(), lr, 0.9, 0.999, 1e-8, self.step, _p(p),
-                                          _p(self.m[key]), _p(self.v[key]), _p(grads[key]),
-                                          None, _s()))
-            pack(self.w32[name], ci, co, out=self.w16[name])
-        return loss
-
-    def gradients(self, img: torch.Tensor, target: torch.Tensor, scale: float,
-                  part: Optional[torch.Tensor] = None):
+    def gradients(self, img: torch.Tensor, target: torch.Tensor, scale: float):
         """Loss 0.5 |net(img) - target|^2 (scaled range) and its gradient with respect to
-        every weight ([tap][co][ci], FP32) and bias (backpropagation through the layers in
-        reverse order with the kernels' adjoints)."""
-        nv = img.numel()
-        _, a = self.forward(img, scale, keep=True)
-        g_out = bf16(self.shape + (16,), self.device, zero=True)  # mse_grad writes channel 0
-        _chk(lib().spdhg_net_mse_grad(nv, 16, _p(a["out"]), _p(img), _p(target), float(scale),
-                                      _p(g_out), _p(self.lparts), _s()))
-        if part is None:
-            part = torch.empty(max(wgrad_part_floats(self.shape, ci, co) for _, ci, co, _ in LAYERS),
-                               dtype=torch.float32, device=self.device)
-        grads: Dict[str, torch.Tensor] = {}
-        spec = {n: (ci, co, relu) for n, ci, co, relu in LAYERS}
+        every weight ([tap][co][ci], FP32) and bias."""
+        grads = torch.empty_like(self.p32)
+        _, addr, nb = self._workspace(True)
+        _chk(lib().spdhg_ws_gradients(self._dims(), _p(self.p32), _p(self.w16blob),
+                                      float(scale), _p(img), _p(target), _p(grads),
+                                      _p(self.loss_dev), ctypes.c_void_p(addr), nb, _s()))
+        _, _, offs = param_layout()
+        out = {}
+        for name, ci, co, _ in LAYERS:
+            ow, ob, _ = offs[name]
+            out[f"{name}.w"] = grads[ow:ow + 27 * ci * co].view(27, co, ci)
+            out[f"{name}.b"] = grads[ob:ob + co]
+        return float(self.loss_dev.item()), out
 
-        def back(name, inp, outp, gout, relu_applied):
-            """Gradient through conv `name` (input inp, output outp): weights, bias, input."""
-            ci, co, relu = spec[name]
-            if relu:
-                relu_bwd(outp, gout)
-            dw, db = conv_wgrad(inp, gout, part)
-            grads[f"{name}.w"], grads[f"{name}.b"] = dw, db
-            wt = adjoint_weights(self.w16[name], ci, co)
-            return conv_fwd(gout, wt, None, False, ci)
-
-        g = back("c11", a["d1"], a["out"], g_out, False)
-        g = back("c10", a["s1"], a["d1"], g, True)
-        g_e1_skip = g  # d s1 / d e1 = identity
-        g = back("c9", a["u1"], a["c9"], g.clone(), True)
-        g = up2_adjoint(g)
-        g = back("c8", a["s2"], a["d2"], g, True)
-        g_e2_skip = g
-        g = back("c7", a["u2"], a["c7"], g.clone(), True)
-        g = up2_adjoint(g)
-        g = back("c6", a["c5"], a["b"], g, True)
-        g = back("c5", a["p2"], a["c5"], g, True)
-        g = add(pool2_adjoint(g), g_e2_skip)
-        g = back("c4", a["c3"], a["e2"], g, True)
-        g = back("c3", a["p1"], a["c3"], g, True)
-        g = add(pool2_adjoint(g), g_e1_skip)
-        g = back("c2", a["c1"], a["e1"], g, True)
-        back("c1", a["in"], a["c1"], g, True)
-        return float(self.lparts.sum().item()), grads
+    def train_step(self, img: torch.Tensor, target: torch.Tensor, scale: float,
+                   lr: float = 1e-3) -> float:
+        """One Adam step on 0.5 |net(img) - target|^2 (in the scaled range); returns the
+        loss before the step."""
+        self.step += 1
+        _, addr, nb = self._workspace(True)
+        _chk(lib().spdhg_ws_train_step(self._dims(), _p(self.p32), _p(self.w16blob),
+                                       _p(self.m), _p(self.v), self.step, float(lr),
+                                       float(scale), _p(img), _p(target), _p(self.loss_dev),
+                                       ctypes.c_void_p(addr), nb, _s()))
+        return float(self.loss_dev.item())
 
 
 # ---------------------------------------------------------------- data and experiment

@@ -204,15 +204,30 @@ def phantom_2d(rng, g: Geometry, n_ellipses: int = 8):
     return act, att
 
 
-def phantom_brain(rng, g: Geometry, n_min: int = 8, n_max: int = 12):
+def phantom_brain(rng, g: Geometry, n_min: int = 8, n_max: int = 12, vary: bool = False):
     """Head ellipsoid (water), brain (activity 1), 8-12 inner ellipsoids with total
-    activity U(0, 4), and two ventricles of activity 0."""
+    activity U(0, 4), and two ventricles of activity 0.  With vary, the head is scaled by
+    U(0.85, 1.1) per axis and rotated by U(-0.2, 0.2) rad, the brain sits at a random
+    offset of up to 6 mm with its own scale U(0.9, 1.05) inside it, and the ventricles'
+    length, width, spread and angle vary too (drawn before the inner ellipsoids)."""
     zext = 0.5 * g.nz * g.vz
-    head = Ellipsoid(0.0, 0.0, 0.0, 80.0, 100.0, min(95.0, 0.9 * zext), 0.0, 0.25)
-    brain = Ellipsoid(0.0, 5.0, 0.0, 68.0, 86.0, min(80.0, 0.8 * zext), 0.0, 0.75)
+    if vary:
+        sh = rng.uniform(0.85, 1.1, 3)
+        rot = float(rng.uniform(-0.2, 0.2))
+        sb = rng.uniform(0.9, 1.05, 3) * sh
+        off = rng.uniform(-6.0, 6.0, 2)
+        vl, vw = float(rng.uniform(18.0, 30.0)), float(rng.uniform(5.0, 9.0))
+        vs, va = float(rng.uniform(9.0, 15.0)), float(rng.uniform(0.05, 0.3))
+    else:
+        sh, rot, sb, off = np.ones(3), 0.0, np.ones(3), np.zeros(2)
+        vl, vw, vs, va = 25.0, 7.0, 12.0, 0.15
+    head = Ellipsoid(0.0, 0.0, 0.0, 80.0 * sh[0], 100.0 * sh[1],
+                     min(95.0 * sh[2], 0.9 * zext), rot, 0.25)
+    brain = Ellipsoid(off[0], 5.0 + off[1], 0.0, 68.0 * sb[0], 86.0 * sb[1],
+                      min(80.0 * sb[2], 0.8 * zext), rot, 0.75)
     vz = min(22.0, 0.35 * brain.az)
-    vent = [Ellipsoid(-12.0, 5.0, 0.0, 7.0, 25.0, vz, 0.15, -1.0),
-            Ellipsoid(12.0, 5.0, 0.0, 7.0, 25.0, vz, -0.15, -1.0)]
+    vent = [Ellipsoid(off[0] - vs, 5.0 + off[1], 0.0, vw, vl, vz, rot + va, -1.0),
+            Ellipsoid(off[0] + vs, 5.0 + off[1], 0.0, vw, vl, vz, rot - va, -1.0)]
     count = int(rng.integers(n_min, n_max + 1))
     inner = _non_overlapping(rng, brain, count, 6.0, 16.0, flat=False, taken=vent)
     for e in inner:
@@ -356,14 +371,14 @@ def line_integrals_torch(g: Geometry, ells, device, batch: int = 12, mean: bool 
 
 
 def brain_problem_torch(g: Geometry, seed: int, counts: float, device, with_side=False,
-                        host_poisson=False, gaps=False):
+                        host_poisson=False, gaps=False, vary=False):
     """The brain-like 3-D problem generated on a torch device (float32 outputs): same
     phantom parameters as brain_problem, analytic data in FP64, randoms + scatter at 30%
     of trues, normalisation U(0.8, 1.2), Poisson counts (torch generator seeded, or with
     host_poisson a NumPy PCG64 generator seeded from `seed` on the host)."""
     import torch
     rng = np.random.Generator(np.random.PCG64(seed))
-    act, att, labels = phantom_brain(rng, g)
+    act, att, labels = phantom_brain(rng, g, vary=vary)
     gen = torch.Generator(device=device)
     gen.manual_seed(seed + 1)
     norm = torch.rand(g.sino_shape, generator=gen, device=device, dtype=torch.float64) * 0.4 + 0.8

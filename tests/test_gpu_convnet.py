@@ -142,3 +142,72 @@ def test_network_learns_a_fixed_pair(W):
     np.testing.assert_allclose(out.cpu().numpy(), img.cpu().numpy(), rtol=2 ** -8)
     losses = [net.train_step(img, tgt, 1.0, lr=3e-3) for _ in range(40)]
     assert losses[-1] < 0.7 * losses[0], losses
+
+
+def _random_net(W, shape, seed):
+    """A network with trained-like random weights and biases (BF16-representable)."""
+    g = r(seed)
+    net = W.WarmStartNet(shape, "cuda", seed=seed)
+    w, b = {}, {}
+    for n, ci, co, relu in W.LAYERS:
+        wn = g.standard_normal((27, co, ci)) * np.sqrt(2.0 / (27 * ci)) * (1.0 if relu else 0.3)
+        w[n] = C.bf16_round(wn)
+        b[n] = (0.05 * g.standard_normal(co)).astype(np.float32).astype(np.float64)
+        net.w32[n].copy_(torch.from_numpy(w[n].astype(np.float32)))
+        net.b32[n].copy_(torch.from_numpy(b[n].astype(np.float32)))
+    net.pack()
+    return net, w, b
+
+
+def test_network_inference_matches_oracle(W):
+    """spdhg_ws_infer (the whole network in the library) against the FP64 forward through
+    BF16-rounded activations."""
+    shape = (8, 12, 8)
+    img_np = np.abs(r(31).standard_normal(shape)).astype(np.float32)
+    net, w, b = _random_net(W, shape, 32)
+    out = net.forward(torch.from_numpy(img_np).cuda(), 1.5).cpu().numpy()
+    ref = C.network_forward(img_np.astype(np.float64), 1.5, w, b)
+    ref = ref[0] if isinstance(ref, tuple) else ref
+    err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    assert err <= 2e-2, err
+
+
+def test_train_step_is_gradients_then_adam(W):
+    """spdhg_ws_train_step = spdhg_ws_gradients, then one Adam step over the parameter blob
+    and the packed copies: bitwise against the separate calls, over two steps."""
+    shape = (8, 8, 12)
+    g = r(41)
+    img = torch.from_numpy(np.abs(g.standard_normal(shape)).astype(np.float32)).cuda()
+    tgt = 0.5 * img + 0.2
+    a, _, _ = _random_net(W, shape, 42)
+    b, _, _ = _random_net(W, shape, 42)
+    for step in (1, 2):
+        la = a.train_step(img, tgt, 1.3, lr=2e-3)
+        lb, grads = b.gradients(img, tgt, 1.3)
+        flat = torch.empty_like(b.p32)
+        for n, ci, co, _ in W.LAYERS:
+            ow, ob, _ = W.param_layout()[2][n]
+            flat[ow:ow + 27 * ci * co] = grads[f"{n}.w"].reshape(-1)
+            flat[ob:ob + co] = grads[f"{n}.b"]
+        W._chk(W.lib().spdhg_net_adam(b.p32.numel(), 2e-3, 0.9, 0.999, 1e-8, step, W._p(b.p32),
+                                      W._p(b.m), W._p(b.v), W._p(flat), None, W._s()))
+        b.pack()
+        torch.cuda.synchronize()
+        assert la == lb
+        assert torch.equal(a.p32, b.p32) and torch.equal(a.w16blob, b.w16blob)
+        assert torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+
+
+def test_whole_network_argument_errors(W):
+    import ctypes
+    shape = (8, 8, 12)
+    net = W.WarmStartNet(shape, "cuda", seed=0)
+    img = torch.zeros(shape, device="cuda")
+    out = torch.empty_like(img)
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    rc = W.lib().spdhg_ws_infer(net._dims(), W._p(net.p32), W._p(net.w16blob), 1.0, W._p(img),
+                                W._p(out), ctypes.c_void_p(ws.data_ptr()), 1024, W._s())
+    assert rc == -5  # workspace too small
+    bad = (ctypes.c_int32 * 3)(8, 8, 10)
+    nb = ctypes.c_size_t()
+    assert W.lib().spdhg_ws_workspace_bytes(bad, 0, ctypes.byref(nb)) == -2
