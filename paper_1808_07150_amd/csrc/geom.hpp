@@ -88,14 +88,18 @@ __device__ __forceinline__ Sample split(double u) {
     return s;
 }
 
-// Centred radial coordinate of bin k.
+// Centred radial coordinate of bin k.  SCAN = false: the caller guarantees that there are
+// no scanner tables (kpos, kobl, kL NULL), so the lookups compile away.
+template <bool SCAN = true>
 __device__ __forceinline__ double kappa(const GeomDev& G, int k) {
-    return G.kpos ? G.kpos[k] : (double)k - G.ck;
+    if (SCAN && G.kpos) return G.kpos[k];
+    return (double)k - G.ck;
 }
 
 // Continuous radial bin of the centred coordinate kk (inverse of kappa; for ray ranges).
+template <bool SCAN = true>
 __device__ __forceinline__ double bin_of(const GeomDev& G, double kk) {
-    if (G.krho > 0.0) return G.ck + G.krho * asin(fmin(fmax(kk / G.krho, -1.0), 1.0));
+    if (SCAN && G.krho > 0.0) return G.ck + G.krho * asin(fmin(fmax(kk / G.krho, -1.0), 1.0));
     return kk + G.ck;
 }
 
@@ -106,10 +110,11 @@ struct SegRay {
     float L;
 };
 
+template <bool SCAN = true>
 __device__ __forceinline__ SegRay seg_ray(const GeomDev& G, int a, int g, int k, double kk) {
     const SegAngleDev S = G.sa[a * G.n_seg + g];
     SegRay r;
-    if (G.kobl) {
+    if (SCAN && G.kobl) {
         const double f = G.kobl[k];
         r.ezj = S.ez_dj * f;
         r.ezk = (S.ez_dk * f) * kk;
@@ -117,6 +122,6 @@ __device__ __forceinline__ SegRay seg_ray(const GeomDev& G, int a, int g, int k,
         r.ezj = S.ez_dj;
         r.ezk = S.ez_dk * kk;
     }
-    r.L = G.kL ? S.L * G.kL[g * G.n_rad + k] : S.L;
+    r.L = (SCAN && G.kL) ? S.L * G.kL[g * G.n_rad + k] : S.L;
     return r;
 }

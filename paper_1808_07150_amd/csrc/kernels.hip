@@ -588,9 +588,10 @@ struct TapCoef {
     float wa, wb;
 };
 
+template <bool SCAN = true>
 __device__ __forceinline__ TapCoef tap_coef(const GeomDev& G, int a, int g, int k, double kk,
                                             double jj) {
-    const SegRay S = seg_ray(G, a, g, k, kk);
+    const SegRay S = seg_ray<SCAN>(G, a, g, k, kk);
     const Sample sz = split(__builtin_fma(S.ezj, jj, S.ezk));
     TapCoef t;
     t.off = -(G.seg_off[g] + sz.i0);
@@ -847,8 +848,9 @@ __device__ __forceinline__ void ray_sum(const float (&s)[4], float& h0, float& h
     }
 }
 
-// NS = 11: every launch has exactly 11 segments (span 11), so the segment table's entries
-// are compile-time indices the compiler keeps in scalar registers; NS = 0: any count.
+// NS = 11: every launch has exactly 11 segments (span 11) and no scanner tables, so the
+// segment table's entries are compile-time indices the compiler keeps in scalar
+// registers and the scanner model's lookups compile away; NS = 0: any count, any model.
 template <int MODE, int PITCH, int NS>
 // Seven waves per SIMD (at most 72 VGPRs): room for the loads of a whole ray (span 11:
 // 22 values) next to the 20 accumulators, so a ray costs one memory round trip.  A wave's
@@ -905,14 +907,15 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
         const double jj = (double)j - A.cj;
         // 1. rays touching the strip: u in [s0 - 1, s0 + BS_W)  (wave-uniform)
         const double base = __builtin_fma(A.du_dj, jj, A.cu);
-        const double ka = bin_of(G, ((double)(s0 - 1) - base) / A.du_dk);
-        const double kb = bin_of(G, ((double)(s0 + BS_W) - base) / A.du_dk);
+        constexpr bool SCAN = NS == 0;
+        const double ka = bin_of<SCAN>(G, ((double)(s0 - 1) - base) / A.du_dk);
+        const double kb = bin_of<SCAN>(G, ((double)(s0 + BS_W) - base) / A.du_dk);
         const int klo = max(0, (int)__builtin_floor(fmin(ka, kb)) - 1);
         const int khi = min(G.n_rad - 1, (int)__builtin_ceil(fmax(ka, kb)) + 1);
         const int nr = min(max(khi - klo + 1, 0), KR);
         __builtin_amdgcn_wave_barrier();  // the previous angle's tables are consumed
         for (int kr = lane; kr < nr; kr += 64) {
-            const Sample sm = split(sec_coord(A, kappa(G, klo + kr), jj));
+            const Sample sm = split(sec_coord(A, kappa<SCAN>(G, klo + kr), jj));
             ri0[kr] = sm.i0 - s0;
             rfu[kr] = sm.fu;
         }
@@ -936,7 +939,7 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
             __builtin_amdgcn_wave_barrier();  // the previous chunk's taps are consumed
             for (int t = lane; t < nr * nsc; t += 64) {
                 const int kr = t / nsc, gl = t - kr * nsc;
-                tc[kr * sc + gl] = tap_coef(G, a, gc + gl, klo + kr, kappa(G, klo + kr), jj);
+                tc[kr * sc + gl] = tap_coef<SCAN>(G, a, gc + gl, klo + kr, kappa<SCAN>(G, klo + kr), jj);
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll

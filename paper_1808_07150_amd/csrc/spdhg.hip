@@ -627,7 +627,7 @@ int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st, const Bwd
     A.n_ang_sub = cnt;
     if (plan.strip && plan.pitch == 2)
         return launch_strip<MODE, 2, 0>(A, cnt, ang0, step, st, plan, host_ang, partial);
-    if (plan.strip && A.G.n_seg == 11)
+    if (plan.strip && A.G.n_seg == 11 && !A.G.kpos && !A.G.kobl && !A.G.kL)
         return launch_strip<MODE, 1, 11>(A, cnt, ang0, step, st, plan, host_ang, partial);
     if (plan.strip)
         return launch_strip<MODE, 1, 0>(A, cnt, ang0, step, st, plan, host_ang, partial);
