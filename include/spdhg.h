@@ -112,6 +112,16 @@ typedef struct spdhg_geom {
                                   * only), instead of the minimum over all blocks for u and w
                                   * alike; Theorem 1 bounds ||S_i^1/2 A_i T^1/2|| per block,
                                   * and T_u does not enter block n's bound */
+#define SPDHG_FLAG_COMPENSATED 4 /* hold the primal state x and z of Algorithm 2 as FP32
+                                  * pairs (value + low part) and take the primal step in
+                                  * FP64 on them, so that per-iteration changes below half
+                                  * an FP32 ulp accumulate instead of being rounded away
+                                  * (with many subsets, e.g. one angle each, they do); the
+                                  * projector reads the FP32 value.  Costs 8 bytes per voxel
+                                  * of workspace and 16 bytes per voxel of traffic per
+                                  * iteration.  TV, aTV, dTV and no prior (SPDHG_E_NOTIMPL
+                                  * with TGV); PDHG iterations use it too.  EM sub-iterations
+                                  * (SPDHG_FLAG_EM) restart the iterate's low part at 0. */
 
 typedef struct spdhg_params {
     int32_t n_subsets; /* m >= 1                                                      */
@@ -332,6 +342,8 @@ int spdhg_gap(spdhg_ctx* ctx, double U, double* out_dev, void* stream);
  *   0 y (full sinogram)   1 z (image)   2 T (image)   3 sigma (full sinogram, or NULL
  *   with scalar steps)   4 prior dual (3 images, current buffer; TGV: q1)
  *   5 TGV w (3 images)   6 TGV q2 (6 images)   7 TGV z_w (3 images)
+ *   8 low part of z   9 low part of the iterate
+ *   (SPDHG_FLAG_COMPENSATED: the state is the sum of the two parts)
  * Images are z-fastest ([y][x][z]) and sinograms [angle][radial][plane] inside the
  * library; *n_floats receives the element count (0 for an array the problem lacks). */
 int spdhg_buffer(spdhg_ctx* ctx, int32_t which, float** ptr, int64_t* n_floats);
@@ -340,7 +352,8 @@ int spdhg_buffer(spdhg_ctx* ctx, int32_t which, float** ptr, int64_t* n_floats);
  * block i - n_subsets, the probability p_i of block i and the operator norm used. */
 int spdhg_block_info(const spdhg_ctx* ctx, int32_t i, double* sigma, double* p, double* norm);
 
-/* Checkpoint: state = x, y, z, prior duals (TGV: also w, z_w) and the iteration counter (which fixes the
+/* Checkpoint: state = x, y, z, prior duals (TGV: also w, z_w; SPDHG_FLAG_COMPENSATED: also
+ * the low parts of z and x) and the iteration counter (which fixes the
  * rest of the random block sequence).  spdhg_state_bytes gives the size; save writes it
  * to `dst` (device), load reads it back; both enqueue copies on `stream`. */
 int spdhg_state_bytes(const spdhg_ctx* ctx, size_t* bytes);

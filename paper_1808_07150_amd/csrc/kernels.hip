@@ -563,7 +563,8 @@ __global__ void __launch_bounds__(64 * PS) fwd_bundle(FwdArgs P) {
 }
 
 // ---------------------------------------------------------------- gather backprojection
-enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2, B_PARTIAL = 3, B_ACCUM = 4, B_EM = 5 };
+enum BwdMode { B_PLAIN = 0, B_SENS = 1, B_ITER = 2, B_PARTIAL = 3, B_ACCUM = 4, B_EM = 5,
+               B_PAIR = 6 };
 #define BWD_THREADS 128
 #define BWD_KC 4  // candidate radial bins per column and angle
 
@@ -578,6 +579,8 @@ struct BwdArgs {
     float inv_p;
     float* z;
     float* x;
+    float* zlo;      // B_PAIR: low parts of z and x (see primal_pair)
+    float* xlo;
 };
 
 // Per (candidate ray, segment): voxel z reads planes p = z + off (weight wa) and p - 1
@@ -628,6 +631,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const GeomDev& G, con
                                              0x00020000);
 }
 
+// The primal part of Algorithm 2 (z += dz; x = max(x - T (z + dz / p_i), 0)) on a state
+// held as FP32 pairs, x = xh + xl and z = zh + zl with |lo| at most half an ulp of hi,
+// evaluated in FP64 on the sums: a change smaller than half an ulp of the FP32 value
+// accumulates in the low part instead of being rounded away (with many subsets each
+// iteration moves x and z by a small fraction of their size).  The projector reads xh.
+__device__ __forceinline__ void primal_pair(float& xh, float& xl, float& zh, float& zl,
+                                            float T, float dz, float inv_p) {
+    const double z = ((double)zh + (double)zl) + (double)dz;
+    zh = (float)z;
+    zl = (float)(z - (double)zh);
+    const double zbar = __builtin_fma((double)dz, (double)inv_p, z);
+    double x = ((double)xh + (double)xl) - (double)T * zbar;
+    x = x > 0.0 ? x : 0.0;
+    xh = (float)x;
+    xl = (float)(x - (double)xh);
+}
+
 __device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t t, float dz) {
     if (MODE == B_PLAIN || MODE == B_PARTIAL) {
         P.out[t] = dz;
@@ -639,6 +659,13 @@ __device__ __forceinline__ void bwd_epilogue(const BwdArgs& P, int MODE, int64_t
         // eq. OSEM: x = x / (A_i^T 1) * A_i^T (b / (A_i x + r)); T holds 1 / (A_i^T 1) (0 off
         // the subset's support)
         P.x[t] = P.x[t] * (dz * P.T[t]);
+    } else if (MODE == B_PAIR) {
+        float xh = P.x[t], xl = P.xlo[t], zh = P.z[t], zl = P.zlo[t];
+        primal_pair(xh, xl, zh, zl, P.T[t], dz, P.inv_p);
+        P.z[t] = zh;
+        P.zlo[t] = zl;
+        P.x[t] = xh;
+        P.xlo[t] = xl;
     } else {
         // Algorithm 2: dual and z updates, extrapolation and the next iteration's primal step:
         // z += dz;  x = max(x - T (z + dz / p_i), 0)
@@ -1129,6 +1156,10 @@ struct PriorArgs {
     // (z-fastest image), added to the prior's before the z update and the primal step;
     // NULL in SPDHG, where each iteration updates one block
     const float* dz_add;
+    // compensated primal (the PAIR instances): low parts of z and x (see primal_pair),
+    // updated in place at the voxel's own lane
+    float* zlo;
+    float* xlo;
 };
 
 __device__ __forceinline__ void zf_coords(const PriorArgs& P, int64_t t, int& cx, int& cy,
@@ -1224,7 +1255,8 @@ __device__ __forceinline__ bool tile_voxel(const PriorTile& TL, int nx, int ny, 
 // Algorithm 2 from the dual step to the extrapolation for the prior block, fused with the
 // next iteration's primal step.
 // x and y are read from one buffer and written to the other (a recomputing neighbour
-// reads the old values).
+// reads the old values).  PAIR: the compensated primal step (primal_pair).
+template <bool PAIR>
 __global__ void __launch_bounds__(1024)
 tv_iter(PriorArgs P, PriorTile TL, const float* __restrict__ x_in, float* __restrict__ x_out,
         const float* __restrict__ y_in, float* __restrict__ y_out, float* __restrict__ z,
@@ -1270,6 +1302,15 @@ tv_iter(PriorArgs P, PriorTile TL, const float* __restrict__ x_in, float* __rest
     y_out[t] = q[0];
     y_out[t + nv] = q[1];
     y_out[t + 2 * nv] = q[2];
+    if (PAIR) {
+        float xh = x_in[t], xl = P.xlo[t], zh = z[t], zl = P.zlo[t];
+        primal_pair(xh, xl, zh, zl, T[t], dz, P.inv_p);
+        z[t] = zh;
+        P.zlo[t] = zl;
+        x_out[t] = xh;
+        P.xlo[t] = xl;
+        return;
+    }
     const float zn = z[t] + dz;
     z[t] = zn;
     const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
@@ -1365,7 +1406,7 @@ __device__ __forceinline__ void tv_row_load(TvRow& r, __amdgpu_buffer_rsrc_t rx,
     }
 }
 
-template <bool DTV>
+template <bool DTV, bool PAIR>
 __global__ void __launch_bounds__(256)
 tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__ x_out,
         const float* __restrict__ y_in, float* __restrict__ y_out, float* __restrict__ z,
@@ -1386,16 +1427,28 @@ tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__
     uint32_t c = 4u * (((uint32_t)cy * P.nx + cx) * P.nz + min(cz, P.nz - 1));
     TvRow cur = {}, nxt = {};
     float xc = 0.0f, xl = 0.0f, dprev = 0.0f;
+    // PAIR: low parts of x and z at the voxel (this row and the prefetched next one)
+    const auto rxl = vol_rsrc(PAIR ? P.xlo : x_in, nvb), rzl = vol_rsrc(PAIR ? P.zlo : z, nvb);
+    float lo_x = 0.0f, lo_z = 0.0f, lo_xn = 0.0f, lo_zn = 0.0f;
     if (act) {
         tv_row_load<DTV>(cur, rx, ry, rz, rt, rxi, c, sx, sy, nvb, hx, cy < P.ny - 1, hz, lx);
         xc = vol_ld(rx, c, 0);
         if (lx) xl = vol_ld(rx, c - sx, 0);
+        if (PAIR) {
+            lo_x = vol_ld(rxl, c, 0);
+            lo_z = vol_ld(rzl, c, 0);
+        }
     }
     for (; cy < y1; ++cy, c += sy) {
         const bool hy = cy < P.ny - 1;
-        if (act && cy + 1 < y1)
+        if (act && cy + 1 < y1) {
             tv_row_load<DTV>(nxt, rx, ry, rz, rt, rxi, c + sy, sx, sy, nvb, hx, cy + 1 < P.ny - 1,
                              hz, lx);
+            if (PAIR) {
+                lo_xn = vol_ld(rxl, c + sy, 0);
+                lo_zn = vol_ld(rzl, c + sy, 0);
+            }
+        }
         float q[3], dy[3] = {0.0f, 0.0f, 0.0f}, qn[3], dn[3] = {0.0f, 0.0f, 0.0f};
         if (act) {
             prior_dual_vals(P, hx ? cur.xp - xc : 0.0f, hy ? cur.xn - xc : 0.0f,
@@ -1420,15 +1473,26 @@ tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__
             vol_st(ryo, c, 0, q[0]);
             vol_st(ryo, c, nvb, q[1]);
             vol_st(ryo, c, 2 * nvb, q[2]);
-            const float zn = cur.z + dz;
-            vol_st(rz, c, 0, zn);
-            const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
-            vol_st(rxo, c, 0, fmaxf(xc - cur.t * zbar, 0.0f));
+            if (PAIR) {
+                float xh = xc, zh = cur.z;
+                primal_pair(xh, lo_x, zh, lo_z, cur.t, dz, P.inv_p);
+                vol_st(rz, c, 0, zh);
+                vol_st(rzl, c, 0, lo_z);
+                vol_st(rxo, c, 0, xh);
+                vol_st(rxl, c, 0, lo_x);
+            } else {
+                const float zn = cur.z + dz;
+                vol_st(rz, c, 0, zn);
+                const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
+                vol_st(rxo, c, 0, fmaxf(xc - cur.t * zbar, 0.0f));
+            }
         }
         dprev = dy[1];
         xc = cur.xn;
         xl = cur.lxn;
         cur = nxt;
+        lo_x = lo_xn;
+        lo_z = lo_zn;
     }
 }
 

@@ -707,6 +707,8 @@ struct spdhg_ctx {
     float* raw = nullptr;  // span compression: ray sums before the data bins are summed
     int raw_angles = 0;
     float *xa = nullptr, *xb = nullptr, *z = nullptr, *T = nullptr, *scr = nullptr;
+    // SPDHG_FLAG_COMPENSATED: low parts of z and of the iterate (in place, not ping-pong)
+    float *zlo = nullptr, *xlo = nullptr;
     float *yn[2] = {nullptr, nullptr}, *xi = nullptr;
     // TGV: w (ping-pong), z_w, q2 (ping-pong); data iterations owe w the line-3 steps
     // w -= T_w z_w, applied together before the next use of w
@@ -755,6 +757,8 @@ struct spdhg_ctx {
     BwdArgs bwd_args() const {
         BwdArgs A{};
         A.G = tab.G;
+        A.zlo = zlo;
+        A.xlo = xlo;
         return A;
     }
     PriorArgs prior_args() const {
@@ -767,6 +771,8 @@ struct spdhg_ctx {
         P.gamma_d = (float)prm.gamma_d;
         P.dtv = prm.prior == SPDHG_PRIOR_DTV;
         P.atv = prm.prior == SPDHG_PRIOR_ATV;
+        P.zlo = zlo;
+        P.xlo = xlo;
         return P;
     }
     TgvArgs tgv_args(int block) const {
@@ -785,7 +791,7 @@ namespace {
 
 struct Layout {
     size_t tables, bp, rp, mp, y, sigma, dscr, raw, xa, xb, z, T, scr, yn, xi, w, zw, q2, em,
-        part, scal, total;
+        lo, part, scal, total;
     int64_t part_n, raw_angles;
 };
 
@@ -827,6 +833,7 @@ Layout layout(const spdhg_geom* g, const spdhg_params* p, const HostTables& tab)
     L.zw = take(tgv ? 3 * nv * 4 : 0);
     L.q2 = take(tgv ? 12 * nv * 4 : 0);
     L.em = take((p->flags & SPDHG_FLAG_EM) ? (size_t)m * nv * 4 : 0);
+    L.lo = take((p->flags & SPDHG_FLAG_COMPENSATED) ? 2 * (size_t)nv * 4 : 0);
     const int64_t fwd_blocks = (int64_t)g->n_ang * g->n_rad;
     L.part_n = std::max<int64_t>({(nb + BLOCK - 1) / BLOCK, (3 * nv + BLOCK - 1) / BLOCK,
                                   fwd_blocks, 1}) * 2;
@@ -860,7 +867,10 @@ int check_params(const spdhg_geom* g, const spdhg_params* p) {
     if (p->prior == SPDHG_PRIOR_DTV && (!(p->eta > 0) || !(p->gamma_d >= 0) || !(p->gamma_d <= 1)))
         return fail(SPDHG_E_ARG, "dTV needs eta > 0 and gamma_d in [0, 1]");
     if (!p->precond && p->power_iters < 1) return fail(SPDHG_E_ARG, "power_iters must be >= 1");
-    if (p->flags & ~(SPDHG_FLAG_EM | SPDHG_FLAG_TGV_SPLIT_T)) return fail(SPDHG_E_ARG, "unknown flags");
+    if (p->flags & ~(SPDHG_FLAG_EM | SPDHG_FLAG_TGV_SPLIT_T | SPDHG_FLAG_COMPENSATED))
+        return fail(SPDHG_E_ARG, "unknown flags");
+    if ((p->flags & SPDHG_FLAG_COMPENSATED) && p->prior == SPDHG_PRIOR_TGV)
+        return fail(SPDHG_E_NOTIMPL, "the compensated primal step is not built for TGV");
     return SPDHG_OK;
 }
 
@@ -1348,6 +1358,10 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     c->part = (double*)(w + L.part);
     c->part_n = L.part_n;
     c->em_inv = (params->flags & SPDHG_FLAG_EM) ? (float*)(w + L.em) : nullptr;
+    if (params->flags & SPDHG_FLAG_COMPENSATED) {
+        c->zlo = (float*)(w + L.lo);
+        c->xlo = c->zlo + c->nv;
+    }
     c->scal = (double*)(w + L.scal);
     c->m = params->n_subsets;
     c->n_prior = tgv ? 2 : (prior ? 1 : 0);
@@ -1513,6 +1527,7 @@ int spdhg_init(spdhg_ctx** out, const spdhg_geom* geom, const spdhg_params* para
     // y = 0, z = 0, prior duals = 0
     fill_f32<<<nblocks(nb), BLOCK, 0, st>>>(c->y, nb, 0.0f);
     fill_f32<<<nblocks(nv), BLOCK, 0, st>>>(c->z, nv, 0.0f);
+    if (c->zlo) fill_f32<<<nblocks(2 * nv), BLOCK, 0, st>>>(c->zlo, 2 * nv, 0.0f);
     if (prior) fill_f32<<<nblocks(6 * nv), BLOCK, 0, st>>>(c->yn[0], 6 * nv, 0.0f);
     if (tgv) {  // w = 0, z_w = 0, q2 = 0
         fill_f32<<<nblocks(6 * nv), BLOCK, 0, st>>>(c->w[0], 6 * nv, 0.0f);
@@ -1597,6 +1612,26 @@ int draw_block(const spdhg_ctx* c) {
     return i;
 }
 
+// The TV-type prior block's fused kernel (dual step, adjoint, z update and primal step)
+// from the current iterate and prior dual into the other buffers.
+int launch_tv(spdhg_ctx* c, const PriorArgs& P, hipStream_t st) {
+    const spdhg_geom& g = c->geom;
+    const float* xin = c->xcur();
+    const float* yin = c->yn[c->yn_cur];
+    const bool pair = c->zlo != nullptr;
+    if (prior_use_wave(g, 3)) {
+        const int ly = std::min(TV_WAVE_LY, g.ny);
+        auto k = P.dtv ? (pair ? tv_wave<true, true> : tv_wave<true, false>)
+                       : (pair ? tv_wave<false, true> : tv_wave<false, false>);
+        return klaunch(k, tv_wave_blocks(g, ly), 256, 0, st, P, ly, xin, c->xother(), yin,
+                       c->yn[1 - c->yn_cur], c->z, (const float*)c->T, (const float*)c->xi);
+    }
+    const PriorTile TL = prior_tile(g);
+    return klaunch(pair ? tv_iter<true> : tv_iter<false>, prior_blocks(g, TL),
+                   TL.tx * TL.ty * g.nz, 0, st, P, TL, xin, c->xother(), yin,
+                   c->yn[1 - c->yn_cur], c->z, (const float*)c->T, (const float*)c->xi);
+}
+
 // One iteration of Algorithm 2 on block i: dual step, backprojected dual change, z update,
 // extrapolation and the next primal step (fused), then the state's buffer parities.
 int one_iteration(spdhg_ctx* c, int i, hipStream_t st) {
@@ -1625,8 +1660,9 @@ int one_iteration(spdhg_ctx* c, int i, hipStream_t st) {
         B.x = c->xcur();
         B.T = c->T;
         if ((rc = prof_begin(c, SPDHG_PROF_BWD, st))) return rc;
-        if ((rc = launch_bwd<B_ITER>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
-            return rc;
+        rc = c->zlo ? launch_bwd<B_PAIR>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)
+                    : launch_bwd<B_ITER>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr);
+        if (rc) return rc;
         if ((rc = prof_end(c, st))) return rc;
         if (c->zw) c->w_pending += 1;  // primal step for w: w -= T_w z_w (z_w unchanged)
     } else if (c->zw) {
@@ -1669,20 +1705,7 @@ int one_iteration(spdhg_ctx* c, int i, hipStream_t st) {
         PriorArgs P = c->prior_args();
         P.inv_p = inv_p;
         if ((rc = prof_begin(c, SPDHG_PROF_PRIOR, st))) return rc;
-        const float* xin = c->xcur();
-        const float* yin = c->yn[c->yn_cur];
-        if (prior_use_wave(c->geom, 3)) {
-            const int ly = std::min(TV_WAVE_LY, c->geom.ny);
-            rc = klaunch(P.dtv ? tv_wave<true> : tv_wave<false>, tv_wave_blocks(c->geom, ly), 256,
-                         0, st, P, ly, xin, c->xother(), yin, c->yn[1 - c->yn_cur], c->z,
-                         (const float*)c->T, (const float*)c->xi);
-        } else {
-            const PriorTile TL = prior_tile(c->geom);
-            rc = klaunch(tv_iter, prior_blocks(c->geom, TL), TL.tx * TL.ty * c->geom.nz, 0, st, P,
-                         TL, xin, c->xother(), yin, c->yn[1 - c->yn_cur], c->z,
-                         (const float*)c->T, (const float*)c->xi);
-        }
-        if (rc) return rc;
+        if ((rc = launch_tv(c, P, st))) return rc;
         if ((rc = prof_end(c, st))) return rc;
         c->x_cur ^= 1;
         c->yn_cur ^= 1;
@@ -2032,8 +2055,10 @@ int spdhg_pdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
             B.z = c->z;
             B.x = c->xcur();
             B.T = c->T;
-            if ((rc = launch_bwd<B_ITER>(B, 0, 1, g.n_ang, st, c->bplan, c->tab.ang.data(), c->scr)))
-                return rc;
+            rc = c->zlo
+                     ? launch_bwd<B_PAIR>(B, 0, 1, g.n_ang, st, c->bplan, c->tab.ang.data(), c->scr)
+                     : launch_bwd<B_ITER>(B, 0, 1, g.n_ang, st, c->bplan, c->tab.ang.data(), c->scr);
+            if (rc) return rc;
             continue;
         }
         // ... with a prior block: the data change dz_data into scr (the other iterate buffer
@@ -2045,23 +2070,7 @@ int spdhg_pdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {
         PriorArgs P = c->prior_args();
         P.inv_p = 1.0f;
         P.dz_add = c->scr;
-        if (prior_use_wave(g, 3)) {
-            const int ly = std::min(TV_WAVE_LY, g.ny);
-            if (P.dtv)
-                tv_wave<true><<<tv_wave_blocks(g, ly), 256, 0, st>>>(
-                    P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
-                    c->T, c->xi);
-            else
-                tv_wave<false><<<tv_wave_blocks(g, ly), 256, 0, st>>>(
-                    P, ly, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
-                    c->T, c->xi);
-        } else {
-            const PriorTile TL = prior_tile(g);
-            tv_iter<<<prior_blocks(g, TL), TL.tx * TL.ty * g.nz, 0, st>>>(
-                P, TL, c->xcur(), c->xother(), c->yn[c->yn_cur], c->yn[1 - c->yn_cur], c->z,
-                c->T, c->xi);
-        }
-        LAUNCH_CHECK();
+        if ((rc = launch_tv(c, P, st))) return rc;
         c->x_cur ^= 1;
         c->yn_cur ^= 1;
     }
@@ -2093,6 +2102,10 @@ int spdhg_em_iterate(spdhg_ctx* c, int64_t n_subiters, void* stream) {
         if ((rc = launch_bwd<B_EM>(B, a0, step, cnt, st, c->bplan, c->tab.ang.data(), c->scr)))
             return rc;
         c->em_k += 1;
+    }
+    if (c->xlo && n_subiters > 0) {  // the EM steps replaced the iterate: its low part restarts
+        fill_f32<<<nblocks(c->nv), BLOCK, 0, st>>>(c->xlo, c->nv, 0.0f);
+        LAUNCH_CHECK();
     }
     return export_x(c, st);
 }
@@ -2145,6 +2158,8 @@ int spdhg_buffer(spdhg_ctx* c, int32_t which, float** ptr, int64_t* n) {
         case 5: *ptr = c->w[c->w_cur]; *n = c->zw ? 3 * c->nv : 0; break;
         case 6: *ptr = c->q2[c->q2_cur]; *n = c->zw ? 6 * c->nv : 0; break;
         case 7: *ptr = c->zw; *n = c->zw ? 3 * c->nv : 0; break;
+        case 8: *ptr = c->zlo; *n = c->zlo ? c->nv : 0; break;
+        case 9: *ptr = c->xlo; *n = c->xlo ? c->nv : 0; break;
         default: return fail(SPDHG_E_ARG, "unknown buffer id");
     }
     return SPDHG_OK;
@@ -2172,7 +2187,7 @@ int spdhg_block_info(const spdhg_ctx* c, int32_t i, double* sigma, double* p, do
 namespace {
 
 // Arrays of a checkpoint, in order: the iterate (and, for TGV, w), z (and z_w), y, the
-// prior duals.  `cur` gives the current buffers (save), else the first ones (load).
+// prior duals, then (SPDHG_FLAG_COMPENSATED) the low parts of z and the iterate.  `cur` gives the current buffers (save), else the first ones (load).
 struct StatePart {
     float* p;
     int64_t n;
@@ -2190,6 +2205,7 @@ std::vector<StatePart> state_parts(spdhg_ctx* c, bool cur) {
         v.push_back({c->zw, 3 * nv});
         v.push_back({cur ? c->q2[c->q2_cur] : c->q2[0], 6 * nv});
     }
+    if (c->zlo) v.push_back({c->zlo, 2 * nv});  // low parts of z and x
     return v;
 }
 

@@ -157,7 +157,8 @@ def cparams(n_subsets: int, prior: str = "tv", sampling: str = "uniform", precon
             alpha: float = 0.1, eta: float = 1e-2, gamma_d: float = 1.0, gamma: float = 1.0,
             rho: float = 0.99, seed: int = 0, power_iters: int = 100,
             alpha1: float = 0.0, em: bool = False, p_prior: float = 0.5,
-            p_tgv_n: float = 0.0, split_T: bool = False) -> CParams:
+            p_tgv_n: float = 0.0, split_T: bool = False,
+            compensated: bool = False) -> CParams:
     p = CParams()
     p.n_subsets = n_subsets
     p.prior = PRIOR[prior]
@@ -167,7 +168,8 @@ def cparams(n_subsets: int, prior: str = "tv", sampling: str = "uniform", precon
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.power_iters = power_iters
     p.alpha1 = alpha1
-    p.flags = (1 if em else 0) | (2 if split_T else 0)  # SPDHG_FLAG_EM, SPDHG_FLAG_TGV_SPLIT_T
+    # SPDHG_FLAG_EM, SPDHG_FLAG_TGV_SPLIT_T, SPDHG_FLAG_COMPENSATED
+    p.flags = (1 if em else 0) | (2 if split_T else 0) | (4 if compensated else 0)
     p.p_prior = p_prior
     p.p_tgv_n = p_tgv_n
     return p
@@ -271,7 +273,8 @@ class Reconstruction:
     """One SPDHG reconstruction (spdhg_init ... spdhg_destroy).  The workspace is a
     torch uint8 tensor; b, r, mult, side and x are borrowed and must stay alive."""
 
-    BUFFERS = {"y": 0, "z": 1, "T": 2, "sigma": 3, "prior_dual": 4, "w": 5, "q2": 6, "zw": 7}
+    BUFFERS = {"y": 0, "z": 1, "T": 2, "sigma": 3, "prior_dual": 4, "w": 5, "q2": 6, "zw": 7,
+               "z_lo": 8, "x_lo": 9}
 
     def __init__(self, g, params: CParams, b, r, mult, x, side=None, stream=None):
         lib = load_library()
@@ -364,7 +367,8 @@ class Reconstruction:
         return out
 
     def buffer(self, name: str, caller_layout: bool = True) -> Optional[torch.Tensor]:
-        """A copy of an internal array (y, z, T, sigma, prior_dual; TGV: w, q2, zw).  The
+        """A copy of an internal array (y, z, T, sigma, prior_dual; TGV: w, q2, zw; with
+        the compensated primal step: z_lo, x_lo, the low parts of z and the iterate).  The
         library stores images z-fastest [y][x][z] and sinograms [angle][radial][plane];
         with caller_layout the copy is returned as [z][y][x] / [angle][plane][radial]
         (fields with c components as [c][z][y][x])."""

@@ -76,6 +76,31 @@ def test_workspace_bytes(lib):
                                      ctypes.byref(n)) == -1
 
 
+def test_compensated_flag_workspace(lib):
+    """The compensated primal step adds the low parts of z and x (8 bytes per voxel);
+    it is refused with TGV and unknown flag bits are refused."""
+    import paper_1808_07150_amd as P
+    g = synth.mmr(nxy=40, n_rad=44, n_ang=24)
+    nv = g.nx * g.ny * g.nz
+    sizes = []
+    for comp in (False, True):
+        n = ctypes.c_size_t()
+        assert lib.spdhg_workspace_bytes(ctypes.byref(P.cgeom(g)),
+                                         ctypes.byref(P.cparams(6, "dtv", compensated=comp)),
+                                         ctypes.byref(n)) == 0
+        sizes.append(n.value)
+    assert sizes[1] - sizes[0] == (8 * nv + 255) // 256 * 256
+    n = ctypes.c_size_t()
+    assert lib.spdhg_workspace_bytes(ctypes.byref(P.cgeom(g)),
+                                     ctypes.byref(P.cparams(6, "tgv", compensated=True)),
+                                     ctypes.byref(n)) == -7
+    assert b"TGV" in lib.spdhg_last_error()
+    p = P.cparams(6, "tv")
+    p.flags = 8
+    assert lib.spdhg_workspace_bytes(ctypes.byref(P.cgeom(g)), ctypes.byref(p),
+                                     ctypes.byref(n)) == -1
+
+
 def test_null_arguments_rejected(lib):
     import paper_1808_07150_amd as P
     g = P.cgeom(synth.slice64_2d())
