@@ -284,6 +284,14 @@ int spdhg_batch_epoch(spdhg_ctx* const* ctxs, int32_t n, int32_t n_epochs, int32
 int spdhg_set_tuning(spdhg_ctx* ctx, int32_t fwd_split);
 int spdhg_autotune(spdhg_ctx* ctx, int32_t* fwd_split, double* ms, void* stream);
 
+/* Ray-to-lane mapping of the forward walk (the projection of Section 4.1, every mode):
+ * 0 (default) = runs of 15 consecutive planes of one segment per lane where the geometry
+ * allows it (all segments on consecutive image planes, at most 64 such runs, e.g. the 837
+ * planes of span 11), else interleaved; 1 = always interleaved (plane q on lane q mod 64).
+ * Both give bitwise identical projections; runs read the LDS column once per run instead
+ * of once per ray.  SPDHG_E_ARG for other values. */
+int spdhg_set_walk(spdhg_ctx* ctx, int32_t interleave);
+
 /* Tiling of the gather backprojection: 1 = strips of 10 voxel columns along the secondary
  * axis (for 32 <= nz <= 127, one plane pitch and tap tables within one workgroup's LDS),
  * one strip per workgroup; 3 = the same strips, those of four consecutive primary indices

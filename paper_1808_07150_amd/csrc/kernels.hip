@@ -144,6 +144,7 @@ struct FwdArgs {
     double* part;        // F_OBJ partials (one per block)
     float gr;            // F_SENS: gamma * rho
     int split;           // host only: wavefronts per ray bundle (0: chosen from the size)
+    int interleave;      // host only: 1 keeps the interleaved rays where RUN instances apply
     float* raw;          // span compression: ray sums [angle of the chunk][k][ray plane]
     int raw_kq;          // 1: the walk writes its ray sums times L to raw (no epilogue)
     int ia0;             // index of the launch's first angle in the output lists
@@ -235,6 +236,16 @@ __global__ void __launch_bounds__(256) fwd_compress(FwdArgs P) {
 // together.  The objective's projection (F_OBJ), which the autotuner times in its place,
 // is held the same way.
 constexpr int FWD_RG = 8;  // rays per lane whose LDS reads are issued together
+// RUN instances (pitch-1 geometries whose segments split into at most 64 runs of FWD_RUN
+// consecutive planes: 61 for the 837 planes of span 11): lane L walks the rays of run L,
+// which lie in one segment on consecutive image planes, so per step a lane reads one
+// segment entry and the FWD_RUN + 1 column values its rays' two taps cover (in pairs),
+// instead of an entry and a pair per ray.  Each ray's arithmetic and the order of the
+// partial sums are those of the interleaved instances, so the sums are bitwise the same;
+// they pass through LDS into plane order before the epilogue.  An odd run length keeps
+// the lanes of a segment, FWD_RUN planes apart, on distinct LDS banks (a power-of-two
+// length puts every other lane on the same bank).
+constexpr int FWD_RUN = 15;
 
 // Per step and segment: byte offset of the axial cell and the axial fraction (one 8-byte
 // LDS read per ray and step).
@@ -243,9 +254,10 @@ struct __align__(8) SegStep {
     float fz;
 };
 
-template <int RPL, int MODE, int NW>
+template <int RPL, int MODE, int NW, bool RUN = false>
 __global__ void __launch_bounds__(64 * NW, ((MODE == F_DUAL || MODE == F_OBJ) && RPL <= 16) ? 5 : 1)
 fwd_wave(FwdArgs P) {
+    static_assert(!RUN || RPL == FWD_RUN, "a run is FWD_RUN rays");
     extern __shared__ float smem[];
     const GeomDev& G = P.G;
     const int ns = G.n_seg;
@@ -272,7 +284,26 @@ fwd_wave(FwdArgs P) {
     // never written), so every step handles all rows without per-lane branches.
     int toff[RPL], boff[RPL];
     float acc[RPL];
-    {
+    int run_q0 = 0, run_n = 0;  // RUN: first plane and ray count of the lane's run
+    if (RUN) {
+        // runs in segment order, FWD_RUN planes each (the last of a segment shorter); a
+        // lane without a run walks segment 0's first planes and writes nothing
+        int g = 0, first = 0, o = 0;
+        for (int sg = 0; sg < ns; ++sg) {
+            const int cnt = (G.seg_planes[sg] + FWD_RUN - 1) / FWD_RUN;
+            if (lane >= first && lane < first + cnt) {
+                g = sg;
+                o = (lane - first) * FWD_RUN;
+                run_n = min(FWD_RUN, G.seg_planes[sg] - o);
+            }
+            first += cnt;
+        }
+        run_q0 = G.seg_base[g] + o;
+        toff[0] = (int)((const char*)(segt + g) - (const char*)smem);
+        boff[0] = (int)((const char*)(Gb + o + G.seg_off[g] + P.pad) - (const char*)smem);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r] = 0.0f;
+    } else {
         const int g0 = G.plane_seg[0];
         const int base0 = G.seg_off[g0] - G.seg_pitch[g0] * G.seg_base[g0] + P.pad;
 #pragma unroll
@@ -362,6 +393,21 @@ fwd_wave(FwdArgs P) {
             segt[sg] = e;
         }
         __builtin_amdgcn_wave_barrier();
+        if (RUN) {
+            // the run's rays r read taps r and r + 1 of one window of the column
+            const SegStep e = *(const SegStep*)(lds + toff[0]);
+            const float* gp = (const float*)(lds + boff[0] + e.c4);
+            float v[RPL + 1];
+#pragma unroll
+            for (int r = 0; r <= RPL; ++r) v[r] = gp[r];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                acc[r] = __builtin_fmaf(1.0f - e.fz, v[r], acc[r]);
+                acc[r] = __builtin_fmaf(e.fz, v[r + 1], acc[r]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
         // rays in groups of RG: the table reads of a group, then its column reads, then
         // its sums, so a group costs two LDS round trips instead of two per ray
         constexpr int RG = RPL < FWD_RG ? RPL : FWD_RG;
@@ -419,10 +465,23 @@ fwd_wave(FwdArgs P) {
 
     // epilogues
     double obj = 0.0;
+    if (RUN) {
+        // the run's sums into plane order, then plane q = lane + 64 r per lane; the walk's
+        // LDS reads are done (a wavefront's LDS accesses execute in issue order)
+        float* T = smem;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int q = lane + 64 * r;
-        if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], acc[r], obj);
+        for (int r = 0; r < RPL; ++r)
+            if (r < run_n) T[run_q0 + r] = acc[r];
+        __builtin_amdgcn_wave_barrier();
+        for (int q = lane; q < G.n_planes; q += 64)
+            fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], T[q], obj);
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int q = lane + 64 * r;
+            if (q < G.n_planes) fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], acc[r], obj);
+        }
     }
     if (MODE == F_OBJ && !P.raw_kq) {  // raw rows: fwd_compress writes the partials
         obj = wave_sum(obj);

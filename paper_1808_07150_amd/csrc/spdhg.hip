@@ -437,12 +437,29 @@ int check_kernel_limits(const spdhg_geom* g) {
 }
 
 // ---------------------------------------------------------------- launch helpers
+// Whether the forward walk's RUN instances apply: every segment on consecutive image
+// planes, and at most 64 runs of FWD_RUN planes.
+bool walk_runs(const GeomDev& G) {
+    int runs = 0;
+    for (int g = 0; g < G.n_seg; ++g) {
+        if (G.seg_pitch[g] != 1) return false;
+        runs += (G.seg_planes[g] + FWD_RUN - 1) / FWD_RUN;
+    }
+    return runs <= 64;
+}
+
 template <int MODE, int NW>
 int launch_fwd_nw(int rpl, const FwdArgs& A, int nblk, hipStream_t st) {
     // per wavefront: axial columns and segment tables, also the staging of its partial
     // ray sums (kernel: wstride)
     const size_t lds = NW * std::max<size_t>(2 * (size_t)A.gsize + 8 * (size_t)A.G.n_seg, 64) * 4;
     const int nt = 64 * NW;
+    if (!A.interleave && walk_runs(A.G)) {
+        // the RUN epilogue also stages the ray sums in plane order
+        const size_t tbytes = (size_t)A.G.n_planes * 4;
+        return klaunch(fwd_wave<FWD_RUN, MODE, NW, true>, nblk, nt, std::max(lds, tbytes), st,
+                       A);
+    }
     // the iteration and the objective also have a 14-row instance (837 planes of span 11
     // take 14 rows: no rows past the last plane)
     constexpr bool hot = MODE == F_DUAL || MODE == F_OBJ;
@@ -717,6 +734,7 @@ struct spdhg_ctx {
     int64_t w_pending = 0;
     double tw = 0.0;
     int fwd_split = 0;  // wavefronts per ray bundle of the subset projection (0: automatic)
+    int interleave = 0; // 1: the forward walk keeps interleaved rays (no RUN instances)
     int gather = 0;     // backprojection tiling: 0 automatic (strips where they apply), 2 columns
     BwdPlan bplan_auto; // the automatic plan (bplan is it, or the per-column gather)
     spdhg_graph* graph = nullptr;  // persistent epoch graph of spdhg_epoch_graph (owned)
@@ -752,6 +770,7 @@ struct spdhg_ctx {
         A.gsize = gsize;
         A.raw = raw;
         A.raw_angles = raw_angles;
+        A.interleave = interleave;
         return A;
     }
     BwdArgs bwd_args() const {
@@ -2263,6 +2282,17 @@ int spdhg_load_state(spdhg_ctx* c, const void* src, size_t bytes, void* stream) 
     }
     c->k = hdr[0];
     return export_x(c, st);
+}
+
+int spdhg_set_walk(spdhg_ctx* c, int32_t interleave) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (interleave != 0 && interleave != 1) return fail(SPDHG_E_ARG, "interleave must be 0 or 1");
+    c->interleave = interleave;
+    if (c->graph) {  // its kernels may change: rebuilt on the next graph epoch
+        spdhg_graph_destroy(c->graph);
+        c->graph = nullptr;
+    }
+    return SPDHG_OK;
 }
 
 int spdhg_set_tuning(spdhg_ctx* c, int32_t fwd_split) {

@@ -28,6 +28,7 @@ EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_op_workspace_bytes",
             "spdhg_epoch_graph", "spdhg_graph_create", "spdhg_graph_epoch",
             "spdhg_graph_destroy", "spdhg_batch_epoch", "spdhg_pdhg_iterate", "spdhg_em_iterate",
             "spdhg_set_tuning", "spdhg_autotune", "spdhg_set_gather", "spdhg_get_tuning",
+            "spdhg_set_walk",
             "spdhg_info",
             "spdhg_objective", "spdhg_gap", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
             "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
@@ -104,6 +105,7 @@ def load_library() -> ctypes.CDLL:
     lib.spdhg_graph_epoch.argtypes = [vp, i32, vp]
     lib.spdhg_graph_destroy.argtypes = [vp]
     lib.spdhg_set_tuning.argtypes = [vp, i32]
+    lib.spdhg_set_walk.argtypes = [vp, i32]
     lib.spdhg_autotune.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
     lib.spdhg_set_gather.argtypes = [vp, i32]
     lib.spdhg_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -321,6 +323,11 @@ class Reconstruction:
 
     def set_tuning(self, fwd_split: int):
         _check(load_library().spdhg_set_tuning(self.ctx, int(fwd_split)))
+
+    def set_walk(self, interleave: bool):
+        """Forward walk's ray-to-lane mapping: False (default) runs of consecutive planes
+        per lane where the geometry allows, True interleaved planes (bitwise the same)."""
+        _check(load_library().spdhg_set_walk(self.ctx, int(bool(interleave))))
 
     def set_gather(self, gather: int):
         """Gather tiling: 0 automatic, 1 strips of 10 columns, 2 whole columns, 3 strips

@@ -114,6 +114,7 @@ def test_null_arguments_rejected(lib):
                           ctypes.byref(P.cparams(10, "tv")), None, None, None, None, None,
                           None, 0, None) == -1
     assert lib.spdhg_iterate(None, 1, None) == -1
+    assert lib.spdhg_set_walk(None, 0) == -1
 
 
 def test_operator_workspace(lib):

@@ -599,3 +599,28 @@ def test_strip_workgroup_rows_bitwise(P, tall3d):
         finally:
             rec.close()
     np.testing.assert_array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("name", ["tall3d", "span11_3d", "maxnz3d"])
+def test_walk_runs_bitwise(P, name, request):
+    """The forward walk's runs of consecutive planes per lane and its interleaved rays give
+    bitwise the same iterates and objective (split 1 and 4: with and without the partial
+    sums of several wavefronts)."""
+    d = request.getfixturevalue(name)
+    g = d["geom"]
+    t = {k: dev(d[k]) for k in ("b", "r", "mult")}
+    prm = P.cparams(4, "tv", "balanced", alpha=0.05, seed=41)
+    for split in (1, 4):
+        out = []
+        for interleave in (False, True):
+            x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+            rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+            rec.set_tuning(split)
+            rec.set_walk(interleave)
+            rec.epoch(2)
+            torch.cuda.synchronize()
+            out.append((x.cpu().numpy(), rec.objective().cpu().numpy(),
+                        rec.buffer("y").cpu().numpy()))
+            rec.close()
+        for a, b in zip(out[0], out[1]):
+            np.testing.assert_array_equal(a, b)
