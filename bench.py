@@ -629,6 +629,8 @@ def main():
     # the same epochs without per-launch events: plain launches and HIP-graph epochs
     alt = {}
     for mode in ("eager", "graph"):
+        if mode == "graph":
+            rec.epoch_graph(1)  # builds and instantiates the persistent graph (untimed)
         torch.cuda.synchronize()
         ev0.record(stream)
         if mode == "eager":

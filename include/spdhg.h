@@ -246,8 +246,10 @@ int spdhg_epoch(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
 
 /* The same iterations as spdhg_epoch (bitwise the same result), launched as a persistent
  * HIP graph: the context's own spdhg_graph (below), built on the first call and kept until
- * spdhg_destroy or a change of the tuning.  Returns after the stream has run the epochs.
- * Not with per-kernel profiling on (SPDHG_E_STATE). */
+ * spdhg_destroy or a change of the tuning or walk.  Asynchronous on `stream` like
+ * spdhg_epoch (the graph's two executable copies alternate; the host waits for a copy's
+ * previous run before rewriting its arguments).  Not with per-kernel profiling on
+ * (SPDHG_E_STATE). */
 int spdhg_epoch_graph(spdhg_ctx* ctx, int32_t n_epochs, void* stream);
 
 /* Persistent epoch graph of one or more problems (Algorithm 2's epochs of independent
@@ -286,8 +288,8 @@ int spdhg_autotune(spdhg_ctx* ctx, int32_t* fwd_split, double* ms, void* stream)
 
 /* Ray-to-lane mapping of the forward walk (the projection of Section 4.1, every mode):
  * 0 (default) = runs of 15 consecutive planes of one segment per lane where the geometry
- * allows it (all segments on consecutive image planes, at most 64 such runs, e.g. the 837
- * planes of span 11), else interleaved; 1 = always interleaved (plane q on lane q mod 64).
+ * allows it (more than 256 planes, all segments on consecutive image planes, at most 64
+ * such runs, e.g. the 837 planes of span 11), else interleaved; 1 = always interleaved (plane q on lane q mod 64).
  * Both give bitwise identical projections; runs read the LDS column once per run instead
  * of once per ray.  SPDHG_E_ARG for other values. */
 int spdhg_set_walk(spdhg_ctx* ctx, int32_t interleave);

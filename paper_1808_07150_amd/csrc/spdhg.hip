@@ -438,8 +438,11 @@ int check_kernel_limits(const spdhg_geom* g) {
 
 // ---------------------------------------------------------------- launch helpers
 // Whether the forward walk's RUN instances apply: every segment on consecutive image
-// planes, and at most 64 runs of FWD_RUN planes.
+// planes, at most 64 runs of FWD_RUN planes, and more than 256 planes (below that the
+// interleaved instances have at most 4 rays per lane and the runs would leave most lanes
+// idle).
 bool walk_runs(const GeomDev& G) {
+    if (G.n_planes <= 256) return false;
     int runs = 0;
     for (int g = 0; g < G.n_seg; ++g) {
         if (G.seg_pitch[g] != 1) return false;
@@ -2039,10 +2042,7 @@ int spdhg_epoch_graph(spdhg_ctx* c, int32_t n_epochs, void* stream) {
         int rc = spdhg_graph_create(one, 1, &c->graph);
         if (rc) return rc;
     }
-    int rc = spdhg_graph_epoch(c->graph, n_epochs, stream);
-    if (rc) return rc;
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    return SPDHG_OK;
+    return spdhg_graph_epoch(c->graph, n_epochs, stream);
 }
 
 int spdhg_pdhg_iterate(spdhg_ctx* c, int64_t n_iters, void* stream) {

@@ -311,14 +311,17 @@ class Reconstruction:
         _check(load_library().spdhg_epoch(self.ctx, int(n_epochs), _stream(stream)))
 
     def epoch_graph(self, n_epochs: int = 1):
-        """spdhg_epoch with every epoch recorded into a HIP graph (on a side stream: the
-        default stream cannot be captured); returns when the epochs have run."""
-        cur = torch.cuda.current_stream()
-        side = torch.cuda.Stream(device=self.x.device)
+        """spdhg_epoch as launches of the context's persistent HIP graph (bitwise the
+        same iterations).  Launched on a side stream (created once, default priority) that
+        waits for the current stream and that the current stream then waits for, so the
+        call is asynchronous like epoch()."""
+        cur = torch.cuda.current_stream(self.x.device)
+        if getattr(self, "_graph_stream", None) is None:
+            self._graph_stream = torch.cuda.Stream(device=self.x.device)
+        side = self._graph_stream
         side.wait_stream(cur)
-        with torch.cuda.stream(side):
-            _check(load_library().spdhg_epoch_graph(self.ctx, int(n_epochs),
-                                                    ctypes.c_void_p(side.cuda_stream)))
+        _check(load_library().spdhg_epoch_graph(self.ctx, int(n_epochs),
+                                                ctypes.c_void_p(side.cuda_stream)))
         cur.wait_stream(side)
 
     def set_tuning(self, fwd_split: int):

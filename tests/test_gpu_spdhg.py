@@ -430,7 +430,7 @@ def test_autotune_keeps_results(P, c1):
         rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
         if tune:
             split, ms = rec.autotune()
-            assert split in (1, 2, 4, 8) and ms > 0
+            assert split in (1, 2, 4, 8, 20, 40) and ms > 0
         rec.epoch(5)
         torch.cuda.synchronize()
         outs.append(x.cpu().numpy())
@@ -601,7 +601,7 @@ def test_strip_workgroup_rows_bitwise(P, tall3d):
     np.testing.assert_array_equal(out[0], out[1])
 
 
-@pytest.mark.parametrize("name", ["tall3d", "span11_3d", "maxnz3d"])
+@pytest.mark.parametrize("name", ["span11_3d", "maxnz3d"])
 def test_walk_runs_bitwise(P, name, request):
     """The forward walk's runs of consecutive planes per lane and its interleaved rays give
     bitwise the same iterates and objective (split 1 and 4: with and without the partial
