@@ -285,6 +285,7 @@ fwd_wave(FwdArgs P) {
     int toff[RPL], boff[RPL];
     float acc[RPL];
     int run_q0 = 0, run_n = 0;  // RUN: first plane and ray count of the lane's run
+    int run_g = 0;              // RUN: the run's segment
     if (RUN) {
         // runs in segment order, FWD_RUN planes each (the last of a segment shorter); a
         // lane without a run walks segment 0's first planes and writes nothing
@@ -299,6 +300,7 @@ fwd_wave(FwdArgs P) {
             first += cnt;
         }
         run_q0 = G.seg_base[g] + o;
+        run_g = g;
         toff[0] = (int)((const char*)(segt + g) - (const char*)smem);
         boff[0] = (int)((const char*)(Gb + o + G.seg_off[g] + P.pad) - (const char*)smem);
 #pragma unroll
@@ -327,6 +329,14 @@ fwd_wave(FwdArgs P) {
         const SegRay S = seg_ray(G, a, sg, k, kk);
         segk[sg] = S.ezk;
         segj[sg] = S.ezj;
+    }
+    // RUN: the run's own segment coefficients in registers (its axial sample per step is
+    // then computed by the lane, with the expression the table uses)
+    double run_ezj = 0.0, run_ezk = 0.0;
+    if (RUN) {
+        __builtin_amdgcn_wave_barrier();
+        run_ezk = segk[run_g];
+        run_ezj = segj[run_g];
     }
     int j0, j1;
     sec_range(A, __builtin_fma(A.du_dk, kk, A.cu), j0, j1);
@@ -385,17 +395,14 @@ fwd_wave(FwdArgs P) {
             }
         }
         if (j + 1 < j1) issue(j + 1);
-        for (int sg = lane; sg < ns; sg += 64) {
-            const Sample sz = split(__builtin_fma(segj[sg], jj, segk[sg]));
+        if (RUN) {
+            // the run's axial sample, then its rays r read taps r and r + 1 of one window
+            // of the column
+            const Sample sz = split(__builtin_fma(run_ezj, jj, run_ezk));
             SegStep e;
             e.c4 = sz.i0 * 4;
             e.fz = sz.fu;
-            segt[sg] = e;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (RUN) {
-            // the run's rays r read taps r and r + 1 of one window of the column
-            const SegStep e = *(const SegStep*)(lds + toff[0]);
+            __builtin_amdgcn_wave_barrier();
             const float* gp = (const float*)(lds + boff[0] + e.c4);
             float v[RPL + 1];
 #pragma unroll
@@ -408,6 +415,14 @@ fwd_wave(FwdArgs P) {
             __builtin_amdgcn_wave_barrier();
             continue;
         }
+        for (int sg = lane; sg < ns; sg += 64) {
+            const Sample sz = split(__builtin_fma(segj[sg], jj, segk[sg]));
+            SegStep e;
+            e.c4 = sz.i0 * 4;
+            e.fz = sz.fu;
+            segt[sg] = e;
+        }
+        __builtin_amdgcn_wave_barrier();
         // rays in groups of RG: the table reads of a group, then its column reads, then
         // its sums, so a group costs two LDS round trips instead of two per ray
         constexpr int RG = RPL < FWD_RG ? RPL : FWD_RG;
