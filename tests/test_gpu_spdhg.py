@@ -624,3 +624,28 @@ def test_walk_runs_bitwise(P, name, request):
             rec.close()
         for a, b in zip(out[0], out[1]):
             np.testing.assert_array_equal(a, b)
+
+
+def test_graph_epochs_async_then_eager(P, small3d):
+    """Graph epochs return before the GPU has run them: three graph epochs launched back
+    to back and an eager epoch right after, with no synchronisation in between, give the
+    result of four eager epochs bitwise (the stream orders them; the graph's two copies
+    alternate, each waiting for its own previous run)."""
+    g = small3d["geom"]
+    t = {k: dev(small3d[k]) for k in ("b", "r", "mult")}
+    prm = P.cparams(6, "tv", "balanced", alpha=0.05, seed=23)
+    xs = []
+    for graph in (False, True):
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+        if graph:
+            for _ in range(3):
+                rec.epoch_graph(1)
+            rec.epoch(1)
+        else:
+            rec.epoch(4)
+        torch.cuda.synchronize()
+        xs.append((x.cpu().numpy(), rec.buffer("z").cpu().numpy()))
+        rec.close()
+    for a, b in zip(xs[0], xs[1]):
+        np.testing.assert_array_equal(a, b)
