@@ -888,7 +888,8 @@ __global__ void __launch_bounds__(BWD_THREADS) bwd_col(BwdArgs P, const float* _
 // loaded value; the one-voxel shift of B is taken once per ray (ray_sum).  PITCH 2 (planes
 // on every other image plane): la, lb = lane, lane + 64; each voxel takes one plane of
 // the segment, u >> 1 with u = z + off, weighted wa (u even) or wb (u odd), so
-// neighbouring lanes load the same plane; s[0] and s[2] are the two halves' sums.
+// neighbouring voxels share planes (one load covers both halves, below); s[0] and s[2]
+// are the two halves' sums.
 template <int N, int PITCH>
 __device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, const TapCoef* tk,
                                             int g, int la, int lb, float (&s)[4]) {
@@ -911,20 +912,29 @@ __device__ __forceinline__ void strip_batch(const GeomDev& G, const float* dk, c
         }
     } else {
         const int sh = G.dstride == 2 ? 3 : 2;  // bytes per plane: 4 dstride
+        // The two halves' voxels (z = la, lb) take planes (z + off) >> 1: 64 consecutive
+        // planes from off >> 1, which one load brings in (lane L holds plane
+        // (off >> 1) + L).  Voxel z = L then takes lane (L + (off & 1)) >> 1's value and
+        // z = L + 64 the lane 32 above it, moved by LDS crossbar permutes (no memory
+        // access): one load per segment instead of two whose lanes pair up on the same
+        // planes.  (z = 127, beyond the image, takes lane 0's.)
+        float w[N];
 #pragma unroll
         for (int u = 0; u < N; ++u) {
             const __amdgpu_buffer_rsrc_t rs = seg_rsrc(G, dk, g + u);
             const int off = tk[g + u].off;
-            v[u][0] = __uint_as_float(
-                __builtin_amdgcn_raw_buffer_load_b32(rs, ((la + off) >> 1) << sh, 0, 0));
-            v[u][1] = __uint_as_float(
-                __builtin_amdgcn_raw_buffer_load_b32(rs, ((lb + off) >> 1) << sh, 0, 0));
+            w[u] = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(rs, (la + (off >> 1)) << sh, 0, 0));
         }
 #pragma unroll
         for (int u = 0; u < N; ++u) {
             const TapCoef& t = tk[g + u];
-            s[0] = __builtin_fmaf(((la + t.off) & 1) ? t.wb : t.wa, v[u][0], s[0]);
-            s[2] = __builtin_fmaf(((lb + t.off) & 1) ? t.wb : t.wa, v[u][1], s[2]);
+            const int src = ((la + (t.off & 1)) >> 1) << 2;
+            const float v0 = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(w[u])));
+            const float v1 =
+                __int_as_float(__builtin_amdgcn_ds_bpermute(src + 128, __float_as_int(w[u])));
+            s[0] = __builtin_fmaf(((la + t.off) & 1) ? t.wb : t.wa, v0, s[0]);
+            s[2] = __builtin_fmaf(((lb + t.off) & 1) ? t.wb : t.wa, v1, s[2]);
         }
     }
 }
