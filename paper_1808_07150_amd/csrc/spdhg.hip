@@ -609,7 +609,7 @@ BwdPlan bwd_plan(const HostTables& T) {
 // row-sampled and column-sampled angles run as two launches; when both classes occur and
 // the epilogue needs the whole sum, the first writes its partial image to `partial`.
 // The strip gather of the angles ang0 + i * step (i < cnt) (see launch_bwd).
-template <int MODE, int PITCH, int NS>
+template <int MODE, int PITCH, int NS, int DS = 1>
 int launch_strip(const BwdArgs& A, int cnt, int ang0, int step, hipStream_t st,
                  const BwdPlan& plan, const AngleDev* host_ang, float* partial) {
     bool has[2] = {false, false};
@@ -623,19 +623,19 @@ int launch_strip(const BwdArgs& A, int cnt, int ang0, int step, hipStream_t st,
     const float* none = nullptr;
     if (has[1] && has[0]) {
         if (MODE == B_ACCUM) {
-            int rc = klaunch(bwd_strip<B_ACCUM, PITCH, NS>, nstr_r, nt, lds, st, A, plan.KR, 1, none);
+            int rc = klaunch(bwd_strip<B_ACCUM, PITCH, NS, DS>, nstr_r, nt, lds, st, A, plan.KR, 1, none);
             if (rc) return rc;
-            return klaunch(bwd_strip<B_ACCUM, PITCH, NS>, nstr_c, nt, lds, st, A, plan.KR, 0, none);
+            return klaunch(bwd_strip<B_ACCUM, PITCH, NS, DS>, nstr_c, nt, lds, st, A, plan.KR, 0, none);
         }
         BwdArgs Pp = A;
         Pp.out = partial;
-        int rc = klaunch(bwd_strip<B_PARTIAL, PITCH, NS>, nstr_r, nt, lds, st, Pp, plan.KR, 1, none);
+        int rc = klaunch(bwd_strip<B_PARTIAL, PITCH, NS, DS>, nstr_r, nt, lds, st, Pp, plan.KR, 1, none);
         if (rc) return rc;
-        return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_c, nt, lds, st, A, plan.KR, 0,
+        return klaunch(bwd_strip<MODE, PITCH, NS, DS>, nstr_c, nt, lds, st, A, plan.KR, 0,
                        (const float*)partial);
     }
-    if (has[1]) return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_r, nt, lds, st, A, plan.KR, 1, none);
-    if (has[0]) return klaunch(bwd_strip<MODE, PITCH, NS>, nstr_c, nt, lds, st, A, plan.KR, 0, none);
+    if (has[1]) return klaunch(bwd_strip<MODE, PITCH, NS, DS>, nstr_r, nt, lds, st, A, plan.KR, 1, none);
+    if (has[0]) return klaunch(bwd_strip<MODE, PITCH, NS, DS>, nstr_c, nt, lds, st, A, plan.KR, 0, none);
     return SPDHG_OK;
 }
 
@@ -646,7 +646,9 @@ int launch_bwd(BwdArgs A, int ang0, int step, int cnt, hipStream_t st, const Bwd
     A.ang_step = step;
     A.n_ang_sub = cnt;
     if (plan.strip && plan.pitch == 2)
-        return launch_strip<MODE, 2, 0>(A, cnt, ang0, step, st, plan, host_ang, partial);
+        return A.G.dstride == 2
+                   ? launch_strip<MODE, 2, 0, 2>(A, cnt, ang0, step, st, plan, host_ang, partial)
+                   : launch_strip<MODE, 2, 0, 1>(A, cnt, ang0, step, st, plan, host_ang, partial);
     if (plan.strip && A.G.n_seg == 11 && !A.G.kpos && !A.G.kobl && !A.G.kL)
         return launch_strip<MODE, 1, 11>(A, cnt, ang0, step, st, plan, host_ang, partial);
     if (plan.strip)
