@@ -1987,10 +1987,12 @@ extern "C" {
 int spdhg_set_profiling(spdhg_ctx* c, int32_t on) {
     if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
     if (on && c->ev.empty()) {
+        // timing-only events: no system-scope fence (and so no cache writeback and
+        // invalidation) at each record, which would slow the kernels being timed
         const size_t pairs = 1024;
         c->ev.resize(2 * pairs);
         c->ev_kind.resize(pairs);
-        for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+        for (auto& e : c->ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     if (!on && c->prof) {
         int rc = prof_collect(c);
