@@ -1473,7 +1473,9 @@ __device__ __forceinline__ bool wave_map(int nx, int ny, int nz, int ly, WaveMap
 }
 
 struct TvRow {
-    float xp, xn, xz, y0, y1, y2, z, t;  // x(c + e_x), x(c + e_y), x(c + e_z), y(c), z(c), T(c)
+    // x(c + e_x), x(c + e_y), x(c + e_z), y(c), z(c), T(c); the x(. + e_z) values only on
+    // the lane that loads them (the run's last: the others take the next lane's x)
+    float xp, xn, xz, y0, y1, y2, z, t;
     float lxn, lxz, ly0, ly1, ly2;       // x-neighbour: x(c - e_x + e_y), x(c - e_x + e_z), y
     float i0, i1, i2, li0, li1, li2;     // dTV field at c and c - e_x
 };
@@ -1531,6 +1533,7 @@ tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__
     const int cx = m.cx, cz = m.cz, y0 = m.y0, y1 = m.y1;
     const bool act = m.act, own = m.own;  // own: writes its voxel
     const bool hx = cx < P.nx - 1, lx = cx > 0, hz = cz < P.nz - 1;
+    const bool hz_ld = hz && m.lane == 63;  // loads its own +z neighbours
     int cy = y0 > 0 ? y0 - 1 : y0;
     uint32_t c = 4u * (((uint32_t)cy * P.nx + cx) * P.nz + min(cz, P.nz - 1));
     TvRow cur = {}, nxt = {};
@@ -1539,7 +1542,7 @@ tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__
     const auto rxl = vol_rsrc(PAIR ? P.xlo : x_in, nvb), rzl = vol_rsrc(PAIR ? P.zlo : z, nvb);
     float lo_x = 0.0f, lo_z = 0.0f, lo_xn = 0.0f, lo_zn = 0.0f;
     if (act) {
-        tv_row_load<DTV>(cur, rx, ry, rz, rt, rxi, c, sx, sy, nvb, hx, cy < P.ny - 1, hz, lx);
+        tv_row_load<DTV>(cur, rx, ry, rz, rt, rxi, c, sx, sy, nvb, hx, cy < P.ny - 1, hz_ld, lx);
         xc = vol_ld(rx, c, 0);
         if (lx) xl = vol_ld(rx, c - sx, 0);
         if (PAIR) {
@@ -1551,20 +1554,26 @@ tv_wave(PriorArgs P, int ly, const float* __restrict__ x_in, float* __restrict__
         const bool hy = cy < P.ny - 1;
         if (act && cy + 1 < y1) {
             tv_row_load<DTV>(nxt, rx, ry, rz, rt, rxi, c + sy, sx, sy, nvb, hx, cy + 1 < P.ny - 1,
-                             hz, lx);
+                             hz_ld, lx);
             if (PAIR) {
                 lo_xn = vol_ld(rxl, c + sy, 0);
                 lo_zn = vol_ld(rzl, c + sy, 0);
             }
         }
+        // +z neighbours: the next lane's x and x-neighbour (wavefront shift left by one
+        // lane, all lanes taking part); the last lane keeps the values it loaded
+        const float xz = __int_as_float(__builtin_amdgcn_update_dpp(
+            __float_as_int(cur.xz), __float_as_int(xc), 0x130 /* wave_shl:1 */, 0xF, 0xF, false));
+        const float lxz = __int_as_float(__builtin_amdgcn_update_dpp(
+            __float_as_int(cur.lxz), __float_as_int(xl), 0x130 /* wave_shl:1 */, 0xF, 0xF, false));
         float q[3], dy[3] = {0.0f, 0.0f, 0.0f}, qn[3], dn[3] = {0.0f, 0.0f, 0.0f};
         if (act) {
             prior_dual_vals(P, hx ? cur.xp - xc : 0.0f, hy ? cur.xn - xc : 0.0f,
-                            hz ? cur.xz - xc : 0.0f, cur.y0, cur.y1, cur.y2, cur.i0, cur.i1,
+                            hz ? xz - xc : 0.0f, cur.y0, cur.y1, cur.y2, cur.i0, cur.i1,
                             cur.i2, q, dy);
             // x-neighbour (cx - 1, cy, cz): its +x difference is x(c) - x(c - e_x)
             if (lx)
-                prior_dual_vals(P, xc - xl, hy ? cur.lxn - xl : 0.0f, hz ? cur.lxz - xl : 0.0f,
+                prior_dual_vals(P, xc - xl, hy ? cur.lxn - xl : 0.0f, hz ? lxz - xl : 0.0f,
                                 cur.ly0, cur.ly1, cur.ly2, cur.li0, cur.li1, cur.li2, qn, dn);
         }
         const float dzn = __shfl_up(dy[2], 1, 64);  // all lanes take part
