@@ -152,12 +152,14 @@ def test_mmr_prior_iteration(P, mmr_inputs, prior, m, alpha, alpha1):
         rec.close()
 
 
-@pytest.mark.parametrize("split", [0, 4])
-def test_mmr_data_iteration(P, mmr_inputs, split):
+@pytest.mark.parametrize("split,gather", [(0, 0), (4, 3)])
+def test_mmr_data_iteration(P, mmr_inputs, split, gather):
     """One data iteration (12 angles, nnz 3.3e9) of mMR with TV, SPDHG+: y of the subset,
     z and the next iterate against the oracle's Algorithm 2 loop; every other subset's y
-    is left untouched.  Split 0 lets the launch size choose the ray-bundle split; 4 is the
-    benchmark's instance (fwd_wave<14, F_DUAL, 4>)."""
+    is left untouched.  Split 0 and gather 0 let the launch size choose the ray-bundle
+    split and take one strip per workgroup; split 4 with gather tiling 3 (four strip rows
+    per workgroup) is the benchmark's autotuned launch: fwd_wave<15, F_DUAL, 4, runs> and
+    bwd_strip<B_PARTIAL / B_ITER, 1, 11> in 256-thread workgroups."""
     g, b, r, mult, x0 = mmr_inputs
     m, seed, alpha = 21, 18080720, 2e-3
     blocks = SA.draw_blocks(seed, SA.balanced(m, 1), 400)
@@ -165,12 +167,15 @@ def test_mmr_data_iteration(P, mmr_inputs, split):
     k = next(i for i in range(2, 400) if blocks[i] < m and any(v < m for v in blocks[:i])
              and any(v >= m for v in blocks[:i]))
     i = blocks[k]
-    print(f"[fullsize] data iteration {k} (subset {i}), split {split}", flush=True)
+    print(f"[fullsize] data iteration {k} (subset {i}), split {split}, gather {gather}",
+          flush=True)
     x = x0.clone()
     rec = P.Reconstruction(g, P.cparams(m, "tv", "balanced", True, alpha=alpha, seed=seed),
                            b, r, mult, x)
     try:
         rec.set_tuning(split)
+        rec.set_gather(gather)
+        assert rec.tuning() == (split, 3 if gather == 3 else 1)
         rec.iterate(k)
         s0 = snap(rec, ["y", "z", "T", "sigma", "prior_dual"])
         x_before = x.cpu().numpy().astype(np.float64)
