@@ -373,12 +373,17 @@ int spdhg_load_state(spdhg_ctx* ctx, const void* src, size_t bytes, void* stream
 /* Per-kernel timing of the iteration (HIP events recorded on the caller's stream around
  * each launch; adds no synchronisation inside spdhg_iterate).  spdhg_set_profiling turns
  * it on or off and clears the totals; spdhg_profile waits for the recorded events and
- * returns, per kernel kind (SPDHG_PROF_*), the summed milliseconds and launch counts. */
+ * returns, per kernel kind (SPDHG_PROF_*), the summed milliseconds and launch counts.
+ * spdhg_set_profiling_kinds limits the timing to the kinds whose bit (1 << SPDHG_PROF_*)
+ * is set in `mask` (default: every kind), for launches enqueued after the call: each
+ * event pair costs the stream a few microseconds, so timing one kind disturbs the
+ * others less.  SPDHG_E_ARG for a mask without a kind or with other bits. */
 #define SPDHG_PROF_FWD 0   /* forward projection fused with the KL-dual prox          */
 #define SPDHG_PROF_BWD 1   /* gather backprojection fused with the primal epilogue    */
 #define SPDHG_PROF_PRIOR 2 /* prior dual update fused with its adjoint and epilogue    */
 #define SPDHG_PROF_KINDS 3
 int spdhg_set_profiling(spdhg_ctx* ctx, int32_t on);
+int spdhg_set_profiling_kinds(spdhg_ctx* ctx, int32_t mask);
 int spdhg_profile(spdhg_ctx* ctx, double* ms, int64_t* launches);
 
 /* Release the context (host memory only; caller memory is untouched). */

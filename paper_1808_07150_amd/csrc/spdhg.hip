@@ -759,8 +759,11 @@ struct spdhg_ctx {
     int64_t k = 0;
     int64_t iters_per_epoch = 1;
     int64_t nv = 0, nb = 0, max_sub_bins = 0;
-    // optional per-kernel timing: event pairs around each launch of the iteration
+    // optional per-kernel timing: event pairs around each launch of the iteration (of the
+    // kinds in prof_mask)
     bool prof = false;
+    int prof_mask = (1 << SPDHG_PROF_KINDS) - 1;
+    bool ev_open = false;  // prof_begin recorded the start of a pair
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;  // kernel kind of each recorded pair
     size_t ev_used = 0;
@@ -1001,20 +1004,23 @@ int prof_collect(spdhg_ctx* c) {
 }
 
 int prof_begin(spdhg_ctx* c, int kind, hipStream_t st) {
-    if (!c->prof) return SPDHG_OK;
+    c->ev_open = false;
+    if (!c->prof || !((c->prof_mask >> kind) & 1)) return SPDHG_OK;
     if (2 * c->ev_used + 2 > c->ev.size()) {
         int rc = prof_collect(c);
         if (rc) return rc;
     }
     c->ev_kind[c->ev_used] = kind;
     HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used], st));
+    c->ev_open = true;
     return SPDHG_OK;
 }
 
 int prof_end(spdhg_ctx* c, hipStream_t st) {
-    if (!c->prof) return SPDHG_OK;
+    if (!c->prof || !c->ev_open) return SPDHG_OK;
     HIP_TRY(hipEventRecord(c->ev[2 * c->ev_used + 1], st));
     c->ev_used += 1;
+    c->ev_open = false;
     return SPDHG_OK;
 }
 
@@ -2003,6 +2009,14 @@ int spdhg_set_profiling(spdhg_ctx* c, int32_t on) {
         c->prof_ms[i] = 0.0;
         c->prof_n[i] = 0;
     }
+    return SPDHG_OK;
+}
+
+int spdhg_set_profiling_kinds(spdhg_ctx* c, int32_t mask) {
+    if (!c) return fail(SPDHG_E_ARG, "ctx is NULL");
+    if (mask <= 0 || mask >= (1 << SPDHG_PROF_KINDS))
+        return fail(SPDHG_E_ARG, "mask must name at least one kernel kind and no other bits");
+    c->prof_mask = mask;
     return SPDHG_OK;
 }
 

@@ -31,7 +31,8 @@ EXPORTED = ["spdhg_last_error", "spdhg_subset_bins", "spdhg_op_workspace_bytes",
             "spdhg_set_walk",
             "spdhg_info",
             "spdhg_objective", "spdhg_gap", "spdhg_buffer", "spdhg_block_info", "spdhg_state_bytes",
-            "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling", "spdhg_profile",
+            "spdhg_save_state", "spdhg_load_state", "spdhg_set_profiling",
+            "spdhg_set_profiling_kinds", "spdhg_profile",
             "spdhg_destroy"]
 PROF_KINDS = ("fwd", "bwd", "prior")
 
@@ -120,6 +121,7 @@ def load_library() -> ctypes.CDLL:
     lib.spdhg_save_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.spdhg_load_state.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.spdhg_set_profiling.argtypes = [vp, i32]
+    lib.spdhg_set_profiling_kinds.argtypes = [vp, i32]
     lib.spdhg_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.spdhg_destroy.argtypes = [vp]
     for name in EXPORTED[2:]:
@@ -423,8 +425,12 @@ class Reconstruction:
         _check(load_library().spdhg_load_state(self.ctx, ctypes.c_void_p(buf.data_ptr()),
                                                buf.numel(), _stream(stream)))
 
-    def set_profiling(self, on: bool):
-        _check(load_library().spdhg_set_profiling(self.ctx, 1 if on else 0))
+    def set_profiling(self, on: bool, kinds=PROF_KINDS):
+        """Per-kernel timing on or off (totals cleared); `kinds`: the kernel kinds timed."""
+        lib = load_library()
+        _check(lib.spdhg_set_profiling_kinds(
+            self.ctx, sum(1 << PROF_KINDS.index(k) for k in kinds)))
+        _check(lib.spdhg_set_profiling(self.ctx, 1 if on else 0))
 
     def profile(self):
         """{kind: (total ms, launches)} of the kernels launched while profiling was on."""

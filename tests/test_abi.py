@@ -115,6 +115,7 @@ def test_null_arguments_rejected(lib):
                           None, 0, None) == -1
     assert lib.spdhg_iterate(None, 1, None) == -1
     assert lib.spdhg_set_walk(None, 0) == -1
+    assert lib.spdhg_set_profiling_kinds(None, 2) == -1
 
 
 def test_operator_workspace(lib):

@@ -649,3 +649,35 @@ def test_graph_epochs_async_then_eager(P, small3d):
         rec.close()
     for a, b in zip(xs[0], xs[1]):
         np.testing.assert_array_equal(a, b)
+
+
+def test_profiling_kinds(P, tall3d):
+    """Per-kernel events limited to one kernel kind: the same seed gives the same image
+    bitwise, the timed kind has the launch count of a run that times every kind, and the
+    other kinds record nothing; a mask without a kind is refused."""
+    from paper_1808_07150_amd.spdhg import SpdhgError
+    g = tall3d["geom"]
+    t = {k: dev(tall3d[k]) for k in ("b", "r", "mult")}
+    prm = P.cparams(8, "tv", "balanced", alpha=0.05, seed=29)
+    out = {}
+    for kinds in (P.spdhg.PROF_KINDS, ("bwd",)):
+        print(f"[spdhg] tall3d TV, events around {kinds}", flush=True)
+        x = torch.zeros(g.image_shape, dtype=torch.float32, device="cuda:0")
+        rec = P.Reconstruction(g, prm, t["b"], t["r"], t["mult"], x)
+        try:
+            rec.set_profiling(True, kinds=kinds)
+            rec.epoch(2)
+            prof = rec.profile()
+            rec.set_profiling(False)
+            torch.cuda.synchronize()
+            out[len(kinds)] = (x.cpu().numpy(), prof)
+            if len(kinds) == 1:
+                with pytest.raises(SpdhgError):
+                    rec.set_profiling(True, kinds=())
+        finally:
+            rec.close()
+    (x_all, p_all), (x_one, p_one) = out[3], out[1]
+    np.testing.assert_array_equal(x_all, x_one)
+    assert p_all["fwd"][1] > 0 and p_all["prior"][1] > 0 and p_all["bwd"][1] > 0
+    assert p_one["bwd"][1] == p_all["bwd"][1] and p_one["bwd"][0] > 0
+    assert p_one["fwd"] == (0.0, 0) and p_one["prior"] == (0.0, 0)
