@@ -617,14 +617,18 @@ def main():
     for _ in range(args.warmup):
         rec.epoch(1)
     torch.cuda.synchronize()
-    # untimed: every kernel kind under events, which names the dominant kernel and gives
+    # Every leg below runs the same epochs: the state saved here is restored before each
+    # (its iteration counter fixes the random draws), so they do the same work.  First,
+    # untimed, every kernel kind under events, which names the dominant kernel and gives
     # the others' launch times; the timed epochs then carry events around the dominant
-    # kernel only (each event pair costs the stream a few microseconds)
+    # kernel only (each event pair costs the stream a few microseconds).
+    snap = rec.save_state()
     rec.set_profiling(True)
     rec.epoch(args.steps)
     prof = rec.profile()
     rec.set_profiling(False)
     dom = max(prof, key=lambda k: prof[k][0])
+    rec.load_state(snap)
     rec.set_profiling(True, kinds=(dom,))
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -636,13 +640,18 @@ def main():
     ms = ev0.elapsed_time(ev1)
     prof_timed = rec.profile()
     rec.set_profiling(False)
-    prof[dom] = prof_timed[dom]  # the dominant kernel's launches of the timed region
+    # the same iterations as the untimed pass, so the same launches of the dominant kind
+    assert prof_timed[dom][1] == prof[dom][1], (prof_timed, prof)
+    prof[dom] = prof_timed[dom]  # the dominant kernel's launch times of the timed region
     psi = float(rec.objective()[0].item())
-    # the same epochs without per-launch events: plain launches and HIP-graph epochs
+    x_timed = x.clone()
+    # the same epochs without per-launch events: plain launches and HIP-graph epochs, each
+    # checked bitwise against the image of the timed epochs
     alt = {}
     for mode in ("eager", "graph"):
         if mode == "graph":
             rec.epoch_graph(1)  # builds and instantiates the persistent graph (untimed)
+        rec.load_state(snap)
         torch.cuda.synchronize()
         ev0.record(stream)
         if mode == "eager":
@@ -652,11 +661,13 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         alt[f"{mode}_epochs_per_s"] = round(args.steps / (ev0.elapsed_time(ev1) * 1e-3), 3)
+        alt[f"{mode}_same_image"] = bool(torch.equal(x, x_timed))
+    del snap, x_timed
     log(f"without per-kernel events: {alt}")
     log(f"{args.steps} epochs in {ms:.1f} ms (events around {dom} only); objective "
         f"{psi0:.6e} -> {psi:.6e}")
     log("kernels: " + ", ".join(f"{k} {v[0]:.1f} ms / {v[1]}" for k, v in prof.items())
-        + f" ({dom}: timed region; others: the untimed pass before it)")
+        + f" ({dom}: timed region; others: the same epochs in the untimed pass)")
 
     nv = g.n_vox
     n_i = P.subset_bins(g, m, 0)
@@ -671,13 +682,8 @@ def main():
         bytes_prior += 16 * nv
     flops_fwd = 2.0 * nnz + 20.0 * n_i     # one FMA per nonzero + the prox per bin
     flops_bwd = 2.0 * nnz + 6.0 * nv
-    # launches of the timed region: every iteration is one data iteration (one fwd and one
-    # bwd launch pair) or one prior iteration (one prior pair), and the dominant kind's
-    # pairs were counted there
-    n_iter = args.steps * rec.iters_per_epoch
-    n_dom = prof_timed[dom][1]
-    n_fwd = n_dom if dom in ("fwd", "bwd") else n_iter - n_dom
-    n_prior = n_iter - n_fwd
+    # launches of the timed epochs (the untimed pass ran the same iterations)
+    n_fwd, n_prior = prof["fwd"][1], prof["prior"][1]
     epoch_bytes = (n_fwd * (bytes_fwd + bytes_bwd) + n_prior * bytes_prior) / args.steps
     kinds = {
         "fwd": dict(bound="alu", work=flops_fwd, unit="TFLOP/s", peak=ALU_PEAK_TFLOPS,
