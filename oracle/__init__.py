@@ -13,8 +13,8 @@ Modules:
   spdhg      problem setup, step sizes (Theorem 2), SPDHG (Alg. 2), PDHG (Alg. 1),
              objective, duality gap, KKT residual, MLEM step, metrics
 
-Parity unpinned: no value printed in the paper pins a reconstructed image, objective
-or iteration count (its figures are not in the text and its data are clinical); the
-oracle is pinned by closed forms, invariants and brute force in tests/test_oracle_*.
+Pins: the paper prints no reconstructed image, objective or iteration count to compare
+against (its figures are not in the text and its data are clinical), so every function
+here is pinned by closed forms, invariants and brute force in tests/test_oracle_*.
 """
 from . import priors, projector, prox, sampling, spdhg  # noqa: F401
