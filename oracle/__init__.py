@@ -14,7 +14,9 @@ Modules:
              objective, duality gap, KKT residual, MLEM step, metrics
 
 Pins: the paper prints no reconstructed image, objective or iteration count to compare
-against (its figures are not in the text and its data are clinical), so every function
-here is pinned by closed forms, invariants and brute force in tests/test_oracle_*.
+against (its figures are not in the text and its data are clinical), so the functions
+the parity tests rest on are pinned by closed forms, invariants and brute force in
+tests/test_oracle_*; the reporting metrics (relative_objective, psnr_paper) are plain
+formulas with no pin of their own.
 """
 from . import priors, projector, prox, sampling, spdhg  # noqa: F401
