@@ -1116,6 +1116,61 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
             }
         }
     }
+    if constexpr (MODE == B_ITER) {
+        // The epilogue of Algorithm 2 (z += dz; x = max(x - T (z + dz / p_i), 0)) in two
+        // batches of five columns: all loads of a batch (z, x, T and the partial image, 40
+        // per lane) are issued before its first store, so a wavefront waits for two round
+        // trips instead of two per voxel.  The loads go through range-checked buffer
+        // resources, so lanes outside the image (z = -1, z >= nz, columns past the edge)
+        // read a neighbouring voxel or zero; only lanes inside it store.  The arithmetic
+        // is that of bwd_epilogue.
+        const int nvb = 4 * G.nx * G.ny * nz;  // below 1 GiB
+        const auto rz = __builtin_amdgcn_make_buffer_rsrc(P.z, (short)0, nvb, 0x00020000);
+        const auto rx = __builtin_amdgcn_make_buffer_rsrc(P.x, (short)0, nvb, 0x00020000);
+        const auto rt = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P.T), (short)0,
+                                                          nvb, 0x00020000);
+        const auto rp = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(partial ? partial : P.T), (short)0, nvb, 0x00020000);
+        constexpr int CB = 5;
+        static_assert(BS_W % CB == 0, "whole batches of columns");
+#pragma unroll
+        for (int cb = 0; cb < BS_W; cb += CB) {
+            float zv[CB][2], xv[CB][2], tv[CB][2], pv[CB][2];
+            uint32_t off[CB][2];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const int sec = s0 + cb + u;
+                const int ix = rowdom ? sec : j, iy = rowdom ? j : sec;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    off[u][hh] = 4u * (uint32_t)((iy * G.nx + ix) * nz + zl + 64 * hh);
+                    zv[u][hh] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rz, off[u][hh], 0, 0));
+                    xv[u][hh] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rx, off[u][hh], 0, 0));
+                    tv[u][hh] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rt, off[u][hh], 0, 0));
+                    pv[u][hh] = partial ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                              rp, off[u][hh], 0, 0))
+                                        : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                if (s0 + cb + u >= n_sec) continue;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int iz = zl + 64 * hh;
+                    if (iz < 0 || iz >= nz) continue;
+                    const float dz = acc[cb + u][hh] + pv[u][hh];
+                    const float zn = zv[u][hh] + dz;
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(zn), rz, off[u][hh], 0, 0);
+                    const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __float_as_uint(fmaxf(xv[u][hh] - tv[u][hh] * zbar, 0.0f)), rx,
+                        off[u][hh], 0, 0);
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < BS_W; ++c) {
         const int sec = s0 + c;
