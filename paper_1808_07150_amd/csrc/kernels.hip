@@ -489,8 +489,45 @@ fwd_wave(FwdArgs P) {
         for (int r = 0; r < RPL; ++r)
             if (r < run_n) T[run_q0 + r] = acc[r];
         __builtin_amdgcn_wave_barrier();
-        for (int q = lane; q < G.n_planes; q += 64)
-            fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], T[q], obj);
+        if (MODE == F_DUAL && !P.raw_kq) {
+            // the KL-dual prox of fwd_bin for 5 planes per lane at a time: every table and
+            // data load of a batch is issued before its first store (the stores to y and d
+            // may alias the next plane's loads, so plane by plane each waited for its own
+            // loads).  Lanes past the last plane load the last plane and store nothing.
+            constexpr int EB = 5;
+            const int nq = G.n_planes;
+            for (int q0 = 0; q0 < nq; q0 += 64 * EB) {
+                float v[EB], sg[EB], m[EB], yo[EB], bb[EB], rr[EB];
+                int64_t full[EB];
+#pragma unroll
+                for (int e = 0; e < EB; ++e) {
+                    const int q = min(q0 + lane + 64 * e, nq - 1);
+                    const int g = G.plane_seg[q];
+                    const float L = G.kL ? G.sa[a * G.n_seg + g].L * G.kL[g * G.n_rad + k]
+                                         : G.sa[a * G.n_seg + g].L;
+                    v[e] = T[q] * L;
+                    full[e] = ((int64_t)a * G.n_rad + k) * G.n_dplanes + q;
+                    sg[e] = P.sigma ? P.sigma[full[e]] : P.sig_s;
+                    m[e] = P.mult[full[e]];
+                    yo[e] = P.y[full[e]];
+                    bb[e] = P.b[full[e]];
+                    rr[e] = P.r[full[e]];
+                }
+#pragma unroll
+                for (int e = 0; e < EB; ++e) {
+                    const int q = q0 + lane + 64 * e;
+                    if (q >= nq) continue;
+                    float yn = yo[e];
+                    if (sg[e] > 0.0f)
+                        yn = prox_kl_dual(__builtin_fmaf(sg[e], m[e] * v[e], yo[e]), sg[e], bb[e], rr[e]);
+                    P.y[full[e]] = yn;
+                    P.d[dual_row(G, ia, k) + q] = m[e] * (yn - yo[e]);
+                }
+            }
+        } else {
+            for (int q = lane; q < G.n_planes; q += 64)
+                fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], T[q], obj);
+        }
     } else {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
