@@ -203,6 +203,42 @@ __device__ __forceinline__ void fwd_epilogue(const FwdArgs& P, int a, int ia, in
     fwd_bin<MODE>(P, a, ia, k, q, v, obj);
 }
 
+// The F_DUAL epilogue of fwd_bin for N rays of a lane (no raw rows): every table and
+// data load is issued before the first store (the stores to y and d may alias the next
+// ray's loads, so ray by ray each waited for its own loads).  A slot with q[e] < 0 loads
+// plane 0 of segment 0 and stores nothing.
+template <int N>
+__device__ __forceinline__ void fwd_dual_batch(const FwdArgs& P, int a, int ia, int k,
+                                               const int (&q)[N], const int (&g)[N],
+                                               const float (&acc)[N]) {
+    const GeomDev& G = P.G;
+    float v[N], sg[N], m[N], yo[N], bb[N], rr[N];
+    int64_t full[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const int qc = q[e] < 0 ? 0 : q[e];
+        const int gc = q[e] < 0 ? 0 : g[e];
+        const float L = G.kL ? G.sa[a * G.n_seg + gc].L * G.kL[gc * G.n_rad + k]
+                             : G.sa[a * G.n_seg + gc].L;
+        v[e] = acc[e] * L;
+        full[e] = ((int64_t)a * G.n_rad + k) * G.n_dplanes + qc;
+        sg[e] = P.sigma ? P.sigma[full[e]] : P.sig_s;
+        m[e] = P.mult[full[e]];
+        yo[e] = P.y[full[e]];
+        bb[e] = P.b[full[e]];
+        rr[e] = P.r[full[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        if (q[e] < 0) continue;
+        float yn = yo[e];
+        if (sg[e] > 0.0f)
+            yn = prox_kl_dual(__builtin_fmaf(sg[e], m[e] * v[e], yo[e]), sg[e], bb[e], rr[e]);
+        P.y[full[e]] = yn;
+        P.d[dual_row(G, ia, k) + q[e]] = m[e] * (yn - yo[e]);
+    }
+}
+
 // Span compression (eq. of the forward model with the scanner's data planes): every data
 // bin of the chunk's angles is the sum of its ring-pair rays (clist order, fixed), then
 // the mode's epilogue.  One block per (angle of the chunk, radial bin), so the objective's
@@ -490,43 +526,41 @@ fwd_wave(FwdArgs P) {
             if (r < run_n) T[run_q0 + r] = acc[r];
         __builtin_amdgcn_wave_barrier();
         if (MODE == F_DUAL && !P.raw_kq) {
-            // the KL-dual prox of fwd_bin for 5 planes per lane at a time: every table and
-            // data load of a batch is issued before its first store (the stores to y and d
-            // may alias the next plane's loads, so plane by plane each waited for its own
-            // loads).  Lanes past the last plane load the last plane and store nothing.
+            // five planes per lane at a time (60 VGPRs, eight waves; seven needed 78)
             constexpr int EB = 5;
             const int nq = G.n_planes;
             for (int q0 = 0; q0 < nq; q0 += 64 * EB) {
-                float v[EB], sg[EB], m[EB], yo[EB], bb[EB], rr[EB];
-                int64_t full[EB];
-#pragma unroll
-                for (int e = 0; e < EB; ++e) {
-                    const int q = min(q0 + lane + 64 * e, nq - 1);
-                    const int g = G.plane_seg[q];
-                    const float L = G.kL ? G.sa[a * G.n_seg + g].L * G.kL[g * G.n_rad + k]
-                                         : G.sa[a * G.n_seg + g].L;
-                    v[e] = T[q] * L;
-                    full[e] = ((int64_t)a * G.n_rad + k) * G.n_dplanes + q;
-                    sg[e] = P.sigma ? P.sigma[full[e]] : P.sig_s;
-                    m[e] = P.mult[full[e]];
-                    yo[e] = P.y[full[e]];
-                    bb[e] = P.b[full[e]];
-                    rr[e] = P.r[full[e]];
-                }
+                int qs[EB], gs[EB];
+                float vs[EB];
 #pragma unroll
                 for (int e = 0; e < EB; ++e) {
                     const int q = q0 + lane + 64 * e;
-                    if (q >= nq) continue;
-                    float yn = yo[e];
-                    if (sg[e] > 0.0f)
-                        yn = prox_kl_dual(__builtin_fmaf(sg[e], m[e] * v[e], yo[e]), sg[e], bb[e], rr[e]);
-                    P.y[full[e]] = yn;
-                    P.d[dual_row(G, ia, k) + q] = m[e] * (yn - yo[e]);
+                    qs[e] = q < nq ? q : -1;
+                    gs[e] = q < nq ? G.plane_seg[q] : 0;
+                    vs[e] = q < nq ? T[q] : 0.0f;
                 }
+                fwd_dual_batch<EB>(P, a, ia, k, qs, gs, vs);
             }
         } else {
             for (int q = lane; q < G.n_planes; q += 64)
                 fwd_epilogue<MODE>(P, a, ia, k, q, G.plane_seg[q], T[q], obj);
+        }
+    } else if (MODE == F_DUAL && !P.raw_kq) {
+        // four rays per lane at a time through fwd_dual_batch
+        constexpr int EB = RPL < 4 ? RPL : 4;
+#pragma unroll
+        for (int r0 = 0; r0 < RPL; r0 += EB) {
+            int qs[EB], gs[EB];
+            float vs[EB];
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int q = lane + 64 * (r0 + e);
+                const bool ok = r0 + e < RPL && q < G.n_planes;
+                qs[e] = ok ? q : -1;
+                gs[e] = ok ? G.plane_seg[q] : 0;
+                vs[e] = r0 + e < RPL ? acc[r0 + e < RPL ? r0 + e : 0] : 0.0f;
+            }
+            fwd_dual_batch<EB>(P, a, ia, k, qs, gs, vs);
         }
     } else {
 #pragma unroll
