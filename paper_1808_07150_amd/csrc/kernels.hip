@@ -1187,14 +1187,16 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
             }
         }
     }
-    if constexpr (MODE == B_ITER) {
-        // The epilogue of Algorithm 2 (z += dz; x = max(x - T (z + dz / p_i), 0)) in two
-        // batches of five columns: all loads of a batch (z, x, T and the partial image, 40
-        // per lane) are issued before its first store, so a wavefront waits for two round
-        // trips instead of two per voxel.  The loads go through range-checked buffer
-        // resources, so lanes outside the image (z = -1, z >= nz, columns past the edge)
-        // read a neighbouring voxel or zero; only lanes inside it store.  The arithmetic
-        // is that of bwd_epilogue.
+    if constexpr (MODE == B_ITER || MODE == B_PAIR) {
+        // The epilogue of Algorithm 2 (z += dz; x = max(x - T (z + dz / p_i), 0)) in
+        // batches of columns (five; two for the compensated state, whose low parts of z
+        // and x add two loads per voxel): all loads of a batch (z, x, T, the partial image
+        // and the low parts) are issued before its first store, so a wavefront waits for
+        // one round trip per batch instead of two per voxel.  The loads go through
+        // range-checked buffer resources, so lanes outside the image (z = -1, z >= nz,
+        // columns past the edge) read a neighbouring voxel or zero; only lanes inside it
+        // store.  The arithmetic is that of bwd_epilogue.
+        constexpr bool PAIR = MODE == B_PAIR;
         const int nvb = 4 * G.nx * G.ny * nz;  // below 1 GiB
         const auto rz = __builtin_amdgcn_make_buffer_rsrc(P.z, (short)0, nvb, 0x00020000);
         const auto rx = __builtin_amdgcn_make_buffer_rsrc(P.x, (short)0, nvb, 0x00020000);
@@ -1202,11 +1204,15 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
                                                           nvb, 0x00020000);
         const auto rp = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float*>(partial ? partial : P.T), (short)0, nvb, 0x00020000);
-        constexpr int CB = 5;
+        const auto rzl = __builtin_amdgcn_make_buffer_rsrc(PAIR ? P.zlo : P.z, (short)0, nvb,
+                                                           0x00020000);
+        const auto rxl = __builtin_amdgcn_make_buffer_rsrc(PAIR ? P.xlo : P.x, (short)0, nvb,
+                                                           0x00020000);
+        constexpr int CB = PAIR ? 2 : 5;
         static_assert(BS_W % CB == 0, "whole batches of columns");
 #pragma unroll
         for (int cb = 0; cb < BS_W; cb += CB) {
-            float zv[CB][2], xv[CB][2], tv[CB][2], pv[CB][2];
+            float zv[CB][2], xv[CB][2], tv[CB][2], pv[CB][2], zlv[CB][2], xlv[CB][2];
             uint32_t off[CB][2];
 #pragma unroll
             for (int u = 0; u < CB; ++u) {
@@ -1221,6 +1227,11 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
                     pv[u][hh] = partial ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
                                               rp, off[u][hh], 0, 0))
                                         : 0.0f;
+                    zlv[u][hh] = xlv[u][hh] = 0.0f;
+                    if constexpr (PAIR) {
+                        zlv[u][hh] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rzl, off[u][hh], 0, 0));
+                        xlv[u][hh] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rxl, off[u][hh], 0, 0));
+                    }
                 }
             }
 #pragma unroll
@@ -1231,12 +1242,21 @@ __global__ void __launch_bounds__(256, 7) bwd_strip(BwdArgs P, int KR, int rowdo
                     const int iz = zl + 64 * hh;
                     if (iz < 0 || iz >= nz) continue;
                     const float dz = acc[cb + u][hh] + pv[u][hh];
-                    const float zn = zv[u][hh] + dz;
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(zn), rz, off[u][hh], 0, 0);
-                    const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
-                    __builtin_amdgcn_raw_buffer_store_b32(
-                        __float_as_uint(fmaxf(xv[u][hh] - tv[u][hh] * zbar, 0.0f)), rx,
-                        off[u][hh], 0, 0);
+                    if constexpr (PAIR) {
+                        float xh = xv[u][hh], xl = xlv[u][hh], zh = zv[u][hh], zlo = zlv[u][hh];
+                        primal_pair(xh, xl, zh, zlo, tv[u][hh], dz, P.inv_p);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(zh), rz, off[u][hh], 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(zlo), rzl, off[u][hh], 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(xh), rx, off[u][hh], 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(xl), rxl, off[u][hh], 0, 0);
+                    } else {
+                        const float zn = zv[u][hh] + dz;
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(zn), rz, off[u][hh], 0, 0);
+                        const float zbar = __builtin_fmaf(dz, P.inv_p, zn);
+                        __builtin_amdgcn_raw_buffer_store_b32(
+                            __float_as_uint(fmaxf(xv[u][hh] - tv[u][hh] * zbar, 0.0f)), rx,
+                            off[u][hh], 0, 0);
+                    }
                 }
             }
         }
